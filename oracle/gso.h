@@ -98,8 +98,12 @@ typedef struct {
 /* Straddle margins for decisions that FP32 and FP64 can take differently. */
 #define GSO_MARGIN_INT   1e-9       /* absolute, on a value about to be floor/ceil'd */
 #define GSO_MARGIN_NEAR  1e-9       /* absolute, on p_z - near */
-#define GSO_MARGIN_ALPHA 1e-4       /* relative, on o*exp(power) vs 1/255 */
-#define GSO_MARGIN_T     1e-4       /* relative, on T(1-alpha) vs 1e-4 */
+/* FP32 bounds the margins cover: a splat's alpha at a pixel carries a
+ * relative error of about 1e-6 (conic rounded once, pixel offsets formed from
+ * an (hi, lo) centre, one exp), and the transmittance after ~70 blends one of
+ * at most ~1.2e-5; 2e-5 covers both. */
+#define GSO_MARGIN_ALPHA 2e-5       /* relative, on o*exp(power) vs 1/255 */
+#define GSO_MARGIN_T     2e-5       /* relative, on T(1-alpha) vs 1e-4 */
 #define GSO_SIGNIFICANT_T 1e-3      /* an alpha straddle below this T is harmless */
 
 int gso_version(void);
