@@ -1,0 +1,198 @@
+/*
+ * gsp.h -- C ABI of the MI355X (gfx950) pose-differentiable 3D Gaussian
+ * splatting rasterizer.
+ *
+ * The library implements the hot path of "Look Gauss, No Pose"
+ * (arXiv 2410.08743): render a view of a Gaussian set from a camera with
+ * intrinsics K and world-to-camera extrinsics T = (R_c, t_c) (Sec. III-A,
+ * Eq. (1)-(4)), and back-propagate an image gradient to the Gaussian
+ * parameters and to the camera pose, the latter as a gradient on the se(3)
+ * tangent vector tau (Sec. III-B, Eq. (5)-(13)).
+ *
+ * Conventions shared by every call:
+ *  - All pointers marked "device" are HIP device (or managed) memory on the
+ *    context's device; pointers marked "host" are ordinary host memory that
+ *    the call reads before returning.  The caller owns every buffer.  The
+ *    library allocates no device memory after gsp_create.
+ *  - Work is enqueued on the given HIP stream (NULL = the default stream) and
+ *    calls return without synchronising, except gsp_instances.
+ *  - Every call returns a gsp_status.  Argument errors return GSP_EINVAL
+ *    before anything is enqueued; gsp_last_error() then describes the
+ *    problem (thread-local, valid until the next call on the same thread).
+ *  - Floats are IEEE binary32.  Poses are world->camera [R | t], row-major
+ *    3 x 4.  Quaternions are (w, x, y, z) and need not be normalised; the
+ *    library normalises them and differentiates through the normalisation.
+ *  - Images are CHW binary32 per view, 3 x roi_h x roi_w, and the views of one
+ *    call are packed one after another in view order.
+ *  - The pose gradient is the left-perturbation twist: for T(tau) =
+ *    Exp(tau) T with tau = (rho, phi) (translation first), d[V][6] holds
+ *    dL/dtau at tau = 0.  Under this convention the camera centre moves by
+ *    -R_c^T rho and not at all under phi, which is how the colour term of
+ *    Eq. (7) enters (the paper's Eq. (11) prints a mixed convention).
+ *  - Rasterizer constants not stated in the paper (16 x 16 tiles, near plane
+ *    0.2, covariance dilation 0.3 px^2, Jacobian clamp 1.3 x tan(fov/2),
+ *    3-sigma radius, alpha <= 0.99, skip alpha < 1/255, stop before the
+ *    transmittance falls below 1e-4) are fixed at build time.
+ */
+#ifndef GSP_H
+#define GSP_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    GSP_OK = 0,
+    GSP_EINVAL = 1,        /* bad argument; nothing was enqueued */
+    GSP_ECAPACITY = 2,     /* more (Gaussian, tile) instances than capacity */
+    GSP_ENOMEM = 3,        /* workspace too small for the request */
+    GSP_EHIP = 4,          /* a HIP runtime call failed */
+    GSP_EUNSUPPORTED = 5   /* not available on this device / build */
+} gsp_status;
+
+typedef struct gsp_ctx gsp_ctx;   /* opaque; one per device */
+
+/* Maximum number of views rendered by one call. */
+#define GSP_MAX_VIEWS 32
+
+/* Gaussian set G of Sec. III-A.  Device pointers, structure-of-arrays:
+ * means [n][3]; scales [n][3] (activated, > 0); quats [n][4] (w, x, y, z,
+ * nonzero); opacities [n] (activated, in (0, 1)); sh [n][S][3] with
+ * S = (sh_degree + 1)^2, colour = max(0, sum_k sh[k] Y_k(d) + 1/2) where Y is
+ * the real spherical-harmonic basis (Condon-Shortley phase, m = -l..l). */
+typedef struct {
+    const float *means;
+    const float *scales;
+    const float *quats;
+    const float *opacities;
+    const float *sh;
+    int64_t n;            /* 0 <= n < 2^31 / views */
+    int32_t sh_degree;    /* 0..3 */
+} gsp_gaussians;
+
+/* One camera (host struct).  Pixel (i, j) of the full image is sampled at
+ * continuous coordinates (i + 1/2, j + 1/2); projection is
+ * x = fx * X / Z + cx.  The rendered region of interest starts at a multiple
+ * of 16 pixels (roi_x, roi_y), lies inside the image and may have any size;
+ * it equals the corresponding crop of the full-image render exactly. */
+typedef struct {
+    int32_t width, height;
+    float fx, fy, cx, cy;
+    int32_t roi_x, roi_y, roi_w, roi_h;
+    float bg[3];          /* background colour, blended with weight T_final */
+} gsp_view;
+
+/* Gradient outputs of gsp_render_bwd (device pointers, same layouts as
+ * gsp_gaussians).  A NULL member is not computed; when every Gaussian member
+ * is NULL only the pose gradient is produced.  Gaussian gradients are summed
+ * over the call's views.  pose: device [V][6], may be NULL. */
+typedef struct {
+    float *means;
+    float *scales;
+    float *quats;
+    float *opacities;
+    float *sh;
+    float *pose;
+} gsp_grads;
+
+/* Flags for gsp_render_bwd. */
+#define GSP_ACCUMULATE 1u  /* add into the gradient buffers instead of overwriting */
+
+/* Hyper-parameters of the tangent-space Adam step (gsp_pose_adam).  The
+ * learning rate follows a cosine decay from lr_start to lr_end over
+ * total_steps steps (constant when they are equal). */
+typedef struct {
+    float lr_start, lr_end;
+    int32_t total_steps;
+    float beta1, beta2, eps;
+} gsp_adam_params;
+
+/* Creates a context on HIP device `device` (validates that it is gfx950). */
+gsp_status gsp_create(int device, gsp_ctx **out);
+gsp_status gsp_destroy(gsp_ctx *ctx);
+
+/* Bytes of device workspace that a render of V views of n Gaussians with room
+ * for `instance_capacity` (Gaussian, tile) pairs needs.  The same workspace
+ * carries the forward state (projected splats, sorted instances, tile ranges,
+ * per-pixel T_final and contributor counts) to the backward. */
+gsp_status gsp_workspace_size(int64_t n, int32_t sh_degree, int32_t V, const gsp_view *views,
+                              int64_t instance_capacity, size_t *bytes);
+
+/* Forward render (Sec. III-A): projection and EWA covariance (Eq. (1)-(2)),
+ * SH colour, tile binning, 64-bit (tile | depth) radix sort, per-tile ranges
+ * and front-to-back compositing (Eq. (3)-(4)).
+ *   g          Gaussians (device arrays)
+ *   V, views   1..GSP_MAX_VIEWS host view descriptors
+ *   poses      device [V][3][4] world->camera
+ *   images     device output, packed [V][3][roi_h][roi_w]
+ *   alphas     device output or NULL, packed [V][roi_h][roi_w] = 1 - T_final
+ *   workspace  device, ws_bytes >= gsp_workspace_size(..., instance_capacity)
+ * When the number of instances M exceeds instance_capacity the excess work is
+ * skipped on the device and the outputs are undefined; gsp_instances then
+ * reports the overflow and the M needed.  Returns GSP_OK once enqueued. */
+gsp_status gsp_render_fwd(gsp_ctx *ctx, const gsp_gaussians *g, int32_t V, const gsp_view *views,
+                          const float *poses, float *images, float *alphas,
+                          void *workspace, size_t ws_bytes, int64_t instance_capacity,
+                          void *stream);
+
+/* Backward of the last gsp_render_fwd made with this workspace and the same
+ * g, views, poses and capacity.  dl_dimages: device, packed like images.
+ * The per-pixel lists are recomputed back to front from T_final and the
+ * contributor count instead of being stored; gradients of the 2D splats are
+ * reduced per (tile, Gaussian) and then per Gaussian in a fixed order, and
+ * the per-view pose gradient (Eq. (7)-(13)) is reduced with wavefront
+ * shuffles and block reductions in a fixed order, so results are
+ * bit-reproducible run to run. */
+gsp_status gsp_render_bwd(gsp_ctx *ctx, const gsp_gaussians *g, int32_t V, const gsp_view *views,
+                          const float *poses, const float *dl_dimages,
+                          void *workspace, size_t ws_bytes, int64_t instance_capacity,
+                          const gsp_grads *grads, uint32_t flags, void *stream);
+
+/* Synchronises `stream` and reports the instance count M of the last forward
+ * in `workspace`, and whether that forward or any earlier one on the same
+ * workspace (since the caller zero-filled it) exceeded its capacity.  The
+ * workspace keeps these counters in its first 64 bytes. */
+gsp_status gsp_instances(gsp_ctx *ctx, const void *workspace, void *stream,
+                         int64_t *m_out, int32_t *overflow_out);
+
+/* Mean absolute error (the L1 part of Eq. (16)): loss = mean |pred - target|
+ * over count values, grad = sign(pred - target) / count (0 where equal).
+ * pred, target, grad: device [count].  loss: device float or NULL; when it
+ * is given, scratch must be device memory of gsp_loss_l1_scratch_bytes(count)
+ * bytes, and the loss is reduced in a fixed order (bit-reproducible). */
+gsp_status gsp_loss_l1(gsp_ctx *ctx, int64_t count, const float *pred, const float *target,
+                       float *grad, float *loss, void *scratch, void *stream);
+size_t gsp_loss_l1_scratch_bytes(int64_t count);
+
+/* One tangent-space Adam step per view (Sec. III-B: pose T = Exp(tau) with
+ * the update retracted on the left): for each v, steps[v] += 1,
+ * m, v moments updated with dpose[v], delta = -lr mhat / (sqrt(vhat) + eps),
+ * poses[v] <- Exp(delta) poses[v].  poses [V][12], dpose/m/v [V][6],
+ * steps [V] int32: device.  V >= 1, no upper limit. */
+gsp_status gsp_pose_adam(gsp_ctx *ctx, int32_t V, float *poses, const float *dpose,
+                         float *m, float *v, int32_t *steps, const gsp_adam_params *params,
+                         void *stream);
+
+/* Workspace introspection for tests: device pointer and element count of an
+ * intermediate array of the last forward/backward.  Names: "geom" (float4
+ * pairs per view-Gaussian: u_hi v_hi u_lo v_lo | A B C o), "color" (float4),
+ * "rect" (uint16 x0 y0 x1 y1), "depth" (uint32 float bits), "tiles"
+ * (uint32 count), "keys" (uint64 sorted), "values" (uint32 sorted),
+ * "ranges" (uint32 pairs per tile), "tfinal" (float per pixel),
+ * "ncontrib" (uint32 per pixel), "grad2d" (float [9][V*n]: du dv dA dB dC
+ * do dr dg db), "counters" (uint32: M, overflow). */
+gsp_status gsp_inspect(gsp_ctx *ctx, const gsp_gaussians *g, int32_t V, const gsp_view *views,
+                       void *workspace, size_t ws_bytes, int64_t instance_capacity,
+                       const char *name, void **ptr, int64_t *count);
+
+const char *gsp_status_string(gsp_status s);
+const char *gsp_last_error(void);
+int gsp_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* GSP_H */

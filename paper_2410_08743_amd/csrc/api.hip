@@ -1,0 +1,397 @@
+// api.hip -- the C ABI of include/gsp.h: argument validation, the per-call
+// view table, workspace carving and the launch sequence of the forward and
+// backward passes.  Host code only; every step of the path runs in the
+// kernels of the other files.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <string>
+
+#include "gsp_internal.h"
+
+struct gsp_ctx {
+    int device;
+};
+
+namespace {
+
+thread_local std::string g_last_error;
+
+gsp_status fail(gsp_status s, const char *fmt, ...) __attribute__((format(printf, 2, 3)));
+gsp_status fail(gsp_status s, const char *fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_last_error = buf;
+    return s;
+}
+
+gsp_status hip_fail(hipError_t e, const char *where) {
+    return fail(GSP_EHIP, "%s: %s", where, hipGetErrorString(e));
+}
+
+size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
+
+gsp_status check_device(const gsp_ctx *ctx) {
+    if (!ctx) return fail(GSP_EINVAL, "null context");
+    int dev = -1;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
+    if (dev != ctx->device)
+        return fail(GSP_EINVAL, "current device %d differs from the context's device %d", dev,
+                    ctx->device);
+    return GSP_OK;
+}
+
+// Validates the views and fills the kernel view table.
+gsp_status make_views(int32_t V, const gsp_view *views, gsp::ViewsK *out, int64_t *total_pix) {
+    if (V < 1 || V > GSP_MAX_VIEWS)
+        return fail(GSP_EINVAL, "view count %d outside 1..%d", V, GSP_MAX_VIEWS);
+    if (!views) return fail(GSP_EINVAL, "null views");
+    std::memset(out, 0, sizeof *out);
+    int64_t tiles = 0, pix = 0;
+    for (int v = 0; v < V; v++) {
+        const gsp_view &w = views[v];
+        if (w.width <= 0 || w.height <= 0 || w.width > 65535 * gsp::kTile ||
+            w.height > 65535 * gsp::kTile)
+            return fail(GSP_EINVAL, "view %d: bad image size %dx%d", v, w.width, w.height);
+        if (!(w.fx > 0.f) || !(w.fy > 0.f) || !std::isfinite(w.cx) || !std::isfinite(w.cy))
+            return fail(GSP_EINVAL, "view %d: bad intrinsics", v);
+        if (w.roi_x < 0 || w.roi_y < 0 || w.roi_w <= 0 || w.roi_h <= 0 ||
+            w.roi_x % gsp::kTile || w.roi_y % gsp::kTile || w.roi_x + w.roi_w > w.width ||
+            w.roi_y + w.roi_h > w.height)
+            return fail(GSP_EINVAL,
+                        "view %d: region of interest (%d,%d,%d,%d) must start on a multiple of "
+                        "16 and lie inside the %dx%d image",
+                        v, w.roi_x, w.roi_y, w.roi_w, w.roi_h, w.width, w.height);
+        gsp::ViewK &k = out->v[v];
+        k.W = w.width;
+        k.H = w.height;
+        k.fx = w.fx;
+        k.fy = w.fy;
+        k.cx = w.cx;
+        k.cy = w.cy;
+        k.roi_x = w.roi_x;
+        k.roi_y = w.roi_y;
+        k.roi_w = w.roi_w;
+        k.roi_h = w.roi_h;
+        k.gw = (w.roi_w + gsp::kTile - 1) / gsp::kTile;
+        k.gh = (w.roi_h + gsp::kTile - 1) / gsp::kTile;
+        k.tile_base = (int)tiles;
+        k.pix_base = (int)pix;
+        for (int c = 0; c < 3; c++) k.bg[c] = w.bg[c];
+        tiles += (int64_t)k.gw * k.gh;
+        pix += (int64_t)w.roi_w * w.roi_h;
+    }
+    if (tiles >= (1ll << 31) || pix >= (1ll << 31))
+        return fail(GSP_EINVAL, "too many tiles or pixels in one call");
+    out->count = V;
+    out->total_tiles = (int)tiles;
+    *total_pix = pix;
+    return GSP_OK;
+}
+
+gsp_status check_gaussians(const gsp_gaussians *g, int32_t V) {
+    if (!g) return fail(GSP_EINVAL, "null Gaussians");
+    if (g->n < 0 || g->n * (int64_t)V >= (1ll << 31))
+        return fail(GSP_EINVAL, "Gaussian count %lld too large for %d views", (long long)g->n, V);
+    if (g->sh_degree < 0 || g->sh_degree > 3)
+        return fail(GSP_EINVAL, "sh_degree %d outside 0..3", g->sh_degree);
+    if (g->n > 0 && (!g->means || !g->scales || !g->quats || !g->opacities || !g->sh))
+        return fail(GSP_EINVAL, "null Gaussian parameter array");
+    return GSP_OK;
+}
+
+gsp::GaussiansK kernel_gaussians(const gsp_gaussians *g) {
+    gsp::GaussiansK k;
+    k.means = g->means;
+    k.scales = g->scales;
+    k.quats = g->quats;
+    k.opacities = g->opacities;
+    k.sh = g->sh;
+    k.n = (int)g->n;
+    k.sh_degree = g->sh_degree;
+    return k;
+}
+
+struct Prepared {
+    gsp::ViewsK views;
+    gsp::Layout L;
+};
+
+gsp_status prepare(const gsp_gaussians *g, int32_t V, const gsp_view *views, int64_t cap,
+                   Prepared *p) {
+    gsp_status s = check_gaussians(g, V);
+    if (s != GSP_OK) return s;
+    int64_t total_pix = 0;
+    s = make_views(V, views, &p->views, &total_pix);
+    if (s != GSP_OK) return s;
+    if (cap < 0 || cap >= (1ll << 32) - 1)
+        return fail(GSP_EINVAL, "instance capacity %lld outside 0..2^32-2", (long long)cap);
+    p->L = gsp::make_layout(g->n, g->sh_degree, V, p->views, cap);
+    return GSP_OK;
+}
+
+}  // namespace
+
+namespace gsp {
+
+Layout make_layout(int64_t n, int32_t sh_degree, int32_t V, const ViewsK &views, int64_t cap) {
+    Layout L;
+    std::memset(&L, 0, sizeof L);
+    L.n = n;
+    L.V = V;
+    L.vn = n * V;
+    L.S = (sh_degree + 1) * (sh_degree + 1);
+    L.cap = cap > 0 ? cap : 1;
+    L.total_tiles = views.total_tiles;
+    int64_t pix = 0;
+    for (int v = 0; v < V; v++) pix += (int64_t)views.v[v].roi_w * views.v[v].roi_h;
+    L.total_pix = pix;
+    L.nblk_pre = (int)((n + kPreprocessBlock - 1) / kPreprocessBlock);
+    L.nblk_sort = (int)((L.cap + kSortItems - 1) / kSortItems);
+    L.sort_passes = sort_passes_for(views.total_tiles);
+    const size_t vn = (size_t)L.vn, capz = (size_t)L.cap;
+    size_t off = 0;
+    auto take = [&](size_t bytes) {
+        const size_t o = off;
+        off += align256(bytes > 0 ? bytes : 1);
+        return o;
+    };
+    L.counters = take(kCntCount * 4);   // first, so that gsp_instances needs no sizes
+    L.geom = take(vn * 32);
+    L.color = take(vn * 16);
+    L.rect = take(vn * 8);
+    L.depth = take(vn * 4);
+    L.tiles = take(vn * 4);
+    L.offsets = take(vn * 4);
+    L.blocksum = take((size_t)V * L.nblk_pre * 8 + 8);
+    L.keys0 = take(capz * 8);
+    L.keys1 = take(capz * 8);
+    L.vals0 = take(capz * 4);
+    L.vals1 = take(capz * 4);
+    L.hist = take((size_t)kSortBins * L.nblk_sort * 4);
+    L.digit_tot = take((size_t)kSortBins * 4);
+    L.ranges = take((size_t)L.total_tiles * 8);
+    L.tfinal = take((size_t)pix * 4);
+    L.ncontrib = take((size_t)pix * 4);
+    L.slots = take(9 * capz * 4);
+    L.grad2d = take(9 * vn * 4);
+    L.posepart = take((size_t)V * L.nblk_pre * 6 * 8);
+    L.total = off;
+    return L;
+}
+
+}  // namespace gsp
+
+extern "C" {
+
+int gsp_version(void) { return 1; }
+
+const char *gsp_status_string(gsp_status s) {
+    switch (s) {
+        case GSP_OK: return "ok";
+        case GSP_EINVAL: return "invalid argument";
+        case GSP_ECAPACITY: return "instance capacity exceeded";
+        case GSP_ENOMEM: return "workspace too small";
+        case GSP_EHIP: return "HIP runtime error";
+        case GSP_EUNSUPPORTED: return "unsupported";
+    }
+    return "unknown status";
+}
+
+const char *gsp_last_error(void) { return g_last_error.c_str(); }
+
+gsp_status gsp_create(int device, gsp_ctx **out) {
+    if (!out) return fail(GSP_EINVAL, "null output pointer");
+    *out = nullptr;
+    int count = 0;
+    hipError_t e = hipGetDeviceCount(&count);
+    if (e != hipSuccess) return hip_fail(e, "hipGetDeviceCount");
+    if (device < 0 || device >= count)
+        return fail(GSP_EINVAL, "device %d outside 0..%d", device, count - 1);
+    hipDeviceProp_t prop;
+    e = hipGetDeviceProperties(&prop, device);
+    if (e != hipSuccess) return hip_fail(e, "hipGetDeviceProperties");
+    if (std::strncmp(prop.gcnArchName, "gfx950", 6) != 0)
+        return fail(GSP_EUNSUPPORTED, "device %d is %s; this library is built for gfx950", device,
+                    prop.gcnArchName);
+    gsp_ctx *ctx = new (std::nothrow) gsp_ctx;
+    if (!ctx) return fail(GSP_ENOMEM, "out of host memory");
+    ctx->device = device;
+    *out = ctx;
+    return GSP_OK;
+}
+
+gsp_status gsp_destroy(gsp_ctx *ctx) {
+    delete ctx;
+    return GSP_OK;
+}
+
+gsp_status gsp_workspace_size(int64_t n, int32_t sh_degree, int32_t V, const gsp_view *views,
+                              int64_t instance_capacity, size_t *bytes) {
+    if (!bytes) return fail(GSP_EINVAL, "null output pointer");
+    gsp_gaussians g;
+    std::memset(&g, 0, sizeof g);
+    g.n = n;
+    g.sh_degree = sh_degree;
+    if (n < 0 || sh_degree < 0 || sh_degree > 3) return fail(GSP_EINVAL, "bad n or sh_degree");
+    Prepared p;
+    int64_t total_pix;
+    gsp_status s = make_views(V, views, &p.views, &total_pix);
+    if (s != GSP_OK) return s;
+    if (instance_capacity < 0 || instance_capacity >= (1ll << 32) - 1)
+        return fail(GSP_EINVAL, "instance capacity out of range");
+    *bytes = gsp::make_layout(n, sh_degree, V, p.views, instance_capacity).total;
+    return GSP_OK;
+}
+
+gsp_status gsp_render_fwd(gsp_ctx *ctx, const gsp_gaussians *g, int32_t V, const gsp_view *views,
+                          const float *poses, float *images, float *alphas, void *workspace,
+                          size_t ws_bytes, int64_t instance_capacity, void *stream) {
+    gsp_status s = check_device(ctx);
+    if (s != GSP_OK) return s;
+    Prepared p;
+    s = prepare(g, V, views, instance_capacity, &p);
+    if (s != GSP_OK) return s;
+    if (!poses || !images || !workspace) return fail(GSP_EINVAL, "null poses, images or workspace");
+    if (ws_bytes < p.L.total)
+        return fail(GSP_ENOMEM, "workspace of %zu bytes is smaller than the %zu needed", ws_bytes,
+                    p.L.total);
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    char *ws = static_cast<char *>(workspace);
+    const gsp::GaussiansK gk = kernel_gaussians(g);
+    hipError_t e;
+    if ((e = gsp::launch_preprocess(gk, p.views, poses, p.L, ws, st)) != hipSuccess)
+        return hip_fail(e, "preprocess");
+    if ((e = gsp::launch_offsets_and_duplicate(p.views, p.L, ws, st)) != hipSuccess)
+        return hip_fail(e, "duplicate");
+    uint64_t *keys;
+    uint32_t *vals;
+    if ((e = gsp::launch_sort(p.L, ws, st, &keys, &vals)) != hipSuccess) return hip_fail(e, "sort");
+    if ((e = gsp::launch_ranges(p.L, ws, keys, st)) != hipSuccess) return hip_fail(e, "ranges");
+    if ((e = gsp::launch_raster_fwd(p.views, p.L, ws, vals, images, alphas, st)) != hipSuccess)
+        return hip_fail(e, "raster forward");
+    return GSP_OK;
+}
+
+gsp_status gsp_render_bwd(gsp_ctx *ctx, const gsp_gaussians *g, int32_t V, const gsp_view *views,
+                          const float *poses, const float *dl_dimages, void *workspace,
+                          size_t ws_bytes, int64_t instance_capacity, const gsp_grads *grads,
+                          uint32_t flags, void *stream) {
+    gsp_status s = check_device(ctx);
+    if (s != GSP_OK) return s;
+    Prepared p;
+    s = prepare(g, V, views, instance_capacity, &p);
+    if (s != GSP_OK) return s;
+    if (!poses || !dl_dimages || !workspace || !grads)
+        return fail(GSP_EINVAL, "null poses, dl_dimages, workspace or grads");
+    if (flags & ~GSP_ACCUMULATE) return fail(GSP_EINVAL, "unknown flags 0x%x", flags);
+    if (ws_bytes < p.L.total)
+        return fail(GSP_ENOMEM, "workspace of %zu bytes is smaller than the %zu needed", ws_bytes,
+                    p.L.total);
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    char *ws = static_cast<char *>(workspace);
+    const bool odd = p.L.sort_passes & 1;
+    const uint32_t *vals = gsp::region<uint32_t>(ws, odd ? p.L.vals1 : p.L.vals0);
+    hipError_t e;
+    if ((e = gsp::launch_raster_bwd(p.views, p.L, ws, vals, dl_dimages, st)) != hipSuccess)
+        return hip_fail(e, "raster backward");
+    if ((e = gsp::launch_preprocess_bwd(kernel_gaussians(g), p.views, poses, p.L, ws, *grads,
+                                        (flags & GSP_ACCUMULATE) != 0, st)) != hipSuccess)
+        return hip_fail(e, "preprocess backward");
+    return GSP_OK;
+}
+
+gsp_status gsp_instances(gsp_ctx *ctx, const void *workspace, void *stream, int64_t *m_out,
+                         int32_t *overflow_out) {
+    gsp_status s = check_device(ctx);
+    if (s != GSP_OK) return s;
+    if (!workspace) return fail(GSP_EINVAL, "null workspace");
+    hipError_t e = hipStreamSynchronize(static_cast<hipStream_t>(stream));
+    if (e != hipSuccess) return hip_fail(e, "hipStreamSynchronize");
+    uint32_t c[gsp::kCntCount];
+    e = hipMemcpy(c, workspace, sizeof c, hipMemcpyDeviceToHost);
+    if (e != hipSuccess) return hip_fail(e, "hipMemcpy");
+    if (m_out) *m_out = (int64_t)(((uint64_t)c[gsp::kCntMHi] << 32) | c[gsp::kCntMLo]);
+    if (overflow_out) *overflow_out = (int32_t)(c[gsp::kCntOverflow] | c[gsp::kCntSticky]);
+    return GSP_OK;
+}
+
+gsp_status gsp_inspect(gsp_ctx *ctx, const gsp_gaussians *g, int32_t V, const gsp_view *views,
+                       void *workspace, size_t ws_bytes, int64_t instance_capacity,
+                       const char *name, void **ptr, int64_t *count) {
+    gsp_status s = check_device(ctx);
+    if (s != GSP_OK) return s;
+    Prepared p;
+    s = prepare(g, V, views, instance_capacity, &p);
+    if (s != GSP_OK) return s;
+    if (!workspace || !name || !ptr || !count) return fail(GSP_EINVAL, "null argument");
+    if (ws_bytes < p.L.total) return fail(GSP_ENOMEM, "workspace too small for these sizes");
+    const gsp::Layout &L = p.L;
+    char *ws = static_cast<char *>(workspace);
+    const bool odd = L.sort_passes & 1;
+    struct Entry { const char *n; size_t off; int64_t cnt; };
+    const Entry table[] = {
+        {"geom", L.geom, 2 * L.vn},
+        {"color", L.color, L.vn},
+        {"rect", L.rect, L.vn},
+        {"depth", L.depth, L.vn},
+        {"tiles", L.tiles, L.vn},
+        {"offsets", L.offsets, L.vn},
+        {"keys", odd ? L.keys1 : L.keys0, L.cap},
+        {"values", odd ? L.vals1 : L.vals0, L.cap},
+        {"ranges", L.ranges, L.total_tiles},
+        {"tfinal", L.tfinal, L.total_pix},
+        {"ncontrib", L.ncontrib, L.total_pix},
+        {"grad2d", L.grad2d, 9 * L.vn},
+        {"counters", L.counters, gsp::kCntCount},
+    };
+    for (const Entry &en : table) {
+        if (std::strcmp(en.n, name) == 0) {
+            *ptr = ws + en.off;
+            *count = en.cnt;
+            return GSP_OK;
+        }
+    }
+    return fail(GSP_EINVAL, "unknown workspace array \"%s\"", name);
+}
+
+gsp_status gsp_loss_l1(gsp_ctx *ctx, int64_t count, const float *pred, const float *target,
+                       float *grad, float *loss, void *scratch, void *stream) {
+    gsp_status s = check_device(ctx);
+    if (s != GSP_OK) return s;
+    if (count < 0) return fail(GSP_EINVAL, "negative count");
+    if (count > 0 && (!pred || !target || !grad)) return fail(GSP_EINVAL, "null array");
+    if (loss && !scratch) return fail(GSP_EINVAL, "loss requires scratch memory");
+    hipError_t e = gsp::launch_loss_l1(count, pred, target, grad, loss, scratch,
+                                       static_cast<hipStream_t>(stream));
+    if (e != hipSuccess) return hip_fail(e, "loss");
+    return GSP_OK;
+}
+
+size_t gsp_loss_l1_scratch_bytes(int64_t count) {
+    return (size_t)(count > 0 ? gsp::loss_blocks(count) : 1) * sizeof(double);
+}
+
+gsp_status gsp_pose_adam(gsp_ctx *ctx, int32_t V, float *poses, const float *dpose, float *m,
+                         float *v, int32_t *steps, const gsp_adam_params *params, void *stream) {
+    gsp_status s = check_device(ctx);
+    if (s != GSP_OK) return s;
+    if (V < 1) return fail(GSP_EINVAL, "view count must be positive");
+    if (!poses || !dpose || !m || !v || !steps || !params) return fail(GSP_EINVAL, "null argument");
+    if (!(params->beta1 >= 0.f && params->beta1 < 1.f && params->beta2 >= 0.f &&
+          params->beta2 < 1.f && params->eps > 0.f))
+        return fail(GSP_EINVAL, "bad Adam hyper-parameters");
+    hipError_t e = gsp::launch_pose_adam(V, poses, dpose, m, v, steps, *params,
+                                         static_cast<hipStream_t>(stream));
+    if (e != hipSuccess) return hip_fail(e, "pose adam");
+    return GSP_OK;
+}
+
+}  // extern "C"

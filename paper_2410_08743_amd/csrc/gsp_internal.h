@@ -1,0 +1,117 @@
+// gsp_internal.h -- internal declarations of the MI355X rasterizer library.
+//
+// Kernel-side constants, the per-call view table passed to kernels by value,
+// the carving of the caller's workspace, and the host launchers of every
+// kernel.  Nothing here is part of the public ABI (include/gsp.h).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+#include "../../include/gsp.h"
+
+namespace gsp {
+
+// ---------------------------------------------------------------------------
+// Rasterizer constants.  The paper defers these to the 3DGS rasterizer it
+// extends (Sec. III-A); the values are the readings fixed for this library.
+// ---------------------------------------------------------------------------
+constexpr int kTile = 16;                // tile edge in pixels
+constexpr double kNear = 0.2;            // cull when camera-frame z <= near
+constexpr double kDilation = 0.3;        // px^2 added to the 2D covariance diagonal
+constexpr double kJClamp = 1.3;          // |x/z| clamp, in units of tan(fov/2)
+constexpr double kLambdaFloor = 0.1;     // floor under the eigenvalue discriminant
+constexpr float kAlphaMax = 0.99f;       // opacity clamp of a splat at a pixel
+constexpr float kAlphaMin = 1.0f / 255.0f;  // splats below this alpha are skipped
+constexpr float kTMin = 1e-4f;           // stop before transmittance drops below
+
+constexpr int kPreprocessBlock = 256;    // Gaussians per preprocess block
+constexpr int kSortThreads = 256;
+constexpr int kSortRounds = 16;
+constexpr int kSortItems = kSortThreads * kSortRounds;  // keys per sort block
+constexpr int kSortBits = 8;             // radix digit width
+constexpr int kSortBins = 1 << kSortBits;
+constexpr int kPoseReduceBlock = 256;
+
+// Per-view constants, computed on the host once per call.
+struct ViewK {
+    int W, H;
+    float fx, fy, cx, cy;
+    int roi_x, roi_y, roi_w, roi_h;
+    int gw, gh;          // tile grid of the region of interest
+    int tile_base;       // first global tile id of this view
+    int pix_base;        // first pixel of this view in packed per-pixel arrays
+    float bg[3];
+};
+
+struct ViewsK {
+    ViewK v[GSP_MAX_VIEWS];
+    int count;
+    int total_tiles;
+};
+
+// Carving of the caller's workspace.  Every region is 256-byte aligned.
+struct Layout {
+    int64_t n, vn, cap, total_pix;
+    int32_t V, S, total_tiles, nblk_pre, nblk_sort, sort_passes;
+    size_t geom, color, rect, depth, tiles, offsets, blocksum, counters;
+    size_t keys0, keys1, vals0, vals1, hist, digit_tot, ranges;
+    size_t tfinal, ncontrib, slots, grad2d, posepart;
+    size_t total;
+};
+
+// Counters at the start of the counters region.
+// kCntSticky keeps the OR of every overflow since the workspace was zeroed.
+enum Counter : int {
+    kCntMLo = 0, kCntMHi = 1, kCntOverflow = 2, kCntMEff = 3, kCntSticky = 4, kCntCount = 16
+};
+
+Layout make_layout(int64_t n, int32_t sh_degree, int32_t V, const ViewsK &views, int64_t cap);
+
+// ---------------------------------------------------------------------------
+// Launchers (each .hip file defines its own kernels and launchers).
+// ---------------------------------------------------------------------------
+struct GaussiansK {
+    const float *means, *scales, *quats, *opacities, *sh;
+    int n, sh_degree;
+};
+
+// preprocess.hip
+hipError_t launch_preprocess(const GaussiansK &g, const ViewsK &views, const float *poses,
+                             const Layout &L, char *ws, hipStream_t s);
+hipError_t launch_offsets_and_duplicate(const ViewsK &views, const Layout &L, char *ws,
+                                        hipStream_t s);
+// sort.hip
+hipError_t launch_sort(const Layout &L, char *ws, hipStream_t s, uint64_t **keys_out,
+                       uint32_t **vals_out);
+// raster_fwd.hip
+hipError_t launch_ranges(const Layout &L, char *ws, const uint64_t *keys, hipStream_t s);
+hipError_t launch_raster_fwd(const ViewsK &views, const Layout &L, char *ws,
+                             const uint32_t *vals, float *images, float *alphas, hipStream_t s);
+// raster_bwd.hip
+hipError_t launch_raster_bwd(const ViewsK &views, const Layout &L, char *ws,
+                             const uint32_t *vals, const float *dl_dimages, hipStream_t s);
+// preprocess_bwd.hip
+hipError_t launch_preprocess_bwd(const GaussiansK &g, const ViewsK &views, const float *poses,
+                                 const Layout &L, char *ws, const gsp_grads &grads,
+                                 bool accumulate, hipStream_t s);
+// misc.hip
+hipError_t launch_fill_u32(uint32_t *p, uint32_t value, int64_t count, hipStream_t s);
+hipError_t launch_loss_l1(int64_t count, const float *pred, const float *target, float *grad,
+                          float *loss, void *scratch, hipStream_t s);
+int64_t loss_blocks(int64_t count);
+hipError_t launch_pose_adam(int V, float *poses, const float *dpose, float *m, float *v,
+                            int32_t *steps, const gsp_adam_params &p, hipStream_t s);
+
+template <typename T>
+inline T *region(char *ws, size_t off) { return reinterpret_cast<T *>(ws + off); }
+
+inline int sort_passes_for(int total_tiles) {
+    int tile_bits = 0;
+    while ((1ll << tile_bits) < (long long)total_tiles) tile_bits++;
+    const int bits = 32 + tile_bits;
+    return (bits + kSortBits - 1) / kSortBits;
+}
+
+}  // namespace gsp

@@ -1,0 +1,142 @@
+// misc.hip -- small kernels around the rasterizer: buffer fill, the L1
+// photometric loss with its gradient (the L1 part of Eq. (16)), and the
+// tangent-space Adam step with left retraction on each pose (Sec. III-B:
+// T = Exp(tau), gradients taken on tau).
+#include "block_ops.h"
+#include "gsp_internal.h"
+
+namespace gsp {
+
+__global__ __launch_bounds__(256) void k_fill_u32(uint32_t *p, uint32_t value, int64_t count) {
+    const int64_t k = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (k < count) p[k] = value;
+}
+
+hipError_t launch_fill_u32(uint32_t *p, uint32_t value, int64_t count, hipStream_t s) {
+    if (count <= 0) return hipSuccess;
+    const int64_t blocks = (count + 255) / 256;
+    hipLaunchKernelGGL(k_fill_u32, dim3((unsigned)blocks), dim3(256), 0, s, p, value, count);
+    return hipGetLastError();
+}
+
+constexpr int kLossItems = 4096;   // elements per loss block
+
+int64_t loss_blocks(int64_t count) { return (count + kLossItems - 1) / kLossItems; }
+
+__global__ __launch_bounds__(256) void k_l1(int64_t count, const float *pred, const float *target,
+                                            float *grad, double *partial) {
+    __shared__ double red[256 / kWave];
+    const float inv = 1.0f / (float)count;
+    const int64_t base = (int64_t)blockIdx.x * kLossItems;
+    double s = 0;
+#pragma unroll 4
+    for (int r = 0; r < kLossItems / 256; r++) {
+        const int64_t k = base + (int64_t)r * 256 + threadIdx.x;
+        if (k < count) {
+            const float d = pred[k] - target[k];
+            grad[k] = d > 0.f ? inv : (d < 0.f ? -inv : 0.f);
+            s += fabs((double)d);
+        }
+    }
+    if (partial) {
+        s = block_sum<double, 256>(s, red);
+        if (threadIdx.x == 0) partial[blockIdx.x] = s;
+    }
+}
+
+__global__ __launch_bounds__(256) void k_l1_final(const double *partial, int64_t nblk, int64_t count,
+                                                  float *loss) {
+    __shared__ double red[256 / kWave];
+    double s = 0;
+    for (int64_t b = threadIdx.x; b < nblk; b += 256) s += partial[b];
+    s = block_sum<double, 256>(s, red);
+    if (threadIdx.x == 0) loss[0] = (float)(s / (double)count);
+}
+
+hipError_t launch_loss_l1(int64_t count, const float *pred, const float *target, float *grad,
+                          float *loss, void *scratch, hipStream_t s) {
+    if (count <= 0) return hipSuccess;
+    const int64_t nblk = loss_blocks(count);
+    double *partial = loss ? static_cast<double *>(scratch) : nullptr;
+    hipLaunchKernelGGL(k_l1, dim3((unsigned)nblk), dim3(256), 0, s, count, pred, target, grad, partial);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess || !loss) return e;
+    hipLaunchKernelGGL(k_l1_final, dim3(1), dim3(256), 0, s, partial, nblk, count, loss);
+    return hipGetLastError();
+}
+
+// SE(3) exponential of (rho, phi) in FP64, composed on the left of T.
+__device__ void se3_retract_left(const double d[6], float *T) {
+    const double px = d[3], py = d[4], pz = d[5];
+    const double th2 = px * px + py * py + pz * pz, th = sqrt(th2);
+    double A, B, C;   // sin t / t, (1 - cos t) / t^2, (t - sin t) / t^3
+    if (th < 1e-4) {
+        A = 1 - th2 / 6 + th2 * th2 / 120;
+        B = 0.5 - th2 / 24 + th2 * th2 / 720;
+        C = 1.0 / 6 - th2 / 120 + th2 * th2 / 5040;
+    } else {
+        A = sin(th) / th;
+        B = (1 - cos(th)) / th2;
+        C = (th - sin(th)) / (th2 * th);
+    }
+    const double K[9] = {0, -pz, py, pz, 0, -px, -py, px, 0};
+    double K2[9];
+    for (int r = 0; r < 3; r++)
+        for (int c = 0; c < 3; c++)
+            K2[3 * r + c] = K[3 * r] * K[c] + K[3 * r + 1] * K[3 + c] + K[3 * r + 2] * K[6 + c];
+    double E[12];
+    for (int r = 0; r < 3; r++) {
+        for (int c = 0; c < 3; c++) {
+            const double I = r == c ? 1.0 : 0.0;
+            E[4 * r + c] = I + A * K[3 * r + c] + B * K2[3 * r + c];
+        }
+        double tr = 0;
+        for (int c = 0; c < 3; c++) {
+            const double I = r == c ? 1.0 : 0.0;
+            tr += (I + B * K[3 * r + c] + C * K2[3 * r + c]) * d[c];
+        }
+        E[4 * r + 3] = tr;
+    }
+    double out[12];
+    for (int r = 0; r < 3; r++)
+        for (int c = 0; c < 4; c++) {
+            double s = E[4 * r] * T[c] + E[4 * r + 1] * T[4 + c] + E[4 * r + 2] * T[8 + c];
+            if (c == 3) s += E[4 * r + 3];
+            out[4 * r + c] = s;
+        }
+    for (int k = 0; k < 12; k++) T[k] = (float)out[k];
+}
+
+__global__ __launch_bounds__(64) void k_pose_adam(int V, float *poses, const float *dpose, float *m,
+                                                  float *v, int32_t *steps, gsp_adam_params p) {
+    const int i = blockIdx.x * 64 + threadIdx.x;
+    if (i >= V) return;
+    const int k = steps[i] + 1;
+    steps[i] = k;
+    double lr = p.lr_start;
+    if (p.total_steps > 1) {
+        const double frac = fmin((double)(k - 1), (double)(p.total_steps - 1)) / (p.total_steps - 1);
+        lr = p.lr_end + 0.5 * ((double)p.lr_start - p.lr_end) * (1.0 + cos(M_PI * frac));
+    }
+    const double b1 = p.beta1, b2 = p.beta2;
+    const double c1 = 1.0 - pow(b1, (double)k), c2 = 1.0 - pow(b2, (double)k);
+    double delta[6];
+    for (int e = 0; e < 6; e++) {
+        const double g = dpose[6 * i + e];
+        const double mm = b1 * m[6 * i + e] + (1.0 - b1) * g;
+        const double vv = b2 * v[6 * i + e] + (1.0 - b2) * g * g;
+        m[6 * i + e] = (float)mm;
+        v[6 * i + e] = (float)vv;
+        delta[e] = -lr * (mm / c1) / (sqrt(vv / c2) + (double)p.eps);
+    }
+    se3_retract_left(delta, poses + 12 * i);
+}
+
+hipError_t launch_pose_adam(int V, float *poses, const float *dpose, float *m, float *v,
+                            int32_t *steps, const gsp_adam_params &p, hipStream_t s) {
+    if (V <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_pose_adam, dim3((V + 63) / 64), dim3(64), 0, s, V, poses, dpose, m, v, steps, p);
+    return hipGetLastError();
+}
+
+}  // namespace gsp

@@ -1,0 +1,300 @@
+// preprocess.hip -- projection of every Gaussian into every view of a call,
+// and duplication of each projected splat into (tile | depth) sort keys.
+//
+// Sec. III-A: Sigma = R(q) diag(s)^2 R(q)^T (Eq. (1)); mu_hat = pi(K T mu);
+// Sigma_hat = [J R_c Sigma R_c^T J^T]_2x2 (Eq. (2)) plus a 0.3 px^2
+// dilation; colour = SH(f, d) with d = (mu - o_c) / |mu - o_c|,
+// o_c = -R_c^T t_c.
+//
+// MI355X design: one thread per Gaussian reads the parameters once and loops
+// over the call's views (one HBM read of the 236 B/Gaussian SH-3 record per
+// call, however many views).  Geometry is computed in FP64 -- the vector
+// FP64 rate of gfx950 is that of unpacked FP32 and this kernel is bound by
+// HBM, so the extra precision is free -- and the projected centre is stored
+// as an FP32 (hi, lo) pair so that the rasterizer can form pixel offsets to
+// ~1e-6 px.  The sort key's depth is float32 of the camera-frame z computed
+// by a fixed FMA chain, which makes keys reproducible bit for bit.
+#include "block_ops.h"
+#include "gsp_internal.h"
+#include "sh_basis.h"
+
+namespace gsp {
+
+struct PreArgs {
+    GaussiansK g;
+    const float *poses;
+    float4 *geom;                  // [vn][2]: (u_hi, v_hi, u_lo, v_lo), (A, B, C, o)
+    float4 *color;                 // [vn]: (r, g, b, 0)
+    uint2 *rect;                   // [vn]: x0 | y0 << 16, x1 | y1 << 16
+    uint32_t *depth;               // [vn]: float bits of the key depth
+    uint32_t *tiles;               // [vn]: tiles touched
+    unsigned long long *blocksum;  // [V][nblk]
+    int nblk;
+};
+
+template <int D>
+__global__ __launch_bounds__(kPreprocessBlock) void k_preprocess(PreArgs a, ViewsK views) {
+    constexpr int S = (D + 1) * (D + 1);
+    __shared__ unsigned long long red[kPreprocessBlock / kWave];
+    const int n = a.g.n;
+    const int i = blockIdx.x * kPreprocessBlock + threadIdx.x;
+    const bool valid = i < n;
+
+    double mu[3] = {0, 0, 0};
+    double Sig[6] = {0, 0, 0, 0, 0, 0};  // xx xy xz yy yz zz
+    float opac = 0.f;
+    float sh[S * 3];
+#pragma unroll
+    for (int k = 0; k < S * 3; k++) sh[k] = 0.f;
+    if (valid) {
+        mu[0] = a.g.means[3 * i];
+        mu[1] = a.g.means[3 * i + 1];
+        mu[2] = a.g.means[3 * i + 2];
+        const double s0 = a.g.scales[3 * i], s1 = a.g.scales[3 * i + 1],
+                     s2 = a.g.scales[3 * i + 2];
+        double qw = a.g.quats[4 * i], qx = a.g.quats[4 * i + 1], qy = a.g.quats[4 * i + 2],
+               qz = a.g.quats[4 * i + 3];
+        const double qn = sqrt(qw * qw + qx * qx + qy * qy + qz * qz);
+        qw /= qn; qx /= qn; qy /= qn; qz /= qn;
+        // rotation of the unit quaternion (w, x, y, z)
+        const double r00 = 1 - 2 * (qy * qy + qz * qz), r01 = 2 * (qx * qy - qw * qz),
+                     r02 = 2 * (qx * qz + qw * qy);
+        const double r10 = 2 * (qx * qy + qw * qz), r11 = 1 - 2 * (qx * qx + qz * qz),
+                     r12 = 2 * (qy * qz - qw * qx);
+        const double r20 = 2 * (qx * qz - qw * qy), r21 = 2 * (qy * qz + qw * qx),
+                     r22 = 1 - 2 * (qx * qx + qy * qy);
+        const double e0 = s0 * s0, e1 = s1 * s1, e2 = s2 * s2;
+        Sig[0] = r00 * r00 * e0 + r01 * r01 * e1 + r02 * r02 * e2;
+        Sig[1] = r00 * r10 * e0 + r01 * r11 * e1 + r02 * r12 * e2;
+        Sig[2] = r00 * r20 * e0 + r01 * r21 * e1 + r02 * r22 * e2;
+        Sig[3] = r10 * r10 * e0 + r11 * r11 * e1 + r12 * r12 * e2;
+        Sig[4] = r10 * r20 * e0 + r11 * r21 * e1 + r12 * r22 * e2;
+        Sig[5] = r20 * r20 * e0 + r21 * r21 * e1 + r22 * r22 * e2;
+        opac = a.g.opacities[i];
+        const float *f = a.g.sh + (size_t)i * (S * 3);
+#pragma unroll
+        for (int k = 0; k < S * 3; k++) sh[k] = f[k];
+    }
+
+    for (int v = 0; v < views.count; v++) {
+        const ViewK &vw = views.v[v];
+        const float *P = a.poses + 12 * v;
+        const size_t idx = (size_t)v * n + i;
+        uint32_t cnt = 0;
+        if (valid) {
+            double R[9], t[3];
+#pragma unroll
+            for (int r = 0; r < 3; r++) {
+                R[3 * r] = P[4 * r];
+                R[3 * r + 1] = P[4 * r + 1];
+                R[3 * r + 2] = P[4 * r + 2];
+                t[r] = P[4 * r + 3];
+            }
+            double p[3];
+#pragma unroll
+            for (int r = 0; r < 3; r++)
+                p[r] = fma(R[3 * r + 2], mu[2], fma(R[3 * r + 1], mu[1], fma(R[3 * r], mu[0], t[r])));
+            const float zkey = (float)p[2];
+            uint2 rect = make_uint2(0, 0);
+            float4 g0 = make_float4(0, 0, 0, 0), g1 = make_float4(0, 0, 0, 0);
+            float4 col = make_float4(0, 0, 0, 0);
+            const double z = p[2];
+            bool keep = z > kNear;
+            double u = 0, vv = 0, A = 0, B = 0, C = 0;
+            if (keep) {
+                u = vw.fx * p[0] / z + vw.cx - 0.5;
+                vv = vw.fy * p[1] / z + vw.cy - 0.5;
+                const double limx = kJClamp * 0.5 * vw.W / (double)vw.fx;
+                const double limy = kJClamp * 0.5 * vw.H / (double)vw.fy;
+                const double xz = fmin(fmax(p[0] / z, -limx), limx);
+                const double yz = fmin(fmax(p[1] / z, -limy), limy);
+                const double j00 = vw.fx / z, j02 = -vw.fx * xz / z;
+                const double j11 = vw.fy / z, j12 = -vw.fy * yz / z;
+                // T2 = J R_c (2 x 3)
+                const double a0 = j00 * R[0] + j02 * R[6], a1 = j00 * R[1] + j02 * R[7],
+                             a2 = j00 * R[2] + j02 * R[8];
+                const double b0 = j11 * R[3] + j12 * R[6], b1 = j11 * R[4] + j12 * R[7],
+                             b2 = j11 * R[5] + j12 * R[8];
+                // Sigma * t for both rows
+                const double sa0 = Sig[0] * a0 + Sig[1] * a1 + Sig[2] * a2;
+                const double sa1 = Sig[1] * a0 + Sig[3] * a1 + Sig[4] * a2;
+                const double sa2 = Sig[2] * a0 + Sig[4] * a1 + Sig[5] * a2;
+                const double sb0 = Sig[0] * b0 + Sig[1] * b1 + Sig[2] * b2;
+                const double sb1 = Sig[1] * b0 + Sig[3] * b1 + Sig[4] * b2;
+                const double sb2 = Sig[2] * b0 + Sig[4] * b1 + Sig[5] * b2;
+                const double ca = a0 * sa0 + a1 * sa1 + a2 * sa2 + kDilation;
+                const double cb = a0 * sb0 + a1 * sb1 + a2 * sb2;
+                const double cc = b0 * sb0 + b1 * sb1 + b2 * sb2 + kDilation;
+                const double det = ca * cc - cb * cb;
+                keep = det > 0;
+                if (keep) {
+                    A = cc / det;
+                    B = -cb / det;
+                    C = ca / det;
+                    const double mid = 0.5 * (ca + cc);
+                    const double lam = mid + sqrt(fmax(mid * mid - det, kLambdaFloor));
+                    const double r = ceil(3.0 * sqrt(lam));
+                    const int ox = vw.roi_x / kTile, oy = vw.roi_y / kTile;
+                    const double x0 = fmin(fmax(floor((u - r) / kTile) - ox, 0.0), (double)vw.gw);
+                    const double x1 = fmin(fmax(floor((u + r + kTile - 1) / kTile) - ox, 0.0), (double)vw.gw);
+                    const double y0 = fmin(fmax(floor((vv - r) / kTile) - oy, 0.0), (double)vw.gh);
+                    const double y1 = fmin(fmax(floor((vv + r + kTile - 1) / kTile) - oy, 0.0), (double)vw.gh);
+                    const uint32_t ix0 = (uint32_t)x0, ix1 = (uint32_t)x1, iy0 = (uint32_t)y0,
+                                   iy1 = (uint32_t)y1;
+                    cnt = (ix1 - ix0) * (iy1 - iy0);
+                    rect = make_uint2(ix0 | (iy0 << 16), ix1 | (iy1 << 16));
+                }
+            }
+            if (cnt > 0) {
+                const float uh = (float)u, vh = (float)vv;
+                g0 = make_float4(uh, vh, (float)(u - (double)uh), (float)(vv - (double)vh));
+                g1 = make_float4((float)A, (float)B, (float)C, opac);
+                // camera centre o_c = -R^T t and the viewing direction
+                const double ocx = -(R[0] * t[0] + R[3] * t[1] + R[6] * t[2]);
+                const double ocy = -(R[1] * t[0] + R[4] * t[1] + R[7] * t[2]);
+                const double ocz = -(R[2] * t[0] + R[5] * t[1] + R[8] * t[2]);
+                double dx = mu[0] - ocx, dy = mu[1] - ocy, dz = mu[2] - ocz;
+                const double inv = 1.0 / sqrt(dx * dx + dy * dy + dz * dz);
+                float Y[S];
+                sh_eval<D, float>((float)(dx * inv), (float)(dy * inv), (float)(dz * inv), Y);
+                float c3[3];
+#pragma unroll
+                for (int ch = 0; ch < 3; ch++) {
+                    float acc = 0.f;
+#pragma unroll
+                    for (int k = 0; k < S; k++) acc = fmaf(sh[3 * k + ch], Y[k], acc);
+                    c3[ch] = fmaxf(acc + 0.5f, 0.f);
+                }
+                col = make_float4(c3[0], c3[1], c3[2], 0.f);
+            }
+            a.geom[2 * idx] = g0;
+            a.geom[2 * idx + 1] = g1;
+            a.color[idx] = col;
+            a.rect[idx] = rect;
+            a.depth[idx] = __float_as_uint(zkey);
+            a.tiles[idx] = cnt;
+        }
+        const unsigned long long bs = block_sum<unsigned long long, kPreprocessBlock>(cnt, red);
+        if (threadIdx.x == 0) a.blocksum[(size_t)v * a.nblk + blockIdx.x] = bs;
+    }
+}
+
+// Exclusive scan of the per-(view, block) instance counts in one block; the
+// grand total is M.  Writes M, the overflow flag and the effective M (0 on
+// overflow, so that every later stage does no work).
+__global__ __launch_bounds__(1024) void k_scan_blocksums(unsigned long long *bs, int count,
+                                                         uint32_t *counters,
+                                                         unsigned long long cap) {
+    __shared__ unsigned long long scratch[1024 / kWave];
+    const int t = threadIdx.x;
+    const int per = (count + 1023) / 1024;
+    const int begin = min(t * per, count), end = min(begin + per, count);
+    unsigned long long local = 0;
+    for (int k = begin; k < end; k++) local += bs[k];
+    unsigned long long total;
+    unsigned long long off = block_exclusive_scan<unsigned long long, 1024>(local, scratch, &total);
+    for (int k = begin; k < end; k++) {
+        const unsigned long long x = bs[k];
+        bs[k] = off;
+        off += x;
+    }
+    if (t == 0) {
+        const bool ovf = total > cap;
+        counters[kCntMLo] = (uint32_t)(total & 0xffffffffull);
+        counters[kCntMHi] = (uint32_t)(total >> 32);
+        counters[kCntOverflow] = ovf ? 1u : 0u;
+        counters[kCntMEff] = ovf ? 0u : (uint32_t)total;
+        if (ovf) counters[kCntSticky] = 1u;
+    }
+}
+
+struct DupArgs {
+    const uint2 *rect;
+    const uint32_t *depth;
+    const uint32_t *tiles;
+    uint32_t *offsets;
+    const unsigned long long *blockoff;
+    const uint32_t *counters;
+    unsigned long long *keys;
+    uint32_t *vals;
+    int n, nblk;
+};
+
+// Emits one (tile | depth, view * n + i) pair per tile of each splat's rect,
+// rows outer and columns inner, at the splat's exclusive offset.
+__global__ __launch_bounds__(kPreprocessBlock) void k_duplicate(DupArgs a, ViewsK views) {
+    __shared__ unsigned long long scratch[kPreprocessBlock / kWave];
+    const int v = blockIdx.y;
+    const int i = blockIdx.x * kPreprocessBlock + threadIdx.x;
+    const size_t idx = (size_t)v * a.n + i;
+    const uint32_t cnt = i < a.n ? a.tiles[idx] : 0u;
+    unsigned long long total;
+    const unsigned long long excl =
+        block_exclusive_scan<unsigned long long, kPreprocessBlock>(cnt, scratch, &total) +
+        a.blockoff[(size_t)v * a.nblk + blockIdx.x];
+    if (a.counters[kCntOverflow] != 0u || i >= a.n) return;
+    a.offsets[idx] = (uint32_t)excl;
+    if (cnt == 0) return;
+    const uint2 r = a.rect[idx];
+    const int x0 = r.x & 0xffff, y0 = r.x >> 16, x1 = r.y & 0xffff, y1 = r.y >> 16;
+    const ViewK &vw = views.v[v];
+    const unsigned long long dbits = a.depth[idx];
+    size_t o = (size_t)excl;
+    for (int ty = y0; ty < y1; ty++) {
+        const unsigned long long rowbase = (unsigned long long)(vw.tile_base + ty * vw.gw);
+        for (int tx = x0; tx < x1; tx++) {
+            a.keys[o] = ((rowbase + tx) << 32) | dbits;
+            a.vals[o] = (uint32_t)idx;
+            o++;
+        }
+    }
+}
+
+hipError_t launch_preprocess(const GaussiansK &g, const ViewsK &views, const float *poses,
+                             const Layout &L, char *ws, hipStream_t s) {
+    if (g.n == 0) return hipSuccess;
+    PreArgs a;
+    a.g = g;
+    a.poses = poses;
+    a.geom = region<float4>(ws, L.geom);
+    a.color = region<float4>(ws, L.color);
+    a.rect = region<uint2>(ws, L.rect);
+    a.depth = region<uint32_t>(ws, L.depth);
+    a.tiles = region<uint32_t>(ws, L.tiles);
+    a.blocksum = region<unsigned long long>(ws, L.blocksum);
+    a.nblk = L.nblk_pre;
+    dim3 grid(L.nblk_pre), block(kPreprocessBlock);
+    switch (g.sh_degree) {
+        case 0: hipLaunchKernelGGL(k_preprocess<0>, grid, block, 0, s, a, views); break;
+        case 1: hipLaunchKernelGGL(k_preprocess<1>, grid, block, 0, s, a, views); break;
+        case 2: hipLaunchKernelGGL(k_preprocess<2>, grid, block, 0, s, a, views); break;
+        default: hipLaunchKernelGGL(k_preprocess<3>, grid, block, 0, s, a, views); break;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_offsets_and_duplicate(const ViewsK &views, const Layout &L, char *ws,
+                                        hipStream_t s) {
+    unsigned long long *bs = region<unsigned long long>(ws, L.blocksum);
+    uint32_t *counters = region<uint32_t>(ws, L.counters);
+    const int count = L.V * L.nblk_pre;
+    hipLaunchKernelGGL(k_scan_blocksums, dim3(1), dim3(1024), 0, s, bs, count, counters,
+                       (unsigned long long)L.cap);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess || L.n == 0) return e;
+    DupArgs a;
+    a.rect = region<uint2>(ws, L.rect);
+    a.depth = region<uint32_t>(ws, L.depth);
+    a.tiles = region<uint32_t>(ws, L.tiles);
+    a.offsets = region<uint32_t>(ws, L.offsets);
+    a.blockoff = bs;
+    a.counters = counters;
+    a.keys = region<unsigned long long>(ws, L.keys0);
+    a.vals = region<uint32_t>(ws, L.vals0);
+    a.n = (int)L.n;
+    a.nblk = L.nblk_pre;
+    hipLaunchKernelGGL(k_duplicate, dim3(L.nblk_pre, L.V), dim3(kPreprocessBlock), 0, s, a, views);
+    return hipGetLastError();
+}
+
+}  // namespace gsp

@@ -1,0 +1,370 @@
+// preprocess_bwd.hip -- chain rule from the per-splat 2D gradients to the
+// Gaussian parameters and to each view's se(3) pose twist.
+//
+// Sec. III-B, Eq. (7): the pose gradient collects, over Gaussians, the 2D
+// mean term (through mu^c = T mu, Eq. (8)/(10): d mu^c / d tau = (I | -[mu^c]x)),
+// the 2D covariance term (through J(mu^c) and through R_c, Eq. (12)-(13):
+// dR_c / d phi_k = [e_k]x R_c) and the colour term (through the camera
+// centre o_c = -R_c^T t_c, which moves by -R_c^T rho under the left
+// perturbation).  Per Gaussian, with g = dL/dmu^c, G_W = dL/dR_c (from
+// Sigma_hat = J R_c Sigma R_c^T J^T) and h = dL/do_c:
+//   dL/drho += g - R_c h,   dL/dphi += mu^c x g + vee(G_W R_c^T).
+//
+// MI355X design: one thread per Gaussian loops over the call's views, first
+// summing its 2D gradient over its instance slots (contiguous, fixed order),
+// then applying the chain rule in FP64 (this kernel is bound by HBM, and the
+// FP64 vector rate equals unpacked FP32).  Gaussian gradients are summed over
+// views in registers and written once; the six pose sums per view are reduced
+// with wavefront shuffles and an LDS block reduction into per-block partials,
+// and one block per view adds the partials in a fixed order.  No atomics
+// anywhere, so the result is bit-reproducible and independent of how many
+// other views share the launch.
+#include "block_ops.h"
+#include "gsp_internal.h"
+#include "sh_basis.h"
+
+namespace gsp {
+
+struct PbArgs {
+    GaussiansK g;
+    const float *poses;
+    const uint32_t *tiles;
+    const uint32_t *offsets;
+    const uint32_t *counters;
+    const float *slots;     // [9][cap]
+    float *grad2d;          // [9][vn]
+    double *posepart;       // [V][nblk][6]
+    gsp_grads out;
+    size_t cap, vn;
+    int nblk;
+    bool accumulate;
+};
+
+// d R(qhat) / d qhat . G for a unit quaternion (w, x, y, z).
+__device__ __forceinline__ void rot_vjp(double w, double x, double y, double z, const double Gm[9],
+                                        double out[4]) {
+    out[0] = 2 * (-z * Gm[1] + y * Gm[2] + z * Gm[3] - x * Gm[5] - y * Gm[6] + x * Gm[7]);
+    out[1] = 2 * (y * Gm[1] + z * Gm[2] + y * Gm[3] - 2 * x * Gm[4] - w * Gm[5] + z * Gm[6] +
+                  w * Gm[7] - 2 * x * Gm[8]);
+    out[2] = 2 * (-2 * y * Gm[0] + x * Gm[1] + w * Gm[2] + x * Gm[3] + z * Gm[5] - w * Gm[6] +
+                  z * Gm[7] - 2 * y * Gm[8]);
+    out[3] = 2 * (-2 * z * Gm[0] - w * Gm[1] + x * Gm[2] + w * Gm[3] - 2 * z * Gm[4] + y * Gm[5] +
+                  x * Gm[6] + y * Gm[7]);
+}
+
+template <int D, bool WANT_GAUSS>
+__global__ __launch_bounds__(kPoseReduceBlock) void k_preprocess_bwd(PbArgs a, ViewsK views) {
+    constexpr int S = (D + 1) * (D + 1);
+    __shared__ double red[kPoseReduceBlock / kWave];
+    const int n = a.g.n;
+    const int i = blockIdx.x * kPoseReduceBlock + threadIdx.x;
+    const bool valid = i < n;
+    const bool ovf = a.counters[kCntOverflow] != 0u;
+
+    double mu[3] = {0, 0, 0}, sc[3] = {1, 1, 1}, qh[4] = {1, 0, 0, 0}, qn = 1;
+    double Rq[9] = {1, 0, 0, 0, 1, 0, 0, 0, 1};
+    double Sig[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
+    float sh[S * 3];
+#pragma unroll
+    for (int k = 0; k < S * 3; k++) sh[k] = 0.f;
+    if (valid) {
+#pragma unroll
+        for (int k = 0; k < 3; k++) {
+            mu[k] = a.g.means[3 * i + k];
+            sc[k] = a.g.scales[3 * i + k];
+        }
+        double q[4];
+#pragma unroll
+        for (int k = 0; k < 4; k++) q[k] = a.g.quats[4 * i + k];
+        qn = sqrt(q[0] * q[0] + q[1] * q[1] + q[2] * q[2] + q[3] * q[3]);
+#pragma unroll
+        for (int k = 0; k < 4; k++) qh[k] = q[k] / qn;
+        const double w = qh[0], x = qh[1], y = qh[2], z = qh[3];
+        Rq[0] = 1 - 2 * (y * y + z * z); Rq[1] = 2 * (x * y - w * z); Rq[2] = 2 * (x * z + w * y);
+        Rq[3] = 2 * (x * y + w * z); Rq[4] = 1 - 2 * (x * x + z * z); Rq[5] = 2 * (y * z - w * x);
+        Rq[6] = 2 * (x * z - w * y); Rq[7] = 2 * (y * z + w * x); Rq[8] = 1 - 2 * (x * x + y * y);
+#pragma unroll
+        for (int r = 0; r < 3; r++)
+#pragma unroll
+            for (int c = 0; c < 3; c++)
+                Sig[3 * r + c] = Rq[3 * r] * Rq[3 * c] * sc[0] * sc[0] +
+                                 Rq[3 * r + 1] * Rq[3 * c + 1] * sc[1] * sc[1] +
+                                 Rq[3 * r + 2] * Rq[3 * c + 2] * sc[2] * sc[2];
+        const float *f = a.g.sh + (size_t)i * (S * 3);
+#pragma unroll
+        for (int k = 0; k < S * 3; k++) sh[k] = f[k];
+    }
+
+    // gradients summed over views
+    double gmu[3] = {0, 0, 0}, gSig[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0}, gop = 0;
+    double gsh[WANT_GAUSS ? S * 3 : 1];
+#pragma unroll
+    for (int k = 0; k < (WANT_GAUSS ? S * 3 : 1); k++) gsh[k] = 0;
+
+    for (int v = 0; v < views.count; v++) {
+        const ViewK &vw = views.v[v];
+        const float *P = a.poses + 12 * v;
+        const size_t idx = (size_t)v * n + i;
+        double pose6[6] = {0, 0, 0, 0, 0, 0};
+        const uint32_t cnt = (valid && !ovf) ? a.tiles[idx] : 0u;
+        if (cnt > 0) {
+            // 2D gradient of this splat: sum of its instance slots
+            float d2f[9];
+            const uint32_t e0 = a.offsets[idx];
+#pragma unroll
+            for (int c = 0; c < 9; c++) {
+                const float *sl = a.slots + c * a.cap + e0;
+                float s = 0.f;
+                for (uint32_t k = 0; k < cnt; k++) s += sl[k];
+                d2f[c] = s;
+                a.grad2d[c * a.vn + idx] = s;
+            }
+            double R[9], t[3];
+#pragma unroll
+            for (int r = 0; r < 3; r++) {
+                R[3 * r] = P[4 * r];
+                R[3 * r + 1] = P[4 * r + 1];
+                R[3 * r + 2] = P[4 * r + 2];
+                t[r] = P[4 * r + 3];
+            }
+            double p[3];
+#pragma unroll
+            for (int r = 0; r < 3; r++)
+                p[r] = fma(R[3 * r + 2], mu[2], fma(R[3 * r + 1], mu[1], fma(R[3 * r], mu[0], t[r])));
+            const double z = p[2], iz = 1.0 / z, iz2 = iz * iz;
+            const double fx = vw.fx, fy = vw.fy;
+            const double limx = kJClamp * 0.5 * vw.W / fx, limy = kJClamp * 0.5 * vw.H / fy;
+            const double xzr = p[0] * iz, yzr = p[1] * iz;
+            const bool clx = xzr < -limx || xzr > limx, cly = yzr < -limy || yzr > limy;
+            const double xz = fmin(fmax(xzr, -limx), limx), yz = fmin(fmax(yzr, -limy), limy);
+            const double j00 = fx * iz, j02 = -fx * xz * iz, j11 = fy * iz, j12 = -fy * yz * iz;
+            // rows of T2 = J R_c
+            const double ta[3] = {j00 * R[0] + j02 * R[6], j00 * R[1] + j02 * R[7],
+                                  j00 * R[2] + j02 * R[8]};
+            const double tb[3] = {j11 * R[3] + j12 * R[6], j11 * R[4] + j12 * R[7],
+                                  j11 * R[5] + j12 * R[8]};
+            double sa[3], sb[3];
+#pragma unroll
+            for (int r = 0; r < 3; r++) {
+                sa[r] = Sig[3 * r] * ta[0] + Sig[3 * r + 1] * ta[1] + Sig[3 * r + 2] * ta[2];
+                sb[r] = Sig[3 * r] * tb[0] + Sig[3 * r + 1] * tb[1] + Sig[3 * r + 2] * tb[2];
+            }
+            const double ca = ta[0] * sa[0] + ta[1] * sa[1] + ta[2] * sa[2] + kDilation;
+            const double cb = ta[0] * sb[0] + ta[1] * sb[1] + ta[2] * sb[2];
+            const double cc = tb[0] * sb[0] + tb[1] * sb[1] + tb[2] * sb[2] + kDilation;
+            const double det = ca * cc - cb * cb, idet2 = 1.0 / (det * det);
+            const double dA = d2f[2], dB = d2f[3], dC = d2f[4];
+            // conic = inverse of the 2D covariance
+            const double dca = (-cc * cc * dA + cb * cc * dB - cb * cb * dC) * idet2;
+            const double dcb = (2 * cb * cc * dA - (ca * cc + cb * cb) * dB + 2 * ca * cb * dC) * idet2;
+            const double dcc = (-cb * cb * dA + ca * cb * dB - ca * ca * dC) * idet2;
+            // dL/dT2 rows: 2 [[dca, dcb/2], [dcb/2, dcc]] T2 Sigma
+            double ga[3], gb[3];
+#pragma unroll
+            for (int r = 0; r < 3; r++) {
+                ga[r] = 2 * dca * sa[r] + dcb * sb[r];
+                gb[r] = dcb * sa[r] + 2 * dcc * sb[r];
+            }
+            // dL/dJ = dL/dT2 R_c^T (only the four entries J depends on)
+            const double gj00 = ga[0] * R[0] + ga[1] * R[1] + ga[2] * R[2];
+            const double gj02 = ga[0] * R[6] + ga[1] * R[7] + ga[2] * R[8];
+            const double gj11 = gb[0] * R[3] + gb[1] * R[4] + gb[2] * R[5];
+            const double gj12 = gb[0] * R[6] + gb[1] * R[7] + gb[2] * R[8];
+            // J and the projected centre -> camera-frame mean
+            double gp[3];
+            gp[0] = d2f[0] * fx * iz;
+            gp[1] = d2f[1] * fy * iz;
+            gp[2] = -(d2f[0] * fx * p[0] + d2f[1] * fy * p[1]) * iz2 - (gj00 * fx + gj11 * fy) * iz2;
+            if (clx) {
+                gp[2] += gj02 * fx * xz * iz2;
+            } else {
+                gp[0] -= gj02 * fx * iz2;
+                gp[2] += gj02 * 2 * fx * p[0] * iz2 * iz;
+            }
+            if (cly) {
+                gp[2] += gj12 * fy * yz * iz2;
+            } else {
+                gp[1] -= gj12 * fy * iz2;
+                gp[2] += gj12 * 2 * fy * p[1] * iz2 * iz;
+            }
+            // mean (geometry part): R_c^T gp
+#pragma unroll
+            for (int k = 0; k < 3; k++) gmu[k] += R[k] * gp[0] + R[3 + k] * gp[1] + R[6 + k] * gp[2];
+            // dL/dSigma = T2^T Gh T2
+#pragma unroll
+            for (int r = 0; r < 3; r++)
+#pragma unroll
+                for (int c = 0; c < 3; c++)
+                    gSig[3 * r + c] += dca * ta[r] * ta[c] + 0.5 * dcb * (ta[r] * tb[c] + tb[r] * ta[c]) +
+                                       dcc * tb[r] * tb[c];
+            gop += d2f[5];
+            // dL/dR_c = J^T dL/dT2 ; the phi part is vee(G_W R_c^T)
+            double GW[9];
+#pragma unroll
+            for (int c = 0; c < 3; c++) {
+                GW[c] = j00 * ga[c];
+                GW[3 + c] = j11 * gb[c];
+                GW[6 + c] = j02 * ga[c] + j12 * gb[c];
+            }
+            double Bm[9];
+#pragma unroll
+            for (int r = 0; r < 3; r++)
+#pragma unroll
+                for (int c = 0; c < 3; c++)
+                    Bm[3 * r + c] = GW[3 * r] * R[3 * c] + GW[3 * r + 1] * R[3 * c + 1] +
+                                    GW[3 * r + 2] * R[3 * c + 2];
+            // colour: viewing direction from the camera centre
+            const double ocx = -(R[0] * t[0] + R[3] * t[1] + R[6] * t[2]);
+            const double ocy = -(R[1] * t[0] + R[4] * t[1] + R[7] * t[2]);
+            const double ocz = -(R[2] * t[0] + R[5] * t[1] + R[8] * t[2]);
+            const double wx = mu[0] - ocx, wy = mu[1] - ocy, wz = mu[2] - ocz;
+            const double dist = sqrt(wx * wx + wy * wy + wz * wz), idist = 1.0 / dist;
+            const double dxn = wx * idist, dyn = wy * idist, dzn = wz * idist;
+            double Y[S];
+            sh_eval<D, double>(dxn, dyn, dzn, Y);
+            double wgt[S];
+#pragma unroll
+            for (int k = 0; k < S; k++) wgt[k] = 0;
+#pragma unroll
+            for (int ch = 0; ch < 3; ch++) {
+                double col = 0.5;
+#pragma unroll
+                for (int k = 0; k < S; k++) col += (double)sh[3 * k + ch] * Y[k];
+                if (col < 0) continue;   // clamped channel: no gradient
+                const double gc = d2f[6 + ch];
+#pragma unroll
+                for (int k = 0; k < S; k++) {
+                    wgt[k] += gc * (double)sh[3 * k + ch];
+                    if constexpr (WANT_GAUSS) gsh[3 * k + ch] += gc * Y[k];
+                }
+            }
+            double gd[3];
+            sh_weighted_grad<D, double>(dxn, dyn, dzn, wgt, gd);
+            const double proj = gd[0] * dxn + gd[1] * dyn + gd[2] * dzn;
+            const double gw[3] = {(gd[0] - dxn * proj) * idist, (gd[1] - dyn * proj) * idist,
+                                  (gd[2] - dzn * proj) * idist};
+#pragma unroll
+            for (int k = 0; k < 3; k++) gmu[k] += gw[k];
+            // pose twist contribution, h = dL/do_c = -gw
+#pragma unroll
+            for (int r = 0; r < 3; r++)
+                pose6[r] = gp[r] + (R[3 * r] * gw[0] + R[3 * r + 1] * gw[1] + R[3 * r + 2] * gw[2]);
+            pose6[3] = p[1] * gp[2] - p[2] * gp[1] + Bm[7] - Bm[5];
+            pose6[4] = p[2] * gp[0] - p[0] * gp[2] + Bm[2] - Bm[6];
+            pose6[5] = p[0] * gp[1] - p[1] * gp[0] + Bm[3] - Bm[1];
+        } else if (valid && !ovf) {
+#pragma unroll
+            for (int c = 0; c < 9; c++) a.grad2d[c * a.vn + idx] = 0.f;
+        }
+#pragma unroll
+        for (int c = 0; c < 6; c++) {
+            const double s = block_sum<double, kPoseReduceBlock>(pose6[c], red);
+            if (threadIdx.x == 0) a.posepart[((size_t)v * a.nblk + blockIdx.x) * 6 + c] = s;
+        }
+    }
+
+    if constexpr (WANT_GAUSS) {
+        if (!valid) return;
+        const gsp_grads &o = a.out;
+        const bool acc = a.accumulate;
+        if (o.means) {
+#pragma unroll
+            for (int k = 0; k < 3; k++) o.means[3 * i + k] = (acc ? o.means[3 * i + k] : 0.f) + (float)gmu[k];
+        }
+        if (o.opacities) o.opacities[i] = (acc ? o.opacities[i] : 0.f) + (float)gop;
+        if (o.sh) {
+#pragma unroll
+            for (int k = 0; k < S * 3; k++)
+                o.sh[(size_t)i * (S * 3) + k] = (acc ? o.sh[(size_t)i * (S * 3) + k] : 0.f) + (float)gsh[k];
+        }
+        if (o.scales || o.quats) {
+            // Sigma = M M^T with M = R_q diag(s): dL/dM = 2 dL/dSigma M (dL/dSigma symmetric)
+            double GM[9];
+#pragma unroll
+            for (int r = 0; r < 3; r++)
+#pragma unroll
+                for (int c = 0; c < 3; c++)
+                    GM[3 * r + c] = 2 * (gSig[3 * r] * Rq[c] + gSig[3 * r + 1] * Rq[3 + c] +
+                                         gSig[3 * r + 2] * Rq[6 + c]) * sc[c];
+            if (o.scales) {
+#pragma unroll
+                for (int c = 0; c < 3; c++) {
+                    const double ds = GM[c] * Rq[c] + GM[3 + c] * Rq[3 + c] + GM[6 + c] * Rq[6 + c];
+                    o.scales[3 * i + c] = (acc ? o.scales[3 * i + c] : 0.f) + (float)ds;
+                }
+            }
+            if (o.quats) {
+                double GR[9];
+#pragma unroll
+                for (int r = 0; r < 3; r++)
+#pragma unroll
+                    for (int c = 0; c < 3; c++) GR[3 * r + c] = GM[3 * r + c] * sc[c];
+                double dqh[4];
+                rot_vjp(qh[0], qh[1], qh[2], qh[3], GR, dqh);
+                const double pr = dqh[0] * qh[0] + dqh[1] * qh[1] + dqh[2] * qh[2] + dqh[3] * qh[3];
+#pragma unroll
+                for (int k = 0; k < 4; k++)
+                    o.quats[4 * i + k] = (acc ? o.quats[4 * i + k] : 0.f) + (float)((dqh[k] - qh[k] * pr) / qn);
+            }
+        }
+    }
+}
+
+// One block per view adds the per-block pose partials in a fixed order.
+__global__ __launch_bounds__(256) void k_pose_final(const double *posepart, int nblk, float *dpose,
+                                                    bool accumulate) {
+    __shared__ double red[256 / kWave];
+    const int v = blockIdx.x;
+    for (int c = 0; c < 6; c++) {
+        double s = 0;
+        for (int b = threadIdx.x; b < nblk; b += 256) s += posepart[((size_t)v * nblk + b) * 6 + c];
+        s = block_sum<double, 256>(s, red);
+        if (threadIdx.x == 0) dpose[6 * v + c] = (accumulate ? dpose[6 * v + c] : 0.f) + (float)s;
+    }
+}
+
+template <int D>
+static void launch_pb(const PbArgs &a, const ViewsK &views, bool want, int nblk, hipStream_t s) {
+    if (want)
+        hipLaunchKernelGGL((k_preprocess_bwd<D, true>), dim3(nblk), dim3(kPoseReduceBlock), 0, s, a, views);
+    else
+        hipLaunchKernelGGL((k_preprocess_bwd<D, false>), dim3(nblk), dim3(kPoseReduceBlock), 0, s, a, views);
+}
+
+hipError_t launch_preprocess_bwd(const GaussiansK &g, const ViewsK &views, const float *poses,
+                                 const Layout &L, char *ws, const gsp_grads &grads,
+                                 bool accumulate, hipStream_t s) {
+    const bool want = grads.means || grads.scales || grads.quats || grads.opacities || grads.sh;
+    PbArgs a;
+    a.g = g;
+    a.poses = poses;
+    a.tiles = region<uint32_t>(ws, L.tiles);
+    a.offsets = region<uint32_t>(ws, L.offsets);
+    a.counters = region<uint32_t>(ws, L.counters);
+    a.slots = region<float>(ws, L.slots);
+    a.grad2d = region<float>(ws, L.grad2d);
+    a.posepart = region<double>(ws, L.posepart);
+    a.out = grads;
+    a.cap = (size_t)L.cap;
+    a.vn = (size_t)L.vn;
+    a.nblk = L.nblk_pre;
+    a.accumulate = accumulate;
+    if (L.n > 0) {
+        switch (g.sh_degree) {
+            case 0: launch_pb<0>(a, views, want, L.nblk_pre, s); break;
+            case 1: launch_pb<1>(a, views, want, L.nblk_pre, s); break;
+            case 2: launch_pb<2>(a, views, want, L.nblk_pre, s); break;
+            default: launch_pb<3>(a, views, want, L.nblk_pre, s); break;
+        }
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    if (grads.pose) {
+        hipLaunchKernelGGL(k_pose_final, dim3(L.V), dim3(256), 0, s, a.posepart, L.nblk_pre,
+                           grads.pose, accumulate);
+        return hipGetLastError();
+    }
+    return hipSuccess;
+}
+
+}  // namespace gsp

@@ -1,0 +1,327 @@
+"""PyTorch-facing layer over libgsp: device tensors in, device tensors out.
+
+PyTorch provides device memory and the current HIP stream; every step of the
+render, the loss, the backward and the pose update runs in the library's
+kernels (include/gsp.h).
+
+Main entry points:
+  Rasterizer            workspace owner; forward / backward / loss / Adam calls
+  render(...)           torch.autograd.Function: image from Gaussians and
+                        pose twists tau (gradient = left se(3) twist, Sec. III-B)
+  solve_poses(...)      tangent-space Adam pose estimation, all on device
+"""
+import ctypes
+from dataclasses import dataclass
+from typing import Optional, Sequence
+
+import torch
+
+from . import _native as N
+
+
+def _ptr(t):
+    return ctypes.c_void_p(t.data_ptr()) if t is not None else ctypes.c_void_p(None)
+
+
+def _stream():
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+_contexts = {}
+
+
+def context(device: int):
+    """Library context of a device (created once per process)."""
+    if device not in _contexts:
+        L = N.lib()
+        h = ctypes.c_void_p()
+        N.check(L.gsp_create(int(device), ctypes.byref(h)), "gsp_create")
+        _contexts[device] = h
+    return _contexts[device]
+
+
+@dataclass
+class GaussianParams:
+    """Activated Gaussian parameters on the device (FP32, contiguous)."""
+    means: torch.Tensor      # [n, 3]
+    scales: torch.Tensor     # [n, 3]
+    quats: torch.Tensor      # [n, 4]
+    opacities: torch.Tensor  # [n]
+    sh: torch.Tensor         # [n, S, 3]
+    sh_degree: int
+
+    @property
+    def n(self):
+        return int(self.means.shape[0])
+
+    @staticmethod
+    def from_set(gs, device="cuda"):
+        f = lambda a: torch.as_tensor(a, dtype=torch.float32).to(device).contiguous()
+        return GaussianParams(f(gs.means), f(gs.scales), f(gs.quats), f(gs.opacities),
+                              f(gs.sh), int(gs.sh_degree))
+
+    def struct(self):
+        for name in ("means", "scales", "quats", "opacities", "sh"):
+            t = getattr(self, name)
+            if t.dtype != torch.float32 or not t.is_contiguous() or not t.is_cuda:
+                raise ValueError(f"{name} must be a contiguous float32 device tensor")
+        return N.Gaussians(self.means.data_ptr(), self.scales.data_ptr(), self.quats.data_ptr(),
+                           self.opacities.data_ptr(), self.sh.data_ptr(), self.n, self.sh_degree)
+
+
+def region(cam):
+    return cam.roi if getattr(cam, "roi", None) is not None else (0, 0, cam.width, cam.height)
+
+
+def pixel_counts(cams):
+    return [region(c)[2] * region(c)[3] for c in cams]
+
+
+def split_images(packed, cams):
+    """Per-view [3, h, w] views of a packed image buffer."""
+    out, off = [], 0
+    for c in cams:
+        _, _, w, h = region(c)
+        out.append(packed[off:off + 3 * w * h].view(3, h, w))
+        off += 3 * w * h
+    return out
+
+
+def pack_images(images):
+    return torch.cat([im.reshape(-1) for im in images]).contiguous()
+
+
+class Rasterizer:
+    """Owns the device workspace of a sequence of renders.
+
+    The workspace is sized for an instance capacity (number of (Gaussian,
+    tile) pairs).  With check=True a forward synchronises once to read the
+    instance count and re-runs with a larger capacity on overflow; with
+    check=False nothing synchronises and `overflowed()` tells afterwards
+    whether any forward since the workspace was allocated ran out of room.
+    """
+
+    def __init__(self, device: Optional[int] = None, capacity: int = 0, growth: float = 1.5):
+        self.device = torch.cuda.current_device() if device is None else int(device)
+        self.capacity = int(capacity)
+        self.growth = float(growth)
+        self.ws = None
+        self._key = None
+
+    # -- workspace ---------------------------------------------------------
+    def _ws_bytes(self, n, degree, views, cap):
+        L = N.lib()
+        sz = ctypes.c_size_t()
+        N.check(L.gsp_workspace_size(n, degree, len(views), views, cap, ctypes.byref(sz)),
+                "gsp_workspace_size")
+        return sz.value
+
+    def _ensure(self, g, views):
+        nbytes = self._ws_bytes(g.n, g.sh_degree, views, self.capacity)
+        if self.ws is None or self.ws.numel() < nbytes:
+            self.ws = torch.zeros(nbytes, dtype=torch.uint8, device=f"cuda:{self.device}")
+        return nbytes
+
+    def reset_overflow(self):
+        if self.ws is not None:
+            self.ws[:64].zero_()
+
+    def instances(self):
+        """(M of the last forward, overflow flag); synchronises the stream."""
+        L = N.lib()
+        m = ctypes.c_int64()
+        o = ctypes.c_int32()
+        N.check(L.gsp_instances(context(self.device), _ptr(self.ws), _stream(), ctypes.byref(m),
+                                ctypes.byref(o)), "gsp_instances")
+        return m.value, bool(o.value)
+
+    def overflowed(self):
+        return self.instances()[1]
+
+    # -- forward / backward ------------------------------------------------
+    def forward(self, g: GaussianParams, cams: Sequence, poses: torch.Tensor,
+                alphas: bool = False, check: bool = True, images: Optional[torch.Tensor] = None):
+        """Renders len(cams) views; returns (packed images, packed alphas or None)."""
+        L = N.lib()
+        views = N.view_array(cams)
+        poses = poses.contiguous()
+        if poses.dtype != torch.float32 or tuple(poses.shape) != (len(cams), 3, 4):
+            raise ValueError("poses must be float32 [V, 3, 4]")
+        P = sum(pixel_counts(cams))
+        dev = f"cuda:{self.device}"
+        if images is None:
+            images = torch.empty(3 * P, dtype=torch.float32, device=dev)
+        al = torch.empty(P, dtype=torch.float32, device=dev) if alphas else None
+        if self.capacity <= 0:
+            self.capacity = max(1024, 8 * g.n * len(cams))
+        gs = g.struct()
+        for _ in range(8):
+            nbytes = self._ensure(g, views)
+            N.check(L.gsp_render_fwd(context(self.device), ctypes.byref(gs), len(cams), views,
+                                     _ptr(poses), _ptr(images), _ptr(al), _ptr(self.ws), nbytes,
+                                     self.capacity, _stream()), "gsp_render_fwd")
+            if not check:
+                break
+            m, ovf = self.instances()
+            if not ovf:
+                break
+            self.capacity = int(m * self.growth) + 1024
+            self.ws = None       # reallocated (zeroed) at the larger size
+        self._key = (g.n, g.sh_degree, tuple(pixel_counts(cams)))
+        return images, al
+
+    def backward(self, g: GaussianParams, cams: Sequence, poses: torch.Tensor,
+                 dl_dimages: torch.Tensor, want=("means", "scales", "quats", "opacities", "sh"),
+                 pose: bool = True, accumulate: bool = False, out=None):
+        """Gradients of the last forward.  Returns a dict with the requested
+        Gaussian gradients and 'pose' ([V, 6], left twist (rho, phi))."""
+        L = N.lib()
+        views = N.view_array(cams)
+        dev = f"cuda:{self.device}"
+        out = dict(out or {})
+        shapes = {"means": (g.n, 3), "scales": (g.n, 3), "quats": (g.n, 4),
+                  "opacities": (g.n,), "sh": tuple(g.sh.shape)}
+        for k in want:
+            if k not in out:
+                out[k] = torch.empty(shapes[k], dtype=torch.float32, device=dev)
+        if pose and "pose" not in out:
+            out["pose"] = torch.empty((len(cams), 6), dtype=torch.float32, device=dev)
+        gr = N.Grads(*[out[k].data_ptr() if k in out else None
+                       for k in ("means", "scales", "quats", "opacities", "sh", "pose")])
+        gs = g.struct()
+        nbytes = self._ws_bytes(g.n, g.sh_degree, views, self.capacity)
+        N.check(L.gsp_render_bwd(context(self.device), ctypes.byref(gs), len(cams), views,
+                                 _ptr(poses.contiguous()), _ptr(dl_dimages.contiguous()),
+                                 _ptr(self.ws), nbytes, self.capacity, ctypes.byref(gr),
+                                 N.GSP_ACCUMULATE if accumulate else 0, _stream()),
+                "gsp_render_bwd")
+        return out
+
+    def inspect(self, g: GaussianParams, cams: Sequence, name: str, dtype=torch.float32):
+        """A copy of an intermediate workspace array of the last call."""
+        L = N.lib()
+        views = N.view_array(cams)
+        gs = g.struct()
+        nbytes = self._ws_bytes(g.n, g.sh_degree, views, self.capacity)
+        p = ctypes.c_void_p()
+        cnt = ctypes.c_int64()
+        N.check(L.gsp_inspect(context(self.device), ctypes.byref(gs), len(cams), views,
+                              _ptr(self.ws), nbytes, self.capacity, name.encode(), ctypes.byref(p),
+                              ctypes.byref(cnt)), "gsp_inspect")
+        itemsize = torch.empty((), dtype=dtype).element_size()
+        base = self.ws.data_ptr()
+        off = p.value - base
+        elem_bytes = {"geom": 16, "color": 16, "rect": 8, "keys": 8, "ranges": 8}.get(name, 4)
+        nbytes_arr = cnt.value * elem_bytes
+        raw = self.ws[off:off + nbytes_arr]
+        return raw.view(dtype).clone() if nbytes_arr % itemsize == 0 else raw.clone()
+
+
+def loss_l1(pred: torch.Tensor, target: torch.Tensor, grad: Optional[torch.Tensor] = None,
+            with_loss: bool = True):
+    """(loss tensor [1] or None, grad): mean |pred - target| and its gradient."""
+    L = N.lib()
+    pred = pred.contiguous()
+    target = target.contiguous()
+    if grad is None:
+        grad = torch.empty_like(pred)
+    loss = scratch = None
+    if with_loss:
+        loss = torch.empty(1, dtype=torch.float32, device=pred.device)
+        scratch = torch.empty(L.gsp_loss_l1_scratch_bytes(pred.numel()), dtype=torch.uint8,
+                              device=pred.device)
+    N.check(L.gsp_loss_l1(context(pred.device.index), pred.numel(), _ptr(pred), _ptr(target),
+                          _ptr(grad), _ptr(loss), _ptr(scratch), _stream()), "gsp_loss_l1")
+    return loss, grad
+
+
+def pose_adam(poses, dpose, m, v, steps, lr_start, lr_end, total_steps, beta1=0.9, beta2=0.999,
+              eps=1e-8):
+    """In-place tangent Adam step with left retraction on every pose."""
+    L = N.lib()
+    prm = N.AdamParams(lr_start, lr_end, int(total_steps), beta1, beta2, eps)
+    N.check(L.gsp_pose_adam(context(poses.device.index), poses.shape[0], _ptr(poses), _ptr(dpose),
+                            _ptr(m), _ptr(v), _ptr(steps), ctypes.byref(prm), _stream()),
+            "gsp_pose_adam")
+
+
+class _RenderFn(torch.autograd.Function):
+    @staticmethod
+    def forward(ctx, means, scales, quats, opacities, sh, tau, poses, cams, sh_degree, rast):
+        g = GaussianParams(means.contiguous(), scales.contiguous(), quats.contiguous(),
+                           opacities.contiguous(), sh.contiguous(), sh_degree)
+        images, _ = rast.forward(g, cams, poses.detach())
+        ctx.g, ctx.cams, ctx.rast = g, cams, rast
+        ctx.save_for_backward(poses)
+        return images
+
+    @staticmethod
+    def backward(ctx, dl):
+        (poses,) = ctx.saved_tensors
+        names = ("means", "scales", "quats", "opacities", "sh")
+        want = tuple(k for k, need in zip(names, ctx.needs_input_grad[:5]) if need)
+        need_pose = ctx.needs_input_grad[5]
+        out = ctx.rast.backward(ctx.g, ctx.cams, poses.detach(), dl.contiguous(), want=want,
+                                pose=need_pose)
+        grads = [out.get(k) for k in names]
+        return (*grads, out.get("pose"), None, None, None, None)
+
+
+def render(g: GaussianParams, cams: Sequence, poses: torch.Tensor, tau: Optional[torch.Tensor] = None,
+           rast: Optional[Rasterizer] = None, params=None):
+    """Differentiable render of len(cams) views; returns the packed images.
+
+    `params` (optional) is a tuple (means, scales, quats, opacities, sh) of
+    tensors that require grad; by default the tensors of `g` are used.  `tau`
+    ([V, 6], zeros) receives dL/dtau, the left se(3) twist gradient at the
+    given poses (tau is a tangent at `poses` and is not applied to them).
+    """
+    rast = rast or Rasterizer()
+    if tau is None:
+        tau = torch.zeros((len(cams), 6), dtype=torch.float32, device=poses.device)
+    p = params or (g.means, g.scales, g.quats, g.opacities, g.sh)
+    return _RenderFn.apply(*p, tau, poses, list(cams), g.sh_degree, rast)
+
+
+def solve_poses(g: GaussianParams, cams: Sequence, targets: torch.Tensor, init_poses: torch.Tensor,
+                steps: int = 100, lr=(1e-2, 1e-4), betas=(0.9, 0.999), eps=1e-8,
+                rast: Optional[Rasterizer] = None, history: bool = False):
+    """Estimates the poses of len(cams) views against packed target images by
+    `steps` tangent-space Adam iterations on the L1 loss (cosine learning-rate
+    decay lr[0] -> lr[1]).  Forward, loss, backward (pose only) and the update
+    all run on the device without host synchronisation; the instance capacity
+    is sized from the first render and the whole solve is repeated if any
+    iteration overflowed it."""
+    rast = rast or Rasterizer()
+    V = len(cams)
+    dev = init_poses.device
+    for _ in range(4):
+        poses = init_poses.clone().contiguous()
+        m = torch.zeros((V, 6), dtype=torch.float32, device=dev)
+        v = torch.zeros((V, 6), dtype=torch.float32, device=dev)
+        st = torch.zeros(V, dtype=torch.int32, device=dev)
+        dpose = torch.zeros((V, 6), dtype=torch.float32, device=dev)
+        P = sum(pixel_counts(cams))
+        images = torch.empty(3 * P, dtype=torch.float32, device=dev)
+        dl = torch.empty_like(images)
+        rast.forward(g, cams, poses, check=True, images=images)
+        if rast.capacity < 1.5 * rast.instances()[0]:
+            rast.capacity = int(1.5 * rast.instances()[0]) + 1024
+            rast.ws = None
+        rast._ensure(g, N.view_array(cams))
+        rast.reset_overflow()
+        hist = []
+        for k in range(steps):
+            rast.forward(g, cams, poses, check=False, images=images)
+            loss, _ = loss_l1(images, targets, grad=dl, with_loss=history)
+            rast.backward(g, cams, poses, dl, want=(), pose=True, out={"pose": dpose})
+            pose_adam(poses, dpose, m, v, st, lr[0], lr[1], steps, betas[0], betas[1], eps)
+            if history:
+                hist.append(loss)
+        if not rast.overflowed():
+            if history:
+                return poses, torch.cat(hist).cpu().numpy()
+            return poses
+        rast.capacity = int(rast.capacity * rast.growth) + 1024
+        rast.ws = None
+    raise RuntimeError("instance capacity kept overflowing during the pose solve")

@@ -1,0 +1,318 @@
+"""HIP path vs the FP64 oracle, stage by stage, through the C ABI.
+
+Bars: per-Gaussian records to rounding; sort keys, values and tile ranges bit
+for bit; images within 1e-4 absolute on every pixel the oracle does not flag
+as straddling an FP32/FP64 decision (straddling pixels are counted and must
+be rare); gradients within 1e-3 relative L2 per parameter group and per pose
+block (rho, phi).
+"""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_2410_08743_amd import render as R
+from paper_2410_08743_amd import synthetic as S
+from tests.parity_util import f32_camera, random_case, rel_l2, unpack_rect
+
+pytestmark = pytest.mark.gpu
+
+DEV = "cuda:0"
+
+
+def _case(name):
+    if name == "tiny":
+        wl = S.tiny()
+        return wl.scene, f32_camera(wl.camera), wl.pose
+    if name == "sh0":
+        return random_case(11, 0, 96, 64, 300)
+    if name == "sh1-ragged":
+        return random_case(12, 1, 70, 53, 250)
+    if name == "sh2-near":
+        return random_case(13, 2, 80, 80, 300, depth=(0.05, 4.0), lateral=2.0)
+    if name == "sh3-roi":
+        return random_case(14, 3, 120, 90, 400, roi=(32, 16, 61, 50))
+    if name == "sh3-dense":
+        return random_case(15, 3, 128, 96, 3000, depth=(1.0, 8.0))
+    raise KeyError(name)
+
+
+CASES = ["tiny", "sh0", "sh1-ragged", "sh2-near", "sh3-roi", "sh3-dense"]
+
+
+def _gpu(sc, cams, poses, up=None, cap=0, want=("means", "scales", "quats", "opacities", "sh")):
+    g = R.GaussianParams.from_set(sc, DEV)
+    P = torch.tensor(np.stack(poses), device=DEV, dtype=torch.float32)
+    rast = R.Rasterizer(0, capacity=cap)
+    img, alpha = rast.forward(g, cams, P, alphas=True)
+    out = {"images": [t.cpu().numpy() for t in R.split_images(img, cams)],
+           "alpha": alpha.cpu().numpy(), "rast": rast, "g": g, "P": P}
+    if up is not None:
+        dl = torch.tensor(np.concatenate([u.ravel() for u in up]), device=DEV)
+        gr = rast.backward(g, cams, P, dl, want=want)
+        out.update({k: v.cpu().numpy() for k, v in gr.items()})
+    torch.cuda.synchronize()
+    return out
+
+
+def _upstream(seed, cam):
+    x, y, w, h = cam.region()
+    return S.upstream(seed, (3, h, w))
+
+
+@pytest.mark.parametrize("name", CASES)
+def test_preprocess_records(name):
+    sc, cam, pose = _case(name)
+    run = _gpu(sc, [cam], [pose])
+    rast, g = run["rast"], run["g"]
+    ref = oracle.preprocess(sc, cam, pose)
+    geom = rast.inspect(g, [cam], "geom").cpu().numpy().reshape(-1, 8)
+    col = rast.inspect(g, [cam], "color").cpu().numpy().reshape(-1, 4)
+    rect = unpack_rect(rast.inspect(g, [cam], "rect", torch.int32).cpu().numpy())
+    depth = rast.inspect(g, [cam], "depth", torch.int32).cpu().numpy().view(np.uint32)
+    tiles = rast.inspect(g, [cam], "tiles", torch.int32).cpu().numpy()
+    solid = (ref["fragile"] == 0)
+    ren = (ref["rendered"] == 1) & solid
+    print(f"{name}: n={sc.n} rendered={int(ren.sum())} fragile={int((~solid).sum())}")
+    assert np.array_equal(depth, ref["depth_key"].view(np.uint32))
+    ref_tiles = np.where(ref["rendered"] == 1,
+                         (ref["rect"][:, 2] - ref["rect"][:, 0]) * (ref["rect"][:, 3] - ref["rect"][:, 1]), 0)
+    assert np.array_equal(tiles[solid], ref_tiles[solid])
+    assert np.array_equal(rect[ren], ref["rect"][ren])
+    u = geom[:, 0].astype(np.float64) + geom[:, 2]
+    v = geom[:, 1].astype(np.float64) + geom[:, 3]
+    assert np.max(np.abs(u[ren] - ref["u"][ren])) < 1e-9 * max(1.0, np.abs(ref["u"][ren]).max())
+    assert np.max(np.abs(v[ren] - ref["v"][ren])) < 1e-9 * max(1.0, np.abs(ref["v"][ren]).max())
+    conic = geom[:, 4:7].astype(np.float64)
+    assert np.max(np.abs(conic[ren] - ref["conic"][ren]) / np.abs(ref["conic"][ren]).max(1, keepdims=True)) < 1e-6
+    assert np.array_equal(geom[ren, 7], sc.opacities[ren])
+    assert np.max(np.abs(col[ren, :3] - ref["color"][ren])) < 2e-6
+
+
+@pytest.mark.parametrize("name", CASES)
+def test_keys_sort_and_ranges_bit_exact(name):
+    sc, cam, pose = _case(name)
+    run = _gpu(sc, [cam], [pose])
+    rast, g = run["rast"], run["g"]
+    ref = oracle.preprocess(sc, cam, pose)
+    gw, gh = oracle.tiles_of(cam)
+    rkeys, rvals = oracle.bin_sort([ref], [(gw, gh)])
+    M, ovf = rast.instances()
+    assert not ovf
+    keys = rast.inspect(g, [cam], "keys", torch.int64).cpu().numpy().view(np.uint64)[:M]
+    vals = rast.inspect(g, [cam], "values", torch.int32).cpu().numpy().view(np.uint32)[:M]
+    fragile = np.nonzero(ref["fragile"])[0].astype(np.uint32)
+    if len(fragile) == 0:
+        assert M == len(rkeys)
+        assert np.array_equal(keys, rkeys)
+        assert np.array_equal(vals, rvals)
+        ranges = rast.inspect(g, [cam], "ranges", torch.int32).cpu().numpy().view(np.uint32)
+        assert np.array_equal(ranges.reshape(-1, 2), oracle.tile_ranges(rkeys, gw * gh))
+    else:
+        keep_g = ~np.isin(vals, fragile)
+        keep_r = ~np.isin(rvals, fragile)
+        assert np.array_equal(keys[keep_g], rkeys[keep_r])
+        assert np.array_equal(vals[keep_g], rvals[keep_r])
+
+
+def _image_check(img, ref, name, max_straddle=2e-3):
+    strad = ref["straddle"]
+    err = np.abs(img - ref["image"]).max(axis=0)
+    ok = ~strad
+    worst = float(err[ok].max()) if ok.any() else 0.0
+    print(f"{name}: max |image - oracle| = {worst:.2e}, straddling pixels {int(strad.sum())}/{strad.size}")
+    assert strad.mean() <= max_straddle
+    assert worst <= 1e-4
+
+
+@pytest.mark.parametrize("name", CASES)
+def test_image_parity(name):
+    sc, cam, pose = _case(name)
+    run = _gpu(sc, [cam], [pose])
+    ref = oracle.render(sc, cam, pose)
+    img = run["images"][0]
+    _image_check(img, ref, name)
+    ok = ~ref["straddle"]
+    alpha = run["alpha"].reshape(ref["T_final"].shape)
+    assert np.max(np.abs((1 - alpha)[ok] - ref["T_final"][ok])) <= 1e-5
+    nc = run["rast"].inspect(run["g"], [cam], "ncontrib", torch.int32).cpu().numpy()
+    nc = nc.reshape(ref["n_contrib"].shape)
+    assert np.mean(nc[ok] == ref["n_contrib"][ok]) >= 0.999
+
+
+@pytest.mark.parametrize("name", CASES)
+def test_backward_parity(name):
+    sc, cam, pose = _case(name)
+    up = _upstream(21, cam)
+    run = _gpu(sc, [cam], [pose], up=[up])
+    ref = oracle.backward(sc, cam, pose, up)
+    g2 = run["rast"].inspect(run["g"], [cam], "grad2d").cpu().numpy().reshape(9, -1).T
+    report = {"splat2d": rel_l2(g2, ref["splat2d"])}
+    for k in ("means", "scales", "quats", "opacities", "sh"):
+        report[k] = rel_l2(run[k], ref[k])
+    report["rho"] = rel_l2(run["pose"][0, :3], ref["pose"][:3])
+    report["phi"] = rel_l2(run["pose"][0, 3:], ref["pose"][3:])
+    print(name, {k: f"{v:.1e}" for k, v in report.items()})
+    for k, v in report.items():
+        assert v <= 1e-3, f"{k}: relative L2 {v:.2e}"
+
+
+def test_multiview_batch_equals_single_views():
+    sc, cam0, pose0 = random_case(31, 3, 96, 64, 800)
+    cam1 = f32_camera(S.Camera(80, 48, 75.0, 70.0, 40.5, 23.75, roi=(16, 0, 50, 48)))
+    cam2 = f32_camera(S.Camera(64, 64, 60.0, 60.0, 32.0, 32.0, bg=(0.5, 0.5, 0.5)))
+    pose1 = S.random_pose_near_identity(32, 3.0, 0.1)
+    pose2 = S.random_pose_near_identity(33, 5.0, 0.1)
+    cams, poses = [cam0, cam1, cam2], [pose0, pose1, pose2]
+    ups = [_upstream(40 + k, c) for k, c in enumerate(cams)]
+    both = _gpu(sc, cams, poses, up=ups)
+    sums = {k: 0 for k in ("means", "scales", "quats", "opacities", "sh")}
+    for k in range(3):
+        one = _gpu(sc, [cams[k]], [poses[k]], up=[ups[k]])
+        assert np.array_equal(both["images"][k], one["images"][0])
+        assert np.array_equal(both["pose"][k], one["pose"][0])
+        for key in sums:
+            sums[key] = sums[key] + one[key].astype(np.float64)
+    for key in sums:
+        assert rel_l2(both[key], sums[key]) <= 1e-6
+
+
+def test_roi_equals_full_image_crop():
+    sc, cam, pose = random_case(41, 3, 112, 80, 600)
+    full = _gpu(sc, [cam], [pose])["images"][0]
+    for roi in [(16, 16, 64, 48), (48, 0, 64, 80), (0, 32, 37, 21)]:
+        crop = _gpu(sc, [cam.with_roi(roi)], [pose])["images"][0]
+        x, y, w, h = roi
+        assert np.array_equal(crop, full[:, y:y + h, x:x + w])
+
+
+def test_bitwise_reproducible():
+    sc, cam, pose = random_case(51, 3, 128, 96, 2000)
+    up = _upstream(52, cam)
+    a = _gpu(sc, [cam], [pose], up=[up])
+    b = _gpu(sc, [cam], [pose], up=[up])
+    assert np.array_equal(a["images"][0], b["images"][0])
+    for k in ("means", "scales", "quats", "opacities", "sh", "pose"):
+        assert np.array_equal(a[k], b[k]), k
+
+
+def test_capacity_overflow_regrows_and_matches():
+    sc, cam, pose = random_case(61, 2, 96, 64, 500)
+    ref = _gpu(sc, [cam], [pose], cap=10_000_000)
+    g = R.GaussianParams.from_set(sc, DEV)
+    P = torch.tensor(pose[None], device=DEV)
+    rast = R.Rasterizer(0, capacity=64)
+    rast.forward(g, [cam], P, check=False)
+    m, ovf = rast.instances()
+    assert ovf and m > 64
+    img, _ = rast.forward(g, [cam], P, check=True)
+    assert rast.capacity >= m
+    assert np.array_equal(R.split_images(img, [cam])[0].cpu().numpy(), ref["images"][0])
+
+
+def test_empty_and_invisible_scenes_render_background():
+    cam = f32_camera(S.Camera(48, 40, 40.0, 40.0, 24.0, 20.0, bg=(0.25, 0.5, 0.75)))
+    empty = S.GaussianSet(np.zeros((0, 3), np.float32), np.zeros((0, 3), np.float32),
+                          np.zeros((0, 4), np.float32), np.zeros(0, np.float32),
+                          np.zeros((0, 1, 3), np.float32), 0)
+    behind, _, _ = random_case(71, 0, 48, 40, 50)
+    behind.means[:, 2] = -np.abs(behind.means[:, 2]) - 1.0
+    for sc in (empty, behind):
+        up = _upstream(72, cam)
+        run = _gpu(sc, [cam], [S.identity_pose()], up=[up])
+        for ch in range(3):
+            assert np.all(run["images"][0][ch] == np.float32(cam.bg[ch]))
+        assert np.all(run["pose"] == 0)
+        if sc.n:
+            assert np.all(run["means"] == 0)
+
+
+def test_l1_loss_kernel():
+    rng = np.random.default_rng(81)
+    a = rng.standard_normal(100_003).astype(np.float32)
+    b = a.copy()
+    b[::5] = rng.standard_normal(len(b[::5])).astype(np.float32)
+    loss, grad = R.loss_l1(torch.tensor(a, device=DEV), torch.tensor(b, device=DEV))
+    rv, rg = oracle.l1(a, b)
+    assert abs(float(loss.item()) - rv) <= 1e-6 * rv
+    assert np.array_equal(np.sign(grad.cpu().numpy()), np.sign(rg))
+    assert np.max(np.abs(grad.cpu().numpy() - rg)) <= 1e-7 * np.abs(rg).max()
+
+
+def test_pose_adam_kernel():
+    rng = np.random.default_rng(91)
+    V, K = 3, 7
+    poses = np.stack([S.random_pose_near_identity(92 + k, 10.0, 0.5) for k in range(V)])
+    grads = rng.standard_normal((K, V, 6)).astype(np.float32)
+    P = torch.tensor(poses, device=DEV)
+    m = torch.zeros((V, 6), device=DEV)
+    v = torch.zeros((V, 6), device=DEV)
+    st = torch.zeros(V, dtype=torch.int32, device=DEV)
+    ref = [(poses[k].astype(np.float64), np.zeros(6), np.zeros(6)) for k in range(V)]
+    for it in range(K):
+        R.pose_adam(P, torch.tensor(grads[it], device=DEV), m, v, st, 1e-2, 1e-3, K)
+        frac = it / (K - 1)
+        lr = 1e-3 + 0.5 * (1e-2 - 1e-3) * (1 + np.cos(np.pi * frac))
+        ref = [oracle.pose_adam(T, mm, vv, grads[it][k], it + 1, lr)[:3] for k, (T, mm, vv) in enumerate(ref)]
+    got = P.cpu().numpy()
+    for k in range(V):
+        assert np.max(np.abs(got[k] - ref[k][0])) <= 2e-6
+    assert np.all(st.cpu().numpy() == K)
+
+
+def test_autograd_function_matches_direct_calls():
+    sc, cam, pose = random_case(101, 3, 64, 48, 300)
+    g = R.GaussianParams.from_set(sc, DEV)
+    params = [t.clone().requires_grad_(True) for t in (g.means, g.scales, g.quats, g.opacities, g.sh)]
+    tau = torch.zeros((1, 6), device=DEV, requires_grad=True)
+    P = torch.tensor(pose[None], device=DEV)
+    W = torch.tensor(_upstream(102, cam).ravel(), device=DEV)
+    img = R.render(g, [cam], P, tau=tau, params=params)
+    (img * W).sum().backward()
+    direct = _gpu(sc, [cam], [pose], up=[_upstream(102, cam)])
+    assert np.array_equal(tau.grad.cpu().numpy(), direct["pose"])
+    for t, k in zip(params, ("means", "scales", "quats", "opacities", "sh")):
+        assert np.array_equal(t.grad.cpu().numpy(), direct[k])
+
+
+def test_pose_solve_reduces_error_tiny():
+    wl = S.tiny()
+    cam = f32_camera(wl.camera)
+    g = R.GaussianParams.from_set(wl.scene, DEV)
+    target_pose = torch.tensor(wl.pose[None], device=DEV)
+    rast = R.Rasterizer(0)
+    target, _ = rast.forward(g, [cam], target_pose)
+    target = target.clone()
+    init = torch.tensor(wl.init_pose[None], device=DEV)
+    est, hist = R.solve_poses(g, [cam], target, init, steps=150, lr=(1e-2, 1e-4), history=True)
+    r0, t0 = S.pose_error(wl.init_pose, wl.pose)
+    r1, t1 = S.pose_error(est[0].cpu().numpy(), wl.pose)
+    print(f"tiny solve: rot {r0:.3f} -> {r1:.3f} deg, trans {t0:.4f} -> {t1:.4f}, loss {hist[0]:.4f} -> {hist[-1]:.4f}")
+    assert hist[-1] < 0.5 * hist[0]
+    assert r1 < 0.5 * r0 and t1 < 0.5 * t0
+
+
+def test_full_size_single_view_workload():
+    """The benchmark workload at its full size (200k Gaussians, SH 3,
+    1008x756): image, sort keys and gradients against the oracle."""
+    wl = S.single_view()
+    cam = f32_camera(wl.camera)
+    sc, pose = wl.scene, wl.init_pose
+    up = _upstream(111, cam)
+    run = _gpu(sc, [cam], [pose], up=[up], want=())
+    ref = oracle.render(sc, cam, pose)
+    _image_check(run["images"][0], ref, "full-size")
+    rref = oracle.backward(sc, cam, pose, up)
+    rho = rel_l2(run["pose"][0, :3], rref["pose"][:3])
+    phi = rel_l2(run["pose"][0, 3:], rref["pose"][3:])
+    print(f"full-size pose gradient rel L2: rho {rho:.2e} phi {phi:.2e}")
+    assert rho <= 1e-3 and phi <= 1e-3
+    sp = oracle.preprocess(sc, cam, pose)
+    if not sp["fragile"].any():
+        gw, gh = oracle.tiles_of(cam)
+        rkeys, rvals = oracle.bin_sort([sp], [(gw, gh)])
+        rast, g = run["rast"], run["g"]
+        M, _ = rast.instances()
+        keys = rast.inspect(g, [cam], "keys", torch.int64).cpu().numpy().view(np.uint64)[:M]
+        vals = rast.inspect(g, [cam], "values", torch.int32).cpu().numpy().view(np.uint32)[:M]
+        assert np.array_equal(keys, rkeys) and np.array_equal(vals, rvals)
