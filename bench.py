@@ -1,0 +1,254 @@
+#!/usr/bin/env python3
+"""Benchmark of the pose-differentiable Gaussian splatting rasterizer on one
+MI355X.
+
+Workload (default): single-view pose estimation on a forward-facing synthetic
+scene -- 200k Gaussians in a frustum slab at depth 1.5-8, SH degree 3,
+1008x756 image, fx = fy = 815, initial pose error 5 deg / 0.1, Adam on the
+pose only, FP32.  The scene, camera and target image are synthetic and
+seeded (they stand in for the paper's LLFF pose-estimation scenes); the
+target is rendered at the ground-truth pose.
+
+A step is one pass of the whole hot path: preprocess, binning, radix sort,
+tile ranges, forward rasterizer, L1 loss, backward rasterizer,
+preprocess-backward with the pose reduction, and the tangent Adam update.
+`--steps K` steps of one pose solve are timed with HIP events on the stream
+the kernels run on, inputs already resident in HBM.
+
+The JSON line also carries, for the dominant kernel, achieved vs peak
+(`roofline`), and the FP64 CPU oracle timed on this host (`cpu_baseline`).
+"""
+import argparse
+import hashlib
+import json
+import os
+import re
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = "fwd+bwd Mpix/s incl. pose grad; pose-solve requests/s + p50/p99 latency"
+PEAK_HBM_GBS = 8000.0
+# FP32 FMA peak of the unpacked VALU: 256 CU x 64 lanes x 2 flops x 2.4 GHz.
+# (The published 157.3 TFLOP/s vector figure needs packed FP32 instructions,
+# which this build disables.)
+PEAK_FP32_TFLOPS = 78.6
+# FP32 flops per (pixel, splat) pair of the compositing formulas (Eq. (3)-(4)
+# forward; their adjoint backward), FMA counted as 2.
+FWD_FLOPS_EVAL, FWD_FLOPS_BLEND = 19, 7
+BWD_FLOPS_EVAL, BWD_FLOPS_BLEND = 16, 49
+KERNEL_SOURCES = {
+    "raster_fwd": ["raster_fwd.hip", "raster_common.h"],
+    "raster_bwd": ["raster_bwd.hip", "raster_common.h"],
+    "preprocess": ["preprocess.hip"],
+    "sort": ["sort.hip"],
+    "preprocess_bwd": ["preprocess_bwd.hip"],
+}
+
+
+def source_hash(stage):
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES.get(stage, []):
+        with open(os.path.join(ROOT, "paper_2410_08743_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def traffic_from_profiles(stage, workload):
+    """HBM bytes per launch from a committed rocprofv3 counter summary, if it
+    was taken on the current kernel source; else None."""
+    path = os.path.join(ROOT, "profiles", f"{stage}_{workload}_pmc.md")
+    if not os.path.exists(path):
+        return None
+    text = open(path).read()
+    m_src = re.search(r"source_sha256_16:\s*([0-9a-f]{16})", text)
+    m_b = re.search(r"hbm_bytes_per_launch:\s*([0-9.eE+]+)", text)
+    if not m_src or not m_b or m_src.group(1) != source_hash(stage):
+        return None
+    return float(m_b.group(1))
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=100)
+    ap.add_argument("--warmup", type=int, default=10)
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--cpu-reps", type=int, default=3)
+    ap.add_argument("--profile-only", action="store_true",
+                    help="run warmup + timed steps only (for rocprofv3), no JSON extras")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "
+              "(the multi-GPU layout is described in DESIGN.md)", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    from paper_2410_08743_amd import _native as N
+    from paper_2410_08743_amd import render as R
+    from paper_2410_08743_amd import synthetic as S
+
+    torch.cuda.set_device(0)
+    dev = "cuda:0"
+    wl = S.single_view()
+    cam = wl.camera
+    P = cam.width * cam.height
+    g = R.GaussianParams.from_set(wl.scene, dev)
+    gt = torch.tensor(wl.pose[None], device=dev)
+    init = torch.tensor(wl.init_pose[None], device=dev)
+    rast = R.Rasterizer(0)
+    target = rast.forward(g, [cam], gt)[0].clone()
+    print(f"[bench] workload {wl.name}: n={g.n}, {cam.width}x{cam.height}", file=sys.stderr, flush=True)
+
+    # capacity from the starting pose, with room for the poses the solve visits
+    rast.forward(g, [cam], init)
+    m0, _ = rast.instances()
+    rast.capacity = int(1.5 * m0) + 4096
+    rast.ws = None
+    images = torch.empty(3 * P, dtype=torch.float32, device=dev)
+    dl = torch.empty_like(images)
+    K = args.steps
+
+    def new_state():
+        return {"pose": init.clone(), "m": torch.zeros((1, 6), device=dev),
+                "v": torch.zeros((1, 6), device=dev),
+                "st": torch.zeros(1, dtype=torch.int32, device=dev),
+                "dpose": torch.zeros((1, 6), device=dev)}
+
+    def step(s, total):
+        rast.forward(g, [cam], s["pose"], check=False, images=images)
+        R.loss_l1(images, target, grad=dl, with_loss=False)
+        rast.backward(g, [cam], s["pose"], dl, want=(), pose=True, out={"pose": s["dpose"]})
+        R.pose_adam(s["pose"], s["dpose"], s["m"], s["v"], s["st"], 1e-2, 1e-4, total)
+
+    rast._ensure(g, N.view_array([cam]))
+    s = new_state()
+    for _ in range(args.warmup):
+        step(s, max(args.warmup, 1))
+    rast.reset_overflow()
+    s = new_state()
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(K):
+        step(s, K)
+    e1.record()
+    torch.cuda.synchronize()
+    total_ms = e0.elapsed_time(e1)
+    M_last, overflow = rast.instances()
+    if overflow:
+        print("[bench] instance capacity overflowed during the timed solve", file=sys.stderr)
+        sys.exit(3)
+    ms_step = total_ms / K
+    value = P * K / (total_ms * 1e-3) / 1e6
+    rot_err, trans_err = S.pose_error(s["pose"][0].cpu().numpy(), wl.pose)
+    rot0, trans0 = S.pose_error(wl.init_pose, wl.pose)
+    print(f"[bench] {K} steps: {ms_step:.3f} ms/step, {value:.1f} Mpix/s; pose error "
+          f"{rot0:.2f} deg/{trans0:.3f} -> {rot_err:.3f} deg/{trans_err:.4f}", file=sys.stderr, flush=True)
+    if args.profile_only:
+        return
+
+    # per-stage timing pass (events bracket each stage on the same stream)
+    R.profile_enable(0, R.PROFILE_TIMING)
+    s = new_state()
+    nprof = min(K, 50)
+    for _ in range(nprof):
+        step(s, nprof)
+    stages = R.profile_read(0)
+    R.profile_enable(0, 0)
+    stage_ms = {k: ms / c for k, (c, ms) in stages.items()}
+
+    # work counts at the starting pose: evaluated / blended pairs per pixel
+    R.profile_enable(0, R.PROFILE_COUNTS)
+    s = new_state()
+    step(s, 1)
+    R.profile_enable(0, 0)
+    neval = rast.inspect(g, [cam], "neval", torch.int32).to(torch.int64).sum().item()
+    nblend = rast.inspect(g, [cam], "nblend", torch.int32).to(torch.int64).sum().item()
+    ncontrib = rast.inspect(g, [cam], "ncontrib", torch.int32).to(torch.int64).sum().item()
+    M, _ = rast.instances()
+    n, S3 = g.n, (g.sh_degree + 1) ** 2
+    param_bytes = 4 * (11 + 3 * S3)
+    work = {
+        "preprocess": ("hbm", (param_bytes + 64) * n),
+        "duplicate": ("hbm", 20 * n + 12 * M),
+        "sort": ("hbm", 24 * M),
+        "ranges": ("hbm", 8 * M + 8 * ((cam.width + 15) // 16) * ((cam.height + 15) // 16)),
+        "raster_fwd": ("alu", FWD_FLOPS_EVAL * neval + FWD_FLOPS_BLEND * nblend),
+        "loss_l1": ("hbm", 12 * 3 * P),
+        "raster_bwd": ("alu", BWD_FLOPS_EVAL * ncontrib + BWD_FLOPS_BLEND * nblend),
+        "preprocess_bwd": ("hbm", (param_bytes - 4) * n + 36 * M + 8 * n),
+        "pose_adam": ("hbm", 0),
+    }
+    stage_report = {}
+    for k, ms in stage_ms.items():
+        kind, amount = work.get(k, ("hbm", 0))
+        if kind == "hbm":
+            ach = amount / (ms * 1e-3) / 1e9
+            stage_report[k] = {"ms": round(ms, 4), "bound": "hbm", "achieved_GBs": round(ach, 1),
+                               "frac": round(ach / PEAK_HBM_GBS, 4)}
+        else:
+            ach = amount / (ms * 1e-3) / 1e12
+            stage_report[k] = {"ms": round(ms, 4), "bound": "alu", "achieved_TFLOPs": round(ach, 2),
+                               "frac": round(ach / PEAK_FP32_TFLOPS, 4)}
+    dominant = max(stage_ms, key=stage_ms.get)
+    kind, amount = work[dominant]
+    dms = stage_ms[dominant]
+    if kind == "alu":
+        ach = amount / (dms * 1e-3) / 1e12
+        roof = {"kernel": dominant, "bound": "alu", "achieved": round(ach, 3),
+                "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s", "frac": round(ach / PEAK_FP32_TFLOPS, 4)}
+    else:
+        ach = amount / (dms * 1e-3) / 1e9
+        roof = {"kernel": dominant, "bound": "hbm", "achieved": round(ach, 1),
+                "peak": PEAK_HBM_GBS, "unit": "GB/s", "frac": round(ach / PEAK_HBM_GBS, 4)}
+    roof["avg_launch_ms"] = round(dms, 4)
+    roof["algorithmic_per_launch"] = amount
+    roof["traffic"] = traffic_from_profiles(dominant, "pose-200k-1008x756")
+
+    cpu = None
+    if not args.no_cpu:
+        import oracle
+        ts = []
+        for _ in range(args.cpu_reps):
+            t0 = time.perf_counter()
+            oracle.render(wl.scene, cam, wl.init_pose)
+            up = np.zeros((3, cam.height, cam.width))
+            oracle.backward(wl.scene, cam, wl.init_pose, up)
+            ts.append(time.perf_counter() - t0)
+        t = float(np.median(ts))
+        cpu = {"value": round(P / t / 1e6, 4), "unit": "Mpix/s", "cores": oracle.max_threads(),
+               "kind": "oracle",
+               "sample": f"one fwd render + one bwd (pose and Gaussian grads) of the full "
+                         f"{cam.width}x{cam.height} view of the 200k-Gaussian scene at the "
+                         f"starting pose, FP64, median of {args.cpu_reps}",
+               "seconds": round(t, 3)}
+
+    line = {
+        "metric": METRIC, "value": round(value, 2), "unit": "Mpix/s", "n_gpus": 1,
+        "steps": K, "warmup": args.warmup, "ms_per_step": round(ms_step, 4),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": wl.name, "gaussians": g.n, "sh_degree": g.sh_degree,
+                   "width": cam.width, "height": cam.height, "views_per_step": 1,
+                   "step": "fwd+L1+bwd(pose)+adam", "parallelism": "single GPU"},
+        "roofline": roof,
+        "cpu_baseline": cpu,
+        "stages": stage_report,
+        "work": {"instances": M, "evaluated_pairs": neval, "blended_pairs": nblend,
+                 "backward_pairs": ncontrib},
+        "pose_solve": {"steps": K, "seconds": round(total_ms * 1e-3, 4),
+                       "sequential_requests_per_s": round(1e3 / total_ms, 3),
+                       "initial_error": [round(rot0, 3), round(trans0, 4)],
+                       "final_error": [round(rot_err, 4), round(trans_err, 5)]},
+    }
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -182,11 +182,30 @@ gsp_status gsp_pose_adam(gsp_ctx *ctx, int32_t V, float *poses, const float *dpo
  * "rect" (uint16 x0 y0 x1 y1), "depth" (uint32 float bits), "tiles"
  * (uint32 count), "keys" (uint64 sorted), "values" (uint32 sorted),
  * "ranges" (uint32 pairs per tile), "tfinal" (float per pixel),
- * "ncontrib" (uint32 per pixel), "grad2d" (float [9][V*n]: du dv dA dB dC
+ * "ncontrib" (uint32 per pixel), "neval", "nblend" (uint32 per pixel, see
+ * GSP_PROFILE_COUNTS), "grad2d" (float [9][V*n]: du dv dA dB dC
  * do dr dg db), "counters" (uint32: M, overflow). */
 gsp_status gsp_inspect(gsp_ctx *ctx, const gsp_gaussians *g, int32_t V, const gsp_view *views,
                        void *workspace, size_t ws_bytes, int64_t instance_capacity,
                        const char *name, void **ptr, int64_t *count);
+
+/* Measurement modes (bit mask for gsp_profile_enable).
+ * GSP_PROFILE_TIMING: every stage of gsp_render_fwd / gsp_render_bwd
+ * (preprocess, duplicate, sort, ranges, raster_fwd, raster_bwd,
+ * preprocess_bwd) and the gsp_loss_l1 and gsp_pose_adam kernels are
+ * bracketed by HIP events recorded on the call's stream.
+ * GSP_PROFILE_COUNTS: the forward rasterizer also counts, per pixel, the
+ * (pixel, splat) pairs it evaluated and blended (gsp_inspect "neval",
+ * "nblend"); a slower variant, meant for a separate measurement pass.
+ * gsp_profile_read waits for the recorded events and returns, for up to
+ * max_stages stages, the stage name (NUL-terminated, < 32 chars), the number
+ * of launches and the summed milliseconds since the previous read; *n_out is
+ * the number of stages written.  Not thread-safe per context. */
+#define GSP_PROFILE_TIMING 1
+#define GSP_PROFILE_COUNTS 2
+gsp_status gsp_profile_enable(gsp_ctx *ctx, int mode);
+gsp_status gsp_profile_read(gsp_ctx *ctx, int32_t max_stages, char *names /* [max][32] */,
+                            int64_t *counts, double *ms, int32_t *n_out);
 
 const char *gsp_status_string(gsp_status s);
 const char *gsp_last_error(void);

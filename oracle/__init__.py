@@ -19,7 +19,7 @@ __all__ = [
     "load", "SPLAT_DTYPE", "TRACE_DTYPE", "sh_basis", "quat_to_rotmat",
     "se3_exp", "se3_retract", "preprocess", "count_instances", "bin_sort",
     "tile_ranges", "render", "render_brute", "pixel_trace", "backward", "l1",
-    "masked_l1", "pose_adam", "TILE", "tiles_of",
+    "masked_l1", "pose_adam", "TILE", "tiles_of", "max_threads",
 ]
 
 TILE = 16
@@ -73,6 +73,7 @@ def load():
         build()
     lib = ctypes.CDLL(LIB)
     P = ctypes.c_void_p
+    lib.gso_max_threads.restype = ctypes.c_int
     lib.gso_sh_basis.argtypes = [ctypes.c_int, P, P, P]
     lib.gso_quat_to_rotmat.argtypes = [P, P]
     lib.gso_se3_exp.argtypes = [P, P]
@@ -138,6 +139,10 @@ def _view(cam):
 
 def _pose(pose):
     return _f64(pose, (12,))
+
+
+def max_threads():
+    return int(load().gso_max_threads())
 
 
 def tiles_of(cam):

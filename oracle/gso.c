@@ -38,6 +38,15 @@
 
 int gso_version(void) { return 1; }
 
+int gso_max_threads(void)
+{
+#ifdef _OPENMP
+    return omp_get_max_threads();
+#else
+    return 1;
+#endif
+}
+
 /* ------------------------------------------------------------------------ */
 /* Real spherical harmonics, degree <= 3 (Sec. III-A: c = SH(f, d)).          */
 /* ------------------------------------------------------------------------ */

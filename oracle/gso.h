@@ -108,6 +108,9 @@ typedef struct {
 
 int gso_version(void);
 
+/* OpenMP threads the oracle's parallel loops use. */
+int gso_max_threads(void);
+
 /* Real spherical harmonics up to degree 3 (Condon-Shortley phase, order
  * m = -l..l) at direction d; writes (degree+1)^2 values and, if grad is not
  * NULL, their partial derivatives [(degree+1)^2][3] as polynomials in d. */

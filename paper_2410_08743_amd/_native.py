@@ -18,6 +18,7 @@ EXPORTS = (
     "gsp_create", "gsp_destroy", "gsp_workspace_size", "gsp_render_fwd", "gsp_render_bwd",
     "gsp_instances", "gsp_loss_l1", "gsp_loss_l1_scratch_bytes", "gsp_pose_adam",
     "gsp_inspect", "gsp_status_string", "gsp_last_error", "gsp_version",
+    "gsp_profile_enable", "gsp_profile_read",
 )
 
 
@@ -83,6 +84,8 @@ def lib():
         "gsp_pose_adam": ([P, I32, P, P, P, P, P, P, P], I32),
         "gsp_inspect": ([P, P, I32, P, P, SZ, I64, ctypes.c_char_p, ctypes.POINTER(P),
                          ctypes.POINTER(I64)], I32),
+        "gsp_profile_enable": ([P, ctypes.c_int], I32),
+        "gsp_profile_read": ([P, I32, P, P, P, ctypes.POINTER(I32)], I32),
         "gsp_status_string": ([I32], ctypes.c_char_p),
         "gsp_last_error": ([], ctypes.c_char_p),
         "gsp_version": ([], ctypes.c_int),

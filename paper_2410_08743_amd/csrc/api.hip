@@ -9,11 +9,29 @@
 #include <cstdio>
 #include <cstring>
 #include <string>
+#include <vector>
 
 #include "gsp_internal.h"
 
+namespace {
+struct StageRec {
+    const char *name;
+    hipEvent_t start, stop;
+};
+struct StageSum {
+    std::string name;
+    int64_t count;
+    double ms;
+};
+}  // namespace
+
 struct gsp_ctx {
     int device;
+    bool profiling = false;   // stage timing
+    bool stats = false;       // per-pixel work counters in the forward
+    std::vector<StageRec> pending;
+    std::vector<hipEvent_t> pool;
+    std::vector<StageSum> sums;
 };
 
 namespace {
@@ -36,6 +54,29 @@ gsp_status hip_fail(hipError_t e, const char *where) {
 }
 
 size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
+
+hipEvent_t take_event(gsp_ctx *ctx) {
+    if (!ctx->pool.empty()) {
+        hipEvent_t e = ctx->pool.back();
+        ctx->pool.pop_back();
+        return e;
+    }
+    hipEvent_t e = nullptr;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    return e;
+}
+
+// Runs one stage's launcher, bracketed by events when profiling is on.
+template <typename F>
+hipError_t stage(gsp_ctx *ctx, const char *name, hipStream_t st, F &&launch) {
+    if (!ctx->profiling) return launch();
+    StageRec r{name, take_event(ctx), take_event(ctx)};
+    if (r.start) hipEventRecord(r.start, st);
+    hipError_t e = launch();
+    if (r.stop) hipEventRecord(r.stop, st);
+    if (r.start && r.stop) ctx->pending.push_back(r);
+    return e;
+}
 
 gsp_status check_device(const gsp_ctx *ctx) {
     if (!ctx) return fail(GSP_EINVAL, "null context");
@@ -180,6 +221,7 @@ Layout make_layout(int64_t n, int32_t sh_degree, int32_t V, const ViewsK &views,
     L.ranges = take((size_t)L.total_tiles * 8);
     L.tfinal = take((size_t)pix * 4);
     L.ncontrib = take((size_t)pix * 4);
+    L.stats = take((size_t)pix * 8);
     L.slots = take(9 * capz * 4);
     L.grad2d = take(9 * vn * 4);
     L.posepart = take((size_t)V * L.nblk_pre * 6 * 8);
@@ -229,7 +271,61 @@ gsp_status gsp_create(int device, gsp_ctx **out) {
 }
 
 gsp_status gsp_destroy(gsp_ctx *ctx) {
+    if (!ctx) return GSP_OK;
+    for (StageRec &r : ctx->pending) {
+        hipEventSynchronize(r.stop);
+        hipEventDestroy(r.start);
+        hipEventDestroy(r.stop);
+    }
+    for (hipEvent_t e : ctx->pool) hipEventDestroy(e);
     delete ctx;
+    return GSP_OK;
+}
+
+gsp_status gsp_profile_enable(gsp_ctx *ctx, int mode) {
+    gsp_status s = check_device(ctx);
+    if (s != GSP_OK) return s;
+    if (mode & ~(GSP_PROFILE_TIMING | GSP_PROFILE_COUNTS)) return fail(GSP_EINVAL, "bad mode");
+    ctx->profiling = (mode & GSP_PROFILE_TIMING) != 0;
+    ctx->stats = (mode & GSP_PROFILE_COUNTS) != 0;
+    return GSP_OK;
+}
+
+gsp_status gsp_profile_read(gsp_ctx *ctx, int32_t max_stages, char *names, int64_t *counts,
+                            double *ms, int32_t *n_out) {
+    gsp_status s = check_device(ctx);
+    if (s != GSP_OK) return s;
+    if (max_stages < 0 || (max_stages > 0 && (!names || !counts || !ms)) || !n_out)
+        return fail(GSP_EINVAL, "bad profile output arguments");
+    for (StageRec &r : ctx->pending) {
+        hipError_t e = hipEventSynchronize(r.stop);
+        if (e != hipSuccess) return hip_fail(e, "hipEventSynchronize");
+        float t = 0.f;
+        e = hipEventElapsedTime(&t, r.start, r.stop);
+        if (e != hipSuccess) return hip_fail(e, "hipEventElapsedTime");
+        StageSum *sum = nullptr;
+        for (StageSum &x : ctx->sums)
+            if (x.name == r.name) sum = &x;
+        if (!sum) {
+            ctx->sums.push_back(StageSum{r.name, 0, 0.0});
+            sum = &ctx->sums.back();
+        }
+        sum->count += 1;
+        sum->ms += t;
+        ctx->pool.push_back(r.start);
+        ctx->pool.push_back(r.stop);
+    }
+    ctx->pending.clear();
+    int32_t k = 0;
+    for (const StageSum &x : ctx->sums) {
+        if (k >= max_stages) break;
+        std::snprintf(names + 32 * k, 32, "%s", x.name.c_str());
+        counts[k] = x.count;
+        ms[k] = x.ms;
+        k++;
+    }
+    *n_out = k;
+    ctx->sums.clear();
     return GSP_OK;
 }
 
@@ -267,15 +363,25 @@ gsp_status gsp_render_fwd(gsp_ctx *ctx, const gsp_gaussians *g, int32_t V, const
     char *ws = static_cast<char *>(workspace);
     const gsp::GaussiansK gk = kernel_gaussians(g);
     hipError_t e;
-    if ((e = gsp::launch_preprocess(gk, p.views, poses, p.L, ws, st)) != hipSuccess)
+    if ((e = stage(ctx, "preprocess", st, [&] {
+             return gsp::launch_preprocess(gk, p.views, poses, p.L, ws, st);
+         })) != hipSuccess)
         return hip_fail(e, "preprocess");
-    if ((e = gsp::launch_offsets_and_duplicate(p.views, p.L, ws, st)) != hipSuccess)
+    if ((e = stage(ctx, "duplicate", st, [&] {
+             return gsp::launch_offsets_and_duplicate(p.views, p.L, ws, st);
+         })) != hipSuccess)
         return hip_fail(e, "duplicate");
-    uint64_t *keys;
-    uint32_t *vals;
-    if ((e = gsp::launch_sort(p.L, ws, st, &keys, &vals)) != hipSuccess) return hip_fail(e, "sort");
-    if ((e = gsp::launch_ranges(p.L, ws, keys, st)) != hipSuccess) return hip_fail(e, "ranges");
-    if ((e = gsp::launch_raster_fwd(p.views, p.L, ws, vals, images, alphas, st)) != hipSuccess)
+    uint64_t *keys = nullptr;
+    uint32_t *vals = nullptr;
+    if ((e = stage(ctx, "sort", st, [&] { return gsp::launch_sort(p.L, ws, st, &keys, &vals); })) !=
+        hipSuccess)
+        return hip_fail(e, "sort");
+    if ((e = stage(ctx, "ranges", st, [&] { return gsp::launch_ranges(p.L, ws, keys, st); })) !=
+        hipSuccess)
+        return hip_fail(e, "ranges");
+    if ((e = stage(ctx, "raster_fwd", st, [&] {
+             return gsp::launch_raster_fwd(p.views, p.L, ws, vals, images, alphas, ctx->stats, st);
+         })) != hipSuccess)
         return hip_fail(e, "raster forward");
     return GSP_OK;
 }
@@ -300,10 +406,14 @@ gsp_status gsp_render_bwd(gsp_ctx *ctx, const gsp_gaussians *g, int32_t V, const
     const bool odd = p.L.sort_passes & 1;
     const uint32_t *vals = gsp::region<uint32_t>(ws, odd ? p.L.vals1 : p.L.vals0);
     hipError_t e;
-    if ((e = gsp::launch_raster_bwd(p.views, p.L, ws, vals, dl_dimages, st)) != hipSuccess)
+    if ((e = stage(ctx, "raster_bwd", st, [&] {
+             return gsp::launch_raster_bwd(p.views, p.L, ws, vals, dl_dimages, st);
+         })) != hipSuccess)
         return hip_fail(e, "raster backward");
-    if ((e = gsp::launch_preprocess_bwd(kernel_gaussians(g), p.views, poses, p.L, ws, *grads,
-                                        (flags & GSP_ACCUMULATE) != 0, st)) != hipSuccess)
+    if ((e = stage(ctx, "preprocess_bwd", st, [&] {
+             return gsp::launch_preprocess_bwd(kernel_gaussians(g), p.views, poses, p.L, ws, *grads,
+                                               (flags & GSP_ACCUMULATE) != 0, st);
+         })) != hipSuccess)
         return hip_fail(e, "preprocess backward");
     return GSP_OK;
 }
@@ -349,6 +459,8 @@ gsp_status gsp_inspect(gsp_ctx *ctx, const gsp_gaussians *g, int32_t V, const gs
         {"ranges", L.ranges, L.total_tiles},
         {"tfinal", L.tfinal, L.total_pix},
         {"ncontrib", L.ncontrib, L.total_pix},
+        {"neval", L.stats, L.total_pix},
+        {"nblend", L.stats + 4 * (size_t)L.total_pix, L.total_pix},
         {"grad2d", L.grad2d, 9 * L.vn},
         {"counters", L.counters, gsp::kCntCount},
     };
@@ -369,8 +481,10 @@ gsp_status gsp_loss_l1(gsp_ctx *ctx, int64_t count, const float *pred, const flo
     if (count < 0) return fail(GSP_EINVAL, "negative count");
     if (count > 0 && (!pred || !target || !grad)) return fail(GSP_EINVAL, "null array");
     if (loss && !scratch) return fail(GSP_EINVAL, "loss requires scratch memory");
-    hipError_t e = gsp::launch_loss_l1(count, pred, target, grad, loss, scratch,
-                                       static_cast<hipStream_t>(stream));
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    hipError_t e = stage(ctx, "loss_l1", st, [&] {
+        return gsp::launch_loss_l1(count, pred, target, grad, loss, scratch, st);
+    });
     if (e != hipSuccess) return hip_fail(e, "loss");
     return GSP_OK;
 }
@@ -388,8 +502,10 @@ gsp_status gsp_pose_adam(gsp_ctx *ctx, int32_t V, float *poses, const float *dpo
     if (!(params->beta1 >= 0.f && params->beta1 < 1.f && params->beta2 >= 0.f &&
           params->beta2 < 1.f && params->eps > 0.f))
         return fail(GSP_EINVAL, "bad Adam hyper-parameters");
-    hipError_t e = gsp::launch_pose_adam(V, poses, dpose, m, v, steps, *params,
-                                         static_cast<hipStream_t>(stream));
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    hipError_t e = stage(ctx, "pose_adam", st, [&] {
+        return gsp::launch_pose_adam(V, poses, dpose, m, v, steps, *params, st);
+    });
     if (e != hipSuccess) return hip_fail(e, "pose adam");
     return GSP_OK;
 }

@@ -57,7 +57,7 @@ struct Layout {
     int32_t V, S, total_tiles, nblk_pre, nblk_sort, sort_passes;
     size_t geom, color, rect, depth, tiles, offsets, blocksum, counters;
     size_t keys0, keys1, vals0, vals1, hist, digit_tot, ranges;
-    size_t tfinal, ncontrib, slots, grad2d, posepart;
+    size_t tfinal, ncontrib, stats, slots, grad2d, posepart;
     size_t total;
 };
 
@@ -88,7 +88,8 @@ hipError_t launch_sort(const Layout &L, char *ws, hipStream_t s, uint64_t **keys
 // raster_fwd.hip
 hipError_t launch_ranges(const Layout &L, char *ws, const uint64_t *keys, hipStream_t s);
 hipError_t launch_raster_fwd(const ViewsK &views, const Layout &L, char *ws,
-                             const uint32_t *vals, float *images, float *alphas, hipStream_t s);
+                             const uint32_t *vals, float *images, float *alphas, bool stats,
+                             hipStream_t s);
 // raster_bwd.hip
 hipError_t launch_raster_bwd(const ViewsK &views, const Layout &L, char *ws,
                              const uint32_t *vals, const float *dl_dimages, hipStream_t s);

@@ -37,8 +37,14 @@ struct FwdArgs {
     float *alphas;
     float *tfinal;
     uint32_t *ncontrib;
+    uint32_t *neval;    // STATS only: entries evaluated per pixel (up to the stop)
+    uint32_t *nblend;   // STATS only: entries blended per pixel
 };
 
+// STATS = true is a measurement variant that also counts, per pixel, the
+// evaluated and blended (pixel, splat) pairs; the work counts define the
+// kernel's algorithmic operation count.
+template <bool STATS>
 __global__ __launch_bounds__(kRasterThreads) void k_raster_fwd(FwdArgs a, ViewsK views) {
     __shared__ StagedSplat stage[kBatch];
     const int tile = blockIdx.x;
@@ -53,8 +59,10 @@ __global__ __launch_bounds__(kRasterThreads) void k_raster_fwd(FwdArgs a, ViewsK
     float T[kPixPerLane], cr[kPixPerLane], cg[kPixPerLane], cb[kPixPerLane];
     int last[kPixPerLane];
     bool live[kPixPerLane];
+    uint32_t ne[kPixPerLane], nb[kPixPerLane];
 #pragma unroll
     for (int q = 0; q < kPixPerLane; q++) {
+        ne[q] = nb[q] = 0;
         T[q] = 1.f;
         cr[q] = cg[q] = cb[q] = 0.f;
         last[q] = 0;
@@ -92,6 +100,8 @@ __global__ __launch_bounds__(kRasterThreads) void k_raster_fwd(FwdArgs a, ViewsK
                 const float alpha = fminf(kAlphaMax, sb.y * __expf(power));
                 const bool hit = live[q] && power <= 0.f && alpha >= kAlphaMin;
                 const float testT = T[q] * (1.f - alpha);
+                if (STATS && live[q]) ne[q]++;
+                if (STATS && hit && testT >= kTMin) nb[q]++;
                 if (hit && testT < kTMin) live[q] = false;
                 if (hit && testT >= kTMin) {
                     const float wgt = alpha * T[q];
@@ -120,6 +130,10 @@ __global__ __launch_bounds__(kRasterThreads) void k_raster_fwd(FwdArgs a, ViewsK
         a.tfinal[vw.pix_base + pix] = T[q];
         a.ncontrib[vw.pix_base + pix] = (uint32_t)last[q];
         if (a.alphas) a.alphas[vw.pix_base + pix] = 1.f - T[q];
+        if (STATS) {
+            a.neval[vw.pix_base + pix] = ne[q];
+            a.nblend[vw.pix_base + pix] = nb[q];
+        }
     }
 }
 
@@ -136,7 +150,7 @@ hipError_t launch_ranges(const Layout &L, char *ws, const uint64_t *keys, hipStr
 }
 
 hipError_t launch_raster_fwd(const ViewsK &views, const Layout &L, char *ws, const uint32_t *vals,
-                             float *images, float *alphas, hipStream_t s) {
+                             float *images, float *alphas, bool stats, hipStream_t s) {
     if (L.total_tiles == 0) return hipSuccess;
     FwdArgs a;
     a.ranges = region<uint2>(ws, L.ranges);
@@ -147,7 +161,12 @@ hipError_t launch_raster_fwd(const ViewsK &views, const Layout &L, char *ws, con
     a.alphas = alphas;
     a.tfinal = region<float>(ws, L.tfinal);
     a.ncontrib = region<uint32_t>(ws, L.ncontrib);
-    hipLaunchKernelGGL(k_raster_fwd, dim3(L.total_tiles), dim3(kRasterThreads), 0, s, a, views);
+    a.neval = region<uint32_t>(ws, L.stats);
+    a.nblend = a.neval + L.total_pix;
+    if (stats)
+        hipLaunchKernelGGL(k_raster_fwd<true>, dim3(L.total_tiles), dim3(kRasterThreads), 0, s, a, views);
+    else
+        hipLaunchKernelGGL(k_raster_fwd<false>, dim3(L.total_tiles), dim3(kRasterThreads), 0, s, a, views);
     return hipGetLastError();
 }
 

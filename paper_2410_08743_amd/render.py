@@ -325,3 +325,29 @@ def solve_poses(g: GaussianParams, cams: Sequence, targets: torch.Tensor, init_p
         rast.capacity = int(rast.capacity * rast.growth) + 1024
         rast.ws = None
     raise RuntimeError("instance capacity kept overflowing during the pose solve")
+
+
+PROFILE_TIMING = 1
+PROFILE_COUNTS = 2
+
+
+def profile_enable(device: int, mode: int):
+    """Sets the library's measurement mode (bit mask of PROFILE_TIMING and
+    PROFILE_COUNTS; 0 turns measurement off)."""
+    N.check(N.lib().gsp_profile_enable(context(device), int(mode)), "gsp_profile_enable")
+
+
+def profile_read(device: int, max_stages: int = 32):
+    """{stage: (launches, total ms)} since the previous read; synchronises."""
+    L = N.lib()
+    names = ctypes.create_string_buffer(32 * max_stages)
+    counts = (ctypes.c_int64 * max_stages)()
+    ms = (ctypes.c_double * max_stages)()
+    n = ctypes.c_int32()
+    N.check(L.gsp_profile_read(context(device), max_stages, names, counts, ms, ctypes.byref(n)),
+            "gsp_profile_read")
+    out = {}
+    for k in range(n.value):
+        name = names.raw[32 * k:32 * (k + 1)].split(b"\0", 1)[0].decode()
+        out[name] = (int(counts[k]), float(ms[k]))
+    return out
