@@ -44,7 +44,8 @@ KERNEL_SOURCES = {
     "raster_fwd": ["raster_fwd.hip", "raster_common.h"],
     "raster_bwd": ["raster_bwd.hip", "raster_common.h"],
     "preprocess": ["preprocess.hip"],
-    "sort": ["sort.hip"],
+    "depth_sort": ["sort.hip"],
+    "tile_sort": ["sort.hip"],
     "preprocess_bwd": ["preprocess_bwd.hip"],
 }
 
@@ -172,12 +173,24 @@ def main():
     nblend = rast.inspect(g, [cam], "nblend", torch.int32).to(torch.int64).sum().item()
     ncontrib = rast.inspect(g, [cam], "ncontrib", torch.int32).to(torch.int64).sum().item()
     M, _ = rast.instances()
+    # lockstep cost: a tile's wave evaluates every pixel up to the tile's
+    # largest stop position (forward) / contributor count (backward)
+    tw, th = (cam.width + 15) // 16, (cam.height + 15) // 16
+
+    def tile_max_sum(name):
+        a = rast.inspect(g, [cam], name, torch.int32).view(cam.height, cam.width).cpu().numpy()
+        pad = np.zeros((th * 16, tw * 16), np.int64)
+        pad[:cam.height, :cam.width] = a
+        return int(256 * pad.reshape(th, 16, tw, 16).max(axis=(1, 3)).sum())
+
+    lockstep = {"fwd_pixel_evals": tile_max_sum("neval"), "bwd_pixel_evals": tile_max_sum("ncontrib")}
     n, S3 = g.n, (g.sh_degree + 1) ** 2
     param_bytes = 4 * (11 + 3 * S3)
     work = {
         "preprocess": ("hbm", (param_bytes + 64) * n),
         "duplicate": ("hbm", 20 * n + 12 * M),
-        "sort": ("hbm", 24 * M),
+        "depth_sort": ("hbm", 16 * n),
+        "tile_sort": ("hbm", 16 * M),
         "ranges": ("hbm", 8 * M + 8 * ((cam.width + 15) // 16) * ((cam.height + 15) // 16)),
         "raster_fwd": ("alu", FWD_FLOPS_EVAL * neval + FWD_FLOPS_BLEND * nblend),
         "loss_l1": ("hbm", 12 * 3 * P),
@@ -241,7 +254,7 @@ def main():
         "cpu_baseline": cpu,
         "stages": stage_report,
         "work": {"instances": M, "evaluated_pairs": neval, "blended_pairs": nblend,
-                 "backward_pairs": ncontrib},
+                 "backward_pairs": ncontrib, **lockstep},
         "pose_solve": {"steps": K, "seconds": round(total_ms * 1e-3, 4),
                        "sequential_requests_per_s": round(1e3 / total_ms, 3),
                        "initial_error": [round(rot0, 3), round(trans0, 4)],

@@ -178,7 +178,9 @@ gsp_status gsp_pose_adam(gsp_ctx *ctx, int32_t V, float *poses, const float *dpo
 
 /* Workspace introspection for tests: device pointer and element count of an
  * intermediate array of the last forward/backward.  Names: "geom" (float4
- * pairs per view-Gaussian: u_hi v_hi u_lo v_lo | A B C o), "color" (float4),
+ * pairs per view-Gaussian: u_hi v_hi u_lo v_lo | A2 B2 C2 log2(o), with
+ * the conic [[A, B], [B, C]] stored as (A2, B2, C2) = -log2(e) (A/2, B, C/2)),
+ * "color" (float4),
  * "rect" (uint16 x0 y0 x1 y1), "depth" (uint32 float bits), "tiles"
  * (uint32 count), "keys" (uint64 sorted), "values" (uint32 sorted),
  * "ranges" (uint32 pairs per tile), "tfinal" (float per pixel),

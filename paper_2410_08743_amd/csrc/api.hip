@@ -195,8 +195,11 @@ Layout make_layout(int64_t n, int32_t sh_degree, int32_t V, const ViewsK &views,
     for (int v = 0; v < V; v++) pix += (int64_t)views.v[v].roi_w * views.v[v].roi_h;
     L.total_pix = pix;
     L.nblk_pre = (int)((n + kPreprocessBlock - 1) / kPreprocessBlock);
-    L.nblk_sort = (int)((L.cap + kSortItems - 1) / kSortItems);
-    L.sort_passes = sort_passes_for(views.total_tiles);
+    L.nblk_vn = (int)((L.vn + kPreprocessBlock - 1) / kPreprocessBlock);
+    const int64_t max_sorted = L.cap > L.vn ? L.cap : L.vn;
+    L.nblk_sort = (int)((max_sorted + kSortItems - 1) / kSortItems);
+    L.tile_bits = tile_bits_for(views.total_tiles);
+    L.tile_passes = (L.tile_bits + kSortBits - 1) / kSortBits;
     const size_t vn = (size_t)L.vn, capz = (size_t)L.cap;
     size_t off = 0;
     auto take = [&](size_t bytes) {
@@ -211,9 +214,13 @@ Layout make_layout(int64_t n, int32_t sh_degree, int32_t V, const ViewsK &views,
     L.depth = take(vn * 4);
     L.tiles = take(vn * 4);
     L.offsets = take(vn * 4);
-    L.blocksum = take((size_t)V * L.nblk_pre * 8 + 8);
-    L.keys0 = take(capz * 8);
-    L.keys1 = take(capz * 8);
+    L.blocksum = take((size_t)L.nblk_vn * 8 + 8);
+    L.dkeys0 = take(vn * 4);
+    L.dkeys1 = take(vn * 4);
+    L.dvals0 = take(vn * 4);
+    L.dvals1 = take(vn * 4);
+    L.keys0 = take(capz * 4);
+    L.keys1 = take(capz * 4);
     L.vals0 = take(capz * 4);
     L.vals1 = take(capz * 4);
     L.hist = take((size_t)kSortBins * L.nblk_sort * 4);
@@ -367,15 +374,18 @@ gsp_status gsp_render_fwd(gsp_ctx *ctx, const gsp_gaussians *g, int32_t V, const
              return gsp::launch_preprocess(gk, p.views, poses, p.L, ws, st);
          })) != hipSuccess)
         return hip_fail(e, "preprocess");
+    if ((e = stage(ctx, "depth_sort", st, [&] { return gsp::launch_depth_sort(p.L, ws, st); })) !=
+        hipSuccess)
+        return hip_fail(e, "depth sort");
     if ((e = stage(ctx, "duplicate", st, [&] {
              return gsp::launch_offsets_and_duplicate(p.views, p.L, ws, st);
          })) != hipSuccess)
         return hip_fail(e, "duplicate");
-    uint64_t *keys = nullptr;
-    uint32_t *vals = nullptr;
-    if ((e = stage(ctx, "sort", st, [&] { return gsp::launch_sort(p.L, ws, st, &keys, &vals); })) !=
+    if ((e = stage(ctx, "tile_sort", st, [&] { return gsp::launch_tile_sort(p.L, ws, st); })) !=
         hipSuccess)
-        return hip_fail(e, "sort");
+        return hip_fail(e, "tile sort");
+    const uint32_t *keys = gsp::region<uint32_t>(ws, gsp::sorted_keys(p.L));
+    const uint32_t *vals = gsp::region<uint32_t>(ws, gsp::sorted_vals(p.L));
     if ((e = stage(ctx, "ranges", st, [&] { return gsp::launch_ranges(p.L, ws, keys, st); })) !=
         hipSuccess)
         return hip_fail(e, "ranges");
@@ -403,8 +413,7 @@ gsp_status gsp_render_bwd(gsp_ctx *ctx, const gsp_gaussians *g, int32_t V, const
                     p.L.total);
     hipStream_t st = static_cast<hipStream_t>(stream);
     char *ws = static_cast<char *>(workspace);
-    const bool odd = p.L.sort_passes & 1;
-    const uint32_t *vals = gsp::region<uint32_t>(ws, odd ? p.L.vals1 : p.L.vals0);
+    const uint32_t *vals = gsp::region<uint32_t>(ws, gsp::sorted_vals(p.L));
     hipError_t e;
     if ((e = stage(ctx, "raster_bwd", st, [&] {
              return gsp::launch_raster_bwd(p.views, p.L, ws, vals, dl_dimages, st);
@@ -445,7 +454,6 @@ gsp_status gsp_inspect(gsp_ctx *ctx, const gsp_gaussians *g, int32_t V, const gs
     if (ws_bytes < p.L.total) return fail(GSP_ENOMEM, "workspace too small for these sizes");
     const gsp::Layout &L = p.L;
     char *ws = static_cast<char *>(workspace);
-    const bool odd = L.sort_passes & 1;
     struct Entry { const char *n; size_t off; int64_t cnt; };
     const Entry table[] = {
         {"geom", L.geom, 2 * L.vn},
@@ -454,8 +462,9 @@ gsp_status gsp_inspect(gsp_ctx *ctx, const gsp_gaussians *g, int32_t V, const gs
         {"depth", L.depth, L.vn},
         {"tiles", L.tiles, L.vn},
         {"offsets", L.offsets, L.vn},
-        {"keys", odd ? L.keys1 : L.keys0, L.cap},
-        {"values", odd ? L.vals1 : L.vals0, L.cap},
+        {"keys", gsp::sorted_keys(L), L.cap},
+        {"values", gsp::sorted_vals(L), L.cap},
+        {"depth_order", L.dvals0, L.vn},
         {"ranges", L.ranges, L.total_tiles},
         {"tfinal", L.tfinal, L.total_pix},
         {"ncontrib", L.ncontrib, L.total_pix},

@@ -78,3 +78,55 @@ __device__ __forceinline__ T block_sum(T v, T *scratch) {
 }
 
 }  // namespace gsp
+
+namespace gsp {
+
+// DPP controls (gfx9 encoding) for row-local (16-lane) butterflies.
+constexpr int kDppQuadXor1 = 0xB1;     // quad_perm [1,0,3,2]
+constexpr int kDppQuadXor2 = 0x4E;     // quad_perm [2,3,0,1]
+constexpr int kDppRowHalfMirror = 0x141;
+constexpr int kDppRowMirror = 0x140;
+
+template <int CTRL>
+__device__ __forceinline__ float dpp_add(float x) {
+    return x + __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), CTRL, 0xF, 0xF, false));
+}
+
+// Sum over the 16 lanes of each row; every lane of the row receives it.
+__device__ __forceinline__ float row_sum16(float x) {
+    x = dpp_add<kDppQuadXor1>(x);
+    x = dpp_add<kDppQuadXor2>(x);
+    x = dpp_add<kDppRowHalfMirror>(x);
+    return dpp_add<kDppRowMirror>(x);
+}
+
+// (a, b) -> lanes 0-31: a[l] + a[l + 32]; lanes 32-63: b[l - 32] + b[l]
+// (gfx950 v_permlane32_swap exchanges rows 2-3 of a with rows 0-1 of b).
+__device__ __forceinline__ float pair_sum32(float a, float b) {
+    const auto r = __builtin_amdgcn_permlane32_swap(__float_as_uint(a), __float_as_uint(b), false, false);
+    return __uint_as_float(r[0]) + __uint_as_float(r[1]);
+}
+
+// (a, b) -> rows [a0 + a1, b0 + b1, a2 + a3, b2 + b3] (rows of 16 lanes;
+// v_permlane16_swap exchanges the odd rows of a with the even rows of b).
+__device__ __forceinline__ float pair_sum16(float a, float b) {
+    const auto r = __builtin_amdgcn_permlane16_swap(__float_as_uint(a), __float_as_uint(b), false, false);
+    return __uint_as_float(r[0]) + __uint_as_float(r[1]);
+}
+
+// Wave-wide sums of nine values with a reduce-scatter butterfly: 32-lane and
+// 16-lane swaps halve the data at each step, then DPP finishes inside rows.
+// Totals land in every lane of a row:
+//   x0 rows 0..3 = v0, v2, v1, v3;  x1 rows 0..3 = v4, v6, v5, v7;  x2 = v8.
+__device__ __forceinline__ void wave_sum9(const float v[9], float &x0, float &x1, float &x2) {
+    const float w0 = pair_sum32(v[0], v[1]);
+    const float w1 = pair_sum32(v[2], v[3]);
+    const float w2 = pair_sum32(v[4], v[5]);
+    const float w3 = pair_sum32(v[6], v[7]);
+    const float w4 = pair_sum32(v[8], v[8]);
+    x0 = row_sum16(pair_sum16(w0, w1));
+    x1 = row_sum16(pair_sum16(w2, w3));
+    x2 = row_sum16(pair_sum16(w4, w4));
+}
+
+}  // namespace gsp

@@ -25,10 +25,14 @@ constexpr double kLambdaFloor = 0.1;     // floor under the eigenvalue discrimin
 constexpr float kAlphaMax = 0.99f;       // opacity clamp of a splat at a pixel
 constexpr float kAlphaMin = 1.0f / 255.0f;  // splats below this alpha are skipped
 constexpr float kTMin = 1e-4f;           // stop before transmittance drops below
+constexpr double kLog2e = 1.4426950408889634;
 
 constexpr int kPreprocessBlock = 256;    // Gaussians per preprocess block
 constexpr int kSortThreads = 256;
-constexpr int kSortRounds = 16;
+#ifndef GSP_SORT_ROUNDS
+#define GSP_SORT_ROUNDS 4
+#endif
+constexpr int kSortRounds = GSP_SORT_ROUNDS;
 constexpr int kSortItems = kSortThreads * kSortRounds;  // keys per sort block
 constexpr int kSortBits = 8;             // radix digit width
 constexpr int kSortBins = 1 << kSortBits;
@@ -54,8 +58,9 @@ struct ViewsK {
 // Carving of the caller's workspace.  Every region is 256-byte aligned.
 struct Layout {
     int64_t n, vn, cap, total_pix;
-    int32_t V, S, total_tiles, nblk_pre, nblk_sort, sort_passes;
+    int32_t V, S, total_tiles, nblk_pre, nblk_vn, nblk_sort, tile_bits, tile_passes;
     size_t geom, color, rect, depth, tiles, offsets, blocksum, counters;
+    size_t dkeys0, dkeys1, dvals0, dvals1;
     size_t keys0, keys1, vals0, vals1, hist, digit_tot, ranges;
     size_t tfinal, ncontrib, stats, slots, grad2d, posepart;
     size_t total;
@@ -83,10 +88,10 @@ hipError_t launch_preprocess(const GaussiansK &g, const ViewsK &views, const flo
 hipError_t launch_offsets_and_duplicate(const ViewsK &views, const Layout &L, char *ws,
                                         hipStream_t s);
 // sort.hip
-hipError_t launch_sort(const Layout &L, char *ws, hipStream_t s, uint64_t **keys_out,
-                       uint32_t **vals_out);
+hipError_t launch_depth_sort(const Layout &L, char *ws, hipStream_t s);
+hipError_t launch_tile_sort(const Layout &L, char *ws, hipStream_t s);
 // raster_fwd.hip
-hipError_t launch_ranges(const Layout &L, char *ws, const uint64_t *keys, hipStream_t s);
+hipError_t launch_ranges(const Layout &L, char *ws, const uint32_t *keys, hipStream_t s);
 hipError_t launch_raster_fwd(const ViewsK &views, const Layout &L, char *ws,
                              const uint32_t *vals, float *images, float *alphas, bool stats,
                              hipStream_t s);
@@ -108,11 +113,14 @@ hipError_t launch_pose_adam(int V, float *poses, const float *dpose, float *m, f
 template <typename T>
 inline T *region(char *ws, size_t off) { return reinterpret_cast<T *>(ws + off); }
 
-inline int sort_passes_for(int total_tiles) {
+inline int tile_bits_for(int total_tiles) {
     int tile_bits = 0;
     while ((1ll << tile_bits) < (long long)total_tiles) tile_bits++;
-    const int bits = 32 + tile_bits;
-    return (bits + kSortBits - 1) / kSortBits;
+    return tile_bits;
 }
+
+// Buffers holding the result of the two sorts (depth: 4 passes, even).
+inline size_t sorted_keys(const Layout &L) { return (L.tile_passes & 1) ? L.keys1 : L.keys0; }
+inline size_t sorted_vals(const Layout &L) { return (L.tile_passes & 1) ? L.vals1 : L.vals0; }
 
 }  // namespace gsp

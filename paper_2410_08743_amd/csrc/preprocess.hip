@@ -23,19 +23,18 @@ namespace gsp {
 struct PreArgs {
     GaussiansK g;
     const float *poses;
-    float4 *geom;                  // [vn][2]: (u_hi, v_hi, u_lo, v_lo), (A, B, C, o)
+    float4 *geom;                  // [vn][2]: (u_hi, v_hi, u_lo, v_lo), (A2, B2, C2, log2 o)
     float4 *color;                 // [vn]: (r, g, b, 0)
     uint2 *rect;                   // [vn]: x0 | y0 << 16, x1 | y1 << 16
     uint32_t *depth;               // [vn]: float bits of the key depth
     uint32_t *tiles;               // [vn]: tiles touched
-    unsigned long long *blocksum;  // [V][nblk]
-    int nblk;
+    uint32_t *dkeys;               // [vn]: depth-sort key (depth bits; ~0 when not drawn)
+    uint32_t *dvals;               // [vn]: view * n + i
 };
 
 template <int D>
 __global__ __launch_bounds__(kPreprocessBlock) void k_preprocess(PreArgs a, ViewsK views) {
     constexpr int S = (D + 1) * (D + 1);
-    __shared__ unsigned long long red[kPreprocessBlock / kWave];
     const int n = a.g.n;
     const int i = blockIdx.x * kPreprocessBlock + threadIdx.x;
     const bool valid = i < n;
@@ -148,7 +147,9 @@ __global__ __launch_bounds__(kPreprocessBlock) void k_preprocess(PreArgs a, View
             if (cnt > 0) {
                 const float uh = (float)u, vh = (float)vv;
                 g0 = make_float4(uh, vh, (float)(u - (double)uh), (float)(vv - (double)vh));
-                g1 = make_float4((float)A, (float)B, (float)C, opac);
+                // conic in base 2 with the -1/2 folded in, and log2 of the opacity
+                g1 = make_float4((float)(-0.5 * kLog2e * A), (float)(-kLog2e * B),
+                                 (float)(-0.5 * kLog2e * C), (float)log2((double)opac));
                 // camera centre o_c = -R^T t and the viewing direction
                 const double ocx = -(R[0] * t[0] + R[3] * t[1] + R[6] * t[2]);
                 const double ocy = -(R[1] * t[0] + R[4] * t[1] + R[7] * t[2]);
@@ -173,10 +174,22 @@ __global__ __launch_bounds__(kPreprocessBlock) void k_preprocess(PreArgs a, View
             a.rect[idx] = rect;
             a.depth[idx] = __float_as_uint(zkey);
             a.tiles[idx] = cnt;
+            a.dkeys[idx] = cnt > 0 ? __float_as_uint(zkey) : 0xffffffffu;
+            a.dvals[idx] = (uint32_t)idx;
         }
-        const unsigned long long bs = block_sum<unsigned long long, kPreprocessBlock>(cnt, red);
-        if (threadIdx.x == 0) a.blocksum[(size_t)v * a.nblk + blockIdx.x] = bs;
     }
+}
+
+// Per-block sums of the tile counts, taken in depth order.
+__global__ __launch_bounds__(kPreprocessBlock) void k_sorted_blocksums(const uint32_t *order,
+                                                                       const uint32_t *tiles,
+                                                                       unsigned long long *bs,
+                                                                       int vn) {
+    __shared__ unsigned long long red[kPreprocessBlock / kWave];
+    const int k = blockIdx.x * kPreprocessBlock + threadIdx.x;
+    const uint32_t cnt = k < vn ? tiles[order[k]] : 0u;
+    const unsigned long long s = block_sum<unsigned long long, kPreprocessBlock>(cnt, red);
+    if (threadIdx.x == 0) bs[blockIdx.x] = s;
 }
 
 // Exclusive scan of the per-(view, block) instance counts in one block; the
@@ -209,42 +222,42 @@ __global__ __launch_bounds__(1024) void k_scan_blocksums(unsigned long long *bs,
 }
 
 struct DupArgs {
+    const uint32_t *order;         // [vn] view * n + i in (depth, index) order
     const uint2 *rect;
-    const uint32_t *depth;
     const uint32_t *tiles;
     uint32_t *offsets;
     const unsigned long long *blockoff;
     const uint32_t *counters;
-    unsigned long long *keys;
+    uint32_t *keys;
     uint32_t *vals;
-    int n, nblk;
+    int vn;
 };
 
-// Emits one (tile | depth, view * n + i) pair per tile of each splat's rect,
-// rows outer and columns inner, at the splat's exclusive offset.
-__global__ __launch_bounds__(kPreprocessBlock) void k_duplicate(DupArgs a, ViewsK views) {
+// Walks the splats in depth order and emits one (tile, view * n + i) pair per
+// tile of each splat's rect, rows outer and columns inner, at the splat's
+// exclusive offset; a stable sort of these pairs by tile then yields every
+// tile's list in (depth, index) order.
+__global__ __launch_bounds__(kPreprocessBlock) void k_duplicate(DupArgs a, ViewsK views, int n) {
     __shared__ unsigned long long scratch[kPreprocessBlock / kWave];
-    const int v = blockIdx.y;
-    const int i = blockIdx.x * kPreprocessBlock + threadIdx.x;
-    const size_t idx = (size_t)v * a.n + i;
-    const uint32_t cnt = i < a.n ? a.tiles[idx] : 0u;
+    const int k = blockIdx.x * kPreprocessBlock + threadIdx.x;
+    const uint32_t idx = k < a.vn ? a.order[k] : 0u;
+    const uint32_t cnt = k < a.vn ? a.tiles[idx] : 0u;
     unsigned long long total;
     const unsigned long long excl =
         block_exclusive_scan<unsigned long long, kPreprocessBlock>(cnt, scratch, &total) +
-        a.blockoff[(size_t)v * a.nblk + blockIdx.x];
-    if (a.counters[kCntOverflow] != 0u || i >= a.n) return;
+        a.blockoff[blockIdx.x];
+    if (a.counters[kCntOverflow] != 0u || k >= a.vn) return;
     a.offsets[idx] = (uint32_t)excl;
     if (cnt == 0) return;
     const uint2 r = a.rect[idx];
     const int x0 = r.x & 0xffff, y0 = r.x >> 16, x1 = r.y & 0xffff, y1 = r.y >> 16;
-    const ViewK &vw = views.v[v];
-    const unsigned long long dbits = a.depth[idx];
+    const ViewK &vw = views.v[idx / (uint32_t)n];
     size_t o = (size_t)excl;
     for (int ty = y0; ty < y1; ty++) {
-        const unsigned long long rowbase = (unsigned long long)(vw.tile_base + ty * vw.gw);
+        const uint32_t rowbase = (uint32_t)(vw.tile_base + ty * vw.gw);
         for (int tx = x0; tx < x1; tx++) {
-            a.keys[o] = ((rowbase + tx) << 32) | dbits;
-            a.vals[o] = (uint32_t)idx;
+            a.keys[o] = rowbase + (uint32_t)tx;
+            a.vals[o] = idx;
             o++;
         }
     }
@@ -261,8 +274,8 @@ hipError_t launch_preprocess(const GaussiansK &g, const ViewsK &views, const flo
     a.rect = region<uint2>(ws, L.rect);
     a.depth = region<uint32_t>(ws, L.depth);
     a.tiles = region<uint32_t>(ws, L.tiles);
-    a.blocksum = region<unsigned long long>(ws, L.blocksum);
-    a.nblk = L.nblk_pre;
+    a.dkeys = region<uint32_t>(ws, L.dkeys0);
+    a.dvals = region<uint32_t>(ws, L.dvals0);
     dim3 grid(L.nblk_pre), block(kPreprocessBlock);
     switch (g.sh_degree) {
         case 0: hipLaunchKernelGGL(k_preprocess<0>, grid, block, 0, s, a, views); break;
@@ -277,23 +290,28 @@ hipError_t launch_offsets_and_duplicate(const ViewsK &views, const Layout &L, ch
                                         hipStream_t s) {
     unsigned long long *bs = region<unsigned long long>(ws, L.blocksum);
     uint32_t *counters = region<uint32_t>(ws, L.counters);
-    const int count = L.V * L.nblk_pre;
-    hipLaunchKernelGGL(k_scan_blocksums, dim3(1), dim3(1024), 0, s, bs, count, counters,
+    const uint32_t *order = region<uint32_t>(ws, L.dvals0);   // depth sort: 4 passes, even
+    const int vn = (int)L.vn;
+    if (vn > 0) {
+        hipLaunchKernelGGL(k_sorted_blocksums, dim3(L.nblk_vn), dim3(kPreprocessBlock), 0, s, order,
+                           region<uint32_t>(ws, L.tiles), bs, vn);
+    }
+    hipLaunchKernelGGL(k_scan_blocksums, dim3(1), dim3(1024), 0, s, bs, L.nblk_vn, counters,
                        (unsigned long long)L.cap);
     hipError_t e = hipGetLastError();
-    if (e != hipSuccess || L.n == 0) return e;
+    if (e != hipSuccess || vn == 0) return e;
     DupArgs a;
+    a.order = order;
     a.rect = region<uint2>(ws, L.rect);
-    a.depth = region<uint32_t>(ws, L.depth);
     a.tiles = region<uint32_t>(ws, L.tiles);
     a.offsets = region<uint32_t>(ws, L.offsets);
     a.blockoff = bs;
     a.counters = counters;
-    a.keys = region<unsigned long long>(ws, L.keys0);
+    a.keys = region<uint32_t>(ws, L.keys0);
     a.vals = region<uint32_t>(ws, L.vals0);
-    a.n = (int)L.n;
-    a.nblk = L.nblk_pre;
-    hipLaunchKernelGGL(k_duplicate, dim3(L.nblk_pre, L.V), dim3(kPreprocessBlock), 0, s, a, views);
+    a.vn = vn;
+    hipLaunchKernelGGL(k_duplicate, dim3(L.nblk_vn), dim3(kPreprocessBlock), 0, s, a, views,
+                       (int)L.n);
     return hipGetLastError();
 }
 

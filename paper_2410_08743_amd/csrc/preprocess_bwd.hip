@@ -10,15 +10,17 @@
 // Sigma_hat = J R_c Sigma R_c^T J^T) and h = dL/do_c:
 //   dL/drho += g - R_c h,   dL/dphi += mu^c x g + vee(G_W R_c^T).
 //
-// MI355X design: one thread per Gaussian loops over the call's views, first
-// summing its 2D gradient over its instance slots (contiguous, fixed order),
-// then applying the chain rule in FP64 (this kernel is bound by HBM, and the
-// FP64 vector rate equals unpacked FP32).  Gaussian gradients are summed over
-// views in registers and written once; the six pose sums per view are reduced
-// with wavefront shuffles and an LDS block reduction into per-block partials,
-// and one block per view adds the partials in a fixed order.  No atomics
-// anywhere, so the result is bit-reproducible and independent of how many
-// other views share the launch.
+// MI355X design: a first kernel walks the splats in depth order -- the order
+// in which their instance slots were laid out, so neighbouring lanes read
+// neighbouring slots -- and sums each splat's slots in a fixed order into its
+// 2D gradient.  The chain-rule kernel then runs one thread per Gaussian over
+// the call's views, geometry in FP64 (the kernel is bound by HBM, and the FP64
+// vector rate equals unpacked FP32), SH in FP32.  Gaussian gradients are
+// summed over views in registers and written once; the six pose sums per view
+// are reduced with wavefront shuffles and an LDS block reduction into
+// per-block partials, and one block per view adds the partials in a fixed
+// order.  No atomics anywhere, so the result is bit-reproducible and a view's
+// pose gradient does not depend on which other views share the launch.
 #include "block_ops.h"
 #include "gsp_internal.h"
 #include "sh_basis.h"
@@ -31,7 +33,7 @@ struct PbArgs {
     const uint32_t *tiles;
     const uint32_t *offsets;
     const uint32_t *counters;
-    const float *slots;     // [9][cap]
+    const float *slots;     // [cap][9]
     float *grad2d;          // [9][vn]
     double *posepart;       // [V][nblk][6]
     gsp_grads out;
@@ -50,6 +52,63 @@ __device__ __forceinline__ void rot_vjp(double w, double x, double y, double z, 
                   z * Gm[7] - 2 * y * Gm[8]);
     out[3] = 2 * (-2 * z * Gm[0] - w * Gm[1] + x * Gm[2] + w * Gm[3] - 2 * z * Gm[4] + y * Gm[5] +
                   x * Gm[6] + y * Gm[7]);
+}
+
+// 2D gradient of each splat: the sum of its instance slots, in slot order.
+// A block takes 256 consecutive splats in depth order; their slots form one
+// contiguous range, which the block copies through LDS in chunks of 1024
+// instances -- every thread issues its 36 loads of a chunk at once, so a
+// chunk costs one memory latency -- and each thread then adds the part of its
+// own segment that the chunk holds.
+constexpr int kSlotChunk = 1024;
+constexpr int kSlotPerThread = kSlotChunk * 9 / 256;
+
+__global__ __launch_bounds__(256) void k_slot_reduce(const uint32_t *order, const uint32_t *tiles,
+                                                     const uint32_t *offsets, const uint32_t *counters,
+                                                     const float *slots, float *grad2d, int vn) {
+    __shared__ float chunk[kSlotChunk * 9];
+    __shared__ uint32_t bounds[2];
+    const int k = blockIdx.x * 256 + threadIdx.x;
+    const bool ovf = counters[kCntOverflow] != 0u;
+    const uint32_t idx = k < vn ? order[k] : 0u;
+    const uint32_t cnt = (k < vn && !ovf) ? tiles[idx] : 0u;
+    const uint32_t e0 = cnt ? offsets[idx] : 0u, e1 = e0 + cnt;
+    // segments are contiguous and ordered by k: the first and last threads
+    // with work bound the block's range
+    const unsigned long long has = __ballot(cnt > 0);
+    if (threadIdx.x == 0) { bounds[0] = 0xffffffffu; bounds[1] = 0u; }
+    __syncthreads();
+    if (cnt > 0 && (has & ((1ull << (threadIdx.x & 63)) - 1ull)) == 0) atomicMin(&bounds[0], e0);
+    if (cnt > 0 && (has >> (threadIdx.x & 63)) == 1ull) atomicMax(&bounds[1], e1);
+    __syncthreads();
+    const uint32_t first = bounds[0], end = bounds[1];
+    float d[9];
+#pragma unroll
+    for (int c = 0; c < 9; c++) d[c] = 0.f;
+    for (uint32_t c0 = first; c0 < end; c0 += kSlotChunk) {
+        const uint32_t nf = 9u * (min(end, c0 + (uint32_t)kSlotChunk) - c0);
+        const float *src = slots + 9 * (size_t)c0;
+        float tmp[kSlotPerThread];
+#pragma unroll
+        for (int r = 0; r < kSlotPerThread; r++) {
+            const uint32_t f = (uint32_t)(r * 256 + threadIdx.x);
+            tmp[r] = f < nf ? src[f] : 0.f;
+        }
+#pragma unroll
+        for (int r = 0; r < kSlotPerThread; r++) chunk[r * 256 + threadIdx.x] = tmp[r];
+        __syncthreads();
+        const uint32_t lo = max(e0, c0), hi = min(e1, c0 + (uint32_t)kSlotChunk);
+        for (uint32_t e = lo; e < hi; e++) {
+            const float *rec = chunk + 9 * (e - c0);
+#pragma unroll
+            for (int c = 0; c < 9; c++) d[c] += rec[c];
+        }
+        __syncthreads();
+    }
+    if (k < vn) {
+#pragma unroll
+        for (int c = 0; c < 9; c++) grad2d[(size_t)c * vn + idx] = d[c];
+    }
 }
 
 template <int D, bool WANT_GAUSS>
@@ -97,9 +156,9 @@ __global__ __launch_bounds__(kPoseReduceBlock) void k_preprocess_bwd(PbArgs a, V
 
     // gradients summed over views
     double gmu[3] = {0, 0, 0}, gSig[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0}, gop = 0;
-    double gsh[WANT_GAUSS ? S * 3 : 1];
+    float gsh[WANT_GAUSS ? S * 3 : 1];
 #pragma unroll
-    for (int k = 0; k < (WANT_GAUSS ? S * 3 : 1); k++) gsh[k] = 0;
+    for (int k = 0; k < (WANT_GAUSS ? S * 3 : 1); k++) gsh[k] = 0.f;
 
     for (int v = 0; v < views.count; v++) {
         const ViewK &vw = views.v[v];
@@ -108,17 +167,9 @@ __global__ __launch_bounds__(kPoseReduceBlock) void k_preprocess_bwd(PbArgs a, V
         double pose6[6] = {0, 0, 0, 0, 0, 0};
         const uint32_t cnt = (valid && !ovf) ? a.tiles[idx] : 0u;
         if (cnt > 0) {
-            // 2D gradient of this splat: sum of its instance slots
             float d2f[9];
-            const uint32_t e0 = a.offsets[idx];
 #pragma unroll
-            for (int c = 0; c < 9; c++) {
-                const float *sl = a.slots + c * a.cap + e0;
-                float s = 0.f;
-                for (uint32_t k = 0; k < cnt; k++) s += sl[k];
-                d2f[c] = s;
-                a.grad2d[c * a.vn + idx] = s;
-            }
+            for (int c = 0; c < 9; c++) d2f[c] = a.grad2d[c * a.vn + idx];
             double R[9], t[3];
 #pragma unroll
             for (int r = 0; r < 3; r++) {
@@ -220,26 +271,28 @@ __global__ __launch_bounds__(kPoseReduceBlock) void k_preprocess_bwd(PbArgs a, V
             const double wx = mu[0] - ocx, wy = mu[1] - ocy, wz = mu[2] - ocz;
             const double dist = sqrt(wx * wx + wy * wy + wz * wz), idist = 1.0 / dist;
             const double dxn = wx * idist, dyn = wy * idist, dzn = wz * idist;
-            double Y[S];
-            sh_eval<D, double>(dxn, dyn, dzn, Y);
-            double wgt[S];
+            const float fxn = (float)dxn, fyn = (float)dyn, fzn = (float)dzn;
+            float Y[S];
+            sh_eval<D, float>(fxn, fyn, fzn, Y);
+            float wgt[S];
 #pragma unroll
-            for (int k = 0; k < S; k++) wgt[k] = 0;
+            for (int k = 0; k < S; k++) wgt[k] = 0.f;
 #pragma unroll
             for (int ch = 0; ch < 3; ch++) {
-                double col = 0.5;
+                float col = 0.5f;
 #pragma unroll
-                for (int k = 0; k < S; k++) col += (double)sh[3 * k + ch] * Y[k];
-                if (col < 0) continue;   // clamped channel: no gradient
-                const double gc = d2f[6 + ch];
+                for (int k = 0; k < S; k++) col = fmaf(sh[3 * k + ch], Y[k], col);
+                if (col < 0.f) continue;   // clamped channel: no gradient
+                const float gc = d2f[6 + ch];
 #pragma unroll
                 for (int k = 0; k < S; k++) {
-                    wgt[k] += gc * (double)sh[3 * k + ch];
-                    if constexpr (WANT_GAUSS) gsh[3 * k + ch] += gc * Y[k];
+                    wgt[k] = fmaf(gc, sh[3 * k + ch], wgt[k]);
+                    if constexpr (WANT_GAUSS) gsh[3 * k + ch] = fmaf(gc, Y[k], gsh[3 * k + ch]);
                 }
             }
-            double gd[3];
-            sh_weighted_grad<D, double>(dxn, dyn, dzn, wgt, gd);
+            float gdf[3];
+            sh_weighted_grad<D, float>(fxn, fyn, fzn, wgt, gdf);
+            const double gd[3] = {gdf[0], gdf[1], gdf[2]};
             const double proj = gd[0] * dxn + gd[1] * dyn + gd[2] * dzn;
             const double gw[3] = {(gd[0] - dxn * proj) * idist, (gd[1] - dyn * proj) * idist,
                                   (gd[2] - dzn * proj) * idist};
@@ -252,9 +305,6 @@ __global__ __launch_bounds__(kPoseReduceBlock) void k_preprocess_bwd(PbArgs a, V
             pose6[3] = p[1] * gp[2] - p[2] * gp[1] + Bm[7] - Bm[5];
             pose6[4] = p[2] * gp[0] - p[0] * gp[2] + Bm[2] - Bm[6];
             pose6[5] = p[0] * gp[1] - p[1] * gp[0] + Bm[3] - Bm[1];
-        } else if (valid && !ovf) {
-#pragma unroll
-            for (int c = 0; c < 9; c++) a.grad2d[c * a.vn + idx] = 0.f;
         }
 #pragma unroll
         for (int c = 0; c < 6; c++) {
@@ -275,7 +325,7 @@ __global__ __launch_bounds__(kPoseReduceBlock) void k_preprocess_bwd(PbArgs a, V
         if (o.sh) {
 #pragma unroll
             for (int k = 0; k < S * 3; k++)
-                o.sh[(size_t)i * (S * 3) + k] = (acc ? o.sh[(size_t)i * (S * 3) + k] : 0.f) + (float)gsh[k];
+                o.sh[(size_t)i * (S * 3) + k] = (acc ? o.sh[(size_t)i * (S * 3) + k] : 0.f) + gsh[k];
         }
         if (o.scales || o.quats) {
             // Sigma = M M^T with M = R_q diag(s): dL/dM = 2 dL/dSigma M (dL/dSigma symmetric)
@@ -349,6 +399,13 @@ hipError_t launch_preprocess_bwd(const GaussiansK &g, const ViewsK &views, const
     a.vn = (size_t)L.vn;
     a.nblk = L.nblk_pre;
     a.accumulate = accumulate;
+    if (L.vn > 0) {
+        hipLaunchKernelGGL(k_slot_reduce, dim3(L.nblk_vn), dim3(256), 0, s,
+                           region<uint32_t>(ws, L.dvals0), a.tiles, a.offsets, a.counters, a.slots,
+                           a.grad2d, (int)L.vn);
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
     if (L.n > 0) {
         switch (g.sh_degree) {
             case 0: launch_pb<0>(a, views, want, L.nblk_pre, s); break;

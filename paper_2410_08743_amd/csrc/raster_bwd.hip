@@ -5,18 +5,22 @@
 //   dL/dc_i     = G alpha_i T_i
 //   dL/dalpha_i = T_i G . (c_i - S_i),  S_i = colour behind i seen through i,
 //   S_last = bg,  S_{i-1} = alpha_i c_i + (1 - alpha_i) S_i
-// and through alpha = o exp(power) (no gradient when clamped at 0.99) to the
-// opacity, the conic and the projected centre.
+// and through alpha = o exp(power) (no gradient when clamped at 0.99):
+//   dL/dpower = dL/dalpha alpha,  dL/do = dL/dpower / o,
+//   dpower/du = -(A dx + B dy), dpower/dv = -(C dy + B dx),
+//   dpower/dA = -dx^2/2, dpower/dB = -dx dy, dpower/dC = -dy^2/2.
 //
 // MI355X design: nothing per pixel is stored by the forward beyond T_final
 // and the contributor count; each wavefront walks its tile's list back to
 // front from the largest contributor count, recovering T_i = T_{i+1} /
-// (1 - alpha_i) with the forward's exact arithmetic.  The four pixels of a
-// lane are summed in registers and the 64 lanes with a butterfly of
-// cross-lane adds, giving one 9-float partial per (tile, splat) that is
-// written to the instance's own slot (its position in emission order).  No
-// atomics: the per-splat reduction over its slots happens later in a fixed
-// order, so gradients are bit-reproducible.
+// (1 - alpha_i) with the forward's exact evaluation.  Each lane sums its four
+// pixels in registers; the nine sums are reduced over the 64 lanes by a
+// reduce-scatter butterfly (v_permlane32_swap, v_permlane16_swap, then DPP
+// inside rows: 28 VALU operations for nine values), and nine lanes store the
+// (tile, splat) partial into the instance's own slot (its position in
+// emission order, 36 contiguous bytes).  No atomics: the per-splat sum over
+// its slots happens later in a fixed order, so gradients are
+// bit-reproducible.
 #include "block_ops.h"
 #include "raster_common.h"
 
@@ -32,9 +36,15 @@ struct BwdArgs {
     const float *dl;
     const float *tfinal;
     const uint32_t *ncontrib;
-    float *slots;          // [9][cap]
-    size_t cap;
+    float *slots;          // [cap][9]
 };
+
+constexpr uint32_t kNoSlot = 0xffffffffu;
+
+#ifndef GSP_BWD_UNROLL
+#define GSP_BWD_UNROLL 4
+#endif
+constexpr int kBwdUnroll = GSP_BWD_UNROLL;   // entries whose LDS records are read ahead
 
 // Slot of the instance of splat `id` in tile (tx, ty): its emission position.
 __device__ __forceinline__ uint32_t slot_of(const BwdArgs &a, uint32_t id, int tx, int ty) {
@@ -44,7 +54,9 @@ __device__ __forceinline__ uint32_t slot_of(const BwdArgs &a, uint32_t id, int t
 }
 
 __global__ __launch_bounds__(kRasterThreads) void k_raster_bwd(BwdArgs a, ViewsK views) {
-    __shared__ StagedSplat stage[kBatch];
+    __shared__ StagedA sA[kBatch];
+    __shared__ StagedB sB[kBatch];
+    __shared__ StagedC sC[kBatch];
     const int tile = blockIdx.x;
     const ViewK &vw = views.v[view_of_tile(views, tile)];
     const int lt = tile - vw.tile_base;
@@ -55,7 +67,16 @@ __global__ __launch_bounds__(kRasterThreads) void k_raster_bwd(BwdArgs a, ViewsK
     const int rx = kTile * tx + lx;
     const int P = vw.roi_w * vw.roi_h;
 
-    float T[kPixPerLane], G[kPixPerLane][3], S[kPixPerLane][3];
+    // Which reduced value this lane stores, and its scale (see wave_sum9 and
+    // the base-2 conic of raster_common.h).
+    const int row = lane >> 4, col = lane & 15;
+    const int c0 = row == 1 ? 2 : (row == 2 ? 1 : row);
+    const int comp = col == 0 ? c0 : (col == 1 ? 4 + c0 : (col == 2 && row == 0 ? 8 : -1));
+    const float scale = comp == 0 || comp == 1 ? kLn2
+                      : comp == 2 || comp == 4 ? -0.5f
+                      : comp == 3 ? -1.f : 1.f;
+
+    float T[kPixPerLane], G[kPixPerLane][3], S[kPixPerLane][3], fy[kPixPerLane];
     int last[kPixPerLane];
     int maxlast = 0;
 #pragma unroll
@@ -63,6 +84,7 @@ __global__ __launch_bounds__(kRasterThreads) void k_raster_bwd(BwdArgs a, ViewsK
         const int ry = kTile * ty + ly + 4 * q;
         const bool in = rx < vw.roi_w && ry < vw.roi_h;
         const size_t pix = (size_t)ry * vw.roi_w + rx;
+        fy[q] = (float)(ly + 4 * q);
         T[q] = in ? a.tfinal[vw.pix_base + pix] : 1.f;
         last[q] = in ? (int)a.ncontrib[vw.pix_base + pix] : 0;
         const float *dl = a.dl + 3 * (size_t)vw.pix_base;
@@ -83,70 +105,96 @@ __global__ __launch_bounds__(kRasterThreads) void k_raster_bwd(BwdArgs a, ViewsK
     for (int k = maxlast + lane; k < len; k += kBatch) {
         const uint32_t e = slot_of(a, a.vals[rg.x + k], tx, ty);
 #pragma unroll
-        for (int c = 0; c < 9; c++) a.slots[c * a.cap + e] = 0.f;
+        for (int c = 0; c < 9; c++) a.slots[9 * (size_t)e + c] = 0.f;
     }
 
-    for (int hi = maxlast; hi > 0; hi -= kBatch) {
-        const int lo = max(0, hi - kBatch);
-        const int k = lo + lane;
-        if (k < hi) {
+    // batches of 64 entries ending at hi, walked back to front; positions
+    // below 0 are inert padding.  Records are gathered one batch ahead.
+    float4 g0, g1, gc;
+    uint32_t gslot;
+    auto gather = [&](int k) {
+        g0 = make_float4(0.f, 0.f, 0.f, 0.f);
+        g1 = make_float4(0.f, 0.f, 0.f, -INFINITY);   // inert: alpha = 0
+        gc = make_float4(0.f, 0.f, 0.f, 0.f);
+        gslot = kNoSlot;
+        if (k >= 0) {
             const uint32_t id = a.vals[rg.x + k];
-            const float4 g0 = a.geom[2 * (size_t)id];
-            const float4 g1 = a.geom[2 * (size_t)id + 1];
-            const float4 c = a.color[id];
-            StagedSplat s;
-            s.a = make_float4(rel_coord(g0.x, g0.z, px0), rel_coord(g0.y, g0.w, py0), g1.x, g1.y);
-            s.b = make_float4(g1.z, g1.w, c.x, c.y);
-            s.c = make_float4(c.z, __uint_as_float(slot_of(a, id, tx, ty)), 0.f, 0.f);
-            stage[lane] = s;
+            g0 = a.geom[2 * (size_t)id];
+            g1 = a.geom[2 * (size_t)id + 1];
+            gc = a.color[id];
+            gslot = slot_of(a, id, tx, ty);
         }
+    };
+    if (maxlast > 0) gather(maxlast - kBatch + lane);
+    for (int hi = maxlast; hi > 0; hi -= kBatch) {
+        const int lo = hi - kBatch;
+        sA[lane] = StagedA{rel_coord(g0.x, g0.z, px0), rel_coord(g0.y, g0.w, py0), g1.x, g1.y};
+        sB[lane] = StagedB{g1.z, g1.w, gc.x, gc.y};
+        sC[lane] = StagedC{gc.z, __builtin_amdgcn_exp2f(-g1.w), gslot, 0u};
         __syncthreads();
-        for (int j = hi - lo - 1; j >= 0; j--) {
-            const int pos = lo + j;
-            const float4 sa = stage[j].a;
-            const float4 sb = stage[j].b;
-            const float4 sc = stage[j].c;
-            const float dx = sa.x - fxl;
-            const float col[3] = {sb.z, sb.w, sc.x};
-            float acc[9];
+        if (lo > 0) gather(lo - kBatch + lane);
+        const int jstop = lo < 0 ? -lo : 0;   // entries below are padding
+        for (int j0 = kBatch - kBwdUnroll; j0 >= 0; j0 -= kBwdUnroll) {
+            StagedA es[kBwdUnroll];
+            StagedB et[kBwdUnroll];
+            StagedC ew[kBwdUnroll];
 #pragma unroll
-            for (int c = 0; c < 9; c++) acc[c] = 0.f;
+            for (int u = 0; u < kBwdUnroll; u++) {
+                es[u] = sA[j0 + u];
+                et[u] = sB[j0 + u];
+                ew[u] = sC[j0 + u];
+            }
 #pragma unroll
-            for (int q = 0; q < kPixPerLane; q++) {
-                const float dy = sa.y - (float)(ly + 4 * q);
-                const float power = splat_power(sa.z, sa.w, sb.x, dx, dy);
-                const float ex = __expf(power);
-                const float apre = sb.y * ex;
-                const float alpha = fminf(kAlphaMax, apre);
-                if (pos < last[q] && power <= 0.f && alpha >= kAlphaMin) {
-                    T[q] = T[q] / (1.f - alpha);
-                    const float wgt = alpha * T[q];
-                    float dalpha = 0.f;
+            for (int u = kBwdUnroll - 1; u >= 0; u--) {
+                const int pos = lo + j0 + u;
+                const StagedA &s = es[u];
+                const StagedB &t = et[u];
+                const float col3[3] = {t.r, t.g, ew[u].b};
+                const ColTerms ct = col_terms(s, fxl);
+                const float a2dx = 2.f * s.A2 * ct.dx;
+                float acc[9];
 #pragma unroll
-                    for (int ch = 0; ch < 3; ch++) {
-                        acc[6 + ch] = fmaf(G[q][ch], wgt, acc[6 + ch]);
-                        dalpha = fmaf(G[q][ch], col[ch] - S[q][ch], dalpha);
-                        S[q][ch] = fmaf(alpha, col[ch] - S[q][ch], S[q][ch]);
-                    }
-                    dalpha *= T[q];
-                    if (apre <= kAlphaMax) {
-                        acc[5] = fmaf(dalpha, ex, acc[5]);
-                        const float dp = dalpha * alpha;
-                        acc[0] -= dp * fmaf(sa.z, dx, sa.w * dy);
-                        acc[1] -= dp * fmaf(sb.x, dy, sa.w * dx);
-                        acc[2] -= 0.5f * dp * dx * dx;
-                        acc[3] -= dp * dx * dy;
-                        acc[4] -= 0.5f * dp * dy * dy;
+                for (int c = 0; c < 9; c++) acc[c] = 0.f;
+                bool touched = false;
+#pragma unroll
+                for (int q = 0; q < kPixPerLane; q++) {
+                    const float dy = s.v - fy[q];
+                    const float p2 = splat_p2(ct, t.C2, dy);
+                    const float apre = splat_alpha_pre(p2, t.lo);
+                    const float alpha = fminf(kAlphaMax, apre);
+                    if (pos < last[q] && p2 <= 0.f && alpha >= kAlphaMin) {
+                        touched = true;
+                        T[q] = T[q] * __builtin_amdgcn_rcpf(1.f - alpha);
+                        const float wgt = alpha * T[q];
+                        float dalpha = 0.f;
+#pragma unroll
+                        for (int ch = 0; ch < 3; ch++) {
+                            const float diff = col3[ch] - S[q][ch];
+                            acc[6 + ch] = fmaf(G[q][ch], wgt, acc[6 + ch]);
+                            dalpha = fmaf(G[q][ch], diff, dalpha);
+                            S[q][ch] = fmaf(alpha, diff, S[q][ch]);
+                        }
+                        if (apre <= kAlphaMax) {
+                            const float dp = dalpha * T[q] * alpha;   // dL/dpower
+                            const float dpy = dp * dy;
+                            acc[0] = fmaf(dp, fmaf(s.B2, dy, a2dx), acc[0]);
+                            acc[1] = fmaf(dp, fmaf(2.f * t.C2, dy, ct.bdx), acc[1]);
+                            acc[2] = fmaf(dp, ct.dx * ct.dx, acc[2]);
+                            acc[3] = fmaf(dpy, ct.dx, acc[3]);
+                            acc[4] = fmaf(dpy, dy, acc[4]);
+                            acc[5] += dp;
+                        }
                     }
                 }
+                float x0 = 0.f, x1 = 0.f, x2 = 0.f;
+                if (__any(touched)) wave_sum9(acc, x0, x1, x2);
+                if (comp >= 0 && ew[u].slot != kNoSlot) {
+                    const float val = col == 0 ? x0 : (col == 1 ? x1 : x2);
+                    const float f = comp == 5 ? ew[u].inv_o : scale;
+                    a.slots[9 * (size_t)ew[u].slot + comp] = val * f;
+                }
             }
-#pragma unroll
-            for (int c = 0; c < 9; c++) acc[c] = wave_sum(acc[c]);
-            if (lane == 0) {
-                const uint32_t e = __float_as_uint(sc.y);
-#pragma unroll
-                for (int c = 0; c < 9; c++) a.slots[c * a.cap + e] = acc[c];
-            }
+            if (j0 <= jstop) break;
         }
         __syncthreads();
     }
@@ -166,7 +214,6 @@ hipError_t launch_raster_bwd(const ViewsK &views, const Layout &L, char *ws, con
     a.tfinal = region<float>(ws, L.tfinal);
     a.ncontrib = region<uint32_t>(ws, L.ncontrib);
     a.slots = region<float>(ws, L.slots);
-    a.cap = (size_t)L.cap;
     hipLaunchKernelGGL(k_raster_bwd, dim3(L.total_tiles), dim3(kRasterThreads), 0, s, a, views);
     return hipGetLastError();
 }

@@ -2,9 +2,16 @@
 // backward rasterizers, so that the backward's recomputation takes exactly
 // the forward's decisions (same operations in the same order).
 //
-// Sec. III-A, Eq. (3): alpha = o exp(-1/2 d^T Sigma_hat^-1 d), d = pixel -
-// mu_hat, with Sigma_hat^-1 = [[A, B], [B, C]] (the paper prints Sigma_hat
-// where its inverse is meant).
+// Sec. III-A, Eq. (3): alpha = o exp(power), power = -1/2 d^T Sigma_hat^-1 d
+// with d = pixel - mu_hat and Sigma_hat^-1 = [[A, B], [B, C]] (the paper
+// prints Sigma_hat where its inverse is meant), so
+// power = -1/2 (A dx^2 + C dy^2) - B dx dy.
+//
+// The preprocess stores the conic pre-scaled to base 2,
+// (A2, B2, C2) = -log2(e) (A/2, B, C/2), and lo = log2(o), so that
+// p2 = log2(e) power = A2 dx^2 + B2 dx dy + C2 dy^2 and alpha = 2^(p2 + lo):
+// two FMAs and one v_exp_f32 per pixel once the dx terms, which the four
+// pixels of a lane share (they lie in one column), are formed.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -18,25 +25,46 @@ namespace gsp {
 constexpr int kRasterThreads = 64;
 constexpr int kPixPerLane = 4;
 constexpr int kBatch = 64;          // list entries staged in LDS at a time
+constexpr int kUnroll = 8;          // entries per step of the inner loop
 
-// Splat as staged in LDS: centre relative to the tile's first pixel, conic,
-// opacity, colour and (backward only) the instance's slot index.
-struct StagedSplat {
-    float4 a;   // u_rel, v_rel, A, B
-    float4 b;   // C, o, r, g
-    float4 c;   // b, slot (bits), 0, 0
-};
+constexpr float kLn2 = 0.6931471805599453f;
 
-__device__ __forceinline__ float splat_power(float A, float B, float C, float dx, float dy) {
-#pragma clang fp contract(off)
-    const float q = __fmaf_rn(A * dx, dx, (C * dy) * dy);
-    return __fmaf_rn(-0.5f, q, -((B * dx) * dy));
-}
+// Splat as staged in LDS: centre relative to the tile's first pixel, scaled
+// conic, log2 opacity and colour; the backward adds the instance's slot.
+struct StagedA { float u, v, A2, B2; };
+struct StagedB { float C2, lo, r, g; };
+struct StagedC { float b, inv_o; uint32_t slot, pad; };
 
 // Centre of a splat relative to pixel (px0, py0), from its (hi, lo) pair.
 __device__ __forceinline__ float rel_coord(float hi, float lo, int origin) {
 #pragma clang fp contract(off)
     return (hi - (float)origin) + lo;
+}
+
+// Per (lane, splat) terms shared by the lane's four pixels.
+struct ColTerms {
+    float dx, adx2, bdx;
+};
+
+__device__ __forceinline__ ColTerms col_terms(const StagedA &s, float px) {
+#pragma clang fp contract(off)
+    ColTerms t;
+    t.dx = s.u - px;
+    t.adx2 = (s.A2 * t.dx) * t.dx;
+    t.bdx = s.B2 * t.dx;
+    return t;
+}
+
+// log2(e) * power at a pixel with offset dy.
+__device__ __forceinline__ float splat_p2(const ColTerms &t, float C2, float dy) {
+#pragma clang fp contract(off)
+    return __fmaf_rn(dy, __fmaf_rn(C2, dy, t.bdx), t.adx2);
+}
+
+// Pre-clamp opacity o * exp(power).
+__device__ __forceinline__ float splat_alpha_pre(float p2, float lo) {
+#pragma clang fp contract(off)
+    return __builtin_amdgcn_exp2f(p2 + lo);
 }
 
 __device__ __forceinline__ int view_of_tile(const ViewsK &views, int tile) {

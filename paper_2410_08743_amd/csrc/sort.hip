@@ -1,49 +1,54 @@
-// sort.hip -- stable LSD radix sort of the (tile | depth) keys with their
-// (view * n + Gaussian) values.
+// sort.hip -- stable LSD radix sort of (uint32 key, uint32 value) pairs.
 //
-// Only the low 32 + ceil(log2(total tiles)) key bits are sorted (8-bit digits).
-// Each pass is reduce-then-scan: per-block digit histograms, a per-digit scan
-// across blocks, then a scatter in which every block ranks its 4096 keys
+// The (tile | depth) order of the instances is produced in two stable sorts
+// that together equal one stable sort on the 64-bit key (tile << 32 | depth):
+// the splats are first sorted by their float32 depth bits (all 32 bits, ties
+// keep index order), instances are then emitted splat by splat in that order,
+// and the instances are stably sorted by tile id alone (ceil(log2 tiles)
+// bits).  The instance sort moves 8-byte pairs over 2 passes at a 1008x756
+// view instead of 12-byte pairs over 6.
+//
+// Each pass is reduce-then-scan: per-block digit histograms, a per-digit
+// scan across blocks, then a scatter in which every block ranks its 4096 keys
 // stably with wavefront ballots (one ballot per digit bit on wave64), sorts
-// them locally in LDS and writes them out digit run by digit run, so that
-// global stores are contiguous within each run.  Stability makes the order
-// of equal keys the emission order (Gaussian index ascending), so the result
-// is unique and comparable bit for bit.
-//
-// The grid is sized by the instance capacity; blocks past the device-side
-// instance count exit at once, so no host synchronisation is needed.
+// them locally in LDS and writes them out digit run by digit run, so global
+// stores are contiguous within each run.  The element count may live in
+// device memory (the instance count), in which case the grid is sized by
+// capacity and blocks past the count exit at once: no host synchronisation.
 #include "block_ops.h"
 #include "gsp_internal.h"
 
 namespace gsp {
 
 struct SortPass {
-    const unsigned long long *keys_in;
+    const uint32_t *keys_in;
     const uint32_t *vals_in;
-    unsigned long long *keys_out;
+    uint32_t *keys_out;
     uint32_t *vals_out;
     uint32_t *hist;        // [bins][nblk]
     uint32_t *digit_tot;   // [bins]
-    const uint32_t *counters;
+    const uint32_t *count_ptr;  // element count in device memory, or null
+    uint32_t count_val;         // element count when count_ptr is null
     int nblk;
     int shift;
 };
+
+__device__ __forceinline__ uint32_t sort_count(const SortPass &a) {
+    return a.count_ptr ? *a.count_ptr : a.count_val;
+}
 
 __global__ __launch_bounds__(kSortThreads) void k_sort_hist(SortPass a) {
     __shared__ uint32_t h[kSortBins];
     const int t = threadIdx.x;
     h[t] = 0;
     __syncthreads();
-    const uint32_t M = a.counters[kCntMEff];
+    const uint32_t M = sort_count(a);
     const size_t base = (size_t)blockIdx.x * kSortItems;
     if (base < M) {
 #pragma unroll 4
         for (int r = 0; r < kSortRounds; r++) {
             const size_t k = base + (size_t)r * kSortThreads + t;
-            if (k < M) {
-                const uint32_t d = (uint32_t)(a.keys_in[k] >> a.shift) & (kSortBins - 1);
-                atomicAdd(&h[d], 1u);
-            }
+            if (k < M) atomicAdd(&h[(a.keys_in[k] >> a.shift) & (kSortBins - 1)], 1u);
         }
     }
     __syncthreads();
@@ -71,7 +76,7 @@ __global__ __launch_bounds__(kSortThreads) void k_sort_scan(SortPass a) {
 
 __global__ __launch_bounds__(kSortThreads) void k_sort_scatter(SortPass a) {
     constexpr int NW = kSortThreads / kWave;
-    __shared__ unsigned long long skeys[kSortItems];
+    __shared__ uint32_t skeys[kSortItems];
     __shared__ uint32_t svals[kSortItems];
     __shared__ uint32_t dstart[kSortBins];
     __shared__ uint32_t gbase[kSortBins];
@@ -80,7 +85,7 @@ __global__ __launch_bounds__(kSortThreads) void k_sort_scatter(SortPass a) {
     __shared__ uint32_t wpre[NW][kSortBins];
     __shared__ uint32_t scratch[kSortThreads / kWave];
 
-    const uint32_t M = a.counters[kCntMEff];
+    const uint32_t M = sort_count(a);
     const size_t base = (size_t)blockIdx.x * kSortItems;
     if (base >= M) return;
     const int cnt = (int)min((size_t)kSortItems, (size_t)M - base);
@@ -89,12 +94,11 @@ __global__ __launch_bounds__(kSortThreads) void k_sort_scatter(SortPass a) {
     const int w = t / kWave;
     const unsigned long long lt_mask = (1ull << lane) - 1ull;
 
-    unsigned long long key[kSortRounds];
-    uint32_t val[kSortRounds];
+    uint32_t key[kSortRounds], val[kSortRounds];
 #pragma unroll
     for (int r = 0; r < kSortRounds; r++) {
         const int k = r * kSortThreads + t;
-        key[r] = k < cnt ? a.keys_in[base + k] : 0ull;
+        key[r] = k < cnt ? a.keys_in[base + k] : 0u;
         val[r] = k < cnt ? a.vals_in[base + k] : 0u;
     }
 
@@ -105,8 +109,7 @@ __global__ __launch_bounds__(kSortThreads) void k_sort_scatter(SortPass a) {
     __syncthreads();
 #pragma unroll
     for (int r = 0; r < kSortRounds; r++) {
-        if (r * kSortThreads + t < cnt)
-            atomicAdd(&run[(uint32_t)(key[r] >> a.shift) & (kSortBins - 1)], 1u);
+        if (r * kSortThreads + t < cnt) atomicAdd(&run[(key[r] >> a.shift) & (kSortBins - 1)], 1u);
     }
     __syncthreads();
     uint32_t tot;
@@ -121,7 +124,7 @@ __global__ __launch_bounds__(kSortThreads) void k_sort_scatter(SortPass a) {
 #pragma unroll 1
     for (int r = 0; r < kSortRounds; r++) {
         const bool valid = r * kSortThreads + t < cnt;
-        const uint32_t d = (uint32_t)(key[r] >> a.shift) & (kSortBins - 1);
+        const uint32_t d = (key[r] >> a.shift) & (kSortBins - 1);
         unsigned long long peers = __ballot(valid);
 #pragma unroll
         for (int b = 0; b < kSortBits; b++) {
@@ -154,41 +157,57 @@ __global__ __launch_bounds__(kSortThreads) void k_sort_scatter(SortPass a) {
     __syncthreads();
 
     for (int i = t; i < cnt; i += kSortThreads) {
-        const unsigned long long k = skeys[i];
-        const uint32_t d = (uint32_t)(k >> a.shift) & (kSortBins - 1);
+        const uint32_t k = skeys[i];
+        const uint32_t d = (k >> a.shift) & (kSortBins - 1);
         const size_t dst = (size_t)gbase[d] + (uint32_t)(i - dstart[d]);
         a.keys_out[dst] = k;
         a.vals_out[dst] = svals[i];
     }
 }
 
-hipError_t launch_sort(const Layout &L, char *ws, hipStream_t s, uint64_t **keys_out,
-                       uint32_t **vals_out) {
-    unsigned long long *k0 = region<unsigned long long>(ws, L.keys0);
-    unsigned long long *k1 = region<unsigned long long>(ws, L.keys1);
-    uint32_t *v0 = region<uint32_t>(ws, L.vals0);
-    uint32_t *v1 = region<uint32_t>(ws, L.vals1);
+int launch_sort_pairs(uint32_t *k0, uint32_t *v0, uint32_t *k1, uint32_t *v1, uint32_t *hist,
+                      uint32_t *digit_tot, const uint32_t *count_ptr, uint32_t count_val,
+                      int64_t max_count, int bits, hipStream_t s, hipError_t *err) {
     SortPass a;
-    a.hist = region<uint32_t>(ws, L.hist);
-    a.digit_tot = region<uint32_t>(ws, L.digit_tot);
-    a.counters = region<uint32_t>(ws, L.counters);
-    a.nblk = L.nblk_sort;
-    for (int p = 0; p < L.sort_passes; p++) {
+    a.hist = hist;
+    a.digit_tot = digit_tot;
+    a.count_ptr = count_ptr;
+    a.count_val = count_val;
+    a.nblk = (int)((max_count + kSortItems - 1) / kSortItems);
+    *err = hipSuccess;
+    const int passes = (bits + kSortBits - 1) / kSortBits;
+    if (a.nblk == 0) return passes;
+    for (int p = 0; p < passes; p++) {
         a.keys_in = (p & 1) ? k1 : k0;
         a.vals_in = (p & 1) ? v1 : v0;
         a.keys_out = (p & 1) ? k0 : k1;
         a.vals_out = (p & 1) ? v0 : v1;
         a.shift = p * kSortBits;
-        hipLaunchKernelGGL(k_sort_hist, dim3(L.nblk_sort), dim3(kSortThreads), 0, s, a);
+        hipLaunchKernelGGL(k_sort_hist, dim3(a.nblk), dim3(kSortThreads), 0, s, a);
         hipLaunchKernelGGL(k_sort_scan, dim3(kSortBins), dim3(kSortThreads), 0, s, a);
-        hipLaunchKernelGGL(k_sort_scatter, dim3(L.nblk_sort), dim3(kSortThreads), 0, s, a);
-        hipError_t e = hipGetLastError();
-        if (e != hipSuccess) return e;
+        hipLaunchKernelGGL(k_sort_scatter, dim3(a.nblk), dim3(kSortThreads), 0, s, a);
+        *err = hipGetLastError();
+        if (*err != hipSuccess) return passes;
     }
-    const bool odd = L.sort_passes & 1;
-    *keys_out = reinterpret_cast<uint64_t *>(odd ? k1 : k0);
-    *vals_out = odd ? v1 : v0;
-    return hipSuccess;
+    return passes;
+}
+
+hipError_t launch_depth_sort(const Layout &L, char *ws, hipStream_t s) {
+    hipError_t e;
+    launch_sort_pairs(region<uint32_t>(ws, L.dkeys0), region<uint32_t>(ws, L.dvals0),
+                      region<uint32_t>(ws, L.dkeys1), region<uint32_t>(ws, L.dvals1),
+                      region<uint32_t>(ws, L.hist), region<uint32_t>(ws, L.digit_tot), nullptr,
+                      (uint32_t)L.vn, L.vn, 32, s, &e);
+    return e;
+}
+
+hipError_t launch_tile_sort(const Layout &L, char *ws, hipStream_t s) {
+    hipError_t e;
+    launch_sort_pairs(region<uint32_t>(ws, L.keys0), region<uint32_t>(ws, L.vals0),
+                      region<uint32_t>(ws, L.keys1), region<uint32_t>(ws, L.vals1),
+                      region<uint32_t>(ws, L.hist), region<uint32_t>(ws, L.digit_tot),
+                      region<uint32_t>(ws, L.counters) + kCntMEff, 0u, L.cap, L.tile_bits, s, &e);
+    return e;
 }
 
 }  // namespace gsp

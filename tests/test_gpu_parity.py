@@ -83,9 +83,12 @@ def test_preprocess_records(name):
     v = geom[:, 1].astype(np.float64) + geom[:, 3]
     assert np.max(np.abs(u[ren] - ref["u"][ren])) < 1e-9 * max(1.0, np.abs(ref["u"][ren]).max())
     assert np.max(np.abs(v[ren] - ref["v"][ren])) < 1e-9 * max(1.0, np.abs(ref["v"][ren]).max())
-    conic = geom[:, 4:7].astype(np.float64)
+    # stored in base 2 with the -1/2 folded in: (A2, B2, C2) = -log2(e) (A/2, B, C/2)
+    log2e = 1.0 / np.log(2.0)
+    conic = geom[:, 4:7].astype(np.float64) * np.array([-2.0, -1.0, -2.0]) / log2e
     assert np.max(np.abs(conic[ren] - ref["conic"][ren]) / np.abs(ref["conic"][ren]).max(1, keepdims=True)) < 1e-6
-    assert np.array_equal(geom[ren, 7], sc.opacities[ren])
+    o = np.exp2(geom[:, 7].astype(np.float64))
+    assert np.max(np.abs(o[ren] - sc.opacities[ren]) / sc.opacities[ren]) < 1e-6
     assert np.max(np.abs(col[ren, :3] - ref["color"][ren])) < 2e-6
 
 
@@ -99,8 +102,7 @@ def test_keys_sort_and_ranges_bit_exact(name):
     rkeys, rvals = oracle.bin_sort([ref], [(gw, gh)])
     M, ovf = rast.instances()
     assert not ovf
-    keys = rast.inspect(g, [cam], "keys", torch.int64).cpu().numpy().view(np.uint64)[:M]
-    vals = rast.inspect(g, [cam], "values", torch.int32).cpu().numpy().view(np.uint32)[:M]
+    keys, vals = _sorted_instances(rast, g, [cam], M)
     fragile = np.nonzero(ref["fragile"])[0].astype(np.uint32)
     if len(fragile) == 0:
         assert M == len(rkeys)
@@ -113,6 +115,31 @@ def test_keys_sort_and_ranges_bit_exact(name):
         keep_r = ~np.isin(rvals, fragile)
         assert np.array_equal(keys[keep_g], rkeys[keep_r])
         assert np.array_equal(vals[keep_g], rvals[keep_r])
+
+
+def test_keys_bit_exact_two_views():
+    sc, cam0, pose0 = random_case(16, 2, 96, 64, 700)
+    cam1 = f32_camera(S.Camera(80, 48, 75.0, 70.0, 40.5, 23.75, roi=(16, 16, 50, 32)))
+    pose1 = S.random_pose_near_identity(17, 3.0, 0.1)
+    run = _gpu(sc, [cam0, cam1], [pose0, pose1])
+    rast, g = run["rast"], run["g"]
+    s0, s1 = oracle.preprocess(sc, cam0, pose0), oracle.preprocess(sc, cam1, pose1)
+    assert not s0["fragile"].any() and not s1["fragile"].any()
+    rkeys, rvals = oracle.bin_sort([s0, s1], [oracle.tiles_of(cam0), oracle.tiles_of(cam1)])
+    M, ovf = rast.instances()
+    assert not ovf and M == len(rkeys)
+    keys, vals = _sorted_instances(rast, g, [cam0, cam1], M)
+    assert np.array_equal(keys, rkeys) and np.array_equal(vals, rvals)
+
+
+def _sorted_instances(rast, g, cams, M):
+    """The GPU's sorted instances as 64-bit (tile << 32 | depth bits) keys:
+    the instance sort carries tile ids; the depth bits are the splat's."""
+    tiles = rast.inspect(g, cams, "keys", torch.int32).cpu().numpy().view(np.uint32)[:M]
+    vals = rast.inspect(g, cams, "values", torch.int32).cpu().numpy().view(np.uint32)[:M]
+    depth = rast.inspect(g, cams, "depth", torch.int32).cpu().numpy().view(np.uint32)
+    keys = (tiles.astype(np.uint64) << np.uint64(32)) | depth[vals].astype(np.uint64)
+    return keys, vals
 
 
 def _image_check(img, ref, name, max_straddle=2e-3):
@@ -313,6 +340,5 @@ def test_full_size_single_view_workload():
         rkeys, rvals = oracle.bin_sort([sp], [(gw, gh)])
         rast, g = run["rast"], run["g"]
         M, _ = rast.instances()
-        keys = rast.inspect(g, [cam], "keys", torch.int64).cpu().numpy().view(np.uint64)[:M]
-        vals = rast.inspect(g, [cam], "values", torch.int32).cpu().numpy().view(np.uint32)[:M]
+        keys, vals = _sorted_instances(rast, g, [cam], M)
         assert np.array_equal(keys, rkeys) and np.array_equal(vals, rvals)
