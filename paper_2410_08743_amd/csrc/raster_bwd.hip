@@ -76,7 +76,9 @@ __global__ __launch_bounds__(kRasterThreads) void k_raster_bwd(BwdArgs a, ViewsK
                       : comp == 2 || comp == 4 ? -0.5f
                       : comp == 3 ? -1.f : 1.f;
 
-    float T[kPixPerLane], G[kPixPerLane][3], S[kPixPerLane][3], fy[kPixPerLane];
+    // GS = G . S: the upstream gradient dotted with the colour behind the
+    // current splat, which is all that dL/dalpha needs of S.
+    float T[kPixPerLane], G[kPixPerLane][3], GS[kPixPerLane], fy[kPixPerLane];
     int last[kPixPerLane];
     int maxlast = 0;
 #pragma unroll
@@ -91,9 +93,7 @@ __global__ __launch_bounds__(kRasterThreads) void k_raster_bwd(BwdArgs a, ViewsK
         G[q][0] = in ? dl[pix] : 0.f;
         G[q][1] = in ? dl[(size_t)P + pix] : 0.f;
         G[q][2] = in ? dl[2 * (size_t)P + pix] : 0.f;
-        S[q][0] = vw.bg[0];
-        S[q][1] = vw.bg[1];
-        S[q][2] = vw.bg[2];
+        GS[q] = G[q][0] * vw.bg[0] + G[q][1] * vw.bg[1] + G[q][2] * vw.bg[2];
         maxlast = max(maxlast, last[q]);
     }
     maxlast = wave_max(maxlast);
@@ -155,27 +155,31 @@ __global__ __launch_bounds__(kRasterThreads) void k_raster_bwd(BwdArgs a, ViewsK
                 float acc[9];
 #pragma unroll
                 for (int c = 0; c < 9; c++) acc[c] = 0.f;
+                float p2[kPixPerLane];
+                bool cand = false;
+#pragma unroll
+                for (int q = 0; q < kPixPerLane; q++) {
+                    p2[q] = splat_p2(ct, t.C2, s.v - fy[q]);
+                    cand |= pos < last[q] && p2[q] <= 0.f && p2[q] + t.lo >= kLog2AlphaMinLoose;
+                }
                 bool touched = false;
+                if (__any(cand)) {
 #pragma unroll
                 for (int q = 0; q < kPixPerLane; q++) {
                     const float dy = s.v - fy[q];
-                    const float p2 = splat_p2(ct, t.C2, dy);
-                    const float apre = splat_alpha_pre(p2, t.lo);
+                    const float apre = splat_alpha_pre(p2[q], t.lo);
                     const float alpha = fminf(kAlphaMax, apre);
-                    if (pos < last[q] && p2 <= 0.f && alpha >= kAlphaMin) {
+                    if (pos < last[q] && p2[q] <= 0.f && alpha >= kAlphaMin) {
                         touched = true;
                         T[q] = T[q] * __builtin_amdgcn_rcpf(1.f - alpha);
                         const float wgt = alpha * T[q];
-                        float dalpha = 0.f;
+                        const float Gc = fmaf(G[q][2], col3[2], fmaf(G[q][1], col3[1], G[q][0] * col3[0]));
+                        const float diff = Gc - GS[q];
 #pragma unroll
-                        for (int ch = 0; ch < 3; ch++) {
-                            const float diff = col3[ch] - S[q][ch];
-                            acc[6 + ch] = fmaf(G[q][ch], wgt, acc[6 + ch]);
-                            dalpha = fmaf(G[q][ch], diff, dalpha);
-                            S[q][ch] = fmaf(alpha, diff, S[q][ch]);
-                        }
+                        for (int ch = 0; ch < 3; ch++) acc[6 + ch] = fmaf(G[q][ch], wgt, acc[6 + ch]);
+                        GS[q] = fmaf(alpha, diff, GS[q]);
                         if (apre <= kAlphaMax) {
-                            const float dp = dalpha * T[q] * alpha;   // dL/dpower
+                            const float dp = wgt * diff;   // dL/dpower
                             const float dpy = dp * dy;
                             acc[0] = fmaf(dp, fmaf(s.B2, dy, a2dx), acc[0]);
                             acc[1] = fmaf(dp, fmaf(2.f * t.C2, dy, ct.bdx), acc[1]);
@@ -185,6 +189,7 @@ __global__ __launch_bounds__(kRasterThreads) void k_raster_bwd(BwdArgs a, ViewsK
                             acc[5] += dp;
                         }
                     }
+                }
                 }
                 float x0 = 0.f, x1 = 0.f, x2 = 0.f;
                 if (__any(touched)) wave_sum9(acc, x0, x1, x2);

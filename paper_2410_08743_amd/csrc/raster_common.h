@@ -28,6 +28,10 @@ constexpr int kBatch = 64;          // list entries staged in LDS at a time
 constexpr int kUnroll = 8;          // entries per step of the inner loop
 
 constexpr float kLn2 = 0.6931471805599453f;
+// A splat can reach alpha >= 1/255 at a pixel only if p2 + log2(o) is at least
+// log2(1/255); the 0.01 margin keeps the test conservative with respect to
+// v_exp_f32's rounding, so skipping on it never changes a decision.
+constexpr float kLog2AlphaMinLoose = -7.994353436858858f - 0.01f;
 
 // Splat as staged in LDS: centre relative to the tile's first pixel, scaled
 // conic, log2 opacity and colour; the backward adds the instance's slot.

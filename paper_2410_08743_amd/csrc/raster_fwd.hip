@@ -119,15 +119,27 @@ __global__ __launch_bounds__(kRasterThreads) void k_raster_fwd(FwdArgs a, ViewsK
             for (int u = 0; u < kUnroll; u++) {
                 const int j = b0 + j0 + u;
                 const ColTerms ct = col_terms(es[u], fxl);
+                float p2[kPixPerLane];
+                bool cand = false;
 #pragma unroll
                 for (int q = 0; q < kPixPerLane; q++) {
-                    const float p2 = splat_p2(ct, et[u].C2, es[u].v - fy[q]);
-                    const float alpha = fminf(kAlphaMax, splat_alpha_pre(p2, et[u].lo));
+                    p2[q] = splat_p2(ct, et[u].C2, es[u].v - fy[q]);
+                    cand |= T[q] > 0.f && p2[q] <= 0.f && p2[q] + et[u].lo >= kLog2AlphaMinLoose;
+                }
+                if (STATS) {
+#pragma unroll
+                    for (int q = 0; q < kPixPerLane; q++)
+                        if (T[q] > 0.f && j < len) ne[q]++;
+                }
+                // no pixel of the tile can reach 1/255: nothing to do
+                if (!__any(cand)) continue;
+#pragma unroll
+                for (int q = 0; q < kPixPerLane; q++) {
+                    const float alpha = fminf(kAlphaMax, splat_alpha_pre(p2[q], et[u].lo));
                     const float testT = T[q] * (1.f - alpha);
-                    const bool hit = p2 <= 0.f && alpha >= kAlphaMin;
+                    const bool hit = p2[q] <= 0.f && alpha >= kAlphaMin;
                     const bool blend = hit && testT >= kTMin;
                     const bool stop = hit && testT < kTMin;
-                    if (STATS && T[q] > 0.f && j < len) ne[q]++;
                     if (STATS && blend) nb[q]++;
                     const float wgt = blend ? alpha * T[q] : 0.f;
                     cr[q] = fmaf(et[u].r, wgt, cr[q]);
