@@ -200,6 +200,7 @@ Layout make_layout(int64_t n, int32_t sh_degree, int32_t V, const ViewsK &views,
     L.nblk_sort = (int)((max_sorted + kSortItems - 1) / kSortItems);
     L.tile_bits = tile_bits_for(views.total_tiles);
     L.tile_passes = (L.tile_bits + kSortBits - 1) / kSortBits;
+    L.nwin_max = (int)((L.vn + L.cap + kWindow - 1) / kWindow + 1);
     const size_t vn = (size_t)L.vn, capz = (size_t)L.cap;
     size_t off = 0;
     auto take = [&](size_t bytes) {
@@ -214,6 +215,8 @@ Layout make_layout(int64_t n, int32_t sh_degree, int32_t V, const ViewsK &views,
     L.depth = take(vn * 4);
     L.tiles = take(vn * 4);
     L.offsets = take(vn * 4);
+    L.offk = take((vn + 1) * 4);
+    L.wstart = take(((size_t)L.nwin_max + 1) * 4);
     L.blocksum = take((size_t)L.nblk_vn * 8 + 8);
     L.dkeys0 = take(vn * 4);
     L.dkeys1 = take(vn * 4);

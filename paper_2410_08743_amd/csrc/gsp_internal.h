@@ -37,6 +37,14 @@ constexpr int kSortItems = kSortThreads * kSortRounds;  // keys per sort block
 constexpr int kSortBits = 8;             // radix digit width
 constexpr int kSortBins = 1 << kSortBits;
 constexpr int kPoseReduceBlock = 256;
+// Work windows of the instance emission and of the slot reduction: the
+// sequence of splats in depth order, each followed by its instances, is cut
+// into pieces of kWindow items, and a block takes the splats whose entry
+// falls in its piece.  Every block then sees at most kWindow splats and
+// kWindow instances plus the tail of its last splat, however unevenly the
+// instances are spread over the splats.
+constexpr int kWindow = 1024;
+constexpr int kWindowThreads = 256;
 
 // Per-view constants, computed on the host once per call.
 struct ViewK {
@@ -58,8 +66,8 @@ struct ViewsK {
 // Carving of the caller's workspace.  Every region is 256-byte aligned.
 struct Layout {
     int64_t n, vn, cap, total_pix;
-    int32_t V, S, total_tiles, nblk_pre, nblk_vn, nblk_sort, tile_bits, tile_passes;
-    size_t geom, color, rect, depth, tiles, offsets, blocksum, counters;
+    int32_t V, S, total_tiles, nblk_pre, nblk_vn, nblk_sort, tile_bits, tile_passes, nwin_max;
+    size_t geom, color, rect, depth, tiles, offsets, offk, wstart, blocksum, counters;
     size_t dkeys0, dkeys1, dvals0, dvals1;
     size_t keys0, keys1, vals0, vals1, hist, digit_tot, ranges;
     size_t tfinal, ncontrib, stats, slots, grad2d, posepart;
@@ -67,9 +75,11 @@ struct Layout {
 };
 
 // Counters at the start of the counters region.
-// kCntSticky keeps the OR of every overflow since the workspace was zeroed.
+// kCntSticky keeps the OR of every overflow since the workspace was zeroed;
+// kCntWin is the number of work windows of this call.
 enum Counter : int {
-    kCntMLo = 0, kCntMHi = 1, kCntOverflow = 2, kCntMEff = 3, kCntSticky = 4, kCntCount = 16
+    kCntMLo = 0, kCntMHi = 1, kCntOverflow = 2, kCntMEff = 3, kCntSticky = 4, kCntWin = 5,
+    kCntCount = 16
 };
 
 Layout make_layout(int64_t n, int32_t sh_degree, int32_t V, const ViewsK &views, int64_t cap);

@@ -225,19 +225,21 @@ struct DupArgs {
     const uint32_t *order;         // [vn] view * n + i in (depth, index) order
     const uint2 *rect;
     const uint32_t *tiles;
-    uint32_t *offsets;
+    uint32_t *offsets;             // [vn] by splat: first emission position
+    uint32_t *offk;                // [vn + 1] by depth rank: first emission position, then M
+    uint32_t *wstart;              // [windows + 1] first depth rank of each work window
     const unsigned long long *blockoff;
-    const uint32_t *counters;
+    uint32_t *counters;
     uint32_t *keys;
     uint32_t *vals;
     int vn;
 };
 
-// Walks the splats in depth order and emits one (tile, view * n + i) pair per
-// tile of each splat's rect, rows outer and columns inner, at the splat's
-// exclusive offset; a stable sort of these pairs by tile then yields every
-// tile's list in (depth, index) order.
-__global__ __launch_bounds__(kPreprocessBlock) void k_duplicate(DupArgs a, ViewsK views, int n) {
+// Exclusive offsets of the splats' instance runs in depth order, and the
+// work windows.  Splat k's entry sits at position h = k + offk[k] of the
+// sequence (splat, its instances, next splat, ...), the next at h + 1 + cnt;
+// window b starts at the first splat whose entry is at or after b * kWindow.
+__global__ __launch_bounds__(kPreprocessBlock) void k_offsets(DupArgs a) {
     __shared__ unsigned long long scratch[kPreprocessBlock / kWave];
     const int k = blockIdx.x * kPreprocessBlock + threadIdx.x;
     const uint32_t idx = k < a.vn ? a.order[k] : 0u;
@@ -248,18 +250,55 @@ __global__ __launch_bounds__(kPreprocessBlock) void k_duplicate(DupArgs a, Views
         a.blockoff[blockIdx.x];
     if (a.counters[kCntOverflow] != 0u || k >= a.vn) return;
     a.offsets[idx] = (uint32_t)excl;
-    if (cnt == 0) return;
-    const uint2 r = a.rect[idx];
-    const int x0 = r.x & 0xffff, y0 = r.x >> 16, x1 = r.y & 0xffff, y1 = r.y >> 16;
-    const ViewK &vw = views.v[idx / (uint32_t)n];
-    size_t o = (size_t)excl;
-    for (int ty = y0; ty < y1; ty++) {
-        const uint32_t rowbase = (uint32_t)(vw.tile_base + ty * vw.gw);
-        for (int tx = x0; tx < x1; tx++) {
-            a.keys[o] = rowbase + (uint32_t)tx;
-            a.vals[o] = idx;
-            o++;
+    a.offk[k] = (uint32_t)excl;
+    const unsigned long long h = (unsigned long long)k + excl, h1 = h + 1 + cnt;
+    if (k == 0) a.wstart[0] = 0u;
+    for (unsigned long long b = h / kWindow + 1; b * kWindow <= h1; b++) a.wstart[b] = (uint32_t)k + 1;
+    if (k == a.vn - 1) {
+        const unsigned long long nwin = (h1 + kWindow - 1) / kWindow;
+        if (nwin * kWindow > h1) a.wstart[nwin] = (uint32_t)a.vn;
+        a.offk[a.vn] = (uint32_t)(excl + cnt);
+        a.counters[kCntWin] = (uint32_t)nwin;
+    }
+}
+
+// Emits one (tile, view * n + i) pair per tile of each splat's rect, rows
+// outer and columns inner, at the splat's offset; a stable sort of these
+// pairs by tile then yields every tile's list in (depth, index) order.  One
+// block per work window; each thread writes consecutive positions and finds
+// the splat owning a position by binary search over the window's offsets.
+__global__ __launch_bounds__(kWindowThreads) void k_emit(DupArgs a, ViewsK views, int n) {
+    __shared__ uint32_t s_off[kWindow + 1];
+    __shared__ uint32_t s_idx[kWindow];
+    __shared__ uint2 s_rect[kWindow];
+    const int b = blockIdx.x;
+    if (a.counters[kCntOverflow] != 0u || (uint32_t)b >= a.counters[kCntWin]) return;
+    const uint32_t kb = a.wstart[b], ke = a.wstart[b + 1];
+    const int nk = (int)(ke - kb);   // at most kWindow
+    for (int j = threadIdx.x; j < nk; j += kWindowThreads) {
+        const uint32_t idx = a.order[kb + j];
+        s_off[j] = a.offk[kb + j];
+        s_idx[j] = idx;
+        s_rect[j] = a.rect[idx];
+    }
+    const uint32_t e0 = a.offk[kb], e1 = a.offk[ke];
+    if (threadIdx.x == 0) s_off[nk] = e1;
+    __syncthreads();
+    for (uint32_t e = e0 + threadIdx.x; e < e1; e += kWindowThreads) {
+        // largest j with s_off[j] <= e; s_off[0] <= e < s_off[nk]
+        int lo = 0, hi = nk;
+        while (hi - lo > 1) {
+            const int mid = (lo + hi) >> 1;
+            if (s_off[mid] <= e) lo = mid; else hi = mid;
         }
+        const uint2 r = s_rect[lo];
+        const int x0 = r.x & 0xffff, y0 = r.x >> 16, x1 = r.y & 0xffff;
+        const uint32_t w = (uint32_t)(x1 - x0), local = e - s_off[lo];
+        const uint32_t idx = s_idx[lo];
+        const ViewK &vw = views.v[idx / (uint32_t)n];
+        const uint32_t ty = (uint32_t)y0 + local / w, tx = (uint32_t)x0 + local % w;
+        a.keys[e] = (uint32_t)vw.tile_base + ty * (uint32_t)vw.gw + tx;
+        a.vals[e] = idx;
     }
 }
 
@@ -305,13 +344,15 @@ hipError_t launch_offsets_and_duplicate(const ViewsK &views, const Layout &L, ch
     a.rect = region<uint2>(ws, L.rect);
     a.tiles = region<uint32_t>(ws, L.tiles);
     a.offsets = region<uint32_t>(ws, L.offsets);
+    a.offk = region<uint32_t>(ws, L.offk);
+    a.wstart = region<uint32_t>(ws, L.wstart);
     a.blockoff = bs;
     a.counters = counters;
     a.keys = region<uint32_t>(ws, L.keys0);
     a.vals = region<uint32_t>(ws, L.vals0);
     a.vn = vn;
-    hipLaunchKernelGGL(k_duplicate, dim3(L.nblk_vn), dim3(kPreprocessBlock), 0, s, a, views,
-                       (int)L.n);
+    hipLaunchKernelGGL(k_offsets, dim3(L.nblk_vn), dim3(kPreprocessBlock), 0, s, a);
+    hipLaunchKernelGGL(k_emit, dim3(L.nwin_max), dim3(kWindowThreads), 0, s, a, views, (int)L.n);
     return hipGetLastError();
 }
 

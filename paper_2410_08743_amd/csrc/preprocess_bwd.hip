@@ -10,10 +10,10 @@
 // Sigma_hat = J R_c Sigma R_c^T J^T) and h = dL/do_c:
 //   dL/drho += g - R_c h,   dL/dphi += mu^c x g + vee(G_W R_c^T).
 //
-// MI355X design: a first kernel walks the splats in depth order -- the order
-// in which their instance slots were laid out, so neighbouring lanes read
-// neighbouring slots -- and sums each splat's slots in a fixed order into its
-// 2D gradient.  The chain-rule kernel then runs one thread per Gaussian over
+// MI355X design: a first kernel walks the instance slots in their emission
+// order (splats in depth order, each splat's slots contiguous), in windows of
+// balanced size, and sums each splat's slots in a fixed order into its 2D
+// gradient.  The chain-rule kernel then runs one thread per Gaussian over
 // the call's views, geometry in FP64 (the kernel is bound by HBM, and the FP64
 // vector rate equals unpacked FP32), SH in FP32.  Gaussian gradients are
 // summed over views in registers and written once; the six pose sums per view
@@ -31,7 +31,6 @@ struct PbArgs {
     GaussiansK g;
     const float *poses;
     const uint32_t *tiles;
-    const uint32_t *offsets;
     const uint32_t *counters;
     const float *slots;     // [cap][9]
     float *grad2d;          // [9][vn]
@@ -54,60 +53,61 @@ __device__ __forceinline__ void rot_vjp(double w, double x, double y, double z, 
                   x * Gm[6] + y * Gm[7]);
 }
 
-// 2D gradient of each splat: the sum of its instance slots, in slot order.
-// A block takes 256 consecutive splats in depth order; their slots form one
-// contiguous range, which the block copies through LDS in chunks of 1024
-// instances -- every thread issues its 36 loads of a chunk at once, so a
-// chunk costs one memory latency -- and each thread then adds the part of its
-// own segment that the chunk holds.
-constexpr int kSlotChunk = 1024;
-constexpr int kSlotPerThread = kSlotChunk * 9 / 256;
+// 2D gradient of each splat: the sum of its instance slots in slot order (one
+// running sum from zero, first slot to last).  One block per work window: the
+// window's slots form one contiguous range, which the block copies into LDS
+// with all of each thread's loads in flight at once; the (splat, component)
+// pairs are then spread over the threads, nine neighbouring threads per
+// splat.  Slots past the first kWindow of the range -- the tail of a long last
+// splat -- are read from global memory.
+constexpr int kSlotPerThread = kWindow * 9 / kWindowThreads;
 
-__global__ __launch_bounds__(256) void k_slot_reduce(const uint32_t *order, const uint32_t *tiles,
-                                                     const uint32_t *offsets, const uint32_t *counters,
-                                                     const float *slots, float *grad2d, int vn) {
-    __shared__ float chunk[kSlotChunk * 9];
-    __shared__ uint32_t bounds[2];
-    const int k = blockIdx.x * 256 + threadIdx.x;
-    const bool ovf = counters[kCntOverflow] != 0u;
-    const uint32_t idx = k < vn ? order[k] : 0u;
-    const uint32_t cnt = (k < vn && !ovf) ? tiles[idx] : 0u;
-    const uint32_t e0 = cnt ? offsets[idx] : 0u, e1 = e0 + cnt;
-    // segments are contiguous and ordered by k: the first and last threads
-    // with work bound the block's range
-    const unsigned long long has = __ballot(cnt > 0);
-    if (threadIdx.x == 0) { bounds[0] = 0xffffffffu; bounds[1] = 0u; }
-    __syncthreads();
-    if (cnt > 0 && (has & ((1ull << (threadIdx.x & 63)) - 1ull)) == 0) atomicMin(&bounds[0], e0);
-    if (cnt > 0 && (has >> (threadIdx.x & 63)) == 1ull) atomicMax(&bounds[1], e1);
-    __syncthreads();
-    const uint32_t first = bounds[0], end = bounds[1];
-    float d[9];
-#pragma unroll
-    for (int c = 0; c < 9; c++) d[c] = 0.f;
-    for (uint32_t c0 = first; c0 < end; c0 += kSlotChunk) {
-        const uint32_t nf = 9u * (min(end, c0 + (uint32_t)kSlotChunk) - c0);
-        const float *src = slots + 9 * (size_t)c0;
-        float tmp[kSlotPerThread];
-#pragma unroll
-        for (int r = 0; r < kSlotPerThread; r++) {
-            const uint32_t f = (uint32_t)(r * 256 + threadIdx.x);
-            tmp[r] = f < nf ? src[f] : 0.f;
-        }
-#pragma unroll
-        for (int r = 0; r < kSlotPerThread; r++) chunk[r * 256 + threadIdx.x] = tmp[r];
-        __syncthreads();
-        const uint32_t lo = max(e0, c0), hi = min(e1, c0 + (uint32_t)kSlotChunk);
-        for (uint32_t e = lo; e < hi; e++) {
-            const float *rec = chunk + 9 * (e - c0);
-#pragma unroll
-            for (int c = 0; c < 9; c++) d[c] += rec[c];
-        }
-        __syncthreads();
+__global__ __launch_bounds__(kWindowThreads) void k_slot_reduce(const uint32_t *order,
+                                                                const uint32_t *offk,
+                                                                const uint32_t *wstart,
+                                                                const uint32_t *counters,
+                                                                const float *slots, float *grad2d,
+                                                                int vn) {
+    __shared__ float s_sl[kWindow * 9];
+    __shared__ uint32_t s_off[kWindow + 1];
+    __shared__ uint32_t s_idx[kWindow];
+    const int b = blockIdx.x;
+    if (counters[kCntOverflow] != 0u) {
+        // no instance was emitted: every 2D gradient is zero
+        for (size_t f = (size_t)b * kWindowThreads + threadIdx.x; f < 9 * (size_t)vn;
+             f += (size_t)gridDim.x * kWindowThreads)
+            grad2d[f] = 0.f;
+        return;
     }
-    if (k < vn) {
+    if ((uint32_t)b >= counters[kCntWin]) return;
+    const uint32_t kb = wstart[b], ke = wstart[b + 1];
+    const int nk = (int)(ke - kb);   // at most kWindow
+    const uint32_t e0 = offk[kb], ne = offk[ke] - e0;
+    const uint32_t nf = 9u * min(ne, (uint32_t)kWindow);
+    const float *src = slots + 9 * (size_t)e0;
+    float tmp[kSlotPerThread];
 #pragma unroll
-        for (int c = 0; c < 9; c++) grad2d[(size_t)c * vn + idx] = d[c];
+    for (int r = 0; r < kSlotPerThread; r++) {
+        const uint32_t f = (uint32_t)(r * kWindowThreads + threadIdx.x);
+        tmp[r] = f < nf ? src[f] : 0.f;
+    }
+    for (int j = threadIdx.x; j < nk; j += kWindowThreads) {
+        s_off[j] = offk[kb + j] - e0;
+        s_idx[j] = order[kb + j];
+    }
+    if (threadIdx.x == 0) s_off[nk] = ne;
+#pragma unroll
+    for (int r = 0; r < kSlotPerThread; r++) s_sl[r * kWindowThreads + threadIdx.x] = tmp[r];
+    __syncthreads();
+    for (int item = threadIdx.x; item < 9 * nk; item += kWindowThreads) {
+        const int j = item / 9, c = item - 9 * j;
+        const uint32_t lo = s_off[j], hi = s_off[j + 1];
+        const uint32_t mid = min(hi, (uint32_t)kWindow);
+        float d = 0.f;
+        uint32_t e = lo;
+        for (; e < mid; e++) d += s_sl[9 * e + c];
+        for (; e < hi; e++) d += src[9 * (size_t)e + c];
+        grad2d[(size_t)c * vn + s_idx[j]] = d;
     }
 }
 
@@ -389,7 +389,6 @@ hipError_t launch_preprocess_bwd(const GaussiansK &g, const ViewsK &views, const
     a.g = g;
     a.poses = poses;
     a.tiles = region<uint32_t>(ws, L.tiles);
-    a.offsets = region<uint32_t>(ws, L.offsets);
     a.counters = region<uint32_t>(ws, L.counters);
     a.slots = region<float>(ws, L.slots);
     a.grad2d = region<float>(ws, L.grad2d);
@@ -400,9 +399,10 @@ hipError_t launch_preprocess_bwd(const GaussiansK &g, const ViewsK &views, const
     a.nblk = L.nblk_pre;
     a.accumulate = accumulate;
     if (L.vn > 0) {
-        hipLaunchKernelGGL(k_slot_reduce, dim3(L.nblk_vn), dim3(256), 0, s,
-                           region<uint32_t>(ws, L.dvals0), a.tiles, a.offsets, a.counters, a.slots,
-                           a.grad2d, (int)L.vn);
+        hipLaunchKernelGGL(k_slot_reduce, dim3(L.nwin_max), dim3(kWindowThreads), 0, s,
+                           region<uint32_t>(ws, L.dvals0), region<uint32_t>(ws, L.offk),
+                           region<uint32_t>(ws, L.wstart), a.counters, a.slots, a.grad2d,
+                           (int)L.vn);
         hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
     }
