@@ -149,50 +149,54 @@ __global__ __launch_bounds__(kRasterThreads) void k_raster_bwd(BwdArgs a, ViewsK
                 const int pos = lo + j0 + u;
                 const StagedA &s = es[u];
                 const StagedB &t = et[u];
-                const float col3[3] = {t.r, t.g, ew[u].b};
                 const ColTerms ct = col_terms(s, fxl);
-                const float a2dx = 2.f * s.A2 * ct.dx;
-                float acc[9];
-#pragma unroll
-                for (int c = 0; c < 9; c++) acc[c] = 0.f;
                 float p2[kPixPerLane];
-                bool cand = false;
+                bool cand[kPixPerLane];
 #pragma unroll
                 for (int q = 0; q < kPixPerLane; q++) {
                     p2[q] = splat_p2(ct, t.C2, s.v - fy[q]);
-                    cand |= pos < last[q] && p2[q] <= 0.f && p2[q] + t.lo >= kLog2AlphaMinLoose;
+                    cand[q] = pos < last[q] && p2[q] <= 0.f && p2[q] + t.lo >= kLog2AlphaMinLoose;
                 }
-                bool touched = false;
-                if (__any(cand)) {
+                float x0 = 0.f, x1 = 0.f, x2 = 0.f;
+                if (__any(cand[0] || cand[1] || cand[2] || cand[3])) {
+                    const float col3[3] = {t.r, t.g, ew[u].b};
+                    const float a2dx = 2.f * s.A2 * ct.dx;
+                    const float c22 = 2.f * t.C2;
+                    const float dx2 = ct.dx * ct.dx;
+                    float acc[9];
 #pragma unroll
-                for (int q = 0; q < kPixPerLane; q++) {
-                    const float dy = s.v - fy[q];
-                    const float apre = splat_alpha_pre(p2[q], t.lo);
-                    const float alpha = fminf(kAlphaMax, apre);
-                    if (pos < last[q] && p2[q] <= 0.f && alpha >= kAlphaMin) {
-                        touched = true;
-                        T[q] = T[q] * __builtin_amdgcn_rcpf(1.f - alpha);
-                        const float wgt = alpha * T[q];
+                    for (int c = 0; c < 9; c++) acc[c] = 0.f;
+                    // q-th pixels of all lanes form a 16 x 4 band of the tile:
+                    // a band with no candidate is skipped as a whole; inside a
+                    // band the update is branch-free, pixels that do not blend
+                    // adding exact zeros.
+#pragma unroll
+                    for (int q = 0; q < kPixPerLane; q++) {
+                        if (!__any(cand[q])) continue;
+                        const float dy = s.v - fy[q];
+                        const float apre = splat_alpha_pre(p2[q], t.lo);
+                        const float alpha = fminf(kAlphaMax, apre);
+                        const bool valid = cand[q] && alpha >= kAlphaMin;
+                        const float Tn = T[q] * __builtin_amdgcn_rcpf(1.f - alpha);
+                        T[q] = valid ? Tn : T[q];
+                        const float wgt = valid ? alpha * T[q] : 0.f;
                         const float Gc = fmaf(G[q][2], col3[2], fmaf(G[q][1], col3[1], G[q][0] * col3[0]));
                         const float diff = Gc - GS[q];
 #pragma unroll
                         for (int ch = 0; ch < 3; ch++) acc[6 + ch] = fmaf(G[q][ch], wgt, acc[6 + ch]);
-                        GS[q] = fmaf(alpha, diff, GS[q]);
-                        if (apre <= kAlphaMax) {
-                            const float dp = wgt * diff;   // dL/dpower
-                            const float dpy = dp * dy;
-                            acc[0] = fmaf(dp, fmaf(s.B2, dy, a2dx), acc[0]);
-                            acc[1] = fmaf(dp, fmaf(2.f * t.C2, dy, ct.bdx), acc[1]);
-                            acc[2] = fmaf(dp, ct.dx * ct.dx, acc[2]);
-                            acc[3] = fmaf(dpy, ct.dx, acc[3]);
-                            acc[4] = fmaf(dpy, dy, acc[4]);
-                            acc[5] += dp;
-                        }
+                        GS[q] = valid ? fmaf(alpha, diff, GS[q]) : GS[q];
+                        // dL/dpower; zero where alpha is clamped at 0.99
+                        const float dp = apre <= kAlphaMax ? wgt * diff : 0.f;
+                        const float dpy = dp * dy;
+                        acc[0] = fmaf(dp, fmaf(s.B2, dy, a2dx), acc[0]);
+                        acc[1] = fmaf(dp, fmaf(c22, dy, ct.bdx), acc[1]);
+                        acc[2] = fmaf(dp, dx2, acc[2]);
+                        acc[3] = fmaf(dpy, ct.dx, acc[3]);
+                        acc[4] = fmaf(dpy, dy, acc[4]);
+                        acc[5] += dp;
                     }
+                    wave_sum9(acc, x0, x1, x2);
                 }
-                }
-                float x0 = 0.f, x1 = 0.f, x2 = 0.f;
-                if (__any(touched)) wave_sum9(acc, x0, x1, x2);
                 if (comp >= 0 && ew[u].slot != kNoSlot) {
                     const float val = col == 0 ? x0 : (col == 1 ? x1 : x2);
                     const float f = comp == 5 ? ew[u].inv_o : scale;
