@@ -53,7 +53,7 @@ __device__ __forceinline__ uint32_t slot_of(const BwdArgs &a, uint32_t id, int t
     return a.offsets[id] + (uint32_t)((ty - y0) * (x1 - x0) + (tx - x0));
 }
 
-__global__ __launch_bounds__(kRasterThreads) void k_raster_bwd(BwdArgs a, ViewsK views) {
+__global__ __launch_bounds__(kRasterThreads) __attribute__((amdgpu_waves_per_eu(4))) void k_raster_bwd(BwdArgs a, ViewsK views) {
     __shared__ StagedA sA[kBatch];
     __shared__ StagedB sB[kBatch];
     __shared__ StagedC sC[kBatch];
@@ -109,12 +109,12 @@ __global__ __launch_bounds__(kRasterThreads) void k_raster_bwd(BwdArgs a, ViewsK
     }
 
     // batches of 64 entries ending at hi, walked back to front; positions
-    // below 0 are inert padding.  Records are gathered one batch ahead.
+    // below 0 are absent.  Records are gathered one batch ahead.
     float4 g0, g1, gc;
     uint32_t gslot;
     auto gather = [&](int k) {
         g0 = make_float4(0.f, 0.f, 0.f, 0.f);
-        g1 = make_float4(0.f, 0.f, 0.f, -INFINITY);   // inert: alpha = 0
+        g1 = make_float4(-1.f, 0.f, -1.f, -INFINITY);
         gc = make_float4(0.f, 0.f, 0.f, 0.f);
         gslot = kNoSlot;
         if (k >= 0) {
@@ -128,13 +128,31 @@ __global__ __launch_bounds__(kRasterThreads) void k_raster_bwd(BwdArgs a, ViewsK
     if (maxlast > 0) gather(maxlast - kBatch + lane);
     for (int hi = maxlast; hi > 0; hi -= kBatch) {
         const int lo = hi - kBatch;
-        sA[lane] = StagedA{rel_coord(g0.x, g0.z, px0), rel_coord(g0.y, g0.w, py0), g1.x, g1.y};
-        sB[lane] = StagedB{g1.z, g1.w, gc.x, gc.y};
-        sC[lane] = StagedC{gc.z, __builtin_amdgcn_exp2f(-g1.w), gslot, 0u};
+        // Stage, in list order, the entries that can reach 1/255 somewhere in
+        // the tile; a dropped entry blends nowhere and gets a zero slot.
+        const float u = rel_coord(g0.x, g0.z, px0), v = rel_coord(g0.y, g0.w, py0);
+        const uint32_t mask = gslot != kNoSlot ? band_mask(u, v, g1.x, g1.y, g1.z, g1.w) : 0u;
+        const unsigned long long kept = __ballot(mask != 0u);
+        const int nk = __popcll(kept);
+        if (mask != 0u) {
+            const int r = kept_rank(kept);
+            sA[r] = StagedA{u, v, g1.x, g1.y};
+            sB[r] = StagedB{g1.z, g1.w, gc.x, gc.y};
+            sC[r] = StagedC{gc.z, __builtin_amdgcn_exp2f(-g1.w), gslot,
+                            ((uint32_t)(lo + lane) << 4) | mask};
+        } else if (gslot != kNoSlot) {
+#pragma unroll
+            for (int c = 0; c < 9; c++) a.slots[9 * (size_t)gslot + c] = 0.f;
+        }
+        const int nkr = (nk + kBwdUnroll - 1) & ~(kBwdUnroll - 1);
+        if (lane >= nk && lane < nkr) {   // padding up to the unroll width
+            sA[lane] = StagedA{0.f, 0.f, -1.f, 0.f};
+            sB[lane] = StagedB{-1.f, -INFINITY, 0.f, 0.f};
+            sC[lane] = StagedC{0.f, 0.f, kNoSlot, 0u};
+        }
         __syncthreads();
         if (lo > 0) gather(lo - kBatch + lane);
-        const int jstop = lo < 0 ? -lo : 0;   // entries below are padding
-        for (int j0 = kBatch - kBwdUnroll; j0 >= 0; j0 -= kBwdUnroll) {
+        for (int j0 = nkr - kBwdUnroll; j0 >= 0; j0 -= kBwdUnroll) {
             StagedA es[kBwdUnroll];
             StagedB et[kBwdUnroll];
             StagedC ew[kBwdUnroll];
@@ -146,7 +164,7 @@ __global__ __launch_bounds__(kRasterThreads) void k_raster_bwd(BwdArgs a, ViewsK
             }
 #pragma unroll
             for (int u = kBwdUnroll - 1; u >= 0; u--) {
-                const int pos = lo + j0 + u;
+                const int pos = (int)(ew[u].pm >> 4);
                 const StagedA &s = es[u];
                 const StagedB &t = et[u];
                 const ColTerms ct = col_terms(s, fxl);
@@ -155,7 +173,7 @@ __global__ __launch_bounds__(kRasterThreads) void k_raster_bwd(BwdArgs a, ViewsK
 #pragma unroll
                 for (int q = 0; q < kPixPerLane; q++) {
                     p2[q] = splat_p2(ct, t.C2, s.v - fy[q]);
-                    cand[q] = pos < last[q] && p2[q] <= 0.f && p2[q] + t.lo >= kLog2AlphaMinLoose;
+                    cand[q] = (pos < last[q]) & (p2[q] <= 0.f) & (p2[q] + t.lo >= kLog2AlphaMinLoose);
                 }
                 float x0 = 0.f, x1 = 0.f, x2 = 0.f;
                 if (__any(cand[0] || cand[1] || cand[2] || cand[3])) {
@@ -203,7 +221,6 @@ __global__ __launch_bounds__(kRasterThreads) void k_raster_bwd(BwdArgs a, ViewsK
                     a.slots[9 * (size_t)ew[u].slot + comp] = val * f;
                 }
             }
-            if (j0 <= jstop) break;
         }
         __syncthreads();
     }

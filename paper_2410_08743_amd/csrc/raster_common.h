@@ -25,7 +25,7 @@ namespace gsp {
 constexpr int kRasterThreads = 64;
 constexpr int kPixPerLane = 4;
 constexpr int kBatch = 64;          // list entries staged in LDS at a time
-constexpr int kUnroll = 8;          // entries per step of the inner loop
+constexpr int kUnroll = 4;          // entries per step of the inner loop
 
 constexpr float kLn2 = 0.6931471805599453f;
 // A splat can reach alpha >= 1/255 at a pixel only if p2 + log2(o) is at least
@@ -34,10 +34,13 @@ constexpr float kLn2 = 0.6931471805599453f;
 constexpr float kLog2AlphaMinLoose = -7.994353436858858f - 0.01f;
 
 // Splat as staged in LDS: centre relative to the tile's first pixel, scaled
-// conic, log2 opacity and colour; the backward adds the instance's slot.
+// conic, log2 opacity and colour; pm packs the entry's list position and its
+// band mask (position << 4 | mask, 0 for padding); the backward adds the
+// instance's slot and 1/o.
 struct StagedA { float u, v, A2, B2; };
 struct StagedB { float C2, lo, r, g; };
-struct StagedC { float b, inv_o; uint32_t slot, pad; };
+struct StagedF { float b; uint32_t pm; };
+struct StagedC { float b, inv_o; uint32_t slot, pm; };
 
 // Centre of a splat relative to pixel (px0, py0), from its (hi, lo) pair.
 __device__ __forceinline__ float rel_coord(float hi, float lo, int origin) {
@@ -69,6 +72,44 @@ __device__ __forceinline__ float splat_p2(const ColTerms &t, float C2, float dy)
 __device__ __forceinline__ float splat_alpha_pre(float p2, float lo) {
 #pragma clang fp contract(off)
     return __builtin_amdgcn_exp2f(p2 + lo);
+}
+
+// Bit q of the result is set when some pixel of rows 4q .. 4q+3 of the tile
+// may reach alpha >= 1/255, i.e. when the rasterizer's own candidate test
+// (p2 + lo >= kLog2AlphaMinLoose) may pass there; a clear bit is a proof that
+// it fails at every pixel of those rows.  Per pixel row, p2 is a concave
+// quadratic in dx whose maximum over the row's dx range [u - 15, u] is taken
+// at the clamped stationary point.  The margin covers the float32 rounding of
+// both this bound and the rasterizer's evaluation: 0.02 plus 1e-5 times the
+// largest magnitude the three terms of p2 take in the row, some forty times
+// the error of either three-operation evaluation.
+__device__ __forceinline__ uint32_t band_mask(float u, float v, float A2, float B2, float C2,
+                                              float lo) {
+    if (!(A2 < 0.f) || !(C2 < 0.f)) return 0xfu;   // not negative definite: keep all
+    const float xa = u - (float)(kTile - 1), xb = u;
+    const float dxm = fmaxf(fabsf(xa), fabsf(xb));
+    const float half_inv = -0.5f / A2;
+    const float thr = kLog2AlphaMinLoose - lo;
+    const float adxm2 = fabsf(A2) * dxm * dxm;
+    uint32_t mask = 0u;
+#pragma unroll
+    for (int r = 0; r < kTile; r++) {
+        const float dy = v - (float)r;
+        const float bdy = B2 * dy;
+        const float cdy2 = C2 * dy * dy;
+        const float xs = fminf(fmaxf(bdy * half_inv, xa), xb);
+        const float m = fmaf(fmaf(A2, xs, bdy), xs, cdy2);
+        const float mag = adxm2 + fabsf(bdy) * dxm + fabsf(cdy2);
+        if (m + fmaf(1e-5f, mag, 0.02f) >= thr) mask |= 1u << (r >> 2);
+    }
+    return mask;
+}
+
+// Position of a lane's entry among the entries of its wavefront that are
+// kept, counting lanes below it.
+__device__ __forceinline__ int kept_rank(unsigned long long kept) {
+    return (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(kept >> 32),
+                                          __builtin_amdgcn_mbcnt_lo((uint32_t)kept, 0u));
 }
 
 __device__ __forceinline__ int view_of_tile(const ViewsK &views, int tile) {

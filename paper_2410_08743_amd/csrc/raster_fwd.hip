@@ -43,13 +43,14 @@ struct FwdArgs {
 };
 
 // STATS = true is a measurement variant that also counts, per pixel, the
-// evaluated and blended (pixel, splat) pairs; the work counts define the
-// kernel's algorithmic operation count.
+// evaluated and blended (pixel, splat) pairs of the algorithm -- every list
+// entry up to the pixel's stop counts as evaluated, culled or not; the work
+// counts define the kernel's algorithmic operation count.
 template <bool STATS>
-__global__ __launch_bounds__(kRasterThreads) void k_raster_fwd(FwdArgs a, ViewsK views) {
+__global__ __launch_bounds__(kRasterThreads) __attribute__((amdgpu_waves_per_eu(4))) void k_raster_fwd(FwdArgs a, ViewsK views) {
     __shared__ StagedA sA[kBatch];
     __shared__ StagedB sB[kBatch];
-    __shared__ float sCb[kBatch];
+    __shared__ StagedF sF[kBatch];
     const int tile = blockIdx.x;
     const ViewK &vw = views.v[view_of_tile(views, tile)];
     const int lt = tile - vw.tile_base;
@@ -79,79 +80,87 @@ __global__ __launch_bounds__(kRasterThreads) void k_raster_fwd(FwdArgs a, ViewsK
     const int len = (int)(rg.y - rg.x);
 
     // records of the batch being staged, gathered one batch ahead
-    float4 g0 = make_float4(0.f, 0.f, 0.f, 0.f), g1 = make_float4(0.f, 0.f, 0.f, -INFINITY),
-           gc = make_float4(0.f, 0.f, 0.f, 0.f);
-    if (lane < len) {
-        const uint32_t id = a.vals[rg.x + lane];
-        g0 = a.geom[2 * (size_t)id];
-        g1 = a.geom[2 * (size_t)id + 1];
-        gc = a.color[id];
-    }
+    float4 g0, g1, gc;
+    auto gather = [&](int k) {
+        g0 = make_float4(0.f, 0.f, 0.f, 0.f);
+        g1 = make_float4(-1.f, 0.f, -1.f, -INFINITY);   // inert: alpha = 0
+        gc = make_float4(0.f, 0.f, 0.f, 0.f);
+        if (k < len) {
+            const uint32_t id = a.vals[rg.x + k];
+            g0 = a.geom[2 * (size_t)id];
+            g1 = a.geom[2 * (size_t)id + 1];
+            gc = a.color[id];
+        }
+    };
+    gather(lane);
     for (int b0 = 0; b0 < len; b0 += kBatch) {
         if (!__any(T[0] > 0.f || T[1] > 0.f || T[2] > 0.f || T[3] > 0.f)) break;
-        sA[lane] = StagedA{rel_coord(g0.x, g0.z, px0), rel_coord(g0.y, g0.w, py0), g1.x, g1.y};
-        sB[lane] = StagedB{g1.z, g1.w, gc.x, gc.y};
-        sCb[lane] = gc.z;
-        __syncthreads();
+        // Stage the entries that can reach 1/255 somewhere in the tile, in
+        // list order; the others cannot change any pixel and are dropped.
         {
-            const int k = b0 + kBatch + lane;
-            g0 = make_float4(0.f, 0.f, 0.f, 0.f);
-            g1 = make_float4(0.f, 0.f, 0.f, -INFINITY);   // inert: alpha = 0
-            gc = make_float4(0.f, 0.f, 0.f, 0.f);
-            if (k < len) {
-                const uint32_t id = a.vals[rg.x + k];
-                g0 = a.geom[2 * (size_t)id];
-                g1 = a.geom[2 * (size_t)id + 1];
-                gc = a.color[id];
+            const float u = rel_coord(g0.x, g0.z, px0), v = rel_coord(g0.y, g0.w, py0);
+            const int k = b0 + lane;
+            const uint32_t mask = k < len ? band_mask(u, v, g1.x, g1.y, g1.z, g1.w) : 0u;
+            const unsigned long long kept = __ballot(mask != 0u);
+            const int nk = __popcll(kept);
+            if (mask != 0u) {
+                const int r = kept_rank(kept);
+                sA[r] = StagedA{u, v, g1.x, g1.y};
+                sB[r] = StagedB{g1.z, g1.w, gc.x, gc.y};
+                sF[r] = StagedF{gc.z, ((uint32_t)k << 4) | mask};
             }
-        }
-        for (int j0 = 0; j0 < kBatch; j0 += kUnroll) {
-            StagedA es[kUnroll];
-            StagedB et[kUnroll];
-            float eb[kUnroll];
-#pragma unroll
-            for (int u = 0; u < kUnroll; u++) {
-                es[u] = sA[j0 + u];
-                et[u] = sB[j0 + u];
-                eb[u] = sCb[j0 + u];
+            // padding up to the unroll width: inert records
+            if (lane >= nk && lane < ((nk + kUnroll - 1) & ~(kUnroll - 1))) {
+                sA[lane] = StagedA{0.f, 0.f, -1.f, 0.f};
+                sB[lane] = StagedB{-1.f, -INFINITY, 0.f, 0.f};
+                sF[lane] = StagedF{0.f, 0u};
             }
+            __syncthreads();
+            gather(b0 + kBatch + lane);
+            for (int j0 = 0; j0 < nk; j0 += kUnroll) {
+                StagedA es[kUnroll];
+                StagedB et[kUnroll];
+                StagedF ef[kUnroll];
 #pragma unroll
-            for (int u = 0; u < kUnroll; u++) {
-                const int j = b0 + j0 + u;
-                const ColTerms ct = col_terms(es[u], fxl);
-                float p2[kPixPerLane];
-                bool cand = false;
-#pragma unroll
-                for (int q = 0; q < kPixPerLane; q++) {
-                    p2[q] = splat_p2(ct, et[u].C2, es[u].v - fy[q]);
-                    cand |= T[q] > 0.f && p2[q] <= 0.f && p2[q] + et[u].lo >= kLog2AlphaMinLoose;
+                for (int u2 = 0; u2 < kUnroll; u2++) {
+                    es[u2] = sA[j0 + u2];
+                    et[u2] = sB[j0 + u2];
+                    ef[u2] = sF[j0 + u2];
                 }
-                if (STATS) {
 #pragma unroll
-                    for (int q = 0; q < kPixPerLane; q++)
-                        if (T[q] > 0.f && j < len) ne[q]++;
-                }
-                // no pixel of the tile can reach 1/255: nothing to do
-                if (!__any(cand)) continue;
+                for (int u2 = 0; u2 < kUnroll; u2++) {
+                    const int j = (int)(ef[u2].pm >> 4);
+                    const ColTerms ct = col_terms(es[u2], fxl);
+                    float p2[kPixPerLane];
+                    bool cand = false;
 #pragma unroll
-                for (int q = 0; q < kPixPerLane; q++) {
-                    const float alpha = fminf(kAlphaMax, splat_alpha_pre(p2[q], et[u].lo));
-                    const float testT = T[q] * (1.f - alpha);
-                    const bool hit = p2[q] <= 0.f && alpha >= kAlphaMin;
-                    const bool blend = hit && testT >= kTMin;
-                    const bool stop = hit && testT < kTMin;
-                    if (STATS && blend) nb[q]++;
-                    const float wgt = blend ? alpha * T[q] : 0.f;
-                    cr[q] = fmaf(et[u].r, wgt, cr[q]);
-                    cg[q] = fmaf(et[u].g, wgt, cg[q]);
-                    cb[q] = fmaf(eb[u], wgt, cb[q]);
-                    last[q] = blend ? j + 1 : last[q];
-                    T[q] = blend ? testT : (stop ? -fabsf(T[q]) : T[q]);
+                    for (int q = 0; q < kPixPerLane; q++) {
+                        p2[q] = splat_p2(ct, et[u2].C2, es[u2].v - fy[q]);
+                        cand |= (T[q] > 0.f) & (p2[q] <= 0.f) & (p2[q] + et[u2].lo >= kLog2AlphaMinLoose);
+                    }
+                    // no pixel of the tile can reach 1/255: nothing to do
+                    if (!__any(cand)) continue;
+#pragma unroll
+                    for (int q = 0; q < kPixPerLane; q++) {
+                        const float alpha = fminf(kAlphaMax, splat_alpha_pre(p2[q], et[u2].lo));
+                        const float testT = T[q] * (1.f - alpha);
+                        const bool hit = p2[q] <= 0.f && alpha >= kAlphaMin;
+                        const bool blend = hit && testT >= kTMin;
+                        const bool stop = hit && testT < kTMin && T[q] > 0.f;
+                        if (STATS) {
+                            nb[q] += blend ? 1u : 0u;
+                            ne[q] = stop ? (uint32_t)j + 1u : ne[q];
+                        }
+                        const float wgt = blend ? alpha * T[q] : 0.f;
+                        cr[q] = fmaf(et[u2].r, wgt, cr[q]);
+                        cg[q] = fmaf(et[u2].g, wgt, cg[q]);
+                        cb[q] = fmaf(ef[u2].b, wgt, cb[q]);
+                        last[q] = blend ? j + 1 : last[q];
+                        T[q] = blend ? testT : (stop ? -T[q] : T[q]);
+                    }
                 }
+                if (!__any(T[0] > 0.f || T[1] > 0.f || T[2] > 0.f || T[3] > 0.f)) break;
             }
-            if (!__any(T[0] > 0.f || T[1] > 0.f || T[2] > 0.f || T[3] > 0.f) ||
-                b0 + j0 + kUnroll >= len)
-                break;
         }
         __syncthreads();
     }
@@ -171,7 +180,8 @@ __global__ __launch_bounds__(kRasterThreads) void k_raster_fwd(FwdArgs a, ViewsK
         a.ncontrib[vw.pix_base + pix] = (uint32_t)last[q];
         if (a.alphas) a.alphas[vw.pix_base + pix] = 1.f - Tf;
         if (STATS) {
-            a.neval[vw.pix_base + pix] = ne[q];
+            // a pixel that never stopped evaluated the whole list
+            a.neval[vw.pix_base + pix] = T[q] < 0.f ? ne[q] : (uint32_t)len;
             a.nblend[vw.pix_base + pix] = nb[q];
         }
     }
