@@ -123,9 +123,9 @@ def main():
 
     def step(s, total):
         rast.forward(g, [cam], s["pose"], check=False, images=images)
-        R.loss_l1(images, target, grad=dl, with_loss=False)
+        R.loss_l1([cam], images, target, grad=dl, with_loss=False)
         rast.backward(g, [cam], s["pose"], dl, want=(), pose=True, out={"pose": s["dpose"]})
-        R.pose_adam(s["pose"], s["dpose"], s["m"], s["v"], s["st"], 1e-2, 1e-4, total)
+        R.pose_adam(s["pose"], s["dpose"], s["m"], s["v"], s["st"], 1e-2, 1e-4, total, guard=rast.ws)
 
     rast._ensure(g, N.view_array([cam]))
     s = new_state()

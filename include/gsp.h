@@ -22,8 +22,11 @@
  *  - Floats are IEEE binary32.  Poses are world->camera [R | t], row-major
  *    3 x 4.  Quaternions are (w, x, y, z) and need not be normalised; the
  *    library normalises them and differentiates through the normalisation.
- *  - Images are CHW binary32 per view, 3 x roi_h x roi_w, and the views of one
- *    call are packed one after another in view order.
+ *  - Images are CHW binary32 per view, 3 x roi_h x roi_w; each view's image
+ *    and image gradient are passed by their own device pointer (host arrays
+ *    of V pointers), so requests of different sizes can share a launch
+ *    without being packed.  Per-pixel workspace arrays (T_final, counts) are
+ *    packed one view after another in view order.
  *  - The pose gradient is the left-perturbation twist: for T(tau) =
  *    Exp(tau) T with tau = (rho, phi) (translation first), d[V][6] holds
  *    dL/dtau at tau = 0.  Under this convention the camera centre moves by
@@ -122,24 +125,28 @@ gsp_status gsp_workspace_size(int64_t n, int32_t sh_degree, int32_t V, const gsp
                               int64_t instance_capacity, size_t *bytes);
 
 /* Forward render (Sec. III-A): projection and EWA covariance (Eq. (1)-(2)),
- * SH colour, tile binning, 64-bit (tile | depth) radix sort, per-tile ranges
- * and front-to-back compositing (Eq. (3)-(4)).
+ * SH colour, tile binning, the (tile, depth, index) order of the instances
+ * (the order a stable sort on the 64-bit key tile << 32 | depth bits gives),
+ * per-tile ranges and front-to-back compositing (Eq. (3)-(4)).
  *   g          Gaussians (device arrays)
  *   V, views   1..GSP_MAX_VIEWS host view descriptors
  *   poses      device [V][3][4] world->camera
- *   images     device output, packed [V][3][roi_h][roi_w]
- *   alphas     device output or NULL, packed [V][roi_h][roi_w] = 1 - T_final
+ *   images     host array of V device pointers; images[v] receives view v,
+ *              3 x roi_h x roi_w
+ *   alphas     NULL, or a host array of V device pointers (entries may be
+ *              NULL); alphas[v] receives 1 - T_final, roi_h x roi_w
  *   workspace  device, ws_bytes >= gsp_workspace_size(..., instance_capacity)
  * When the number of instances M exceeds instance_capacity the excess work is
  * skipped on the device and the outputs are undefined; gsp_instances then
  * reports the overflow and the M needed.  Returns GSP_OK once enqueued. */
 gsp_status gsp_render_fwd(gsp_ctx *ctx, const gsp_gaussians *g, int32_t V, const gsp_view *views,
-                          const float *poses, float *images, float *alphas,
+                          const float *poses, float *const *images, float *const *alphas,
                           void *workspace, size_t ws_bytes, int64_t instance_capacity,
                           void *stream);
 
 /* Backward of the last gsp_render_fwd made with this workspace and the same
- * g, views, poses and capacity.  dl_dimages: device, packed like images.
+ * g, views, poses and capacity.  dl_dimages: host array of V device pointers,
+ * dl_dimages[v] laid out like images[v].
  * The per-pixel lists are recomputed back to front from T_final and the
  * contributor count instead of being stored; gradients of the 2D splats are
  * reduced per (tile, Gaussian) and then per Gaussian in a fixed order, and
@@ -147,34 +154,45 @@ gsp_status gsp_render_fwd(gsp_ctx *ctx, const gsp_gaussians *g, int32_t V, const
  * shuffles and block reductions in a fixed order, so results are
  * bit-reproducible run to run. */
 gsp_status gsp_render_bwd(gsp_ctx *ctx, const gsp_gaussians *g, int32_t V, const gsp_view *views,
-                          const float *poses, const float *dl_dimages,
+                          const float *poses, const float *const *dl_dimages,
                           void *workspace, size_t ws_bytes, int64_t instance_capacity,
                           const gsp_grads *grads, uint32_t flags, void *stream);
 
 /* Synchronises `stream` and reports the instance count M of the last forward
  * in `workspace`, and whether that forward or any earlier one on the same
  * workspace (since the caller zero-filled it) exceeded its capacity.  The
- * workspace keeps these counters in its first 64 bytes. */
+ * workspace keeps these counters in its first 64 bytes, as uint32: [0], [1]
+ * the low and high words of M, [2] nonzero when the last forward overflowed,
+ * [4] nonzero when any forward did; a caller may copy them asynchronously
+ * instead of calling this function. */
 gsp_status gsp_instances(gsp_ctx *ctx, const void *workspace, void *stream,
                          int64_t *m_out, int32_t *overflow_out);
 
-/* Mean absolute error (the L1 part of Eq. (16)): loss = mean |pred - target|
- * over count values, grad = sign(pred - target) / count (0 where equal).
- * pred, target, grad: device [count].  loss: device float or NULL; when it
- * is given, scratch must be device memory of gsp_loss_l1_scratch_bytes(count)
- * bytes, and the loss is reduced in a fixed order (bit-reproducible). */
-gsp_status gsp_loss_l1(gsp_ctx *ctx, int64_t count, const float *pred, const float *target,
-                       float *grad, float *loss, void *scratch, void *stream);
-size_t gsp_loss_l1_scratch_bytes(int64_t count);
+/* Mean absolute error (the L1 part of Eq. (16)) of each view:
+ * loss[v] = mean |pred[v] - target[v]| over its 3 x roi_h x roi_w values,
+ * grad[v] = sign(pred[v] - target[v]) / (3 roi_h roi_w) (0 where equal), so
+ * that a view's loss and gradient do not depend on the other views of the
+ * call.  pred, target, grad: host arrays of V device pointers.  loss: device
+ * float [V] or NULL; when it is given, scratch must be device memory of
+ * gsp_loss_l1_scratch_bytes(V, views) bytes, and each loss is reduced in a
+ * fixed order (bit-reproducible). */
+gsp_status gsp_loss_l1(gsp_ctx *ctx, int32_t V, const gsp_view *views, const float *const *pred,
+                       const float *const *target, float *const *grad, float *loss,
+                       void *scratch, void *stream);
+size_t gsp_loss_l1_scratch_bytes(int32_t V, const gsp_view *views);
 
 /* One tangent-space Adam step per view (Sec. III-B: pose T = Exp(tau) with
  * the update retracted on the left): for each v, steps[v] += 1,
  * m, v moments updated with dpose[v], delta = -lr mhat / (sqrt(vhat) + eps),
  * poses[v] <- Exp(delta) poses[v].  poses [V][12], dpose/m/v [V][6],
- * steps [V] int32: device.  V >= 1, no upper limit. */
+ * steps [V] int32: device.  V >= 1, no upper limit.  guard_workspace: NULL,
+ * or the workspace of the render that produced dpose; when that render
+ * overflowed its instance capacity the step is skipped on the device (poses,
+ * moments and steps unchanged), so that a caller who learns of the overflow
+ * later can repeat the iteration. */
 gsp_status gsp_pose_adam(gsp_ctx *ctx, int32_t V, float *poses, const float *dpose,
                          float *m, float *v, int32_t *steps, const gsp_adam_params *params,
-                         void *stream);
+                         const void *guard_workspace, void *stream);
 
 /* Workspace introspection for tests: device pointer and element count of an
  * intermediate array of the last forward/backward.  Names: "geom" (float4
@@ -182,7 +200,10 @@ gsp_status gsp_pose_adam(gsp_ctx *ctx, int32_t V, float *poses, const float *dpo
  * the conic [[A, B], [B, C]] stored as (A2, B2, C2) = -log2(e) (A/2, B, C/2)),
  * "color" (float4),
  * "rect" (uint16 x0 y0 x1 y1), "depth" (uint32 float bits), "tiles"
- * (uint32 count), "keys" (uint64 sorted), "values" (uint32 sorted),
+ * (uint32 count), "offsets" (uint32 first instance of each view-Gaussian),
+ * "keys" (uint32 global tile id of each sorted instance; the depth part of
+ * the 64-bit key is "depth" of its value), "values" (uint32 sorted),
+ * "depth_order" (uint32 view-Gaussians in (depth, index) order),
  * "ranges" (uint32 pairs per tile), "tfinal" (float per pixel),
  * "ncontrib" (uint32 per pixel), "neval", "nblend" (uint32 per pixel, see
  * GSP_PROFILE_COUNTS), "grad2d" (float [9][V*n]: du dv dA dB dC

@@ -79,9 +79,9 @@ def lib():
         "gsp_render_fwd": ([P, P, I32, P, P, P, P, P, SZ, I64, P], I32),
         "gsp_render_bwd": ([P, P, I32, P, P, P, P, SZ, I64, P, ctypes.c_uint32, P], I32),
         "gsp_instances": ([P, P, P, ctypes.POINTER(I64), ctypes.POINTER(I32)], I32),
-        "gsp_loss_l1": ([P, I64, P, P, P, P, P, P], I32),
-        "gsp_loss_l1_scratch_bytes": ([I64], SZ),
-        "gsp_pose_adam": ([P, I32, P, P, P, P, P, P, P], I32),
+        "gsp_loss_l1": ([P, I32, P, P, P, P, P, P, P], I32),
+        "gsp_loss_l1_scratch_bytes": ([I32, P], SZ),
+        "gsp_pose_adam": ([P, I32, P, P, P, P, P, P, P, P], I32),
         "gsp_inspect": ([P, P, I32, P, P, SZ, I64, ctypes.c_char_p, ctypes.POINTER(P),
                          ctypes.POINTER(I64)], I32),
         "gsp_profile_enable": ([P, ctypes.c_int], I32),
@@ -111,6 +111,11 @@ def make_view(cam):
     return View(int(cam.width), int(cam.height), float(cam.fx), float(cam.fy), float(cam.cx),
                 float(cam.cy), int(roi[0]), int(roi[1]), int(roi[2]), int(roi[3]),
                 (ctypes.c_float * 3)(*[float(b) for b in bg]))
+
+
+def ptr_array(ptrs):
+    """Host array of device pointers (None for NULL entries)."""
+    return (ctypes.c_void_p * len(ptrs))(*[p if p else None for p in ptrs])
 
 
 def view_array(cams):

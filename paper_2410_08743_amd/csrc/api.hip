@@ -358,14 +358,20 @@ gsp_status gsp_workspace_size(int64_t n, int32_t sh_degree, int32_t V, const gsp
 }
 
 gsp_status gsp_render_fwd(gsp_ctx *ctx, const gsp_gaussians *g, int32_t V, const gsp_view *views,
-                          const float *poses, float *images, float *alphas, void *workspace,
-                          size_t ws_bytes, int64_t instance_capacity, void *stream) {
+                          const float *poses, float *const *images, float *const *alphas,
+                          void *workspace, size_t ws_bytes, int64_t instance_capacity,
+                          void *stream) {
     gsp_status s = check_device(ctx);
     if (s != GSP_OK) return s;
     Prepared p;
     s = prepare(g, V, views, instance_capacity, &p);
     if (s != GSP_OK) return s;
     if (!poses || !images || !workspace) return fail(GSP_EINVAL, "null poses, images or workspace");
+    for (int v = 0; v < V; v++) {
+        if (!images[v]) return fail(GSP_EINVAL, "null image pointer of view %d", v);
+        p.views.v[v].img = images[v];
+        p.views.v[v].alpha = alphas ? alphas[v] : nullptr;
+    }
     if (ws_bytes < p.L.total)
         return fail(GSP_ENOMEM, "workspace of %zu bytes is smaller than the %zu needed", ws_bytes,
                     p.L.total);
@@ -393,14 +399,14 @@ gsp_status gsp_render_fwd(gsp_ctx *ctx, const gsp_gaussians *g, int32_t V, const
         hipSuccess)
         return hip_fail(e, "ranges");
     if ((e = stage(ctx, "raster_fwd", st, [&] {
-             return gsp::launch_raster_fwd(p.views, p.L, ws, vals, images, alphas, ctx->stats, st);
+             return gsp::launch_raster_fwd(p.views, p.L, ws, vals, ctx->stats, st);
          })) != hipSuccess)
         return hip_fail(e, "raster forward");
     return GSP_OK;
 }
 
 gsp_status gsp_render_bwd(gsp_ctx *ctx, const gsp_gaussians *g, int32_t V, const gsp_view *views,
-                          const float *poses, const float *dl_dimages, void *workspace,
+                          const float *poses, const float *const *dl_dimages, void *workspace,
                           size_t ws_bytes, int64_t instance_capacity, const gsp_grads *grads,
                           uint32_t flags, void *stream) {
     gsp_status s = check_device(ctx);
@@ -410,6 +416,10 @@ gsp_status gsp_render_bwd(gsp_ctx *ctx, const gsp_gaussians *g, int32_t V, const
     if (s != GSP_OK) return s;
     if (!poses || !dl_dimages || !workspace || !grads)
         return fail(GSP_EINVAL, "null poses, dl_dimages, workspace or grads");
+    for (int v = 0; v < V; v++) {
+        if (!dl_dimages[v]) return fail(GSP_EINVAL, "null dl_dimages pointer of view %d", v);
+        p.views.v[v].dl = dl_dimages[v];
+    }
     if (flags & ~GSP_ACCUMULATE) return fail(GSP_EINVAL, "unknown flags 0x%x", flags);
     if (ws_bytes < p.L.total)
         return fail(GSP_ENOMEM, "workspace of %zu bytes is smaller than the %zu needed", ws_bytes,
@@ -419,7 +429,7 @@ gsp_status gsp_render_bwd(gsp_ctx *ctx, const gsp_gaussians *g, int32_t V, const
     const uint32_t *vals = gsp::region<uint32_t>(ws, gsp::sorted_vals(p.L));
     hipError_t e;
     if ((e = stage(ctx, "raster_bwd", st, [&] {
-             return gsp::launch_raster_bwd(p.views, p.L, ws, vals, dl_dimages, st);
+             return gsp::launch_raster_bwd(p.views, p.L, ws, vals, st);
          })) != hipSuccess)
         return hip_fail(e, "raster backward");
     if ((e = stage(ctx, "preprocess_bwd", st, [&] {
@@ -486,27 +496,46 @@ gsp_status gsp_inspect(gsp_ctx *ctx, const gsp_gaussians *g, int32_t V, const gs
     return fail(GSP_EINVAL, "unknown workspace array \"%s\"", name);
 }
 
-gsp_status gsp_loss_l1(gsp_ctx *ctx, int64_t count, const float *pred, const float *target,
-                       float *grad, float *loss, void *scratch, void *stream) {
+gsp_status gsp_loss_l1(gsp_ctx *ctx, int32_t V, const gsp_view *views, const float *const *pred,
+                       const float *const *target, float *const *grad, float *loss,
+                       void *scratch, void *stream) {
     gsp_status s = check_device(ctx);
     if (s != GSP_OK) return s;
-    if (count < 0) return fail(GSP_EINVAL, "negative count");
-    if (count > 0 && (!pred || !target || !grad)) return fail(GSP_EINVAL, "null array");
+    gsp::ViewsK vk;
+    int64_t total_pix = 0;
+    s = make_views(V, views, &vk, &total_pix);
+    if (s != GSP_OK) return s;
+    if (!pred || !target || !grad) return fail(GSP_EINVAL, "null pointer array");
     if (loss && !scratch) return fail(GSP_EINVAL, "loss requires scratch memory");
+    gsp::LossViewsK lv;
+    std::memset(&lv, 0, sizeof lv);
+    lv.V = V;
+    lv.blk_base[0] = 0;
+    for (int v = 0; v < V; v++) {
+        if (!pred[v] || !target[v] || !grad[v])
+            return fail(GSP_EINVAL, "null pred, target or grad of view %d", v);
+        lv.pred[v] = pred[v];
+        lv.target[v] = target[v];
+        lv.grad[v] = grad[v];
+        lv.count[v] = 3 * (int64_t)views[v].roi_w * views[v].roi_h;
+        lv.blk_base[v + 1] = lv.blk_base[v] + gsp::loss_blocks(lv.count[v]);
+    }
     hipStream_t st = static_cast<hipStream_t>(stream);
-    hipError_t e = stage(ctx, "loss_l1", st, [&] {
-        return gsp::launch_loss_l1(count, pred, target, grad, loss, scratch, st);
-    });
+    hipError_t e = stage(ctx, "loss_l1", st, [&] { return gsp::launch_loss_l1(lv, loss, scratch, st); });
     if (e != hipSuccess) return hip_fail(e, "loss");
     return GSP_OK;
 }
 
-size_t gsp_loss_l1_scratch_bytes(int64_t count) {
-    return (size_t)(count > 0 ? gsp::loss_blocks(count) : 1) * sizeof(double);
+size_t gsp_loss_l1_scratch_bytes(int32_t V, const gsp_view *views) {
+    int64_t blocks = 0;
+    for (int v = 0; views && v < V; v++)
+        blocks += gsp::loss_blocks(3 * (int64_t)views[v].roi_w * views[v].roi_h);
+    return (size_t)(blocks > 0 ? blocks : 1) * sizeof(double);
 }
 
 gsp_status gsp_pose_adam(gsp_ctx *ctx, int32_t V, float *poses, const float *dpose, float *m,
-                         float *v, int32_t *steps, const gsp_adam_params *params, void *stream) {
+                         float *v, int32_t *steps, const gsp_adam_params *params,
+                         const void *guard_workspace, void *stream) {
     gsp_status s = check_device(ctx);
     if (s != GSP_OK) return s;
     if (V < 1) return fail(GSP_EINVAL, "view count must be positive");
@@ -516,7 +545,8 @@ gsp_status gsp_pose_adam(gsp_ctx *ctx, int32_t V, float *poses, const float *dpo
         return fail(GSP_EINVAL, "bad Adam hyper-parameters");
     hipStream_t st = static_cast<hipStream_t>(stream);
     hipError_t e = stage(ctx, "pose_adam", st, [&] {
-        return gsp::launch_pose_adam(V, poses, dpose, m, v, steps, *params, st);
+        return gsp::launch_pose_adam(V, poses, dpose, m, v, steps, *params,
+                                     static_cast<const uint32_t *>(guard_workspace), st);
     });
     if (e != hipSuccess) return hip_fail(e, "pose adam");
     return GSP_OK;

@@ -55,6 +55,9 @@ struct ViewK {
     int tile_base;       // first global tile id of this view
     int pix_base;        // first pixel of this view in packed per-pixel arrays
     float bg[3];
+    float *img;          // forward: the view's image, 3 x roi_h x roi_w
+    float *alpha;        // forward: 1 - T_final per pixel, or null
+    const float *dl;     // backward: dL/dimage, laid out like img
 };
 
 struct ViewsK {
@@ -103,22 +106,29 @@ hipError_t launch_tile_sort(const Layout &L, char *ws, hipStream_t s);
 // raster_fwd.hip
 hipError_t launch_ranges(const Layout &L, char *ws, const uint32_t *keys, hipStream_t s);
 hipError_t launch_raster_fwd(const ViewsK &views, const Layout &L, char *ws,
-                             const uint32_t *vals, float *images, float *alphas, bool stats,
-                             hipStream_t s);
+                             const uint32_t *vals, bool stats, hipStream_t s);
 // raster_bwd.hip
 hipError_t launch_raster_bwd(const ViewsK &views, const Layout &L, char *ws,
-                             const uint32_t *vals, const float *dl_dimages, hipStream_t s);
+                             const uint32_t *vals, hipStream_t s);
 // preprocess_bwd.hip
 hipError_t launch_preprocess_bwd(const GaussiansK &g, const ViewsK &views, const float *poses,
                                  const Layout &L, char *ws, const gsp_grads &grads,
                                  bool accumulate, hipStream_t s);
 // misc.hip
 hipError_t launch_fill_u32(uint32_t *p, uint32_t value, int64_t count, hipStream_t s);
-hipError_t launch_loss_l1(int64_t count, const float *pred, const float *target, float *grad,
-                          float *loss, void *scratch, hipStream_t s);
+struct LossViewsK {
+    const float *pred[GSP_MAX_VIEWS];
+    const float *target[GSP_MAX_VIEWS];
+    float *grad[GSP_MAX_VIEWS];
+    int64_t count[GSP_MAX_VIEWS];
+    int64_t blk_base[GSP_MAX_VIEWS + 1];   // first loss block of each view
+    int V;
+};
 int64_t loss_blocks(int64_t count);
+hipError_t launch_loss_l1(const LossViewsK &lv, float *loss, void *scratch, hipStream_t s);
 hipError_t launch_pose_adam(int V, float *poses, const float *dpose, float *m, float *v,
-                            int32_t *steps, const gsp_adam_params &p, hipStream_t s);
+                            int32_t *steps, const gsp_adam_params &p, const uint32_t *guard,
+                            hipStream_t s);
 
 template <typename T>
 inline T *region(char *ws, size_t off) { return reinterpret_cast<T *>(ws + off); }

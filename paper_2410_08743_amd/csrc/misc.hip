@@ -23,11 +23,18 @@ constexpr int kLossItems = 4096;   // elements per loss block
 
 int64_t loss_blocks(int64_t count) { return (count + kLossItems - 1) / kLossItems; }
 
-__global__ __launch_bounds__(256) void k_l1(int64_t count, const float *pred, const float *target,
-                                            float *grad, double *partial) {
+// One launch over the views of a call: block b belongs to the view whose block
+// range holds it; each view's gradient is normalised by its own value count,
+// so a view's loss and gradient do not depend on the other views.
+__global__ __launch_bounds__(256) void k_l1(LossViewsK lv, double *partial) {
     __shared__ double red[256 / kWave];
+    int v = 0;
+    while (v + 1 < lv.V && (int64_t)blockIdx.x >= lv.blk_base[v + 1]) v++;
+    const int64_t count = lv.count[v];
+    const float *pred = lv.pred[v], *target = lv.target[v];
+    float *grad = lv.grad[v];
     const float inv = 1.0f / (float)count;
-    const int64_t base = (int64_t)blockIdx.x * kLossItems;
+    const int64_t base = ((int64_t)blockIdx.x - lv.blk_base[v]) * kLossItems;
     double s = 0;
 #pragma unroll 4
     for (int r = 0; r < kLossItems / 256; r++) {
@@ -44,24 +51,25 @@ __global__ __launch_bounds__(256) void k_l1(int64_t count, const float *pred, co
     }
 }
 
-__global__ __launch_bounds__(256) void k_l1_final(const double *partial, int64_t nblk, int64_t count,
+// One block per view: the view's partial sums in block order.
+__global__ __launch_bounds__(256) void k_l1_final(LossViewsK lv, const double *partial,
                                                   float *loss) {
     __shared__ double red[256 / kWave];
+    const int v = blockIdx.x;
     double s = 0;
-    for (int64_t b = threadIdx.x; b < nblk; b += 256) s += partial[b];
+    for (int64_t b = lv.blk_base[v] + threadIdx.x; b < lv.blk_base[v + 1]; b += 256) s += partial[b];
     s = block_sum<double, 256>(s, red);
-    if (threadIdx.x == 0) loss[0] = (float)(s / (double)count);
+    if (threadIdx.x == 0) loss[v] = (float)(s / (double)lv.count[v]);
 }
 
-hipError_t launch_loss_l1(int64_t count, const float *pred, const float *target, float *grad,
-                          float *loss, void *scratch, hipStream_t s) {
-    if (count <= 0) return hipSuccess;
-    const int64_t nblk = loss_blocks(count);
+hipError_t launch_loss_l1(const LossViewsK &lv, float *loss, void *scratch, hipStream_t s) {
+    const int64_t nblk = lv.blk_base[lv.V];
+    if (nblk <= 0) return hipSuccess;
     double *partial = loss ? static_cast<double *>(scratch) : nullptr;
-    hipLaunchKernelGGL(k_l1, dim3((unsigned)nblk), dim3(256), 0, s, count, pred, target, grad, partial);
+    hipLaunchKernelGGL(k_l1, dim3((unsigned)nblk), dim3(256), 0, s, lv, partial);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess || !loss) return e;
-    hipLaunchKernelGGL(k_l1_final, dim3(1), dim3(256), 0, s, partial, nblk, count, loss);
+    hipLaunchKernelGGL(k_l1_final, dim3(lv.V), dim3(256), 0, s, lv, partial, loss);
     return hipGetLastError();
 }
 
@@ -107,10 +115,15 @@ __device__ void se3_retract_left(const double d[6], float *T) {
     for (int k = 0; k < 12; k++) T[k] = (float)out[k];
 }
 
+// guard: the counters of the workspace whose render produced dpose, or null;
+// when that render overflowed its instance capacity the step is skipped
+// (poses, moments and step counts unchanged).
 __global__ __launch_bounds__(64) void k_pose_adam(int V, float *poses, const float *dpose, float *m,
-                                                  float *v, int32_t *steps, gsp_adam_params p) {
+                                                  float *v, int32_t *steps, gsp_adam_params p,
+                                                  const uint32_t *guard) {
     const int i = blockIdx.x * 64 + threadIdx.x;
     if (i >= V) return;
+    if (guard && guard[kCntOverflow] != 0u) return;
     const int k = steps[i] + 1;
     steps[i] = k;
     double lr = p.lr_start;
@@ -133,9 +146,11 @@ __global__ __launch_bounds__(64) void k_pose_adam(int V, float *poses, const flo
 }
 
 hipError_t launch_pose_adam(int V, float *poses, const float *dpose, float *m, float *v,
-                            int32_t *steps, const gsp_adam_params &p, hipStream_t s) {
+                            int32_t *steps, const gsp_adam_params &p, const uint32_t *guard,
+                            hipStream_t s) {
     if (V <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_pose_adam, dim3((V + 63) / 64), dim3(64), 0, s, V, poses, dpose, m, v, steps, p);
+    hipLaunchKernelGGL(k_pose_adam, dim3((V + 63) / 64), dim3(64), 0, s, V, poses, dpose, m, v, steps, p,
+                       guard);
     return hipGetLastError();
 }
 

@@ -33,7 +33,6 @@ struct BwdArgs {
     const float4 *color;
     const uint2 *rect;
     const uint32_t *offsets;
-    const float *dl;
     const float *tfinal;
     const uint32_t *ncontrib;
     float *slots;          // [cap][9]
@@ -89,7 +88,7 @@ __global__ __launch_bounds__(kRasterThreads) __attribute__((amdgpu_waves_per_eu(
         fy[q] = (float)(ly + 4 * q);
         T[q] = in ? a.tfinal[vw.pix_base + pix] : 1.f;
         last[q] = in ? (int)a.ncontrib[vw.pix_base + pix] : 0;
-        const float *dl = a.dl + 3 * (size_t)vw.pix_base;
+        const float *dl = vw.dl;
         G[q][0] = in ? dl[pix] : 0.f;
         G[q][1] = in ? dl[(size_t)P + pix] : 0.f;
         G[q][2] = in ? dl[2 * (size_t)P + pix] : 0.f;
@@ -227,7 +226,7 @@ __global__ __launch_bounds__(kRasterThreads) __attribute__((amdgpu_waves_per_eu(
 }
 
 hipError_t launch_raster_bwd(const ViewsK &views, const Layout &L, char *ws, const uint32_t *vals,
-                             const float *dl_dimages, hipStream_t s) {
+                             hipStream_t s) {
     if (L.total_tiles == 0) return hipSuccess;
     BwdArgs a;
     a.ranges = region<uint2>(ws, L.ranges);
@@ -236,7 +235,6 @@ hipError_t launch_raster_bwd(const ViewsK &views, const Layout &L, char *ws, con
     a.color = region<float4>(ws, L.color);
     a.rect = region<uint2>(ws, L.rect);
     a.offsets = region<uint32_t>(ws, L.offsets);
-    a.dl = dl_dimages;
     a.tfinal = region<float>(ws, L.tfinal);
     a.ncontrib = region<uint32_t>(ws, L.ncontrib);
     a.slots = region<float>(ws, L.slots);

@@ -34,8 +34,6 @@ struct FwdArgs {
     const uint32_t *vals;
     const float4 *geom;
     const float4 *color;
-    float *images;
-    float *alphas;
     float *tfinal;
     uint32_t *ncontrib;
     uint32_t *neval;    // STATS only: entries evaluated per pixel (up to the stop)
@@ -172,13 +170,13 @@ __global__ __launch_bounds__(kRasterThreads) __attribute__((amdgpu_waves_per_eu(
         if (rx >= vw.roi_w || ry >= vw.roi_h) continue;
         const size_t pix = (size_t)ry * vw.roi_w + rx;
         const float Tf = fabsf(T[q]);
-        float *img = a.images + 3 * (size_t)vw.pix_base;
+        float *img = vw.img;
         img[pix] = cr[q] + Tf * vw.bg[0];
         img[(size_t)P + pix] = cg[q] + Tf * vw.bg[1];
         img[2 * (size_t)P + pix] = cb[q] + Tf * vw.bg[2];
         a.tfinal[vw.pix_base + pix] = Tf;
         a.ncontrib[vw.pix_base + pix] = (uint32_t)last[q];
-        if (a.alphas) a.alphas[vw.pix_base + pix] = 1.f - Tf;
+        if (vw.alpha) vw.alpha[pix] = 1.f - Tf;
         if (STATS) {
             // a pixel that never stopped evaluated the whole list
             a.neval[vw.pix_base + pix] = T[q] < 0.f ? ne[q] : (uint32_t)len;
@@ -199,15 +197,13 @@ hipError_t launch_ranges(const Layout &L, char *ws, const uint32_t *keys, hipStr
 }
 
 hipError_t launch_raster_fwd(const ViewsK &views, const Layout &L, char *ws, const uint32_t *vals,
-                             float *images, float *alphas, bool stats, hipStream_t s) {
+                             bool stats, hipStream_t s) {
     if (L.total_tiles == 0) return hipSuccess;
     FwdArgs a;
     a.ranges = region<uint2>(ws, L.ranges);
     a.vals = vals;
     a.geom = region<float4>(ws, L.geom);
     a.color = region<float4>(ws, L.color);
-    a.images = images;
-    a.alphas = alphas;
     a.tfinal = region<float>(ws, L.tfinal);
     a.ncontrib = region<uint32_t>(ws, L.ncontrib);
     a.neval = region<uint32_t>(ws, L.stats);

@@ -91,6 +91,34 @@ def pack_images(images):
     return torch.cat([im.reshape(-1) for im in images]).contiguous()
 
 
+def view_ptrs(buf, cams, channels):
+    """Device pointers of each view's `channels` x h x w block: `buf` is either
+    one packed tensor (views one after another) or a list of per-view
+    tensors."""
+    if buf is None:
+        return None
+    if isinstance(buf, (list, tuple)):
+        if len(buf) != len(cams):
+            raise ValueError("one tensor per view expected")
+        out = []
+        for t, c in zip(buf, cams):
+            _, _, w, h = region(c)
+            if t.dtype != torch.float32 or not t.is_contiguous() or t.numel() != channels * w * h:
+                raise ValueError(f"per-view tensor must be contiguous float32 with {channels}*h*w values")
+            out.append(t.data_ptr())
+        return N.ptr_array(out)
+    if buf.dtype != torch.float32 or not buf.is_contiguous():
+        raise ValueError("packed buffer must be contiguous float32")
+    counts = [channels * n for n in pixel_counts(cams)]
+    if buf.numel() < sum(counts):
+        raise ValueError("packed buffer too small for the views")
+    out, off = [], 0
+    for n in counts:
+        out.append(buf.data_ptr() + 4 * off)
+        off += n
+    return N.ptr_array(out)
+
+
 class Rasterizer:
     """Owns the device workspace of a sequence of renders.
 
@@ -140,8 +168,10 @@ class Rasterizer:
 
     # -- forward / backward ------------------------------------------------
     def forward(self, g: GaussianParams, cams: Sequence, poses: torch.Tensor,
-                alphas: bool = False, check: bool = True, images: Optional[torch.Tensor] = None):
-        """Renders len(cams) views; returns (packed images, packed alphas or None)."""
+                alphas: bool = False, check: bool = True, images=None):
+        """Renders len(cams) views; returns (images, packed alphas or None).
+        `images` is an optional output: one packed tensor or a list of
+        per-view [3, h, w] tensors; by default a packed tensor is made."""
         L = N.lib()
         views = N.view_array(cams)
         poses = poses.contiguous()
@@ -155,10 +185,12 @@ class Rasterizer:
         if self.capacity <= 0:
             self.capacity = max(1024, 8 * g.n * len(cams))
         gs = g.struct()
+        img_ptrs = view_ptrs(images, cams, 3)
+        al_ptrs = view_ptrs(al, cams, 1)
         for _ in range(8):
             nbytes = self._ensure(g, views)
             N.check(L.gsp_render_fwd(context(self.device), ctypes.byref(gs), len(cams), views,
-                                     _ptr(poses), _ptr(images), _ptr(al), _ptr(self.ws), nbytes,
+                                     _ptr(poses), img_ptrs, al_ptrs, _ptr(self.ws), nbytes,
                                      self.capacity, _stream()), "gsp_render_fwd")
             if not check:
                 break
@@ -171,10 +203,11 @@ class Rasterizer:
         return images, al
 
     def backward(self, g: GaussianParams, cams: Sequence, poses: torch.Tensor,
-                 dl_dimages: torch.Tensor, want=("means", "scales", "quats", "opacities", "sh"),
+                 dl_dimages, want=("means", "scales", "quats", "opacities", "sh"),
                  pose: bool = True, accumulate: bool = False, out=None):
-        """Gradients of the last forward.  Returns a dict with the requested
-        Gaussian gradients and 'pose' ([V, 6], left twist (rho, phi))."""
+        """Gradients of the last forward.  `dl_dimages` is packed like the
+        images or a list of per-view tensors.  Returns a dict with the
+        requested Gaussian gradients and 'pose' ([V, 6], left twist (rho, phi))."""
         L = N.lib()
         views = N.view_array(cams)
         dev = f"cuda:{self.device}"
@@ -191,7 +224,7 @@ class Rasterizer:
         gs = g.struct()
         nbytes = self._ws_bytes(g.n, g.sh_degree, views, self.capacity)
         N.check(L.gsp_render_bwd(context(self.device), ctypes.byref(gs), len(cams), views,
-                                 _ptr(poses.contiguous()), _ptr(dl_dimages.contiguous()),
+                                 _ptr(poses.contiguous()), view_ptrs(dl_dimages, cams, 3),
                                  _ptr(self.ws), nbytes, self.capacity, ctypes.byref(gr),
                                  N.GSP_ACCUMULATE if accumulate else 0, _stream()),
                 "gsp_render_bwd")
@@ -211,38 +244,42 @@ class Rasterizer:
         itemsize = torch.empty((), dtype=dtype).element_size()
         base = self.ws.data_ptr()
         off = p.value - base
-        elem_bytes = {"geom": 16, "color": 16, "rect": 8, "keys": 8, "ranges": 8}.get(name, 4)
+        elem_bytes = {"geom": 16, "color": 16, "rect": 8, "ranges": 8}.get(name, 4)
         nbytes_arr = cnt.value * elem_bytes
         raw = self.ws[off:off + nbytes_arr]
         return raw.view(dtype).clone() if nbytes_arr % itemsize == 0 else raw.clone()
 
 
-def loss_l1(pred: torch.Tensor, target: torch.Tensor, grad: Optional[torch.Tensor] = None,
-            with_loss: bool = True):
-    """(loss tensor [1] or None, grad): mean |pred - target| and its gradient."""
+def loss_l1(cams: Sequence, pred, target, grad=None, with_loss: bool = True):
+    """(per-view losses [V] or None, grad): mean |pred - target| of each view
+    and its gradient.  pred, target and grad are packed tensors (views one
+    after another) or lists of per-view tensors."""
     L = N.lib()
-    pred = pred.contiguous()
-    target = target.contiguous()
+    views = N.view_array(cams)
     if grad is None:
-        grad = torch.empty_like(pred)
+        grad = ([torch.empty_like(p) for p in pred] if isinstance(pred, (list, tuple))
+                else torch.empty_like(pred))
+    dev = (pred[0] if isinstance(pred, (list, tuple)) else pred).device
     loss = scratch = None
     if with_loss:
-        loss = torch.empty(1, dtype=torch.float32, device=pred.device)
-        scratch = torch.empty(L.gsp_loss_l1_scratch_bytes(pred.numel()), dtype=torch.uint8,
-                              device=pred.device)
-    N.check(L.gsp_loss_l1(context(pred.device.index), pred.numel(), _ptr(pred), _ptr(target),
-                          _ptr(grad), _ptr(loss), _ptr(scratch), _stream()), "gsp_loss_l1")
+        loss = torch.empty(len(cams), dtype=torch.float32, device=dev)
+        scratch = torch.empty(L.gsp_loss_l1_scratch_bytes(len(cams), views), dtype=torch.uint8,
+                              device=dev)
+    N.check(L.gsp_loss_l1(context(dev.index), len(cams), views, view_ptrs(pred, cams, 3),
+                          view_ptrs(target, cams, 3), view_ptrs(grad, cams, 3), _ptr(loss),
+                          _ptr(scratch), _stream()), "gsp_loss_l1")
     return loss, grad
 
 
 def pose_adam(poses, dpose, m, v, steps, lr_start, lr_end, total_steps, beta1=0.9, beta2=0.999,
-              eps=1e-8):
-    """In-place tangent Adam step with left retraction on every pose."""
+              eps=1e-8, guard: Optional[torch.Tensor] = None):
+    """In-place tangent Adam step with left retraction on every pose; with a
+    `guard` workspace whose last render overflowed, the step is skipped."""
     L = N.lib()
     prm = N.AdamParams(lr_start, lr_end, int(total_steps), beta1, beta2, eps)
     N.check(L.gsp_pose_adam(context(poses.device.index), poses.shape[0], _ptr(poses), _ptr(dpose),
-                            _ptr(m), _ptr(v), _ptr(steps), ctypes.byref(prm), _stream()),
-            "gsp_pose_adam")
+                            _ptr(m), _ptr(v), _ptr(steps), ctypes.byref(prm), _ptr(guard),
+                            _stream()), "gsp_pose_adam")
 
 
 class _RenderFn(torch.autograd.Function):
@@ -313,9 +350,10 @@ def solve_poses(g: GaussianParams, cams: Sequence, targets: torch.Tensor, init_p
         hist = []
         for k in range(steps):
             rast.forward(g, cams, poses, check=False, images=images)
-            loss, _ = loss_l1(images, targets, grad=dl, with_loss=history)
+            loss, _ = loss_l1(cams, images, targets, grad=dl, with_loss=history)
             rast.backward(g, cams, poses, dl, want=(), pose=True, out={"pose": dpose})
-            pose_adam(poses, dpose, m, v, st, lr[0], lr[1], steps, betas[0], betas[1], eps)
+            pose_adam(poses, dpose, m, v, st, lr[0], lr[1], steps, betas[0], betas[1], eps,
+                      guard=rast.ws)
             if history:
                 hist.append(loss)
         if not rast.overflowed():

@@ -224,6 +224,36 @@ def joint(seed=1003, n=1_000_000, n_views=20):
     return wl
 
 
+REQUEST_SIZES = ((320, 240), (640, 480), (1008, 756))
+
+
+def serving_requests(seed=1005, n_requests=64, sizes=REQUEST_SIZES, radius=4.75,
+                     half_angle_deg=10.0):
+    """Pose-estimation requests against the joint scene (served resident):
+    image size uniform over `sizes`, same field of view as the 1008x756
+    camera (fx = fy = 815 W / 1008, principal point at the centre); ground
+    truth a uniform point of the arc of `joint` with the camera centre
+    jittered by U(-0.05, 0.05) per axis, still looking at the arc's centre;
+    starting pose the ground truth turned by U(1, 5) degrees and moved by
+    U(0.02, 0.1).  `gap` is a unit-rate exponential inter-arrival time (scale
+    by 1/rate for Poisson arrivals at that rate)."""
+    rng = rng_for(seed, 0)
+    target = np.array([0.0, 0.0, radius])
+    out = []
+    for k in range(n_requests):
+        W, H = sizes[int(rng.integers(len(sizes)))]
+        f = 815.0 * W / 1008.0
+        cam = Camera(W, H, f, f, W / 2.0, H / 2.0)
+        th = np.deg2rad(rng.uniform(-half_angle_deg, half_angle_deg))
+        center = target + radius * np.array([np.sin(th), 0.0, -np.cos(th)])
+        center = center + rng.uniform(-0.05, 0.05, 3)
+        gt = look_at_pose(center, target)
+        init = perturb_pose(gt, rng.uniform(1.0, 5.0), rng.uniform(0.02, 0.1), rng_for(seed, 1 + k))
+        out.append({"rid": k, "camera": cam, "gt_pose": gt.astype(np.float32),
+                    "init_pose": init.astype(np.float32), "gap": float(rng.exponential(1.0))})
+    return out
+
+
 def random_scene(seed, n, sh_degree, cam, depth=(1.0, 6.0), log_scale=(np.log(0.02), np.log(0.3)),
                  opacity=(0.05, 0.99), lateral=1.3, higher_std=0.3):
     """Small random scenes for property and parity tests: Gaussians in (and

@@ -64,7 +64,8 @@ def test_workspace_size_validates_views(lib):
 def test_calls_reject_null_context(lib):
     from paper_2410_08743_amd import _native as N
     assert lib.gsp_render_fwd(None, None, 1, None, None, None, None, None, 0, 0, None) == N.GSP_EINVAL
-    assert lib.gsp_loss_l1(None, 10, None, None, None, None, None, None) == N.GSP_EINVAL
+    assert lib.gsp_loss_l1(None, 1, None, None, None, None, None, None, None) == N.GSP_EINVAL
+    assert lib.gsp_pose_adam(None, 1, None, None, None, None, None, None, None, None) == N.GSP_EINVAL
     assert lib.gsp_create(0, None) == N.GSP_EINVAL
 
 

@@ -254,16 +254,32 @@ def test_empty_and_invisible_scenes_render_background():
             assert np.all(run["means"] == 0)
 
 
-def test_l1_loss_kernel():
+def test_l1_loss_kernel_per_view():
+    # two views of different, non-tile-multiple sizes in one launch: each view
+    # is normalised by its own value count
     rng = np.random.default_rng(81)
-    a = rng.standard_normal(100_003).astype(np.float32)
-    b = a.copy()
-    b[::5] = rng.standard_normal(len(b[::5])).astype(np.float32)
-    loss, grad = R.loss_l1(torch.tensor(a, device=DEV), torch.tensor(b, device=DEV))
-    rv, rg = oracle.l1(a, b)
-    assert abs(float(loss.item()) - rv) <= 1e-6 * rv
-    assert np.array_equal(np.sign(grad.cpu().numpy()), np.sign(rg))
-    assert np.max(np.abs(grad.cpu().numpy() - rg)) <= 1e-7 * np.abs(rg).max()
+    cams = [S.Camera(101, 37, 90.0, 90.0, 50.0, 18.0), S.Camera(64, 48, 60.0, 60.0, 32.0, 24.0)]
+    preds, targets = [], []
+    for c in cams:
+        a = rng.standard_normal(3 * c.width * c.height).astype(np.float32)
+        b = a.copy()
+        b[::5] = rng.standard_normal(len(b[::5])).astype(np.float32)
+        preds.append(a)
+        targets.append(b)
+    loss, grads = R.loss_l1(cams, [torch.tensor(a, device=DEV) for a in preds],
+                            [torch.tensor(b, device=DEV) for b in targets])
+    loss = loss.cpu().numpy()
+    for v in range(len(cams)):
+        rv, rg = oracle.l1(preds[v], targets[v])
+        g = grads[v].cpu().numpy()
+        assert abs(float(loss[v]) - rv) <= 1e-6 * rv
+        assert np.array_equal(np.sign(g), np.sign(rg))
+        assert np.max(np.abs(g - rg)) <= 1e-7 * np.abs(rg).max()
+    # the packed layout gives the same result
+    lp, gp = R.loss_l1(cams, torch.tensor(np.concatenate(preds), device=DEV),
+                       torch.tensor(np.concatenate(targets), device=DEV))
+    assert np.array_equal(lp.cpu().numpy(), loss)
+    assert np.array_equal(gp.cpu().numpy(), np.concatenate([g.cpu().numpy() for g in grads]))
 
 
 def test_pose_adam_kernel():
@@ -285,6 +301,16 @@ def test_pose_adam_kernel():
     for k in range(V):
         assert np.max(np.abs(got[k] - ref[k][0])) <= 2e-6
     assert np.all(st.cpu().numpy() == K)
+    # a guard workspace whose counters report an overflow skips the step
+    guard = torch.zeros(64, dtype=torch.uint8, device=DEV)
+    guard.view(torch.int32)[2] = 1
+    before = [t.clone() for t in (P, m, v, st)]
+    R.pose_adam(P, torch.tensor(grads[0], device=DEV), m, v, st, 1e-2, 1e-3, K, guard=guard)
+    for a, b in zip(before, (P, m, v, st)):
+        assert torch.equal(a, b)
+    guard.zero_()
+    R.pose_adam(P, torch.tensor(grads[0], device=DEV), m, v, st, 1e-2, 1e-3, K, guard=guard)
+    assert np.all(st.cpu().numpy() == K + 1)
 
 
 def test_autograd_function_matches_direct_calls():

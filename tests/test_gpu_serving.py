@@ -1,0 +1,90 @@
+"""Continuous-batching pose server: each request's result is the same alone
+and in a mix, overflowing iterations are repeated, HBM admission holds."""
+import numpy as np
+import pytest
+import torch
+
+from paper_2410_08743_amd import render as R
+from paper_2410_08743_amd import serve as SV
+from paper_2410_08743_amd import synthetic as S
+
+pytestmark = pytest.mark.gpu
+DEV = "cuda:0"
+SIZES = ((64, 48), (96, 64), (128, 96))
+
+
+def _setup(seed=501, n=20_000, n_req=6):
+    cam0 = S.Camera(128, 96, 110.0, 110.0, 64.0, 48.0)
+    sc = S.random_scene(seed, n, 3, cam0, depth=(2.0, 7.0), log_scale=(np.log(0.01), np.log(0.06)))
+    g = R.GaussianParams.from_set(sc, DEV)
+    rng = S.rng_for(seed, 1)
+    reqs = []
+    rast = R.Rasterizer(0)
+    for k in range(n_req):
+        W, H = SIZES[k % len(SIZES)]
+        f = 110.0 * W / 128.0
+        cam = S.Camera(W, H, f, f, W / 2.0, H / 2.0)
+        gt = S.random_pose_near_identity(seed + 10 + k, 1.0, 0.05)
+        init = S.perturb_pose(gt, float(rng.uniform(1.0, 3.0)), float(rng.uniform(0.02, 0.05)), rng)
+        tgt, _ = rast.forward(g, [cam], torch.tensor(gt[None], device=DEV))
+        reqs.append(SV.PoseRequest(cam, tgt.clone().view(3, H, W),
+                                   torch.tensor(init.astype(np.float32), device=DEV), 0.0, k))
+    return g, reqs
+
+
+def _with_arrivals(reqs, arrivals):
+    return [SV.PoseRequest(r.camera, r.target, r.init_pose, float(a), r.rid)
+            for r, a in zip(reqs, arrivals)]
+
+
+def test_result_same_alone_and_in_the_mix():
+    g, reqs = _setup()
+    iters = 12
+    mixed = SV.PoseServer(g, iters=iters, max_batch=4).run(
+        _with_arrivals(reqs, [0, 0, 3, 7, 7, 20]), clock="iterations")
+    assert max(max(r.batch_sizes) for r in mixed) == 4          # requests did share launches
+    assert any(len(set(r.batch_sizes)) > 1 for r in mixed)       # and the mix changed under them
+    for r, res in zip(reqs, mixed):
+        alone = SV.PoseServer(g, iters=iters, max_batch=1).run([r], clock="iterations")[0]
+        assert res.iterations == iters and alone.iterations == iters
+        assert np.array_equal(res.pose, alone.pose), f"request {r.rid}"
+
+
+def test_overflowing_iterations_are_repeated():
+    g, reqs = _setup(seed=511, n_req=3)
+    iters = 8
+    ref = SV.PoseServer(g, iters=iters, max_batch=3).run(reqs, clock="iterations")
+    srv = SV.PoseServer(g, iters=iters, max_batch=3, margin=1.0)
+    for r in reqs:
+        srv.calibrate(r.camera, r.init_pose)
+    for k in srv.est:                     # far too little room: the first launches overflow
+        srv.est[k] = 64
+    got = srv.run(reqs, clock="iterations")
+    for a, b in zip(ref, got):
+        assert b.iterations == iters
+        assert np.array_equal(a.pose, b.pose)
+
+
+def test_admission_respects_the_hbm_budget():
+    g, reqs = _setup(seed=521, n_req=5)
+    srv = SV.PoseServer(g, iters=4, max_batch=8)
+    for r in reqs:
+        srv.calibrate(r.camera, r.init_pose)
+    two = sorted(srv.request_bytes(r.camera) for r in reqs)[-2:]
+    srv.budget = sum(two)
+    res = srv.run(reqs, clock="iterations")
+    assert max(max(r.batch_sizes) for r in res) <= 2
+    assert all(r.iterations == 4 for r in res)
+    too_small = SV.PoseServer(g, iters=4, hbm_budget=1 << 20)
+    with pytest.raises(ValueError):
+        too_small.run(reqs[:1], clock="iterations")
+
+
+def test_batched_solve_converges():
+    g, reqs = _setup(seed=531, n_req=3)
+    res = SV.PoseServer(g, iters=60, lr=(1e-2, 1e-4)).run(reqs, clock="iterations")
+    for k, (r, out) in enumerate(zip(reqs, res)):
+        gt = S.random_pose_near_identity(531 + 10 + k, 1.0, 0.05)
+        e0 = S.pose_error(r.init_pose.cpu().numpy(), gt)
+        e1 = S.pose_error(out.pose, gt)
+        assert e1[0] < 0.5 * e0[0] and e1[1] < 0.5 * e0[1], (e0, e1)
