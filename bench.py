@@ -17,6 +17,17 @@ the kernels run on, inputs already resident in HBM.
 
 The JSON line also carries, for the dominant kernel, achieved vs peak
 (`roofline`), and the FP64 CPU oracle timed on this host (`cpu_baseline`).
+
+Serving (`serving` in the JSON line, skipped with --no-serve): a resident
+1M-Gaussian SH-3 scene (the joint-reconstruction scene) and pose-estimation
+requests of mixed sizes {320x240, 640x480, 1008x756}, starting errors
+U(1, 5) deg / U(0.02, 0.1), 50 Adam iterations each, targets rendered at the
+ground-truth poses.  The requests are first solved one at a time (the
+sequential baseline: its rate mu_seq and per-request service times), then
+served with continuous batching at Poisson arrival rates of 0.5, 1 and 2 x
+mu_seq; latency = completion - arrival.  The sequential server's latencies at
+the same arrival times follow from its measured service times (first come,
+first served).  Final poses of the two are compared bit for bit.
 """
 import argparse
 import hashlib
@@ -79,6 +90,10 @@ def main():
     ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--cpu-reps", type=int, default=3)
+    ap.add_argument("--no-serve", action="store_true", help="skip the serving measurement")
+    ap.add_argument("--serve-requests", type=int, default=48)
+    ap.add_argument("--serve-rates", type=str, default="0.5,1,2",
+                    help="arrival rates as multiples of the sequential rate")
     ap.add_argument("--profile-only", action="store_true",
                     help="run warmup + timed steps only (for rocprofv3), no JSON extras")
     args = ap.parse_args()
@@ -242,6 +257,10 @@ def main():
                          f"starting pose, FP64, median of {args.cpu_reps}",
                "seconds": round(t, 3)}
 
+    serving = None
+    if not args.no_serve:
+        serving = serving_section(args, dev, with_cpu=not args.no_cpu)
+
     line = {
         "metric": METRIC, "value": round(value, 2), "unit": "Mpix/s", "n_gpus": 1,
         "steps": K, "warmup": args.warmup, "ms_per_step": round(ms_step, 4),
@@ -252,6 +271,7 @@ def main():
                    "step": "fwd+L1+bwd(pose)+adam", "parallelism": "single GPU"},
         "roofline": roof,
         "cpu_baseline": cpu,
+        "serving": serving,
         "stages": stage_report,
         "work": {"instances": M, "evaluated_pairs": neval, "blended_pairs": nblend,
                  "backward_pairs": ncontrib, **lockstep},
@@ -261,6 +281,100 @@ def main():
                        "final_error": [round(rot_err, 4), round(trans_err, 5)]},
     }
     print(json.dumps(line), flush=True)
+
+
+def serving_section(args, dev, with_cpu=True):
+    import numpy as np
+    import torch
+
+    from paper_2410_08743_amd import render as R
+    from paper_2410_08743_amd import serve as SV
+    from paper_2410_08743_amd import synthetic as S
+
+    iters = 50
+    wl = S.joint()
+    g = R.GaussianParams.from_set(wl.scene, dev)
+    specs = S.serving_requests(n_requests=args.serve_requests)
+    rast = R.Rasterizer(0)
+    reqs = []
+    for sp in specs:
+        cam = sp["camera"]
+        tgt, _ = rast.forward(g, [cam], torch.tensor(sp["gt_pose"][None], device=dev))
+        reqs.append(SV.PoseRequest(cam, tgt.clone().view(3, cam.height, cam.width),
+                                   torch.tensor(sp["init_pose"], device=dev), 0.0, sp["rid"]))
+    del rast
+    torch.cuda.synchronize()
+    print(f"[bench] serving: {g.n} Gaussians resident, {len(reqs)} requests", file=sys.stderr,
+          flush=True)
+
+    # sequential baseline: one request at a time, back to back
+    seq_srv = SV.PoseServer(g, iters=iters, max_batch=1)
+    seq_srv.run(reqs[:2])            # warm-up (calibration, allocations)
+    seq = seq_srv.run(reqs)
+    done = [r.completed for r in seq]
+    service = [done[0]] + [b - a for a, b in zip(done, done[1:])]
+    mu_seq = len(seq) / done[-1]
+    print(f"[bench] sequential: {mu_seq:.2f} requests/s", file=sys.stderr, flush=True)
+
+    def errors(results):
+        e = np.array([S.pose_error(r.pose, sp["gt_pose"]) for r, sp in zip(results, specs)])
+        return {"rot_deg_p50": float(np.percentile(e[:, 0], 50)),
+                "rot_deg_p99": float(np.percentile(e[:, 0], 99)),
+                "trans_p50": float(np.percentile(e[:, 1], 50)),
+                "trans_p99": float(np.percentile(e[:, 1], 99))}
+
+    gaps = np.array([sp["gap"] for sp in specs])
+    rates = []
+    srv = SV.PoseServer(g, iters=iters)
+    srv.run(reqs[:4])                # warm-up
+    for rel in [float(x) for x in args.serve_rates.split(",")]:
+        lam = rel * mu_seq
+        arr = np.cumsum(gaps) / lam
+        arr -= arr[0]
+        batched = srv.run([SV.PoseRequest(r.camera, r.target, r.init_pose, float(a), r.rid)
+                           for r, a in zip(reqs, arr)])
+        st = SV.latency_stats(batched)
+        comp = SV.fifo_latencies(arr, service)
+        lat_seq = np.array(comp) - arr
+        same = sum(bool(np.array_equal(a.pose, b.pose)) for a, b in zip(batched, seq))
+        rates.append({
+            "arrival_rate_rel": rel, "arrival_rate": round(lam, 3),
+            "batched": {"requests_per_s": round(st["requests_per_s"], 3),
+                        "p50_ms": round(st["p50_ms"], 2), "p99_ms": round(st["p99_ms"], 2),
+                        "mean_batch": round(st["mean_batch"], 2)},
+            "sequential": {"requests_per_s": round(len(comp) / (comp[-1] - arr[0]), 3),
+                           "p50_ms": round(float(np.percentile(lat_seq, 50)) * 1e3, 2),
+                           "p99_ms": round(float(np.percentile(lat_seq, 99)) * 1e3, 2)},
+            "identical_final_poses": f"{same}/{len(batched)}",
+        })
+        print(f"[bench] rate {rel} x mu_seq: batched {st['requests_per_s']:.2f} req/s "
+              f"p50 {st['p50_ms']:.1f} ms p99 {st['p99_ms']:.1f} ms; identical {same}/{len(batched)}",
+              file=sys.stderr, flush=True)
+
+    out = {
+        "workload": "serve-1M-sh3-mixed-320x240-640x480-1008x756",
+        "gaussians": g.n, "requests": len(reqs), "iterations_per_request": iters,
+        "sequential_requests_per_s": round(mu_seq, 3),
+        "sequential_service_ms_p50": round(float(np.percentile(service, 50)) * 1e3, 2),
+        "rates": rates,
+        "final_error": errors(seq),
+    }
+    if with_cpu:
+        import oracle
+        per_size = {}
+        for sp in specs:
+            cam = sp["camera"]
+            key = f"{cam.width}x{cam.height}"
+            if key in per_size:
+                continue
+            t0 = time.perf_counter()
+            oracle.render(wl.scene, cam, sp["init_pose"])
+            oracle.backward(wl.scene, cam, sp["init_pose"],
+                            np.zeros((3, cam.height, cam.width)))
+            per_size[key] = round(iters * (time.perf_counter() - t0), 2)
+        out["cpu_oracle_seconds_per_request"] = per_size
+        out["cpu_oracle_cores"] = oracle.max_threads()
+    return out
 
 
 if __name__ == "__main__":
