@@ -91,9 +91,18 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--cpu-reps", type=int, default=3)
     ap.add_argument("--no-serve", action="store_true", help="skip the serving measurement")
+    ap.add_argument("--serve-only", action="store_true",
+                    help="run only the serving measurement and print its JSON (for profiling)")
     ap.add_argument("--serve-requests", type=int, default=48)
+    ap.add_argument("--no-joint", action="store_true", help="skip the joint-step measurement")
+    ap.add_argument("--no-track", action="store_true", help="skip the tracking measurement")
+    ap.add_argument("--track-frames", type=int, default=100)
+    ap.add_argument("--joint-steps", type=int, default=20)
     ap.add_argument("--serve-rates", type=str, default="0.5,1,2",
                     help="arrival rates as multiples of the sequential rate")
+    ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
+                    help="with --profile-only: also run a device-to-device copy of MIB MiB "
+                         "(a plain copy of known size, to scale HBM counters)")
     ap.add_argument("--profile-only", action="store_true",
                     help="run warmup + timed steps only (for rocprofv3), no JSON extras")
     args = ap.parse_args()
@@ -111,6 +120,9 @@ def main():
 
     torch.cuda.set_device(0)
     dev = "cuda:0"
+    if args.serve_only:
+        print(json.dumps(serving_section(args, dev, with_cpu=False)), flush=True)
+        return
     wl = S.single_view()
     cam = wl.camera
     P = cam.width * cam.height
@@ -167,6 +179,14 @@ def main():
     print(f"[bench] {K} steps: {ms_step:.3f} ms/step, {value:.1f} Mpix/s; pose error "
           f"{rot0:.2f} deg/{trans0:.3f} -> {rot_err:.3f} deg/{trans_err:.4f}", file=sys.stderr, flush=True)
     if args.profile_only:
+        if args.calibrate_copy > 0:
+            n = args.calibrate_copy << 18
+            src = torch.ones(n, dtype=torch.float32, device=dev)
+            dst = torch.empty_like(src)
+            for _ in range(3):
+                dst.copy_(src)
+            torch.cuda.synchronize()
+            print(f"[bench] calibration copy: {args.calibrate_copy} MiB x 3", file=sys.stderr)
         return
 
     # per-stage timing pass (events bracket each stage on the same stream)
@@ -257,6 +277,12 @@ def main():
                          f"starting pose, FP64, median of {args.cpu_reps}",
                "seconds": round(t, 3)}
 
+    joint = None
+    if not args.no_joint:
+        joint = joint_section(args, dev)
+    track = None
+    if not args.no_track:
+        track = tracking_section(args, dev)
     serving = None
     if not args.no_serve:
         serving = serving_section(args, dev, with_cpu=not args.no_cpu)
@@ -271,6 +297,8 @@ def main():
                    "step": "fwd+L1+bwd(pose)+adam", "parallelism": "single GPU"},
         "roofline": roof,
         "cpu_baseline": cpu,
+        "joint": joint,
+        "tracking": track,
         "serving": serving,
         "stages": stage_report,
         "work": {"instances": M, "evaluated_pairs": neval, "blended_pairs": nblend,
@@ -283,6 +311,178 @@ def main():
     print(json.dumps(line), flush=True)
 
 
+_JOINT = None
+
+
+def joint_scene():
+    global _JOINT
+    if _JOINT is None:
+        from paper_2410_08743_amd import synthetic as S
+        _JOINT = S.joint()
+    return _JOINT
+
+
+def joint_section(args, dev):
+    """Joint reconstruction step at one GPU's share: 1M Gaussians (SH 3), 4 of
+    the 20 arc views (1008x756) per step, forward + per-view L1 + backward to
+    every Gaussian parameter and the 4 pose twists + the pose Adam step.  The
+    optimised scene is the ground-truth scene with mu += N(0, 0.01^2),
+    log s += N(0, 0.1^2) and resampled colours; targets are rendered from the
+    ground truth at the ground-truth poses."""
+    import numpy as np
+    import torch
+
+    from paper_2410_08743_amd import render as R
+    from paper_2410_08743_amd import synthetic as S
+
+    wl = joint_scene()
+    cam = wl.camera
+    gt = R.GaussianParams.from_set(wl.scene, dev)
+    rng = S.rng_for(1003, 5)
+    sc = wl.scene
+    noisy = S.GaussianSet((sc.means + rng.normal(0, 0.01, sc.means.shape)).astype(np.float32),
+                          (sc.scales * np.exp(rng.normal(0, 0.1, sc.scales.shape))).astype(np.float32),
+                          sc.quats, sc.opacities, S.colour_sh(rng, sc.n, 3), 3)
+    g = R.GaussianParams.from_set(noisy, dev)
+    V = 4
+    nv = wl.extra["gt_poses"].shape[0]
+    perm = S.rng_for(1003, 6).permutation(nv)
+    rast = R.Rasterizer(0)
+    P = cam.width * cam.height
+    targets = []
+    for k in range(nv):
+        t, _ = rast.forward(gt, [cam], torch.tensor(wl.extra["gt_poses"][k:k + 1], device=dev))
+        targets.append(t.clone())
+    poses = torch.tensor(wl.extra["noisy_poses"], device=dev)
+    m = torch.zeros((nv, 6), device=dev)
+    v = torch.zeros((nv, 6), device=dev)
+    st = torch.zeros(nv, dtype=torch.int32, device=dev)
+    cams = [cam] * V
+    imgs = [torch.empty(3 * P, device=dev) for _ in range(V)]
+    dls = [torch.empty(3 * P, device=dev) for _ in range(V)]
+    out = {k: torch.empty(sh, device=dev) for k, sh in
+           (("means", (g.n, 3)), ("scales", (g.n, 3)), ("quats", (g.n, 4)),
+            ("opacities", (g.n,)), ("sh", tuple(g.sh.shape)))}
+    out["pose"] = torch.empty((V, 6), device=dev)
+    # capacity for 4 views from one render of each batch's first view
+    rast.forward(g, [cam] * V, poses[perm[:V]].contiguous())
+    m0, _ = rast.instances()
+    rast.capacity = int(1.5 * m0) + 4096
+    rast.ws = None
+
+    def step(k):
+        idx = perm[(k * V + np.arange(V)) % nv]
+        pv = poses[idx].contiguous()
+        rast.forward(g, cams, pv, check=False, images=imgs)
+        R.loss_l1(cams, imgs, [targets[i] for i in idx], grad=dls, with_loss=False)
+        rast.backward(g, cams, pv, dls, out=out)
+        pm, pvv, pst = m[idx].contiguous(), v[idx].contiguous(), st[idx].contiguous()
+        R.pose_adam(pv, out["pose"], pm, pvv, pst, 1e-3, 1e-5, 1000, guard=rast.ws)
+        poses[idx] = pv
+        m[idx] = pm
+        v[idx] = pvv
+        st[idx] = pst
+
+    rast._ensure(g, R.N.view_array(cams))
+    for k in range(3):
+        step(k)
+    rast.reset_overflow()
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    K = args.joint_steps
+    e0.record()
+    for k in range(K):
+        step(3 + k)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / K
+    M, ovf = rast.instances()
+    if ovf:
+        print("[bench] joint step overflowed its instance capacity", file=sys.stderr)
+        return None
+    print(f"[bench] joint step: {ms:.3f} ms for {V} views ({V * P / (ms * 1e3):.1f} Mpix/s)",
+          file=sys.stderr, flush=True)
+    return {"workload": "joint-1M-4x1008x756-sh3", "gaussians": g.n, "views_per_step": V,
+            "steps": K, "ms_per_step": round(ms, 4), "mpix_per_s": round(V * P / (ms * 1e3), 2),
+            "instances": M, "step": "fwd+L1+bwd(all Gaussian params + 4 poses)+pose adam"}
+
+
+def tracking_section(args, dev):
+    """Sequential tracking through the torch.autograd.Function: the 500k-
+    Gaussian room (SH 3), 1200x680, each frame starting from the previous
+    frame's estimate (frame 0 from the ground truth turned by 1 deg and moved
+    by 0.02) and running 50 pose-only Adam iterations on the L1 loss; the
+    render and its backward are the library's, the loss and its gradient are
+    torch's autograd.  Peak HBM of this recompute design is measured; the
+    per-pixel state a store-the-lists design would add (an id and an alpha
+    per blended pair, 8 B each pair) is computed from the contributor
+    counts."""
+    import numpy as np
+    import torch
+
+    from paper_2410_08743_amd import render as R
+    from paper_2410_08743_amd import synthetic as S
+
+    wl = S.room(n_frames=args.track_frames)
+    cam = wl.camera
+    traj = wl.extra["trajectory"]
+    g = R.GaussianParams.from_set(wl.scene, dev)
+    rast = R.Rasterizer(0)
+    targets = []
+    stored_pairs = []
+    for k in range(len(traj)):
+        t, _ = rast.forward(g, [cam], torch.tensor(traj[k:k + 1], device=dev))
+        targets.append(t.clone())
+        stored_pairs.append(int(rast.inspect(g, [cam], "ncontrib", torch.int32)
+                                .to(torch.int64).sum().item()))
+    m0, _ = rast.instances()
+    rast.capacity = int(1.5 * m0) + 4096
+    rast.ws = None
+    rast._ensure(g, R.N.view_array([cam]))
+    iters = 50
+    pose = torch.tensor(S.perturb_pose(traj[0], 1.0, 0.02, S.rng_for(1004, 2))[None]
+                        .astype(np.float32), device=dev)
+    errs = []
+    torch.cuda.synchronize()
+    torch.cuda.reset_peak_memory_stats()
+    t0 = time.perf_counter()
+    for k in range(len(traj)):
+        m = torch.zeros((1, 6), device=dev)
+        v = torch.zeros((1, 6), device=dev)
+        st = torch.zeros(1, dtype=torch.int32, device=dev)
+        for _ in range(iters):
+            tau = torch.zeros((1, 6), device=dev, requires_grad=True)
+            img = R.render(g, [cam], pose, tau=tau, rast=rast, check=False)
+            loss = (img - targets[k]).abs().mean()
+            loss.backward()
+            R.pose_adam(pose, tau.grad, m, v, st, 1e-2, 1e-4, iters, guard=rast.ws)
+        errs.append(S.pose_error(pose[0].cpu().numpy(), traj[k]))
+    torch.cuda.synchronize()
+    sec = time.perf_counter() - t0
+    peak = torch.cuda.max_memory_allocated()
+    if rast.overflowed():
+        print("[bench] tracking overflowed its instance capacity", file=sys.stderr)
+        return None
+    e = np.array(errs)
+    P = cam.width * cam.height
+    n_it = len(traj) * iters
+    print(f"[bench] tracking: {len(traj)} frames x {iters} iterations in {sec:.2f} s "
+          f"({1e3 * sec / n_it:.3f} ms/iteration); median error {np.median(e[:, 0]):.3f} deg / "
+          f"{np.median(e[:, 1]):.4f}", file=sys.stderr, flush=True)
+    return {"workload": wl.name, "gaussians": g.n, "frames": len(traj),
+            "iterations_per_frame": iters, "seconds": round(sec, 3),
+            "ms_per_iteration": round(1e3 * sec / n_it, 4),
+            "mpix_per_s": round(P * n_it / sec / 1e6, 2),
+            "error_deg_median": round(float(np.median(e[:, 0])), 4),
+            "error_deg_max": round(float(np.max(e[:, 0])), 4),
+            "error_trans_median": round(float(np.median(e[:, 1])), 5),
+            "error_trans_max": round(float(np.max(e[:, 1])), 5),
+            "peak_hbm_bytes_recompute": int(peak),
+            "per_pixel_state_bytes_recompute": 8 * P,
+            "per_pixel_state_bytes_stored_lists_mean": int(8 * np.mean(stored_pairs)) + 8 * P,
+            "note": "loss and its gradient in torch autograd; render, backward and Adam in the library"}
+
+
 def serving_section(args, dev, with_cpu=True):
     import numpy as np
     import torch
@@ -292,7 +492,7 @@ def serving_section(args, dev, with_cpu=True):
     from paper_2410_08743_amd import synthetic as S
 
     iters = 50
-    wl = S.joint()
+    wl = joint_scene()
     g = R.GaussianParams.from_set(wl.scene, dev)
     specs = S.serving_requests(n_requests=args.serve_requests)
     rast = R.Rasterizer(0)

@@ -206,7 +206,7 @@ gsp_status gsp_pose_adam(gsp_ctx *ctx, int32_t V, float *poses, const float *dpo
  * "depth_order" (uint32 view-Gaussians in (depth, index) order),
  * "ranges" (uint32 pairs per tile), "tfinal" (float per pixel),
  * "ncontrib" (uint32 per pixel), "neval", "nblend" (uint32 per pixel, see
- * GSP_PROFILE_COUNTS), "grad2d" (float [9][V*n]: du dv dA dB dC
+ * GSP_PROFILE_COUNTS), "grad2d" (float [V*n][9]: du dv dA dB dC
  * do dr dg db), "counters" (uint32: M, overflow). */
 gsp_status gsp_inspect(gsp_ctx *ctx, const gsp_gaussians *g, int32_t V, const gsp_view *views,
                        void *workspace, size_t ws_bytes, int64_t instance_capacity,

@@ -124,9 +124,21 @@ __device__ __forceinline__ void wave_sum9(const float v[9], float &x0, float &x1
     const float w2 = pair_sum32(v[4], v[5]);
     const float w3 = pair_sum32(v[6], v[7]);
     const float w4 = pair_sum32(v[8], v[8]);
-    x0 = row_sum16(pair_sum16(w0, w1));
-    x1 = row_sum16(pair_sum16(w2, w3));
-    x2 = row_sum16(pair_sum16(w4, w4));
+    float a = pair_sum16(w0, w1), b = pair_sum16(w2, w3), c = pair_sum16(w4, w4);
+    // the three row butterflies interleaved, so that no DPP step waits on the
+    // one just issued
+    a = dpp_add<kDppQuadXor1>(a);
+    b = dpp_add<kDppQuadXor1>(b);
+    c = dpp_add<kDppQuadXor1>(c);
+    a = dpp_add<kDppQuadXor2>(a);
+    b = dpp_add<kDppQuadXor2>(b);
+    c = dpp_add<kDppQuadXor2>(c);
+    a = dpp_add<kDppRowHalfMirror>(a);
+    b = dpp_add<kDppRowHalfMirror>(b);
+    c = dpp_add<kDppRowHalfMirror>(c);
+    x0 = dpp_add<kDppRowMirror>(a);
+    x1 = dpp_add<kDppRowMirror>(b);
+    x2 = dpp_add<kDppRowMirror>(c);
 }
 
 }  // namespace gsp

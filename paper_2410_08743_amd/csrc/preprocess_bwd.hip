@@ -33,7 +33,7 @@ struct PbArgs {
     const uint32_t *tiles;
     const uint32_t *counters;
     const float *slots;     // [cap][9]
-    float *grad2d;          // [9][vn]
+    float *grad2d;          // [vn][9]
     double *posepart;       // [V][nblk][6]
     gsp_grads out;
     size_t cap, vn;
@@ -107,7 +107,7 @@ __global__ __launch_bounds__(kWindowThreads) void k_slot_reduce(const uint32_t *
         uint32_t e = lo;
         for (; e < mid; e++) d += s_sl[9 * e + c];
         for (; e < hi; e++) d += src[9 * (size_t)e + c];
-        grad2d[(size_t)c * vn + s_idx[j]] = d;
+        grad2d[9 * (size_t)s_idx[j] + c] = d;
     }
 }
 
@@ -169,7 +169,7 @@ __global__ __launch_bounds__(kPoseReduceBlock) void k_preprocess_bwd(PbArgs a, V
         if (cnt > 0) {
             float d2f[9];
 #pragma unroll
-            for (int c = 0; c < 9; c++) d2f[c] = a.grad2d[c * a.vn + idx];
+            for (int c = 0; c < 9; c++) d2f[c] = a.grad2d[9 * (size_t)idx + c];
             double R[9], t[3];
 #pragma unroll
             for (int r = 0; r < 3; r++) {

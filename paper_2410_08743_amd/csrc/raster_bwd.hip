@@ -167,22 +167,21 @@ __global__ __launch_bounds__(kRasterThreads) __attribute__((amdgpu_waves_per_eu(
                 const StagedA &s = es[u];
                 const StagedB &t = et[u];
                 const ColTerms ct = col_terms(s, fxl);
+                const float lim = kLog2AlphaMinLoose - t.lo;
                 float p2[kPixPerLane];
                 bool cand[kPixPerLane];
 #pragma unroll
                 for (int q = 0; q < kPixPerLane; q++) {
                     p2[q] = splat_p2(ct, t.C2, s.v - fy[q]);
-                    cand[q] = (pos < last[q]) & (p2[q] <= 0.f) & (p2[q] + t.lo >= kLog2AlphaMinLoose);
+                    cand[q] = (pos < last[q]) & (p2[q] <= 0.f) & (p2[q] >= lim);
                 }
                 float x0 = 0.f, x1 = 0.f, x2 = 0.f;
                 if (__any(cand[0] || cand[1] || cand[2] || cand[3])) {
                     const float col3[3] = {t.r, t.g, ew[u].b};
-                    const float a2dx = 2.f * s.A2 * ct.dx;
-                    const float c22 = 2.f * t.C2;
-                    const float dx2 = ct.dx * ct.dx;
-                    float acc[9];
-#pragma unroll
-                    for (int c = 0; c < 9; c++) acc[c] = 0.f;
+                    // Per lane, dx is the same for its four pixels, so the
+                    // conic and centre gradients need only the moments
+                    // sum dp, sum dp dy, sum dp dy^2 of dL/dpower over them.
+                    float m0 = 0.f, my = 0.f, myy = 0.f, gc[3] = {0.f, 0.f, 0.f};
                     // q-th pixels of all lanes form a 16 x 4 band of the tile:
                     // a band with no candidate is skipped as a whole; inside a
                     // band the update is branch-free, pixels that do not blend
@@ -200,18 +199,28 @@ __global__ __launch_bounds__(kRasterThreads) __attribute__((amdgpu_waves_per_eu(
                         const float Gc = fmaf(G[q][2], col3[2], fmaf(G[q][1], col3[1], G[q][0] * col3[0]));
                         const float diff = Gc - GS[q];
 #pragma unroll
-                        for (int ch = 0; ch < 3; ch++) acc[6 + ch] = fmaf(G[q][ch], wgt, acc[6 + ch]);
+                        for (int ch = 0; ch < 3; ch++) gc[ch] = fmaf(G[q][ch], wgt, gc[ch]);
                         GS[q] = valid ? fmaf(alpha, diff, GS[q]) : GS[q];
                         // dL/dpower; zero where alpha is clamped at 0.99
                         const float dp = apre <= kAlphaMax ? wgt * diff : 0.f;
                         const float dpy = dp * dy;
-                        acc[0] = fmaf(dp, fmaf(s.B2, dy, a2dx), acc[0]);
-                        acc[1] = fmaf(dp, fmaf(c22, dy, ct.bdx), acc[1]);
-                        acc[2] = fmaf(dp, dx2, acc[2]);
-                        acc[3] = fmaf(dpy, ct.dx, acc[3]);
-                        acc[4] = fmaf(dpy, dy, acc[4]);
-                        acc[5] += dp;
+                        m0 += dp;
+                        my += dpy;
+                        myy = fmaf(dpy, dy, myy);
                     }
+                    // dpower/du = -(A dx + B dy), dpower/dv = -(C dy + B dx),
+                    // dpower/d(A, B, C) = -(dx^2 / 2, dx dy, dy^2 / 2), in the
+                    // base-2 conic and before the per-component scale below
+                    float acc[9];
+                    acc[0] = fmaf(s.B2, my, 2.f * s.A2 * ct.dx * m0);
+                    acc[1] = fmaf(2.f * t.C2, my, ct.bdx * m0);
+                    acc[2] = ct.dx * ct.dx * m0;
+                    acc[3] = ct.dx * my;
+                    acc[4] = myy;
+                    acc[5] = m0;
+                    acc[6] = gc[0];
+                    acc[7] = gc[1];
+                    acc[8] = gc[2];
                     wave_sum9(acc, x0, x1, x2);
                 }
                 if (comp >= 0 && ew[u].slot != kNoSlot) {

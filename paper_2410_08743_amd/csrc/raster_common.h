@@ -29,8 +29,9 @@ constexpr int kUnroll = 4;          // entries per step of the inner loop
 
 constexpr float kLn2 = 0.6931471805599453f;
 // A splat can reach alpha >= 1/255 at a pixel only if p2 + log2(o) is at least
-// log2(1/255); the 0.01 margin keeps the test conservative with respect to
-// v_exp_f32's rounding, so skipping on it never changes a decision.
+// log2(1/255); the 0.01 margin keeps the test (taken as p2 >= this - log2(o))
+// conservative with respect to v_exp_f32's and the subtraction's rounding, so
+// skipping on it never changes a decision.
 constexpr float kLog2AlphaMinLoose = -7.994353436858858f - 0.01f;
 
 // Splat as staged in LDS: centre relative to the tile's first pixel, scaled
@@ -76,7 +77,7 @@ __device__ __forceinline__ float splat_alpha_pre(float p2, float lo) {
 
 // Bit q of the result is set when some pixel of rows 4q .. 4q+3 of the tile
 // may reach alpha >= 1/255, i.e. when the rasterizer's own candidate test
-// (p2 + lo >= kLog2AlphaMinLoose) may pass there; a clear bit is a proof that
+// (p2 >= kLog2AlphaMinLoose - lo) may pass there; a clear bit is a proof that
 // it fails at every pixel of those rows.  Per pixel row, p2 is a concave
 // quadratic in dx whose maximum over the row's dx range [u - 15, u] is taken
 // at the clamped stationary point.  The margin covers the float32 rounding of

@@ -129,27 +129,31 @@ __global__ __launch_bounds__(kRasterThreads) __attribute__((amdgpu_waves_per_eu(
                 for (int u2 = 0; u2 < kUnroll; u2++) {
                     const int j = (int)(ef[u2].pm >> 4);
                     const ColTerms ct = col_terms(es[u2], fxl);
+                    // candidates: pixels still compositing, power <= 0, and
+                    // p2 high enough that alpha may reach 1/255
+                    const float lim = kLog2AlphaMinLoose - et[u2].lo;
                     float p2[kPixPerLane];
-                    bool cand = false;
+                    bool cand[kPixPerLane];
 #pragma unroll
                     for (int q = 0; q < kPixPerLane; q++) {
                         p2[q] = splat_p2(ct, et[u2].C2, es[u2].v - fy[q]);
-                        cand |= (T[q] > 0.f) & (p2[q] <= 0.f) & (p2[q] + et[u2].lo >= kLog2AlphaMinLoose);
+                        cand[q] = (T[q] > 0.f) & (p2[q] <= 0.f) & (p2[q] >= lim);
                     }
                     // no pixel of the tile can reach 1/255: nothing to do
-                    if (!__any(cand)) continue;
+                    if (!__any(cand[0] | cand[1] | cand[2] | cand[3])) continue;
 #pragma unroll
                     for (int q = 0; q < kPixPerLane; q++) {
                         const float alpha = fminf(kAlphaMax, splat_alpha_pre(p2[q], et[u2].lo));
-                        const float testT = T[q] * (1.f - alpha);
-                        const bool hit = p2[q] <= 0.f && alpha >= kAlphaMin;
+                        const float aT = alpha * T[q];
+                        const float testT = T[q] - aT;   // T (1 - alpha)
+                        const bool hit = cand[q] && alpha >= kAlphaMin;
                         const bool blend = hit && testT >= kTMin;
-                        const bool stop = hit && testT < kTMin && T[q] > 0.f;
+                        const bool stop = hit && !(testT >= kTMin);
                         if (STATS) {
                             nb[q] += blend ? 1u : 0u;
                             ne[q] = stop ? (uint32_t)j + 1u : ne[q];
                         }
-                        const float wgt = blend ? alpha * T[q] : 0.f;
+                        const float wgt = blend ? aT : 0.f;
                         cr[q] = fmaf(et[u2].r, wgt, cr[q]);
                         cg[q] = fmaf(et[u2].g, wgt, cg[q]);
                         cb[q] = fmaf(ef[u2].b, wgt, cb[q]);

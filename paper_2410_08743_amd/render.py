@@ -284,10 +284,10 @@ def pose_adam(poses, dpose, m, v, steps, lr_start, lr_end, total_steps, beta1=0.
 
 class _RenderFn(torch.autograd.Function):
     @staticmethod
-    def forward(ctx, means, scales, quats, opacities, sh, tau, poses, cams, sh_degree, rast):
+    def forward(ctx, means, scales, quats, opacities, sh, tau, poses, cams, sh_degree, rast, check):
         g = GaussianParams(means.contiguous(), scales.contiguous(), quats.contiguous(),
                            opacities.contiguous(), sh.contiguous(), sh_degree)
-        images, _ = rast.forward(g, cams, poses.detach())
+        images, _ = rast.forward(g, cams, poses.detach(), check=check)
         ctx.g, ctx.cams, ctx.rast = g, cams, rast
         ctx.save_for_backward(poses)
         return images
@@ -301,23 +301,25 @@ class _RenderFn(torch.autograd.Function):
         out = ctx.rast.backward(ctx.g, ctx.cams, poses.detach(), dl.contiguous(), want=want,
                                 pose=need_pose)
         grads = [out.get(k) for k in names]
-        return (*grads, out.get("pose"), None, None, None, None)
+        return (*grads, out.get("pose"), None, None, None, None, None)
 
 
 def render(g: GaussianParams, cams: Sequence, poses: torch.Tensor, tau: Optional[torch.Tensor] = None,
-           rast: Optional[Rasterizer] = None, params=None):
+           rast: Optional[Rasterizer] = None, params=None, check: bool = True):
     """Differentiable render of len(cams) views; returns the packed images.
 
     `params` (optional) is a tuple (means, scales, quats, opacities, sh) of
     tensors that require grad; by default the tensors of `g` are used.  `tau`
     ([V, 6], zeros) receives dL/dtau, the left se(3) twist gradient at the
     given poses (tau is a tangent at `poses` and is not applied to them).
+    With check=False nothing synchronises; `rast.overflowed()` then tells
+    afterwards whether any render ran out of instance capacity.
     """
     rast = rast or Rasterizer()
     if tau is None:
         tau = torch.zeros((len(cams), 6), dtype=torch.float32, device=poses.device)
     p = params or (g.means, g.scales, g.quats, g.opacities, g.sh)
-    return _RenderFn.apply(*p, tau, poses, list(cams), g.sh_degree, rast)
+    return _RenderFn.apply(*p, tau, poses, list(cams), g.sh_degree, rast, check)
 
 
 def solve_poses(g: GaussianParams, cams: Sequence, targets: torch.Tensor, init_poses: torch.Tensor,

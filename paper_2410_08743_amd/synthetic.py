@@ -224,6 +224,70 @@ def joint(seed=1003, n=1_000_000, n_views=20):
     return wl
 
 
+def room(seed=1004, n=500_000, n_frames=100):
+    """Synthetic indoor scene for sequential tracking: a 6 x 3 x 5 box room
+    (x in [-3, 3], y in [-1.5, 1.5] with y down, z in [-2.5, 2.5]); 80 % of
+    the means on the six walls (normal jitter N(0, 0.01^2), scale along the
+    wall normal x0.1), 20 % inside 10 random boxes; log-scales
+    U[log .01, log .04], opacities U(.3, .95), SH degree 3 with a smoothly
+    varying base colour and higher terms N(0, 0.05^2).  Camera 1200x680, fx = fy = 600, principal point at
+    the centre.  Trajectory: a smooth random walk of n_frames poses inside
+    the room, about 0.05 units and 1.5 degrees of yaw per frame, looking
+    roughly along the room's long axis."""
+    rng = rng_for(seed, 0)
+    half = np.array([3.0, 1.5, 2.5])
+    n_wall = int(0.8 * n)
+    face = rng.integers(0, 6, n_wall)
+    axis = face // 2
+    sign = np.where(face % 2 == 0, -1.0, 1.0)
+    means = rng.uniform(-1.0, 1.0, (n, 3)) * half
+    idx = np.arange(n_wall)
+    means[idx, axis] = sign * half[axis] + rng.normal(0.0, 0.01, n_wall)
+    centres = rng.uniform(-1.0, 1.0, (10, 3)) * (half - 0.6)
+    sizes = rng.uniform(0.15, 0.5, (10, 3))
+    which = rng.integers(0, 10, n - n_wall)
+    means[n_wall:] = centres[which] + rng.uniform(-1.0, 1.0, (n - n_wall, 3)) * sizes[which]
+    scales = np.exp(rng.uniform(np.log(0.01), np.log(0.04), (n, 3)))
+    scales[idx, axis] *= 0.1
+    # wall Gaussians keep the identity rotation, so their thin axis is the
+    # wall normal; the others are turned at random
+    quats = np.zeros((n, 4), dtype=np.float32)
+    quats[:, 0] = 1.0
+    quats[n_wall:] = random_quats(rng, n - n_wall)
+    opac = rng.uniform(0.3, 0.95, n).astype(np.float32)
+    # colour varies smoothly over the room (a sum of plane waves of 0.3-1.5
+    # wavelength per channel, plus small per-Gaussian jitter), like painted
+    # walls and furniture: per-Gaussian white-noise colour would leave frame
+    # to frame tracking no basin of attraction at these motions
+    base = np.full((n, 3), 0.5)
+    for ch in range(3):
+        for _ in range(4):
+            kvec = rng.normal(0.0, 1.0, 3)
+            kvec *= 2.0 * np.pi / (rng.uniform(0.3, 1.5) * np.linalg.norm(kvec))
+            base[:, ch] += 0.12 * np.sin(means @ kvec + rng.uniform(0.0, 2.0 * np.pi))
+    base = np.clip(base + rng.normal(0.0, 0.03, (n, 3)), 0.0, 1.0)
+    sh = colour_sh(rng, n, 3, base=base, higher_std=0.05)
+    cam = Camera(1200, 680, 600.0, 600.0, 600.0, 340.0)
+    trng = rng_for(seed, 1)
+    pos = np.array([0.0, 0.2, -1.6])
+    yaw = 0.0
+    vel = np.zeros(3)
+    poses = []
+    for _ in range(n_frames):
+        vel = 0.7 * vel + 0.3 * trng.normal(0.0, 0.05, 3) * np.array([1.0, 0.2, 1.0])
+        vel *= 0.05 / max(np.linalg.norm(vel), 1e-9)
+        pos = np.clip(pos + vel, -half + 0.8, half - 0.8)
+        yaw += np.deg2rad(trng.normal(0.0, 1.5))
+        yaw = float(np.clip(yaw, -np.deg2rad(30.0), np.deg2rad(30.0)))
+        fwd = np.array([np.sin(yaw), 0.0, np.cos(yaw)])
+        poses.append(look_at_pose(pos, pos + fwd))
+    wl = Workload("track-500k-1200x680-sh3", GaussianSet(means.astype(np.float32),
+                  scales.astype(np.float32), quats, opac, sh, 3), cam,
+                  poses[0].astype(np.float32), None)
+    wl.extra["trajectory"] = np.stack(poses).astype(np.float32)
+    return wl
+
+
 REQUEST_SIZES = ((320, 240), (640, 480), (1008, 756))
 
 

@@ -34,10 +34,21 @@ def _case(name):
         return random_case(14, 3, 120, 90, 400, roi=(32, 16, 61, 50))
     if name == "sh3-dense":
         return random_case(15, 3, 128, 96, 3000, depth=(1.0, 8.0))
+    if name == "sh1-thin":
+        # needle-like splats (one axis x0.02, one x3) and opacities down to
+        # just above 1/255: the per-entry culling bound at its margins
+        sc, cam, pose = random_case(16, 1, 96, 80, 600, depth=(0.5, 5.0))
+        rng = S.rng_for(16, 9)
+        k = rng.integers(0, 3, sc.n)
+        idx = np.arange(sc.n)
+        sc.scales[idx, k] *= np.float32(0.02)
+        sc.scales[idx, (k + 1) % 3] *= np.float32(3.0)
+        sc.opacities[:] = rng.uniform(0.005, 0.99, sc.n).astype(np.float32)
+        return sc, cam, pose
     raise KeyError(name)
 
 
-CASES = ["tiny", "sh0", "sh1-ragged", "sh2-near", "sh3-roi", "sh3-dense"]
+CASES = ["tiny", "sh0", "sh1-ragged", "sh2-near", "sh3-roi", "sh3-dense", "sh1-thin"]
 
 
 def _gpu(sc, cams, poses, up=None, cap=0, want=("means", "scales", "quats", "opacities", "sh")):
@@ -173,7 +184,7 @@ def test_backward_parity(name):
     up = _upstream(21, cam)
     run = _gpu(sc, [cam], [pose], up=[up])
     ref = oracle.backward(sc, cam, pose, up)
-    g2 = run["rast"].inspect(run["g"], [cam], "grad2d").cpu().numpy().reshape(9, -1).T
+    g2 = run["rast"].inspect(run["g"], [cam], "grad2d").cpu().numpy().reshape(-1, 9)
     report = {"splat2d": rel_l2(g2, ref["splat2d"])}
     for k in ("means", "scales", "quats", "opacities", "sh"):
         report[k] = rel_l2(run[k], ref[k])
