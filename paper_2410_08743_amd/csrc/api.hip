@@ -229,10 +229,11 @@ Layout make_layout(int64_t n, int32_t sh_degree, int32_t V, const ViewsK &views,
     L.hist = take((size_t)kSortBins * L.nblk_sort * 4);
     L.digit_tot = take((size_t)kSortBins * 4);
     L.ranges = take((size_t)L.total_tiles * 8);
+    L.tile_order = take((size_t)L.total_tiles * 4);
     L.tfinal = take((size_t)pix * 4);
     L.ncontrib = take((size_t)pix * 4);
     L.stats = take((size_t)pix * 8);
-    L.slots = take(9 * capz * 4);
+    L.slots = take(9 * (size_t)kSplitBwd * capz * 4);
     L.grad2d = take(9 * vn * 4);
     L.posepart = take((size_t)V * L.nblk_pre * 6 * 8);
     L.total = off;

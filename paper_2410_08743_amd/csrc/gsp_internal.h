@@ -45,6 +45,17 @@ constexpr int kPoseReduceBlock = 256;
 // instances are spread over the splats.
 constexpr int kWindow = 1024;
 constexpr int kWindowThreads = 256;
+// Workgroups per 16 x 16 tile in the forward and the backward rasterizer
+// (each takes a strip of 16 / split rows); every instance has one 9-float
+// gradient slot per backward part.
+#ifndef GSP_SPLIT_FWD
+#define GSP_SPLIT_FWD 4
+#endif
+#ifndef GSP_SPLIT_BWD
+#define GSP_SPLIT_BWD 1
+#endif
+constexpr int kSplitFwd = GSP_SPLIT_FWD;
+constexpr int kSplitBwd = GSP_SPLIT_BWD;
 
 // Per-view constants, computed on the host once per call.
 struct ViewK {
@@ -72,7 +83,7 @@ struct Layout {
     int32_t V, S, total_tiles, nblk_pre, nblk_vn, nblk_sort, tile_bits, tile_passes, nwin_max;
     size_t geom, color, rect, depth, tiles, offsets, offk, wstart, blocksum, counters;
     size_t dkeys0, dkeys1, dvals0, dvals1;
-    size_t keys0, keys1, vals0, vals1, hist, digit_tot, ranges;
+    size_t keys0, keys1, vals0, vals1, hist, digit_tot, ranges, tile_order;
     size_t tfinal, ncontrib, stats, slots, grad2d, posepart;
     size_t total;
 };

@@ -54,13 +54,15 @@ __device__ __forceinline__ void rot_vjp(double w, double x, double y, double z, 
 }
 
 // 2D gradient of each splat: the sum of its instance slots in slot order (one
-// running sum from zero, first slot to last).  One block per work window: the
+// running sum from zero, first instance to last, and within an instance its
+// rasterizer parts in order).  One block per work window: the
 // window's slots form one contiguous range, which the block copies into LDS
 // with all of each thread's loads in flight at once; the (splat, component)
 // pairs are then spread over the threads, nine neighbouring threads per
 // splat.  Slots past the first kWindow of the range -- the tail of a long last
 // splat -- are read from global memory.
-constexpr int kSlotPerThread = kWindow * 9 / kWindowThreads;
+constexpr int kSlotFloats = 9 * kSplitBwd;   // one 9-float slot per backward part
+constexpr int kSlotPerThread = kWindow * kSlotFloats / kWindowThreads;
 
 __global__ __launch_bounds__(kWindowThreads) void k_slot_reduce(const uint32_t *order,
                                                                 const uint32_t *offk,
@@ -68,9 +70,8 @@ __global__ __launch_bounds__(kWindowThreads) void k_slot_reduce(const uint32_t *
                                                                 const uint32_t *counters,
                                                                 const float *slots, float *grad2d,
                                                                 int vn) {
-    __shared__ float s_sl[kWindow * 9];
+    __shared__ float s_sl[kWindow * kSlotFloats];
     __shared__ uint32_t s_off[kWindow + 1];
-    __shared__ uint32_t s_idx[kWindow];
     const int b = blockIdx.x;
     if (counters[kCntOverflow] != 0u) {
         // no instance was emitted: every 2D gradient is zero
@@ -83,18 +84,15 @@ __global__ __launch_bounds__(kWindowThreads) void k_slot_reduce(const uint32_t *
     const uint32_t kb = wstart[b], ke = wstart[b + 1];
     const int nk = (int)(ke - kb);   // at most kWindow
     const uint32_t e0 = offk[kb], ne = offk[ke] - e0;
-    const uint32_t nf = 9u * min(ne, (uint32_t)kWindow);
-    const float *src = slots + 9 * (size_t)e0;
+    const uint32_t nf = (uint32_t)kSlotFloats * min(ne, (uint32_t)kWindow);
+    const float *src = slots + kSlotFloats * (size_t)e0;
     float tmp[kSlotPerThread];
 #pragma unroll
     for (int r = 0; r < kSlotPerThread; r++) {
         const uint32_t f = (uint32_t)(r * kWindowThreads + threadIdx.x);
         tmp[r] = f < nf ? src[f] : 0.f;
     }
-    for (int j = threadIdx.x; j < nk; j += kWindowThreads) {
-        s_off[j] = offk[kb + j] - e0;
-        s_idx[j] = order[kb + j];
-    }
+    for (int j = threadIdx.x; j < nk; j += kWindowThreads) s_off[j] = offk[kb + j] - e0;
     if (threadIdx.x == 0) s_off[nk] = ne;
 #pragma unroll
     for (int r = 0; r < kSlotPerThread; r++) s_sl[r * kWindowThreads + threadIdx.x] = tmp[r];
@@ -105,9 +103,15 @@ __global__ __launch_bounds__(kWindowThreads) void k_slot_reduce(const uint32_t *
         const uint32_t mid = min(hi, (uint32_t)kWindow);
         float d = 0.f;
         uint32_t e = lo;
-        for (; e < mid; e++) d += s_sl[9 * e + c];
-        for (; e < hi; e++) d += src[9 * (size_t)e + c];
-        grad2d[9 * (size_t)s_idx[j] + c] = d;
+        for (; e < mid; e++) {
+#pragma unroll
+            for (int p = 0; p < kSplitBwd; p++) d += s_sl[kSlotFloats * e + 9 * p + c];
+        }
+        for (; e < hi; e++) {
+#pragma unroll
+            for (int p = 0; p < kSplitBwd; p++) d += src[kSlotFloats * (size_t)e + 9 * p + c];
+        }
+        grad2d[9 * (size_t)order[kb + j] + c] = d;
     }
 }
 

@@ -26,7 +26,11 @@
 
 namespace gsp {
 
+constexpr int kSplit = kSplitBwd;
+constexpr int kPixPerLane = 4 / kSplit;   // pixels per lane, one column
+
 struct BwdArgs {
+    const uint32_t *order;   // launch order of the tiles (longest lists first)
     const uint2 *ranges;
     const uint32_t *vals;
     const float4 *geom;
@@ -35,7 +39,8 @@ struct BwdArgs {
     const uint32_t *offsets;
     const float *tfinal;
     const uint32_t *ncontrib;
-    float *slots;          // [cap][9]
+    float *slots;          // [cap][kSplit][9]
+    int total_tiles;
 };
 
 constexpr uint32_t kNoSlot = 0xffffffffu;
@@ -56,7 +61,10 @@ __global__ __launch_bounds__(kRasterThreads) __attribute__((amdgpu_waves_per_eu(
     __shared__ StagedA sA[kBatch];
     __shared__ StagedB sB[kBatch];
     __shared__ StagedC sC[kBatch];
-    const int tile = blockIdx.x;
+    int rank, part;
+    part_of_block<kSplit>(blockIdx.x, rank, part);
+    if (rank >= a.total_tiles) return;
+    const int tile = (int)a.order[rank];
     const ViewK &vw = views.v[view_of_tile(views, tile)];
     const int lt = tile - vw.tile_base;
     const int tx = lt % vw.gw, ty = lt / vw.gw;
@@ -65,6 +73,8 @@ __global__ __launch_bounds__(kRasterThreads) __attribute__((amdgpu_waves_per_eu(
     const int lx = lane & 15, ly = lane >> 4;
     const int rx = kTile * tx + lx;
     const int P = vw.roi_w * vw.roi_h;
+    const int row0 = part * (kTile / kSplit);   // first tile row of this part
+    float *const pslots = a.slots + 9 * part;   // this part's slot of each instance
 
     // Which reduced value this lane stores, and its scale (see wave_sum9 and
     // the base-2 conic of raster_common.h).
@@ -82,10 +92,11 @@ __global__ __launch_bounds__(kRasterThreads) __attribute__((amdgpu_waves_per_eu(
     int maxlast = 0;
 #pragma unroll
     for (int q = 0; q < kPixPerLane; q++) {
-        const int ry = kTile * ty + ly + 4 * q;
+        const int ryl = row0 + ly + 4 * q;
+        const int ry = kTile * ty + ryl;
         const bool in = rx < vw.roi_w && ry < vw.roi_h;
         const size_t pix = (size_t)ry * vw.roi_w + rx;
-        fy[q] = (float)(ly + 4 * q);
+        fy[q] = (float)ryl;
         T[q] = in ? a.tfinal[vw.pix_base + pix] : 1.f;
         last[q] = in ? (int)a.ncontrib[vw.pix_base + pix] : 0;
         const float *dl = vw.dl;
@@ -100,11 +111,11 @@ __global__ __launch_bounds__(kRasterThreads) __attribute__((amdgpu_waves_per_eu(
 
     const uint2 rg = a.ranges[tile];
     const int len = (int)(rg.y - rg.x);
-    // entries no pixel blended get zero slots
+    // entries no pixel of this part blended get zero slots
     for (int k = maxlast + lane; k < len; k += kBatch) {
         const uint32_t e = slot_of(a, a.vals[rg.x + k], tx, ty);
 #pragma unroll
-        for (int c = 0; c < 9; c++) a.slots[9 * (size_t)e + c] = 0.f;
+        for (int c = 0; c < 9; c++) pslots[9 * kSplit * (size_t)e + c] = 0.f;
     }
 
     // batches of 64 entries ending at hi, walked back to front; positions
@@ -128,9 +139,11 @@ __global__ __launch_bounds__(kRasterThreads) __attribute__((amdgpu_waves_per_eu(
     for (int hi = maxlast; hi > 0; hi -= kBatch) {
         const int lo = hi - kBatch;
         // Stage, in list order, the entries that can reach 1/255 somewhere in
-        // the tile; a dropped entry blends nowhere and gets a zero slot.
+        // this part's rows; a dropped entry blends nowhere there and gets a
+        // zero slot.
         const float u = rel_coord(g0.x, g0.z, px0), v = rel_coord(g0.y, g0.w, py0);
-        const uint32_t mask = gslot != kNoSlot ? band_mask(u, v, g1.x, g1.y, g1.z, g1.w) : 0u;
+        const uint32_t mask =
+            gslot != kNoSlot ? band_mask<kSplit>(u, v, g1.x, g1.y, g1.z, g1.w, row0) : 0u;
         const unsigned long long kept = __ballot(mask != 0u);
         const int nk = __popcll(kept);
         if (mask != 0u) {
@@ -141,7 +154,7 @@ __global__ __launch_bounds__(kRasterThreads) __attribute__((amdgpu_waves_per_eu(
                             ((uint32_t)(lo + lane) << 4) | mask};
         } else if (gslot != kNoSlot) {
 #pragma unroll
-            for (int c = 0; c < 9; c++) a.slots[9 * (size_t)gslot + c] = 0.f;
+            for (int c = 0; c < 9; c++) pslots[9 * kSplit * (size_t)gslot + c] = 0.f;
         }
         const int nkr = (nk + kBwdUnroll - 1) & ~(kBwdUnroll - 1);
         if (lane >= nk && lane < nkr) {   // padding up to the unroll width
@@ -170,15 +183,17 @@ __global__ __launch_bounds__(kRasterThreads) __attribute__((amdgpu_waves_per_eu(
                 const float lim = kLog2AlphaMinLoose - t.lo;
                 float p2[kPixPerLane];
                 bool cand[kPixPerLane];
+                bool any = false;
 #pragma unroll
                 for (int q = 0; q < kPixPerLane; q++) {
                     p2[q] = splat_p2(ct, t.C2, s.v - fy[q]);
                     cand[q] = (pos < last[q]) & (p2[q] <= 0.f) & (p2[q] >= lim);
+                    any |= cand[q];
                 }
                 float x0 = 0.f, x1 = 0.f, x2 = 0.f;
-                if (__any(cand[0] || cand[1] || cand[2] || cand[3])) {
+                if (__any(any)) {
                     const float col3[3] = {t.r, t.g, ew[u].b};
-                    // Per lane, dx is the same for its four pixels, so the
+                    // Per lane, dx is the same for all its pixels, so the
                     // conic and centre gradients need only the moments
                     // sum dp, sum dp dy, sum dp dy^2 of dL/dpower over them.
                     float m0 = 0.f, my = 0.f, myy = 0.f, gc[3] = {0.f, 0.f, 0.f};
@@ -226,7 +241,7 @@ __global__ __launch_bounds__(kRasterThreads) __attribute__((amdgpu_waves_per_eu(
                 if (comp >= 0 && ew[u].slot != kNoSlot) {
                     const float val = col == 0 ? x0 : (col == 1 ? x1 : x2);
                     const float f = comp == 5 ? ew[u].inv_o : scale;
-                    a.slots[9 * (size_t)ew[u].slot + comp] = val * f;
+                    pslots[9 * kSplit * (size_t)ew[u].slot + comp] = val * f;
                 }
             }
         }
@@ -238,6 +253,7 @@ hipError_t launch_raster_bwd(const ViewsK &views, const Layout &L, char *ws, con
                              hipStream_t s) {
     if (L.total_tiles == 0) return hipSuccess;
     BwdArgs a;
+    a.order = region<uint32_t>(ws, L.tile_order);
     a.ranges = region<uint2>(ws, L.ranges);
     a.vals = vals;
     a.geom = region<float4>(ws, L.geom);
@@ -247,7 +263,9 @@ hipError_t launch_raster_bwd(const ViewsK &views, const Layout &L, char *ws, con
     a.tfinal = region<float>(ws, L.tfinal);
     a.ncontrib = region<uint32_t>(ws, L.ncontrib);
     a.slots = region<float>(ws, L.slots);
-    hipLaunchKernelGGL(k_raster_bwd, dim3(L.total_tiles), dim3(kRasterThreads), 0, s, a, views);
+    a.total_tiles = L.total_tiles;
+    hipLaunchKernelGGL(k_raster_bwd, dim3(raster_blocks<kSplit>(L.total_tiles)), dim3(kRasterThreads), 0, s,
+                       a, views);
     return hipGetLastError();
 }
 

@@ -20,12 +20,19 @@
 
 namespace gsp {
 
-// One wavefront (64 lanes) rasterizes one 16 x 16 tile; lane l owns pixels
-// (l % 16, l / 16 + 4 q) for q = 0..3.
+// SPLIT wavefronts (64 lanes each) rasterize one 16 x 16 tile, each a
+// horizontal strip of 16 / SPLIT rows; in part h, lane l owns pixels
+// (l % 16, 16 h / SPLIT + l / 16 + 4 q) for q < 4 / SPLIT, so the q-th
+// pixels of all lanes form the 16 x 4 band 4 h / SPLIT + q of the tile.
+// The parts of a tile are independent workgroups: more of them keep the
+// SIMDs busy (a 1008 x 756 view has only 3024 tiles) and each walks, culls
+// and stops for its own rows.
 constexpr int kRasterThreads = 64;
-constexpr int kPixPerLane = 4;
 constexpr int kBatch = 64;          // list entries staged in LDS at a time
-constexpr int kUnroll = 4;          // entries per step of the inner loop
+#ifndef GSP_FWD_UNROLL
+#define GSP_FWD_UNROLL 4
+#endif
+constexpr int kUnroll = GSP_FWD_UNROLL;   // entries per step of the inner loop
 
 constexpr float kLn2 = 0.6931471805599453f;
 // A splat can reach alpha >= 1/255 at a pixel only if p2 + log2(o) is at least
@@ -75,8 +82,8 @@ __device__ __forceinline__ float splat_alpha_pre(float p2, float lo) {
     return __builtin_amdgcn_exp2f(p2 + lo);
 }
 
-// Bit q of the result is set when some pixel of rows 4q .. 4q+3 of the tile
-// may reach alpha >= 1/255, i.e. when the rasterizer's own candidate test
+// Bit q of the result is set when some pixel of rows row0 + 4q .. row0 + 4q + 3
+// of the tile (q < 4 / SPLIT) may reach alpha >= 1/255, i.e. when the rasterizer's own candidate test
 // (p2 >= kLog2AlphaMinLoose - lo) may pass there; a clear bit is a proof that
 // it fails at every pixel of those rows.  Per pixel row, p2 is a concave
 // quadratic in dx whose maximum over the row's dx range [u - 15, u] is taken
@@ -84,9 +91,11 @@ __device__ __forceinline__ float splat_alpha_pre(float p2, float lo) {
 // both this bound and the rasterizer's evaluation: 0.02 plus 1e-5 times the
 // largest magnitude the three terms of p2 take in the row, some forty times
 // the error of either three-operation evaluation.
+template <int SPLIT>
 __device__ __forceinline__ uint32_t band_mask(float u, float v, float A2, float B2, float C2,
-                                              float lo) {
-    if (!(A2 < 0.f) || !(C2 < 0.f)) return 0xfu;   // not negative definite: keep all
+                                              float lo, int row0) {
+    constexpr int kRows = kTile / SPLIT;
+    if (!(A2 < 0.f) || !(C2 < 0.f)) return (1u << (4 / SPLIT)) - 1u;   // not negative definite
     const float xa = u - (float)(kTile - 1), xb = u;
     const float dxm = fmaxf(fabsf(xa), fabsf(xb));
     const float half_inv = -0.5f / A2;
@@ -94,8 +103,8 @@ __device__ __forceinline__ uint32_t band_mask(float u, float v, float A2, float 
     const float adxm2 = fabsf(A2) * dxm * dxm;
     uint32_t mask = 0u;
 #pragma unroll
-    for (int r = 0; r < kTile; r++) {
-        const float dy = v - (float)r;
+    for (int r = 0; r < kRows; r++) {
+        const float dy = v - (float)(row0 + r);
         const float bdy = B2 * dy;
         const float cdy2 = C2 * dy * dy;
         const float xs = fminf(fmaxf(bdy * half_inv, xa), xb);
@@ -111,6 +120,29 @@ __device__ __forceinline__ uint32_t band_mask(float u, float v, float A2, float 
 __device__ __forceinline__ int kept_rank(unsigned long long kept) {
     return (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(kept >> 32),
                                           __builtin_amdgcn_mbcnt_lo((uint32_t)kept, 0u));
+}
+
+// Workgroup -> (rank of the tile in launch order, part).  The SPLIT parts
+// of one tile go to workgroups 8 apart, which the dispatcher places on the
+// same XCD (workgroups are dealt round-robin over the 8 XCDs), so the later
+// parts find the tile's splat records in that XCD's L2.
+template <int SPLIT>
+__device__ __forceinline__ void part_of_block(int b, int &rank, int &part) {
+    if (SPLIT == 1) {
+        rank = b;
+        part = 0;
+    } else {
+        const int grp = b / (8 * SPLIT), r = b % (8 * SPLIT);
+        rank = grp * 8 + (r & 7);
+        part = r >> 3;
+    }
+}
+
+// Workgroups of a rasterizer launch over `tiles` tiles (a multiple of
+// 8 SPLIT when split; the extra ones exit at once).
+template <int SPLIT>
+inline int raster_blocks(int tiles) {
+    return SPLIT == 1 ? tiles : ((tiles + 7) / 8) * 8 * SPLIT;
 }
 
 __device__ __forceinline__ int view_of_tile(const ViewsK &views, int tile) {

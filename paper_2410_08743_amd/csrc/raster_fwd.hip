@@ -6,18 +6,23 @@
 // alpha < 1/255 are skipped; compositing stops before a splat that would
 // take the transmittance below 1e-4; colour = sum c alpha T + T_final bg.
 //
-// MI355X design: one wavefront per 16 x 16 tile and four pixels per lane, the
-// four in one column so that they share the splat's dx terms.  The wave
-// stages 64 list entries at a time in LDS (list ids read coalesced, splat
-// records gathered from L2/MALL; entries past the end are inert), and the
-// inner loop runs eight entries per step without bounds checks, each entry a
-// broadcast LDS read that feeds four pixel evaluations of two FMAs and one
-// v_exp_f32.  A tile needs no barrier across waves, and the wave leaves as
-// soon as its 256 pixels are saturated.
+// MI355X design: kSplit wavefronts per 16 x 16 tile, each a strip of rows
+// with the pixels of a lane in one column so that they share the splat's dx
+// terms.  A wave stages 64 list entries at a time in LDS (list ids read
+// coalesced, splat records gathered one batch ahead), keeping only the
+// entries that can reach 1/255 in its rows (each lane bounds its own entry,
+// then a ballot compacts the batch), and its inner loop runs the kept
+// entries a few at a time, each a broadcast LDS read that feeds the lane's
+// pixel evaluations of two FMAs and one v_exp_f32.  The waves of a tile need
+// no barrier between them, and each leaves as soon as its pixels are
+// saturated.
 #include "block_ops.h"
 #include "raster_common.h"
 
 namespace gsp {
+
+constexpr int kSplit = kSplitFwd;
+constexpr int kPixPerLane = 4 / kSplit;   // pixels per lane, one column
 
 __global__ __launch_bounds__(256) void k_ranges(const uint32_t *keys, const uint32_t *counters,
                                                 uint2 *ranges) {
@@ -29,7 +34,37 @@ __global__ __launch_bounds__(256) void k_ranges(const uint32_t *keys, const uint
     if (k == M - 1 || keys[k + 1] != tile) ranges[tile].y = (uint32_t)(k + 1);
 }
 
+// Launch order of the tiles: longest lists first (in buckets of 16
+// entries), so that the longest tiles do not start last and leave a tail.
+// The order only decides which workgroup takes which tile; every tile's
+// result is the same in any order.
+constexpr int kOrderBuckets = 64;
+
+__global__ __launch_bounds__(1024) void k_tile_order(const uint2 *ranges, int total_tiles,
+                                                     uint32_t *order) {
+    __shared__ uint32_t cnt[kOrderBuckets], base[kOrderBuckets];
+    const int t = threadIdx.x;
+    if (t < kOrderBuckets) cnt[t] = 0;
+    __syncthreads();
+    auto bucket = [&](int tile) {
+        const uint2 r = ranges[tile];
+        return kOrderBuckets - 1 - (int)min((r.y - r.x) >> 4, (uint32_t)(kOrderBuckets - 1));
+    };
+    for (int k = t; k < total_tiles; k += 1024) atomicAdd(&cnt[bucket(k)], 1u);
+    __syncthreads();
+    if (t == 0) {
+        uint32_t acc = 0;
+        for (int b = 0; b < kOrderBuckets; b++) {
+            base[b] = acc;
+            acc += cnt[b];
+        }
+    }
+    __syncthreads();
+    for (int k = t; k < total_tiles; k += 1024) order[atomicAdd(&base[bucket(k)], 1u)] = (uint32_t)k;
+}
+
 struct FwdArgs {
+    const uint32_t *order;
     const uint2 *ranges;
     const uint32_t *vals;
     const float4 *geom;
@@ -38,7 +73,16 @@ struct FwdArgs {
     uint32_t *ncontrib;
     uint32_t *neval;    // STATS only: entries evaluated per pixel (up to the stop)
     uint32_t *nblend;   // STATS only: entries blended per pixel
+    int total_tiles;
 };
+
+template <int N>
+__device__ __forceinline__ bool any_active(const float (&T)[N]) {
+    bool a = false;
+#pragma unroll
+    for (int q = 0; q < N; q++) a |= T[q] > 0.f;
+    return __any(a);
+}
 
 // STATS = true is a measurement variant that also counts, per pixel, the
 // evaluated and blended (pixel, splat) pairs of the algorithm -- every list
@@ -49,7 +93,10 @@ __global__ __launch_bounds__(kRasterThreads) __attribute__((amdgpu_waves_per_eu(
     __shared__ StagedA sA[kBatch];
     __shared__ StagedB sB[kBatch];
     __shared__ StagedF sF[kBatch];
-    const int tile = blockIdx.x;
+    int rank, part;
+    part_of_block<kSplit>(blockIdx.x, rank, part);
+    if (rank >= a.total_tiles) return;
+    const int tile = (int)a.order[rank];
     const ViewK &vw = views.v[view_of_tile(views, tile)];
     const int lt = tile - vw.tile_base;
     const int tx = lt % vw.gw, ty = lt / vw.gw;
@@ -57,6 +104,7 @@ __global__ __launch_bounds__(kRasterThreads) __attribute__((amdgpu_waves_per_eu(
     const int lane = threadIdx.x;
     const int lx = lane & 15, ly = lane >> 4;
     const int rx = kTile * tx + lx;
+    const int row0 = part * (kTile / kSplit);   // first tile row of this part
 
     // T > 0 while a pixel composites; a pixel that stopped (or lies outside
     // the region) keeps -T, so later splats can neither blend nor restart it.
@@ -66,11 +114,12 @@ __global__ __launch_bounds__(kRasterThreads) __attribute__((amdgpu_waves_per_eu(
 #pragma unroll
     for (int q = 0; q < kPixPerLane; q++) {
         ne[q] = nb[q] = 0;
-        const bool in = rx < vw.roi_w && kTile * ty + ly + 4 * q < vw.roi_h;
+        const int ryl = row0 + ly + 4 * q;
+        const bool in = rx < vw.roi_w && kTile * ty + ryl < vw.roi_h;
         T[q] = in ? 1.f : -1.f;
         cr[q] = cg[q] = cb[q] = 0.f;
         last[q] = 0;
-        fy[q] = (float)(ly + 4 * q);
+        fy[q] = (float)ryl;
     }
     const float fxl = (float)lx;
 
@@ -92,77 +141,77 @@ __global__ __launch_bounds__(kRasterThreads) __attribute__((amdgpu_waves_per_eu(
     };
     gather(lane);
     for (int b0 = 0; b0 < len; b0 += kBatch) {
-        if (!__any(T[0] > 0.f || T[1] > 0.f || T[2] > 0.f || T[3] > 0.f)) break;
-        // Stage the entries that can reach 1/255 somewhere in the tile, in
-        // list order; the others cannot change any pixel and are dropped.
-        {
-            const float u = rel_coord(g0.x, g0.z, px0), v = rel_coord(g0.y, g0.w, py0);
-            const int k = b0 + lane;
-            const uint32_t mask = k < len ? band_mask(u, v, g1.x, g1.y, g1.z, g1.w) : 0u;
-            const unsigned long long kept = __ballot(mask != 0u);
-            const int nk = __popcll(kept);
-            if (mask != 0u) {
-                const int r = kept_rank(kept);
-                sA[r] = StagedA{u, v, g1.x, g1.y};
-                sB[r] = StagedB{g1.z, g1.w, gc.x, gc.y};
-                sF[r] = StagedF{gc.z, ((uint32_t)k << 4) | mask};
-            }
-            // padding up to the unroll width: inert records
-            if (lane >= nk && lane < ((nk + kUnroll - 1) & ~(kUnroll - 1))) {
-                sA[lane] = StagedA{0.f, 0.f, -1.f, 0.f};
-                sB[lane] = StagedB{-1.f, -INFINITY, 0.f, 0.f};
-                sF[lane] = StagedF{0.f, 0u};
-            }
-            __syncthreads();
-            gather(b0 + kBatch + lane);
-            for (int j0 = 0; j0 < nk; j0 += kUnroll) {
-                StagedA es[kUnroll];
-                StagedB et[kUnroll];
-                StagedF ef[kUnroll];
+        if (!any_active(T)) break;
+        // Stage the entries that can reach 1/255 somewhere in this part's
+        // rows, in list order; the others cannot change any of its pixels.
+        const float u = rel_coord(g0.x, g0.z, px0), v = rel_coord(g0.y, g0.w, py0);
+        const int k = b0 + lane;
+        const uint32_t mask = k < len ? band_mask<kSplit>(u, v, g1.x, g1.y, g1.z, g1.w, row0) : 0u;
+        const unsigned long long kept = __ballot(mask != 0u);
+        const int nk = __popcll(kept);
+        if (mask != 0u) {
+            const int r = kept_rank(kept);
+            sA[r] = StagedA{u, v, g1.x, g1.y};
+            sB[r] = StagedB{g1.z, g1.w, gc.x, gc.y};
+            sF[r] = StagedF{gc.z, ((uint32_t)k << 4) | mask};
+        }
+        // padding up to the unroll width: inert records
+        if (lane >= nk && lane < ((nk + kUnroll - 1) & ~(kUnroll - 1))) {
+            sA[lane] = StagedA{0.f, 0.f, -1.f, 0.f};
+            sB[lane] = StagedB{-1.f, -INFINITY, 0.f, 0.f};
+            sF[lane] = StagedF{0.f, 0u};
+        }
+        __syncthreads();
+        gather(b0 + kBatch + lane);
+        for (int j0 = 0; j0 < nk; j0 += kUnroll) {
+            StagedA es[kUnroll];
+            StagedB et[kUnroll];
+            StagedF ef[kUnroll];
 #pragma unroll
-                for (int u2 = 0; u2 < kUnroll; u2++) {
-                    es[u2] = sA[j0 + u2];
-                    et[u2] = sB[j0 + u2];
-                    ef[u2] = sF[j0 + u2];
+            for (int u2 = 0; u2 < kUnroll; u2++) {
+                es[u2] = sA[j0 + u2];
+                et[u2] = sB[j0 + u2];
+                ef[u2] = sF[j0 + u2];
+            }
+#pragma unroll
+            for (int u2 = 0; u2 < kUnroll; u2++) {
+                const int j = (int)(ef[u2].pm >> 4);
+                const ColTerms ct = col_terms(es[u2], fxl);
+                // candidates: pixels still compositing, power <= 0, and p2
+                // high enough that alpha may reach 1/255
+                const float lim = kLog2AlphaMinLoose - et[u2].lo;
+                float p2[kPixPerLane];
+                bool cand[kPixPerLane];
+                bool any = false;
+#pragma unroll
+                for (int q = 0; q < kPixPerLane; q++) {
+                    p2[q] = splat_p2(ct, et[u2].C2, es[u2].v - fy[q]);
+                    cand[q] = (T[q] > 0.f) & (p2[q] <= 0.f) & (p2[q] >= lim);
+                    any |= cand[q];
                 }
+                // no pixel of this part can reach 1/255: nothing to do
+                if (!__any(any)) continue;
 #pragma unroll
-                for (int u2 = 0; u2 < kUnroll; u2++) {
-                    const int j = (int)(ef[u2].pm >> 4);
-                    const ColTerms ct = col_terms(es[u2], fxl);
-                    // candidates: pixels still compositing, power <= 0, and
-                    // p2 high enough that alpha may reach 1/255
-                    const float lim = kLog2AlphaMinLoose - et[u2].lo;
-                    float p2[kPixPerLane];
-                    bool cand[kPixPerLane];
-#pragma unroll
-                    for (int q = 0; q < kPixPerLane; q++) {
-                        p2[q] = splat_p2(ct, et[u2].C2, es[u2].v - fy[q]);
-                        cand[q] = (T[q] > 0.f) & (p2[q] <= 0.f) & (p2[q] >= lim);
+                for (int q = 0; q < kPixPerLane; q++) {
+                    const float alpha = fminf(kAlphaMax, splat_alpha_pre(p2[q], et[u2].lo));
+                    const float aT = alpha * T[q];
+                    const float testT = T[q] - aT;   // T (1 - alpha)
+                    const bool hit = cand[q] && alpha >= kAlphaMin;
+                    const bool blend = hit && testT >= kTMin;
+                    const bool stop = hit && !(testT >= kTMin);
+                    if (STATS) {
+                        nb[q] += blend ? 1u : 0u;
+                        ne[q] = stop ? (uint32_t)j + 1u : ne[q];
                     }
-                    // no pixel of the tile can reach 1/255: nothing to do
-                    if (!__any(cand[0] | cand[1] | cand[2] | cand[3])) continue;
-#pragma unroll
-                    for (int q = 0; q < kPixPerLane; q++) {
-                        const float alpha = fminf(kAlphaMax, splat_alpha_pre(p2[q], et[u2].lo));
-                        const float aT = alpha * T[q];
-                        const float testT = T[q] - aT;   // T (1 - alpha)
-                        const bool hit = cand[q] && alpha >= kAlphaMin;
-                        const bool blend = hit && testT >= kTMin;
-                        const bool stop = hit && !(testT >= kTMin);
-                        if (STATS) {
-                            nb[q] += blend ? 1u : 0u;
-                            ne[q] = stop ? (uint32_t)j + 1u : ne[q];
-                        }
-                        const float wgt = blend ? aT : 0.f;
-                        cr[q] = fmaf(et[u2].r, wgt, cr[q]);
-                        cg[q] = fmaf(et[u2].g, wgt, cg[q]);
-                        cb[q] = fmaf(ef[u2].b, wgt, cb[q]);
-                        last[q] = blend ? j + 1 : last[q];
-                        T[q] = blend ? testT : (stop ? -T[q] : T[q]);
-                    }
+                    const float wgt = blend ? aT : 0.f;
+                    cr[q] = fmaf(et[u2].r, wgt, cr[q]);
+                    cg[q] = fmaf(et[u2].g, wgt, cg[q]);
+                    cb[q] = fmaf(ef[u2].b, wgt, cb[q]);
+                    last[q] = blend ? j + 1 : last[q];
+                    T[q] = blend ? testT : (stop ? -T[q] : T[q]);
                 }
-                if (!__any(T[0] > 0.f || T[1] > 0.f || T[2] > 0.f || T[3] > 0.f)) break;
             }
+            if (!any_active(T)) break;
         }
         __syncthreads();
     }
@@ -170,7 +219,7 @@ __global__ __launch_bounds__(kRasterThreads) __attribute__((amdgpu_waves_per_eu(
     const int P = vw.roi_w * vw.roi_h;
 #pragma unroll
     for (int q = 0; q < kPixPerLane; q++) {
-        const int ry = kTile * ty + ly + 4 * q;
+        const int ry = kTile * ty + row0 + ly + 4 * q;
         if (rx >= vw.roi_w || ry >= vw.roi_h) continue;
         const size_t pix = (size_t)ry * vw.roi_w + rx;
         const float Tf = fabsf(T[q]);
@@ -197,6 +246,10 @@ hipError_t launch_ranges(const Layout &L, char *ws, const uint32_t *keys, hipStr
     const int64_t blocks = (L.cap + 255) / 256;
     hipLaunchKernelGGL(k_ranges, dim3((unsigned)blocks), dim3(256), 0, s, keys,
                        region<uint32_t>(ws, L.counters), ranges);
+    e = hipGetLastError();
+    if (e != hipSuccess || L.total_tiles == 0) return e;
+    hipLaunchKernelGGL(k_tile_order, dim3(1), dim3(1024), 0, s, ranges, L.total_tiles,
+                       region<uint32_t>(ws, L.tile_order));
     return hipGetLastError();
 }
 
@@ -204,6 +257,7 @@ hipError_t launch_raster_fwd(const ViewsK &views, const Layout &L, char *ws, con
                              bool stats, hipStream_t s) {
     if (L.total_tiles == 0) return hipSuccess;
     FwdArgs a;
+    a.order = region<uint32_t>(ws, L.tile_order);
     a.ranges = region<uint2>(ws, L.ranges);
     a.vals = vals;
     a.geom = region<float4>(ws, L.geom);
@@ -212,10 +266,12 @@ hipError_t launch_raster_fwd(const ViewsK &views, const Layout &L, char *ws, con
     a.ncontrib = region<uint32_t>(ws, L.ncontrib);
     a.neval = region<uint32_t>(ws, L.stats);
     a.nblend = a.neval + L.total_pix;
+    a.total_tiles = L.total_tiles;
+    const dim3 grid(raster_blocks<kSplit>(L.total_tiles));
     if (stats)
-        hipLaunchKernelGGL(k_raster_fwd<true>, dim3(L.total_tiles), dim3(kRasterThreads), 0, s, a, views);
+        hipLaunchKernelGGL(k_raster_fwd<true>, grid, dim3(kRasterThreads), 0, s, a, views);
     else
-        hipLaunchKernelGGL(k_raster_fwd<false>, dim3(L.total_tiles), dim3(kRasterThreads), 0, s, a, views);
+        hipLaunchKernelGGL(k_raster_fwd<false>, grid, dim3(kRasterThreads), 0, s, a, views);
     return hipGetLastError();
 }
 
