@@ -52,7 +52,7 @@ constexpr int kWindowThreads = 256;
 #define GSP_SPLIT_FWD 4
 #endif
 #ifndef GSP_SPLIT_BWD
-#define GSP_SPLIT_BWD 1
+#define GSP_SPLIT_BWD 2
 #endif
 constexpr int kSplitFwd = GSP_SPLIT_FWD;
 constexpr int kSplitBwd = GSP_SPLIT_BWD;
