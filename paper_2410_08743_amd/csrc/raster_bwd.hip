@@ -61,6 +61,7 @@ __global__ __launch_bounds__(kRasterThreads) __attribute__((amdgpu_waves_per_eu(
     __shared__ StagedA sA[kBatch];
     __shared__ StagedB sB[kBatch];
     __shared__ StagedC sC[kBatch];
+    __shared__ float sL[kBatch];   // candidate limit kLog2AlphaMinLoose - lo
     int rank, part;
     part_of_block<kSplit>(blockIdx.x, rank, part);
     if (rank >= a.total_tiles) return;
@@ -150,8 +151,8 @@ __global__ __launch_bounds__(kRasterThreads) __attribute__((amdgpu_waves_per_eu(
             const int r = kept_rank(kept);
             sA[r] = StagedA{u, v, g1.x, g1.y};
             sB[r] = StagedB{g1.z, g1.w, gc.x, gc.y};
-            sC[r] = StagedC{gc.z, __builtin_amdgcn_exp2f(-g1.w), gslot,
-                            ((uint32_t)(lo + lane) << 4) | mask};
+            sC[r] = StagedC{gc.z, __builtin_amdgcn_exp2f(-g1.w), gslot, (uint32_t)(lo + lane)};
+            sL[r] = kLog2AlphaMinLoose - g1.w;
         } else if (gslot != kNoSlot) {
 #pragma unroll
             for (int c = 0; c < 9; c++) pslots[9 * kSplit * (size_t)gslot + c] = 0.f;
@@ -161,6 +162,7 @@ __global__ __launch_bounds__(kRasterThreads) __attribute__((amdgpu_waves_per_eu(
             sA[lane] = StagedA{0.f, 0.f, -1.f, 0.f};
             sB[lane] = StagedB{-1.f, -INFINITY, 0.f, 0.f};
             sC[lane] = StagedC{0.f, 0.f, kNoSlot, 0u};
+            sL[lane] = INFINITY;
         }
         __syncthreads();
         if (lo > 0) gather(lo - kBatch + lane);
@@ -168,19 +170,21 @@ __global__ __launch_bounds__(kRasterThreads) __attribute__((amdgpu_waves_per_eu(
             StagedA es[kBwdUnroll];
             StagedB et[kBwdUnroll];
             StagedC ew[kBwdUnroll];
+            float el[kBwdUnroll];
 #pragma unroll
             for (int u = 0; u < kBwdUnroll; u++) {
                 es[u] = sA[j0 + u];
                 et[u] = sB[j0 + u];
                 ew[u] = sC[j0 + u];
+                el[u] = sL[j0 + u];
             }
 #pragma unroll
             for (int u = kBwdUnroll - 1; u >= 0; u--) {
-                const int pos = (int)(ew[u].pm >> 4);
+                const int pos = (int)ew[u].pm;   // list position
                 const StagedA &s = es[u];
                 const StagedB &t = et[u];
                 const ColTerms ct = col_terms(s, fxl);
-                const float lim = kLog2AlphaMinLoose - t.lo;
+                const float lim = el[u];
                 float p2[kPixPerLane];
                 bool cand[kPixPerLane];
                 bool any = false;

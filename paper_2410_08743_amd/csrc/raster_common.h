@@ -42,13 +42,17 @@ constexpr float kLn2 = 0.6931471805599453f;
 constexpr float kLog2AlphaMinLoose = -7.994353436858858f - 0.01f;
 
 // Splat as staged in LDS: centre relative to the tile's first pixel, scaled
-// conic, log2 opacity and colour; pm packs the entry's list position and its
-// band mask (position << 4 | mask, 0 for padding); the backward adds the
-// instance's slot and 1/o.
+// conic, log2 opacity and colour; the forward adds its list position + 1, the
+// backward its list position, the instance's slot and 1/o.  Every lane reads
+// every staged byte, so the forward's record is kept to 40 bytes.
 struct StagedA { float u, v, A2, B2; };
 struct StagedB { float C2, lo, r, g; };
-struct StagedF { float b; uint32_t pm; };
-struct StagedC { float b, inv_o; uint32_t slot, pm; };
+struct StagedF { float b; uint32_t jp1; };
+struct StagedC { float b, inv_o; uint32_t slot, pm; };   // pm: list position
+
+// Row offset that marks a pixel as done: every splat's p2 there is -inf, so
+// the candidate test (p2 >= lim) fails without a separate flag.
+constexpr float kInactiveRow = 1e30f;
 
 // Centre of a splat relative to pixel (px0, py0), from its (hi, lo) pair.
 __device__ __forceinline__ float rel_coord(float hi, float lo, int origin) {

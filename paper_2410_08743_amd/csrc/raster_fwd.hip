@@ -77,10 +77,10 @@ struct FwdArgs {
 };
 
 template <int N>
-__device__ __forceinline__ bool any_active(const float (&T)[N]) {
+__device__ __forceinline__ bool any_active(const float (&fy)[N]) {
     bool a = false;
 #pragma unroll
-    for (int q = 0; q < N; q++) a |= T[q] > 0.f;
+    for (int q = 0; q < N; q++) a |= fy[q] != kInactiveRow;
     return __any(a);
 }
 
@@ -106,8 +106,9 @@ __global__ __launch_bounds__(kRasterThreads) __attribute__((amdgpu_waves_per_eu(
     const int rx = kTile * tx + lx;
     const int row0 = part * (kTile / kSplit);   // first tile row of this part
 
-    // T > 0 while a pixel composites; a pixel that stopped (or lies outside
-    // the region) keeps -T, so later splats can neither blend nor restart it.
+    // A pixel composites while its row offset fy is finite; one that stopped
+    // (or lies outside the region) gets kInactiveRow, so that no later splat
+    // is a candidate there.
     float T[kPixPerLane], cr[kPixPerLane], cg[kPixPerLane], cb[kPixPerLane], fy[kPixPerLane];
     int last[kPixPerLane];
     uint32_t ne[kPixPerLane], nb[kPixPerLane];
@@ -116,10 +117,10 @@ __global__ __launch_bounds__(kRasterThreads) __attribute__((amdgpu_waves_per_eu(
         ne[q] = nb[q] = 0;
         const int ryl = row0 + ly + 4 * q;
         const bool in = rx < vw.roi_w && kTile * ty + ryl < vw.roi_h;
-        T[q] = in ? 1.f : -1.f;
+        T[q] = 1.f;
         cr[q] = cg[q] = cb[q] = 0.f;
         last[q] = 0;
-        fy[q] = (float)ryl;
+        fy[q] = in ? (float)ryl : kInactiveRow;
     }
     const float fxl = (float)lx;
 
@@ -141,7 +142,7 @@ __global__ __launch_bounds__(kRasterThreads) __attribute__((amdgpu_waves_per_eu(
     };
     gather(lane);
     for (int b0 = 0; b0 < len; b0 += kBatch) {
-        if (!any_active(T)) break;
+        if (!any_active(fy)) break;
         // Stage the entries that can reach 1/255 somewhere in this part's
         // rows, in list order; the others cannot change any of its pixels.
         const float u = rel_coord(g0.x, g0.z, px0), v = rel_coord(g0.y, g0.w, py0);
@@ -153,7 +154,7 @@ __global__ __launch_bounds__(kRasterThreads) __attribute__((amdgpu_waves_per_eu(
             const int r = kept_rank(kept);
             sA[r] = StagedA{u, v, g1.x, g1.y};
             sB[r] = StagedB{g1.z, g1.w, gc.x, gc.y};
-            sF[r] = StagedF{gc.z, ((uint32_t)k << 4) | mask};
+            sF[r] = StagedF{gc.z, (uint32_t)k + 1u};
         }
         // padding up to the unroll width: inert records
         if (lane >= nk && lane < ((nk + kUnroll - 1) & ~(kUnroll - 1))) {
@@ -175,10 +176,10 @@ __global__ __launch_bounds__(kRasterThreads) __attribute__((amdgpu_waves_per_eu(
             }
 #pragma unroll
             for (int u2 = 0; u2 < kUnroll; u2++) {
-                const int j = (int)(ef[u2].pm >> 4);
+                const int jp1 = (int)ef[u2].jp1;   // list position + 1
                 const ColTerms ct = col_terms(es[u2], fxl);
-                // candidates: pixels still compositing, power <= 0, and p2
-                // high enough that alpha may reach 1/255
+                // candidates: pixels still compositing (finite fy), power <= 0,
+                // and p2 high enough that alpha may reach 1/255
                 const float lim = kLog2AlphaMinLoose - et[u2].lo;
                 float p2[kPixPerLane];
                 bool cand[kPixPerLane];
@@ -186,7 +187,7 @@ __global__ __launch_bounds__(kRasterThreads) __attribute__((amdgpu_waves_per_eu(
 #pragma unroll
                 for (int q = 0; q < kPixPerLane; q++) {
                     p2[q] = splat_p2(ct, et[u2].C2, es[u2].v - fy[q]);
-                    cand[q] = (T[q] > 0.f) & (p2[q] <= 0.f) & (p2[q] >= lim);
+                    cand[q] = (p2[q] <= 0.f) & (p2[q] >= lim);
                     any |= cand[q];
                 }
                 // no pixel of this part can reach 1/255: nothing to do
@@ -201,17 +202,18 @@ __global__ __launch_bounds__(kRasterThreads) __attribute__((amdgpu_waves_per_eu(
                     const bool stop = hit && !(testT >= kTMin);
                     if (STATS) {
                         nb[q] += blend ? 1u : 0u;
-                        ne[q] = stop ? (uint32_t)j + 1u : ne[q];
+                        ne[q] = stop ? (uint32_t)jp1 : ne[q];
                     }
                     const float wgt = blend ? aT : 0.f;
                     cr[q] = fmaf(et[u2].r, wgt, cr[q]);
                     cg[q] = fmaf(et[u2].g, wgt, cg[q]);
                     cb[q] = fmaf(ef[u2].b, wgt, cb[q]);
-                    last[q] = blend ? j + 1 : last[q];
-                    T[q] = blend ? testT : (stop ? -T[q] : T[q]);
+                    last[q] = blend ? jp1 : last[q];
+                    T[q] = blend ? testT : T[q];
+                    fy[q] = stop ? kInactiveRow : fy[q];
                 }
             }
-            if (!any_active(T)) break;
+            if (!any_active(fy)) break;
         }
         __syncthreads();
     }
@@ -222,7 +224,7 @@ __global__ __launch_bounds__(kRasterThreads) __attribute__((amdgpu_waves_per_eu(
         const int ry = kTile * ty + row0 + ly + 4 * q;
         if (rx >= vw.roi_w || ry >= vw.roi_h) continue;
         const size_t pix = (size_t)ry * vw.roi_w + rx;
-        const float Tf = fabsf(T[q]);
+        const float Tf = T[q];
         float *img = vw.img;
         img[pix] = cr[q] + Tf * vw.bg[0];
         img[(size_t)P + pix] = cg[q] + Tf * vw.bg[1];
@@ -232,7 +234,7 @@ __global__ __launch_bounds__(kRasterThreads) __attribute__((amdgpu_waves_per_eu(
         if (vw.alpha) vw.alpha[pix] = 1.f - Tf;
         if (STATS) {
             // a pixel that never stopped evaluated the whole list
-            a.neval[vw.pix_base + pix] = T[q] < 0.f ? ne[q] : (uint32_t)len;
+            a.neval[vw.pix_base + pix] = fy[q] == kInactiveRow ? ne[q] : (uint32_t)len;
             a.nblend[vw.pix_base + pix] = nb[q];
         }
     }
