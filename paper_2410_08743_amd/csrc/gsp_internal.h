@@ -43,7 +43,10 @@ constexpr int kPoseReduceBlock = 256;
 // falls in its piece.  Every block then sees at most kWindow splats and
 // kWindow instances plus the tail of its last splat, however unevenly the
 // instances are spread over the splats.
-constexpr int kWindow = 1024;
+#ifndef GSP_WINDOW
+#define GSP_WINDOW 512
+#endif
+constexpr int kWindow = GSP_WINDOW;
 constexpr int kWindowThreads = 256;
 // Workgroups per 16 x 16 tile in the forward and the backward rasterizer
 // (each takes a strip of 16 / split rows); every instance has one 9-float
