@@ -93,6 +93,8 @@ def main():
     ap.add_argument("--no-serve", action="store_true", help="skip the serving measurement")
     ap.add_argument("--serve-only", action="store_true",
                     help="run only the serving measurement and print its JSON (for profiling)")
+    ap.add_argument("--joint-only", action="store_true",
+                    help="run only the joint-step measurement and print its JSON (for profiling)")
     ap.add_argument("--serve-requests", type=int, default=48)
     ap.add_argument("--no-joint", action="store_true", help="skip the joint-step measurement")
     ap.add_argument("--no-track", action="store_true", help="skip the tracking measurement")
@@ -122,6 +124,9 @@ def main():
     dev = "cuda:0"
     if args.serve_only:
         print(json.dumps(serving_section(args, dev, with_cpu=False)), flush=True)
+        return
+    if args.joint_only:
+        print(json.dumps(joint_section(args, dev)), flush=True)
         return
     wl = S.single_view()
     cam = wl.camera

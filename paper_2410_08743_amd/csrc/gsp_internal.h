@@ -87,7 +87,7 @@ struct Layout {
     size_t geom, color, rect, depth, tiles, offsets, offk, wstart, blocksum, counters;
     size_t dkeys0, dkeys1, dvals0, dvals1;
     size_t keys0, keys1, vals0, vals1, hist, digit_tot, ranges, tile_order;
-    size_t tfinal, ncontrib, stats, slots, grad2d, posepart;
+    size_t tfinal, ncontrib, stats, slots, slot_flags, grad2d, posepart;
     size_t total;
 };
 

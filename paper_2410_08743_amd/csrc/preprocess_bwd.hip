@@ -60,7 +60,8 @@ __device__ __forceinline__ void rot_vjp(double w, double x, double y, double z, 
 // with all of each thread's loads in flight at once; the (splat, component)
 // pairs are then spread over the threads, nine neighbouring threads per
 // splat.  Slots past the first kWindow of the range -- the tail of a long last
-// splat -- are read from global memory.
+// splat -- are read from global memory.  A slot the backward rasterizer did
+// not write (flag 0: no pixel of that strip blended the entry) counts as zero.
 constexpr int kSlotFloats = 9 * kSplitBwd;   // one 9-float slot per backward part
 constexpr int kSlotPerThread = kWindow * kSlotFloats / kWindowThreads;
 
@@ -68,9 +69,11 @@ __global__ __launch_bounds__(kWindowThreads) void k_slot_reduce(const uint32_t *
                                                                 const uint32_t *offk,
                                                                 const uint32_t *wstart,
                                                                 const uint32_t *counters,
-                                                                const float *slots, float *grad2d,
-                                                                int vn) {
+                                                                const float *slots,
+                                                                const uint8_t *flags,
+                                                                float *grad2d, int vn) {
     __shared__ float s_sl[kWindow * kSlotFloats];
+    __shared__ uint8_t s_fl[kWindow * kSplitBwd];
     __shared__ uint32_t s_off[kWindow + 1];
     const int b = blockIdx.x;
     if (counters[kCntOverflow] != 0u) {
@@ -86,6 +89,9 @@ __global__ __launch_bounds__(kWindowThreads) void k_slot_reduce(const uint32_t *
     const uint32_t e0 = offk[kb], ne = offk[ke] - e0;
     const uint32_t nf = (uint32_t)kSlotFloats * min(ne, (uint32_t)kWindow);
     const float *src = slots + kSlotFloats * (size_t)e0;
+    const uint8_t *fsrc = flags + kSplitBwd * (size_t)e0;
+    const uint32_t nfl = (uint32_t)kSplitBwd * min(ne, (uint32_t)kWindow);
+    for (uint32_t f = threadIdx.x; f < nfl; f += kWindowThreads) s_fl[f] = fsrc[f];
     float tmp[kSlotPerThread];
 #pragma unroll
     for (int r = 0; r < kSlotPerThread; r++) {
@@ -105,11 +111,17 @@ __global__ __launch_bounds__(kWindowThreads) void k_slot_reduce(const uint32_t *
         uint32_t e = lo;
         for (; e < mid; e++) {
 #pragma unroll
-            for (int p = 0; p < kSplitBwd; p++) d += s_sl[kSlotFloats * e + 9 * p + c];
+            for (int p = 0; p < kSplitBwd; p++) {
+                const float v = s_sl[kSlotFloats * e + 9 * p + c];
+                d += s_fl[kSplitBwd * e + p] ? v : 0.f;
+            }
         }
         for (; e < hi; e++) {
 #pragma unroll
-            for (int p = 0; p < kSplitBwd; p++) d += src[kSlotFloats * (size_t)e + 9 * p + c];
+            for (int p = 0; p < kSplitBwd; p++) {
+                const float v = src[kSlotFloats * (size_t)e + 9 * p + c];
+                d += fsrc[kSplitBwd * (size_t)e + p] ? v : 0.f;
+            }
         }
         grad2d[9 * (size_t)order[kb + j] + c] = d;
     }
@@ -405,7 +417,8 @@ hipError_t launch_preprocess_bwd(const GaussiansK &g, const ViewsK &views, const
     if (L.vn > 0) {
         hipLaunchKernelGGL(k_slot_reduce, dim3(L.nwin_max), dim3(kWindowThreads), 0, s,
                            region<uint32_t>(ws, L.dvals0), region<uint32_t>(ws, L.offk),
-                           region<uint32_t>(ws, L.wstart), a.counters, a.slots, a.grad2d,
+                           region<uint32_t>(ws, L.wstart), a.counters, a.slots,
+                           region<uint8_t>(ws, L.slot_flags), a.grad2d,
                            (int)L.vn);
         hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;

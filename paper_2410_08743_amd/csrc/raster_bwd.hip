@@ -40,6 +40,7 @@ struct BwdArgs {
     const float *tfinal;
     const uint32_t *ncontrib;
     float *slots;          // [cap][kSplit][9]
+    uint8_t *slot_flags;   // [cap][kSplit]: 1 where this kernel wrote the slot
     int total_tiles;
 };
 
@@ -76,6 +77,7 @@ __global__ __launch_bounds__(kRasterThreads) __attribute__((amdgpu_waves_per_eu(
     const int P = vw.roi_w * vw.roi_h;
     const int row0 = part * (kTile / kSplit);   // first tile row of this part
     float *const pslots = a.slots + 9 * part;   // this part's slot of each instance
+    uint8_t *const pflags = a.slot_flags + part;
 
     // Which reduced value this lane stores, and its scale (see wave_sum9 and
     // the base-2 conic of raster_common.h).
@@ -112,13 +114,6 @@ __global__ __launch_bounds__(kRasterThreads) __attribute__((amdgpu_waves_per_eu(
 
     const uint2 rg = a.ranges[tile];
     const int len = (int)(rg.y - rg.x);
-    // entries no pixel of this part blended get zero slots
-    for (int k = maxlast + lane; k < len; k += kBatch) {
-        const uint32_t e = slot_of(a, a.vals[rg.x + k], tx, ty);
-#pragma unroll
-        for (int c = 0; c < 9; c++) pslots[9 * kSplit * (size_t)e + c] = 0.f;
-    }
-
     // batches of 64 entries ending at hi, walked back to front; positions
     // below 0 are absent.  Records are gathered one batch ahead.
     float4 g0, g1, gc;
@@ -140,8 +135,8 @@ __global__ __launch_bounds__(kRasterThreads) __attribute__((amdgpu_waves_per_eu(
     for (int hi = maxlast; hi > 0; hi -= kBatch) {
         const int lo = hi - kBatch;
         // Stage, in list order, the entries that can reach 1/255 somewhere in
-        // this part's rows; a dropped entry blends nowhere there and gets a
-        // zero slot.
+        // this part's rows; a dropped entry blends nowhere there, and its slot
+        // stays unwritten (flag 0, read as zero).
         const float u = rel_coord(g0.x, g0.z, px0), v = rel_coord(g0.y, g0.w, py0);
         const uint32_t mask =
             gslot != kNoSlot ? band_mask<kSplit>(u, v, g1.x, g1.y, g1.z, g1.w, row0) : 0u;
@@ -153,9 +148,6 @@ __global__ __launch_bounds__(kRasterThreads) __attribute__((amdgpu_waves_per_eu(
             sB[r] = StagedB{g1.z, g1.w, gc.x, gc.y};
             sC[r] = StagedC{gc.z, __builtin_amdgcn_exp2f(-g1.w), gslot, (uint32_t)(lo + lane)};
             sL[r] = kLog2AlphaMinLoose - g1.w;
-        } else if (gslot != kNoSlot) {
-#pragma unroll
-            for (int c = 0; c < 9; c++) pslots[9 * kSplit * (size_t)gslot + c] = 0.f;
         }
         const int nkr = (nk + kBwdUnroll - 1) & ~(kBwdUnroll - 1);
         if (lane >= nk && lane < nkr) {   // padding up to the unroll width
@@ -241,11 +233,12 @@ __global__ __launch_bounds__(kRasterThreads) __attribute__((amdgpu_waves_per_eu(
                     acc[7] = gc[1];
                     acc[8] = gc[2];
                     wave_sum9(acc, x0, x1, x2);
-                }
-                if (comp >= 0 && ew[u].slot != kNoSlot) {
-                    const float val = col == 0 ? x0 : (col == 1 ? x1 : x2);
-                    const float f = comp == 5 ? ew[u].inv_o : scale;
-                    pslots[9 * kSplit * (size_t)ew[u].slot + comp] = val * f;
+                    if (comp >= 0 && ew[u].slot != kNoSlot) {
+                        const float val = col == 0 ? x0 : (col == 1 ? x1 : x2);
+                        const float f = comp == 5 ? ew[u].inv_o : scale;
+                        pslots[9 * kSplit * (size_t)ew[u].slot + comp] = val * f;
+                        if (comp == 0) pflags[kSplit * (size_t)ew[u].slot] = 1;
+                    }
                 }
             }
         }
@@ -267,7 +260,12 @@ hipError_t launch_raster_bwd(const ViewsK &views, const Layout &L, char *ws, con
     a.tfinal = region<float>(ws, L.tfinal);
     a.ncontrib = region<uint32_t>(ws, L.ncontrib);
     a.slots = region<float>(ws, L.slots);
+    a.slot_flags = region<uint8_t>(ws, L.slot_flags);
     a.total_tiles = L.total_tiles;
+    // slots no entry writes stay flagged 0 and count as zero
+    hipError_t e = launch_fill_u32(region<uint32_t>(ws, L.slot_flags), 0u,
+                                   ((int64_t)kSplit * L.cap + 3) / 4, s);
+    if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_raster_bwd, dim3(raster_blocks<kSplit>(L.total_tiles)), dim3(kRasterThreads), 0, s,
                        a, views);
     return hipGetLastError();
