@@ -11,16 +11,18 @@
 //   dpower/dA = -dx^2/2, dpower/dB = -dx dy, dpower/dC = -dy^2/2.
 //
 // MI355X design: nothing per pixel is stored by the forward beyond T_final
-// and the contributor count; each wavefront walks its tile's list back to
-// front from the largest contributor count, recovering T_i = T_{i+1} /
-// (1 - alpha_i) with the forward's exact evaluation.  Each lane sums its four
-// pixels in registers; the nine sums are reduced over the 64 lanes by a
-// reduce-scatter butterfly (v_permlane32_swap, v_permlane16_swap, then DPP
-// inside rows: 28 VALU operations for nine values), and nine lanes store the
-// (tile, splat) partial into the instance's own slot (its position in
-// emission order, 36 contiguous bytes).  No atomics: the per-splat sum over
-// its slots happens later in a fixed order, so gradients are
-// bit-reproducible.
+// and the contributor count.  kSplit wavefronts per tile, each a strip of
+// rows, walk the tile's list back to front from the largest contributor
+// count of their pixels, recovering T_i = T_{i+1} / (1 - alpha_i) with the
+// forward's exact evaluation, and skip (per lane-parallel bound, as in the
+// forward) the entries that reach 1/255 nowhere in their rows.  Each lane
+// sums its pixels in registers; the nine sums are reduced over the 64 lanes
+// by a reduce-scatter butterfly (v_permlane32_swap, v_permlane16_swap, then
+// DPP inside rows: about 30 VALU operations for nine values), and nine lanes
+// store the (strip, splat) partial into the strip's part of the instance's
+// own slot (its position in emission order), flagging it written.  No
+// atomics: the per-splat sum over its slots happens later in a fixed order,
+// so gradients are bit-reproducible.
 #include "block_ops.h"
 #include "raster_common.h"
 

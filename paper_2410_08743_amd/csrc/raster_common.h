@@ -10,8 +10,8 @@
 // The preprocess stores the conic pre-scaled to base 2,
 // (A2, B2, C2) = -log2(e) (A/2, B, C/2), and lo = log2(o), so that
 // p2 = log2(e) power = A2 dx^2 + B2 dx dy + C2 dy^2 and alpha = 2^(p2 + lo):
-// two FMAs and one v_exp_f32 per pixel once the dx terms, which the four
-// pixels of a lane share (they lie in one column), are formed.
+// two FMAs and one v_exp_f32 per pixel once the dx terms, which the pixels
+// of a lane share (they lie in one column), are formed.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -60,7 +60,7 @@ __device__ __forceinline__ float rel_coord(float hi, float lo, int origin) {
     return (hi - (float)origin) + lo;
 }
 
-// Per (lane, splat) terms shared by the lane's four pixels.
+// Per (lane, splat) terms shared by the pixels of a lane (one column).
 struct ColTerms {
     float dx, adx2, bdx;
 };
