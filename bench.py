@@ -97,6 +97,7 @@ def main():
                     help="run only the joint-step measurement and print its JSON (for profiling)")
     ap.add_argument("--serve-requests", type=int, default=48)
     ap.add_argument("--no-joint", action="store_true", help="skip the joint-step measurement")
+    ap.add_argument("--no-tiny", action="store_true", help="skip the tiny-scene measurement")
     ap.add_argument("--no-track", action="store_true", help="skip the tracking measurement")
     ap.add_argument("--track-frames", type=int, default=100)
     ap.add_argument("--joint-steps", type=int, default=20)
@@ -282,6 +283,9 @@ def main():
                          f"starting pose, FP64, median of {args.cpu_reps}",
                "seconds": round(t, 3)}
 
+    tiny = None
+    if not args.no_tiny:
+        tiny = tiny_section(args, dev)
     joint = None
     if not args.no_joint:
         joint = joint_section(args, dev)
@@ -302,6 +306,7 @@ def main():
                    "step": "fwd+L1+bwd(pose)+adam", "parallelism": "single GPU"},
         "roofline": roof,
         "cpu_baseline": cpu,
+        "tiny": tiny,
         "joint": joint,
         "tracking": track,
         "serving": serving,
@@ -314,6 +319,66 @@ def main():
                        "final_error": [round(rot_err, 4), round(trans_err, 5)]},
     }
     print(json.dumps(line), flush=True)
+
+
+def tiny_section(args, dev):
+    """The tiny correctness workload (1000 Gaussians, SH 0, 128x128): forward,
+    L1 against the target pose's render, backward to every Gaussian
+    parameter and the pose, Adam -- once with one view per launch (launch
+    latency bound) and once with 32 copies of the view in one launch."""
+    import numpy as np
+    import torch
+
+    from paper_2410_08743_amd import render as R
+    from paper_2410_08743_amd import synthetic as S
+
+    wl = S.tiny()
+    cam = wl.camera
+    g = R.GaussianParams.from_set(wl.scene, dev)
+    P = cam.width * cam.height
+    out = {"workload": wl.name, "gaussians": g.n, "step": "fwd+L1+bwd(all params + pose)+adam"}
+    for V in (1, 32):
+        cams = [cam] * V
+        rast = R.Rasterizer(0)
+        tgt, _ = rast.forward(g, cams, torch.tensor(np.repeat(wl.init_pose[None], V, 0), device=dev))
+        tgt = tgt.clone()
+        pose = torch.tensor(np.repeat(wl.pose[None], V, 0), device=dev)
+        m = torch.zeros((V, 6), device=dev)
+        v = torch.zeros((V, 6), device=dev)
+        st = torch.zeros(V, dtype=torch.int32, device=dev)
+        img = torch.empty(3 * P * V, device=dev)
+        dl = torch.empty_like(img)
+        grads = {k: torch.empty(sh, device=dev) for k, sh in
+                 (("means", (g.n, 3)), ("scales", (g.n, 3)), ("quats", (g.n, 4)),
+                  ("opacities", (g.n,)), ("sh", tuple(g.sh.shape)))}
+        grads["pose"] = torch.empty((V, 6), device=dev)
+        rast.forward(g, cams, pose, images=img)
+        rast.capacity = int(1.5 * rast.instances()[0]) + 1024
+        rast.ws = None
+        rast._ensure(g, R.N.view_array(cams))
+
+        def step():
+            rast.forward(g, cams, pose, check=False, images=img)
+            R.loss_l1(cams, img, tgt, grad=dl, with_loss=False)
+            rast.backward(g, cams, pose, dl, out=grads)
+            R.pose_adam(pose, grads["pose"], m, v, st, 1e-2, 1e-4, 1000, guard=rast.ws)
+
+        for _ in range(10):
+            step()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        K = 200
+        e0.record()
+        for _ in range(K):
+            step()
+        e1.record()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / K
+        out[f"views_{V}"] = {"ms_per_step": round(ms, 4), "mpix_per_s": round(V * P / (ms * 1e3), 2)}
+    print(f"[bench] tiny: {out['views_1']['ms_per_step']:.3f} ms/step (1 view), "
+          f"{out['views_32']['ms_per_step']:.3f} ms/step (32 views, "
+          f"{out['views_32']['mpix_per_s']:.0f} Mpix/s)", file=sys.stderr, flush=True)
+    return out
 
 
 _JOINT = None
