@@ -195,9 +195,10 @@ Layout make_layout(int64_t n, int32_t sh_degree, int32_t V, const ViewsK &views,
     for (int v = 0; v < V; v++) pix += (int64_t)views.v[v].roi_w * views.v[v].roi_h;
     L.total_pix = pix;
     L.nblk_pre = (int)((n + kPreprocessBlock - 1) / kPreprocessBlock);
-    L.nblk_vn = (int)((L.vn + kPreprocessBlock - 1) / kPreprocessBlock);
+    L.nblk_scan = (int)((L.vn + kScanItems - 1) / kScanItems);
     const int64_t max_sorted = L.cap > L.vn ? L.cap : L.vn;
     L.nblk_sort = (int)((max_sorted + kSortItems - 1) / kSortItems);
+    L.nblk_emit = (int)((L.cap + kSortItems - 1) / kSortItems);   // blocks of the instance sort
     L.tile_bits = tile_bits_for(views.total_tiles);
     L.tile_passes = (L.tile_bits + kSortBits - 1) / kSortBits;
     L.nwin_max = (int)((L.vn + L.cap + kWindow - 1) / kWindow + 1);
@@ -217,7 +218,8 @@ Layout make_layout(int64_t n, int32_t sh_degree, int32_t V, const ViewsK &views,
     L.offsets = take(vn * 4);
     L.offk = take((vn + 1) * 4);
     L.wstart = take(((size_t)L.nwin_max + 1) * 4);
-    L.blocksum = take((size_t)L.nblk_vn * 8 + 8);
+    L.pstart = take(((size_t)L.nblk_emit + 1) * 4);
+    L.blocksum = take((size_t)L.nblk_scan * 8 + 8);
     L.dkeys0 = take(vn * 4);
     L.dkeys1 = take(vn * 4);
     L.dvals0 = take(vn * 4);

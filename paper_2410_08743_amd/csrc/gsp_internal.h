@@ -37,6 +37,10 @@ constexpr int kSortItems = kSortThreads * kSortRounds;  // keys per sort block
 constexpr int kSortBits = 8;             // radix digit width
 constexpr int kSortBins = 1 << kSortBits;
 constexpr int kPoseReduceBlock = 256;
+// Instance-offset scan over the depth-sorted splats: splats per thread and
+// per block.
+constexpr int kScanPerThread = 4;
+constexpr int kScanItems = kPreprocessBlock * kScanPerThread;
 // Work windows of the instance emission and of the slot reduction: the
 // sequence of splats in depth order, each followed by its instances, is cut
 // into pieces of kWindow items, and a block takes the splats whose entry
@@ -83,8 +87,9 @@ struct ViewsK {
 // Carving of the caller's workspace.  Every region is 256-byte aligned.
 struct Layout {
     int64_t n, vn, cap, total_pix;
-    int32_t V, S, total_tiles, nblk_pre, nblk_vn, nblk_sort, tile_bits, tile_passes, nwin_max;
-    size_t geom, color, rect, depth, tiles, offsets, offk, wstart, blocksum, counters;
+    int32_t V, S, total_tiles, nblk_pre, nblk_scan, nblk_sort, nblk_emit, tile_bits, tile_passes,
+        nwin_max;
+    size_t geom, color, rect, depth, tiles, offsets, offk, wstart, pstart, blocksum, counters;
     size_t dkeys0, dkeys1, dvals0, dvals1;
     size_t keys0, keys1, vals0, vals1, hist, digit_tot, ranges, tile_order;
     size_t tfinal, ncontrib, stats, slots, slot_flags, grad2d, posepart;
@@ -129,7 +134,6 @@ hipError_t launch_preprocess_bwd(const GaussiansK &g, const ViewsK &views, const
                                  const Layout &L, char *ws, const gsp_grads &grads,
                                  bool accumulate, hipStream_t s);
 // misc.hip
-hipError_t launch_fill_u32(uint32_t *p, uint32_t value, int64_t count, hipStream_t s);
 struct LossViewsK {
     const float *pred[GSP_MAX_VIEWS];
     const float *target[GSP_MAX_VIEWS];

@@ -1,4 +1,4 @@
-// misc.hip -- small kernels around the rasterizer: buffer fill, the L1
+// misc.hip -- small kernels around the rasterizer: the L1
 // photometric loss with its gradient (the L1 part of Eq. (16)), and the
 // tangent-space Adam step with left retraction on each pose (Sec. III-B:
 // T = Exp(tau), gradients taken on tau).
@@ -6,18 +6,6 @@
 #include "gsp_internal.h"
 
 namespace gsp {
-
-__global__ __launch_bounds__(256) void k_fill_u32(uint32_t *p, uint32_t value, int64_t count) {
-    const int64_t k = (int64_t)blockIdx.x * 256 + threadIdx.x;
-    if (k < count) p[k] = value;
-}
-
-hipError_t launch_fill_u32(uint32_t *p, uint32_t value, int64_t count, hipStream_t s) {
-    if (count <= 0) return hipSuccess;
-    const int64_t blocks = (count + 255) / 256;
-    hipLaunchKernelGGL(k_fill_u32, dim3((unsigned)blocks), dim3(256), 0, s, p, value, count);
-    return hipGetLastError();
-}
 
 constexpr int kLossItems = 4096;   // elements per loss block
 

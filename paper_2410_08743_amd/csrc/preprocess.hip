@@ -180,45 +180,20 @@ __global__ __launch_bounds__(kPreprocessBlock) void k_preprocess(PreArgs a, View
     }
 }
 
-// Per-block sums of the tile counts, taken in depth order.
+// Per-block sums of the tile counts, taken in depth order (kScanItems
+// splats per block, kScanPerThread consecutive ones per thread).
 __global__ __launch_bounds__(kPreprocessBlock) void k_sorted_blocksums(const uint32_t *order,
                                                                        const uint32_t *tiles,
                                                                        unsigned long long *bs,
                                                                        int vn) {
     __shared__ unsigned long long red[kPreprocessBlock / kWave];
-    const int k = blockIdx.x * kPreprocessBlock + threadIdx.x;
-    const uint32_t cnt = k < vn ? tiles[order[k]] : 0u;
+    const int k0 = blockIdx.x * kScanItems + kScanPerThread * threadIdx.x;
+    unsigned long long cnt = 0;
+#pragma unroll
+    for (int j = 0; j < kScanPerThread; j++)
+        if (k0 + j < vn) cnt += tiles[order[k0 + j]];
     const unsigned long long s = block_sum<unsigned long long, kPreprocessBlock>(cnt, red);
     if (threadIdx.x == 0) bs[blockIdx.x] = s;
-}
-
-// Exclusive scan of the per-(view, block) instance counts in one block; the
-// grand total is M.  Writes M, the overflow flag and the effective M (0 on
-// overflow, so that every later stage does no work).
-__global__ __launch_bounds__(1024) void k_scan_blocksums(unsigned long long *bs, int count,
-                                                         uint32_t *counters,
-                                                         unsigned long long cap) {
-    __shared__ unsigned long long scratch[1024 / kWave];
-    const int t = threadIdx.x;
-    const int per = (count + 1023) / 1024;
-    const int begin = min(t * per, count), end = min(begin + per, count);
-    unsigned long long local = 0;
-    for (int k = begin; k < end; k++) local += bs[k];
-    unsigned long long total;
-    unsigned long long off = block_exclusive_scan<unsigned long long, 1024>(local, scratch, &total);
-    for (int k = begin; k < end; k++) {
-        const unsigned long long x = bs[k];
-        bs[k] = off;
-        off += x;
-    }
-    if (t == 0) {
-        const bool ovf = total > cap;
-        counters[kCntMLo] = (uint32_t)(total & 0xffffffffull);
-        counters[kCntMHi] = (uint32_t)(total >> 32);
-        counters[kCntOverflow] = ovf ? 1u : 0u;
-        counters[kCntMEff] = ovf ? 0u : (uint32_t)total;
-        if (ovf) counters[kCntSticky] = 1u;
-    }
 }
 
 struct DupArgs {
@@ -228,78 +203,145 @@ struct DupArgs {
     uint32_t *offsets;             // [vn] by splat: first emission position
     uint32_t *offk;                // [vn + 1] by depth rank: first emission position, then M
     uint32_t *wstart;              // [windows + 1] first depth rank of each work window
-    const unsigned long long *blockoff;
+    uint32_t *pstart;              // [emission blocks + 1] depth rank owning each block's start
+    const unsigned long long *blocksum;  // [nblk] per-block tile counts in depth order
     uint32_t *counters;
     uint32_t *keys;
     uint32_t *vals;
-    int vn;
+    uint32_t *hist;                // [kSortBins][eblk] low-digit counts of each emission block
+    uint32_t *ranges;              // [2 * total_tiles], cleared here
+    uint8_t *slot_flags;           // [cap][kSplitBwd], cleared here for positions < M
+    unsigned long long cap;
+    int vn, nblk, eblk, total_tiles;
 };
 
-// Exclusive offsets of the splats' instance runs in depth order, and the
-// work windows.  Splat k's entry sits at position h = k + offk[k] of the
+// Exclusive offsets of the splats' instance runs in depth order, the work
+// windows and the emission blocks.  Each block first sums the block sums
+// before it (and all of them, for M and the overflow flag; block 0 writes
+// the counters).  Splat k's entry sits at position h = k + offk[k] of the
 // sequence (splat, its instances, next splat, ...), the next at h + 1 + cnt;
 // window b starts at the first splat whose entry is at or after b * kWindow.
+// Emission block p covers instance positions [p, p + 1) * kSortItems and
+// starts at the splat whose run holds position p * kSortItems; entry
+// ceil(M / kSortItems) is the last splat with instances.
 __global__ __launch_bounds__(kPreprocessBlock) void k_offsets(DupArgs a) {
     __shared__ unsigned long long scratch[kPreprocessBlock / kWave];
-    const int k = blockIdx.x * kPreprocessBlock + threadIdx.x;
-    const uint32_t idx = k < a.vn ? a.order[k] : 0u;
-    const uint32_t cnt = k < a.vn ? a.tiles[idx] : 0u;
+    const int t = threadIdx.x;
+    unsigned long long before = 0, all = 0;
+    for (int j = t; j < a.nblk; j += kPreprocessBlock) {
+        const unsigned long long x = a.blocksum[j];
+        all += x;
+        before += j < (int)blockIdx.x ? x : 0ull;
+    }
+    before = block_sum<unsigned long long, kPreprocessBlock>(before, scratch);
+    all = block_sum<unsigned long long, kPreprocessBlock>(all, scratch);
+    const bool ovf = all > a.cap;
+    if (blockIdx.x == 0 && t == 0) {
+        a.counters[kCntMLo] = (uint32_t)(all & 0xffffffffull);
+        a.counters[kCntMHi] = (uint32_t)(all >> 32);
+        a.counters[kCntOverflow] = ovf ? 1u : 0u;
+        a.counters[kCntMEff] = ovf ? 0u : (uint32_t)all;
+        if (ovf) a.counters[kCntSticky] = 1u;
+        if (a.vn == 0) a.counters[kCntWin] = 0u;
+    }
+    const int k0 = blockIdx.x * kScanItems + kScanPerThread * t;
+    uint32_t idx[kScanPerThread], cnt[kScanPerThread];
+    unsigned long long local = 0;
+#pragma unroll
+    for (int j = 0; j < kScanPerThread; j++) {
+        idx[j] = k0 + j < a.vn ? a.order[k0 + j] : 0u;
+        cnt[j] = k0 + j < a.vn ? a.tiles[idx[j]] : 0u;
+        local += cnt[j];
+    }
     unsigned long long total;
-    const unsigned long long excl =
-        block_exclusive_scan<unsigned long long, kPreprocessBlock>(cnt, scratch, &total) +
-        a.blockoff[blockIdx.x];
-    if (a.counters[kCntOverflow] != 0u || k >= a.vn) return;
-    a.offsets[idx] = (uint32_t)excl;
-    a.offk[k] = (uint32_t)excl;
-    const unsigned long long h = (unsigned long long)k + excl, h1 = h + 1 + cnt;
-    if (k == 0) a.wstart[0] = 0u;
-    for (unsigned long long b = h / kWindow + 1; b * kWindow <= h1; b++) a.wstart[b] = (uint32_t)k + 1;
-    if (k == a.vn - 1) {
-        const unsigned long long nwin = (h1 + kWindow - 1) / kWindow;
-        if (nwin * kWindow > h1) a.wstart[nwin] = (uint32_t)a.vn;
-        a.offk[a.vn] = (uint32_t)(excl + cnt);
-        a.counters[kCntWin] = (uint32_t)nwin;
+    unsigned long long excl =
+        block_exclusive_scan<unsigned long long, kPreprocessBlock>(local, scratch, &total) + before;
+    if (ovf) return;
+#pragma unroll
+    for (int j = 0; j < kScanPerThread; j++) {
+        const int k = k0 + j;
+        if (k >= a.vn) break;
+        a.offsets[idx[j]] = (uint32_t)excl;
+        a.offk[k] = (uint32_t)excl;
+        const unsigned long long h = (unsigned long long)k + excl, h1 = h + 1 + cnt[j];
+        if (k == 0) a.wstart[0] = 0u;
+        for (unsigned long long b = h / kWindow + 1; b * kWindow <= h1; b++)
+            a.wstart[b] = (uint32_t)k + 1;
+        const unsigned long long e1 = excl + cnt[j];
+        for (unsigned long long p = (excl + kSortItems - 1) / kSortItems; p * kSortItems < e1; p++)
+            a.pstart[p] = (uint32_t)k;
+        if (cnt[j] > 0 && e1 == all) a.pstart[(all + kSortItems - 1) / kSortItems] = (uint32_t)k;
+        if (k == a.vn - 1) {
+            const unsigned long long nwin = (h1 + kWindow - 1) / kWindow;
+            if (nwin * kWindow > h1) a.wstart[nwin] = (uint32_t)a.vn;
+            a.offk[a.vn] = (uint32_t)e1;
+            a.counters[kCntWin] = (uint32_t)nwin;
+        }
+        excl = e1;
     }
 }
 
 // Emits one (tile, view * n + i) pair per tile of each splat's rect, rows
 // outer and columns inner, at the splat's offset; a stable sort of these
-// pairs by tile then yields every tile's list in (depth, index) order.  One
-// block per work window; each thread writes consecutive positions and finds
-// the splat owning a position by binary search over the window's offsets.
+// pairs by tile then yields every tile's list in (depth, index) order.
+// Block p writes instance positions [p, p + 1) * kSortItems, which are the
+// keys of block p of the first pass of that sort, so it also writes their
+// low-digit histogram (zeros past M); each thread finds the splat owning a
+// position by binary search over the block's offsets in LDS.  The blocks
+// also clear the tile ranges and the backward's slot flags of their
+// positions, which the later stages of this forward and of its backward
+// fill in.
 __global__ __launch_bounds__(kWindowThreads) void k_emit(DupArgs a, ViewsK views, int n) {
-    __shared__ uint32_t s_off[kWindow + 1];
-    __shared__ uint32_t s_idx[kWindow];
-    __shared__ uint2 s_rect[kWindow];
-    const int b = blockIdx.x;
-    if (a.counters[kCntOverflow] != 0u || (uint32_t)b >= a.counters[kCntWin]) return;
-    const uint32_t kb = a.wstart[b], ke = a.wstart[b + 1];
-    const int nk = (int)(ke - kb);   // at most kWindow
-    for (int j = threadIdx.x; j < nk; j += kWindowThreads) {
-        const uint32_t idx = a.order[kb + j];
-        s_off[j] = a.offk[kb + j];
-        s_idx[j] = idx;
-        s_rect[j] = a.rect[idx];
-    }
-    const uint32_t e0 = a.offk[kb], e1 = a.offk[ke];
-    if (threadIdx.x == 0) s_off[nk] = e1;
-    __syncthreads();
-    for (uint32_t e = e0 + threadIdx.x; e < e1; e += kWindowThreads) {
-        // largest j with s_off[j] <= e; s_off[0] <= e < s_off[nk]
-        int lo = 0, hi = nk;
-        while (hi - lo > 1) {
-            const int mid = (lo + hi) >> 1;
-            if (s_off[mid] <= e) lo = mid; else hi = mid;
+    static_assert(kWindowThreads == kSortBins, "one histogram bin per thread");
+    constexpr int kMaxSplats = kSortItems + 1;
+    __shared__ uint32_t s_off[kMaxSplats + 1];
+    __shared__ uint32_t s_idx[kMaxSplats];
+    __shared__ uint2 s_rect[kMaxSplats];
+    __shared__ uint32_t s_hist[kSortBins];
+    const int b = blockIdx.x, t = threadIdx.x;
+    for (int i = b * kWindowThreads + t; i < 2 * a.total_tiles; i += gridDim.x * kWindowThreads)
+        a.ranges[i] = 0u;
+    s_hist[t] = 0u;
+    const uint32_t M = a.counters[kCntMEff];
+    const uint32_t p0 = (uint32_t)b * kSortItems;
+    if (p0 < M) {
+        const uint32_t p1 = min(p0 + (uint32_t)kSortItems, M);
+        const uint32_t kb = a.pstart[b];
+        const int nk = min((int)(a.pstart[b + 1] + 1 - kb), kMaxSplats);
+        for (int j = t; j < nk; j += kWindowThreads) {
+            const uint32_t idx = a.order[kb + j];
+            s_off[j] = a.offk[kb + j];
+            s_idx[j] = idx;
+            s_rect[j] = a.rect[idx];
         }
-        const uint2 r = s_rect[lo];
-        const int x0 = r.x & 0xffff, y0 = r.x >> 16, x1 = r.y & 0xffff;
-        const uint32_t w = (uint32_t)(x1 - x0), local = e - s_off[lo];
-        const uint32_t idx = s_idx[lo];
-        const ViewK &vw = views.v[idx / (uint32_t)n];
-        const uint32_t ty = (uint32_t)y0 + local / w, tx = (uint32_t)x0 + local % w;
-        a.keys[e] = (uint32_t)vw.tile_base + ty * (uint32_t)vw.gw + tx;
-        a.vals[e] = idx;
+        if (t == 0) s_off[nk] = a.offk[kb + nk];
+        __syncthreads();
+        for (uint32_t e = p0 + t; e < p1; e += kWindowThreads) {
+            // largest j with s_off[j] <= e; s_off[0] <= p0 <= e < p1 <= s_off[nk]
+            int lo = 0, hi = nk;
+            while (hi - lo > 1) {
+                const int mid = (lo + hi) >> 1;
+                if (s_off[mid] <= e) lo = mid; else hi = mid;
+            }
+            const uint2 r = s_rect[lo];
+            const int x0 = r.x & 0xffff, y0 = r.x >> 16, x1 = r.y & 0xffff;
+            const uint32_t w = (uint32_t)(x1 - x0), local = e - s_off[lo];
+            const uint32_t idx = s_idx[lo];
+            const ViewK &vw = views.v[idx / (uint32_t)n];
+            const uint32_t ty = (uint32_t)y0 + local / w, tx = (uint32_t)x0 + local % w;
+            const uint32_t key = (uint32_t)vw.tile_base + ty * (uint32_t)vw.gw + tx;
+            a.keys[e] = key;
+            a.vals[e] = idx;
+            atomicAdd(&s_hist[key & (kSortBins - 1)], 1u);
+            if constexpr (kSplitBwd == 1) a.slot_flags[e] = 0;
+            else if constexpr (kSplitBwd == 2) reinterpret_cast<uint16_t *>(a.slot_flags)[e] = 0;
+            else if constexpr (kSplitBwd == 4) reinterpret_cast<uint32_t *>(a.slot_flags)[e] = 0u;
+            else
+                for (int q = 0; q < kSplitBwd; q++) a.slot_flags[(size_t)kSplitBwd * e + q] = 0;
+        }
     }
+    __syncthreads();
+    a.hist[(size_t)t * a.eblk + b] = s_hist[t];
 }
 
 hipError_t launch_preprocess(const GaussiansK &g, const ViewsK &views, const float *poses,
@@ -327,32 +369,33 @@ hipError_t launch_preprocess(const GaussiansK &g, const ViewsK &views, const flo
 
 hipError_t launch_offsets_and_duplicate(const ViewsK &views, const Layout &L, char *ws,
                                         hipStream_t s) {
-    unsigned long long *bs = region<unsigned long long>(ws, L.blocksum);
-    uint32_t *counters = region<uint32_t>(ws, L.counters);
-    const uint32_t *order = region<uint32_t>(ws, L.dvals0);   // depth sort: 4 passes, even
-    const int vn = (int)L.vn;
-    if (vn > 0) {
-        hipLaunchKernelGGL(k_sorted_blocksums, dim3(L.nblk_vn), dim3(kPreprocessBlock), 0, s, order,
-                           region<uint32_t>(ws, L.tiles), bs, vn);
-    }
-    hipLaunchKernelGGL(k_scan_blocksums, dim3(1), dim3(1024), 0, s, bs, L.nblk_vn, counters,
-                       (unsigned long long)L.cap);
-    hipError_t e = hipGetLastError();
-    if (e != hipSuccess || vn == 0) return e;
     DupArgs a;
-    a.order = order;
+    a.order = region<uint32_t>(ws, L.dvals0);   // depth sort: 4 passes, even
     a.rect = region<uint2>(ws, L.rect);
     a.tiles = region<uint32_t>(ws, L.tiles);
     a.offsets = region<uint32_t>(ws, L.offsets);
     a.offk = region<uint32_t>(ws, L.offk);
     a.wstart = region<uint32_t>(ws, L.wstart);
-    a.blockoff = bs;
-    a.counters = counters;
+    a.pstart = region<uint32_t>(ws, L.pstart);
+    a.blocksum = region<unsigned long long>(ws, L.blocksum);
+    a.counters = region<uint32_t>(ws, L.counters);
     a.keys = region<uint32_t>(ws, L.keys0);
     a.vals = region<uint32_t>(ws, L.vals0);
-    a.vn = vn;
-    hipLaunchKernelGGL(k_offsets, dim3(L.nblk_vn), dim3(kPreprocessBlock), 0, s, a);
-    hipLaunchKernelGGL(k_emit, dim3(L.nwin_max), dim3(kWindowThreads), 0, s, a, views, (int)L.n);
+    a.hist = region<uint32_t>(ws, L.hist);
+    a.ranges = region<uint32_t>(ws, L.ranges);
+    a.slot_flags = region<uint8_t>(ws, L.slot_flags);
+    a.cap = (unsigned long long)L.cap;
+    a.vn = (int)L.vn;
+    a.nblk = L.nblk_scan;
+    a.eblk = L.nblk_emit;
+    a.total_tiles = L.total_tiles;
+    if (a.vn > 0) {
+        hipLaunchKernelGGL(k_sorted_blocksums, dim3(L.nblk_scan), dim3(kPreprocessBlock), 0, s,
+                           a.order, a.tiles, region<unsigned long long>(ws, L.blocksum), a.vn);
+    }
+    hipLaunchKernelGGL(k_offsets, dim3(L.nblk_scan > 0 ? L.nblk_scan : 1), dim3(kPreprocessBlock),
+                       0, s, a);
+    hipLaunchKernelGGL(k_emit, dim3(L.nblk_emit), dim3(kWindowThreads), 0, s, a, views, (int)L.n);
     return hipGetLastError();
 }
 

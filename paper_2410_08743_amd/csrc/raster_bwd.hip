@@ -264,10 +264,9 @@ hipError_t launch_raster_bwd(const ViewsK &views, const Layout &L, char *ws, con
     a.slots = region<float>(ws, L.slots);
     a.slot_flags = region<uint8_t>(ws, L.slot_flags);
     a.total_tiles = L.total_tiles;
-    // slots no entry writes stay flagged 0 and count as zero
-    hipError_t e = launch_fill_u32(region<uint32_t>(ws, L.slot_flags), 0u,
-                                   ((int64_t)kSplit * L.cap + 3) / 4, s);
-    if (e != hipSuccess) return e;
+    // Slots that no entry writes keep the flag 0 that the forward's emission
+    // stored and count as zero.  The set of written slots depends only on the
+    // forward's state, so repeated backwards of one forward agree on it.
     hipLaunchKernelGGL(k_raster_bwd, dim3(raster_blocks<kSplit>(L.total_tiles)), dim3(kRasterThreads), 0, s,
                        a, views);
     return hipGetLastError();

@@ -241,14 +241,11 @@ __global__ __launch_bounds__(kRasterThreads) __attribute__((amdgpu_waves_per_eu(
 }
 
 hipError_t launch_ranges(const Layout &L, char *ws, const uint32_t *keys, hipStream_t s) {
-    uint2 *ranges = region<uint2>(ws, L.ranges);
-    hipError_t e = launch_fill_u32(reinterpret_cast<uint32_t *>(ranges), 0u,
-                                   2 * (int64_t)L.total_tiles, s);
-    if (e != hipSuccess) return e;
+    uint2 *ranges = region<uint2>(ws, L.ranges);   // cleared by the emission
     const int64_t blocks = (L.cap + 255) / 256;
     hipLaunchKernelGGL(k_ranges, dim3((unsigned)blocks), dim3(256), 0, s, keys,
                        region<uint32_t>(ws, L.counters), ranges);
-    e = hipGetLastError();
+    hipError_t e = hipGetLastError();
     if (e != hipSuccess || L.total_tiles == 0) return e;
     hipLaunchKernelGGL(k_tile_order, dim3(1), dim3(1024), 0, s, ranges, L.total_tiles,
                        region<uint32_t>(ws, L.tile_order));

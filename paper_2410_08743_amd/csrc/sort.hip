@@ -9,12 +9,15 @@
 // view instead of 12-byte pairs over 6.
 //
 // Each pass is reduce-then-scan: per-block digit histograms, a per-digit
-// scan across blocks, then a scatter in which every block ranks its 4096 keys
-// stably with wavefront ballots (one ballot per digit bit on wave64), sorts
-// them locally in LDS and writes them out digit run by digit run, so global
-// stores are contiguous within each run.  The element count may live in
-// device memory (the instance count), in which case the grid is sized by
-// capacity and blocks past the count exit at once: no host synchronisation.
+// scan across blocks, then a scatter in which every block ranks its
+// kSortItems keys stably with wavefront ballots (one ballot per digit bit on
+// wave64), sorts them locally in LDS and writes them out digit run by digit
+// run, so global stores are contiguous within each run.  The element count
+// may live in device memory (the instance count), in which case the grid is
+// sized by capacity and blocks past the count exit at once: no host
+// synchronisation.  The instance emission writes the first pass's
+// histograms of the instance sort itself (its blocks are the sort's blocks),
+// which saves that pass's histogram launch.
 #include "block_ops.h"
 #include "gsp_internal.h"
 
@@ -167,7 +170,8 @@ __global__ __launch_bounds__(kSortThreads) void k_sort_scatter(SortPass a) {
 
 int launch_sort_pairs(uint32_t *k0, uint32_t *v0, uint32_t *k1, uint32_t *v1, uint32_t *hist,
                       uint32_t *digit_tot, const uint32_t *count_ptr, uint32_t count_val,
-                      int64_t max_count, int bits, hipStream_t s, hipError_t *err) {
+                      int64_t max_count, int bits, bool hist0_given, hipStream_t s,
+                      hipError_t *err) {
     SortPass a;
     a.hist = hist;
     a.digit_tot = digit_tot;
@@ -183,7 +187,8 @@ int launch_sort_pairs(uint32_t *k0, uint32_t *v0, uint32_t *k1, uint32_t *v1, ui
         a.keys_out = (p & 1) ? k0 : k1;
         a.vals_out = (p & 1) ? v0 : v1;
         a.shift = p * kSortBits;
-        hipLaunchKernelGGL(k_sort_hist, dim3(a.nblk), dim3(kSortThreads), 0, s, a);
+        if (p > 0 || !hist0_given)
+            hipLaunchKernelGGL(k_sort_hist, dim3(a.nblk), dim3(kSortThreads), 0, s, a);
         hipLaunchKernelGGL(k_sort_scan, dim3(kSortBins), dim3(kSortThreads), 0, s, a);
         hipLaunchKernelGGL(k_sort_scatter, dim3(a.nblk), dim3(kSortThreads), 0, s, a);
         *err = hipGetLastError();
@@ -197,7 +202,7 @@ hipError_t launch_depth_sort(const Layout &L, char *ws, hipStream_t s) {
     launch_sort_pairs(region<uint32_t>(ws, L.dkeys0), region<uint32_t>(ws, L.dvals0),
                       region<uint32_t>(ws, L.dkeys1), region<uint32_t>(ws, L.dvals1),
                       region<uint32_t>(ws, L.hist), region<uint32_t>(ws, L.digit_tot), nullptr,
-                      (uint32_t)L.vn, L.vn, 32, s, &e);
+                      (uint32_t)L.vn, L.vn, 32, false, s, &e);
     return e;
 }
 
@@ -206,7 +211,8 @@ hipError_t launch_tile_sort(const Layout &L, char *ws, hipStream_t s) {
     launch_sort_pairs(region<uint32_t>(ws, L.keys0), region<uint32_t>(ws, L.vals0),
                       region<uint32_t>(ws, L.keys1), region<uint32_t>(ws, L.vals1),
                       region<uint32_t>(ws, L.hist), region<uint32_t>(ws, L.digit_tot),
-                      region<uint32_t>(ws, L.counters) + kCntMEff, 0u, L.cap, L.tile_bits, s, &e);
+                      region<uint32_t>(ws, L.counters) + kCntMEff, 0u, L.cap, L.tile_bits, true, s,
+                      &e);
     return e;
 }
 
