@@ -200,7 +200,7 @@ Layout make_layout(int64_t n, int32_t sh_degree, int32_t V, const ViewsK &views,
     L.nblk_sort = (int)((max_sorted + kSortItems - 1) / kSortItems);
     L.nblk_emit = (int)((L.cap + kSortItems - 1) / kSortItems);   // blocks of the instance sort
     L.tile_bits = tile_bits_for(views.total_tiles);
-    L.tile_passes = (L.tile_bits + kSortBits - 1) / kSortBits;
+    L.tile_passes = sort_passes(L.tile_bits);
     L.nwin_max = (int)((L.vn + L.cap + kWindow - 1) / kWindow + 1);
     const size_t vn = (size_t)L.vn, capz = (size_t)L.cap;
     size_t off = 0;

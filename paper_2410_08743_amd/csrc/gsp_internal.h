@@ -157,6 +157,16 @@ inline int tile_bits_for(int total_tiles) {
     return tile_bits;
 }
 
+// Passes of a radix sort on `bits` key bits, and the digit width of each:
+// the bits are shared out evenly (12 bits: two 6-bit passes rather than 8 +
+// 4), which keeps the digit runs of the first pass long enough for
+// full-line stores.
+inline int sort_passes(int bits) { return (bits + kSortBits - 1) / kSortBits; }
+inline int digit_bits(int bits) {
+    const int p = sort_passes(bits);
+    return p > 0 ? (bits + p - 1) / p : 0;
+}
+
 // Buffers holding the result of the two sorts (depth: 4 passes, even).
 inline size_t sorted_keys(const Layout &L) { return (L.tile_passes & 1) ? L.keys1 : L.keys0; }
 inline size_t sorted_vals(const Layout &L) { return (L.tile_passes & 1) ? L.vals1 : L.vals0; }

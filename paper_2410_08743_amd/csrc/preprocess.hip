@@ -209,6 +209,7 @@ struct DupArgs {
     uint32_t *keys;
     uint32_t *vals;
     uint32_t *hist;                // [kSortBins][eblk] low-digit counts of each emission block
+    uint32_t mask0;                // low digit of the instance sort's first pass
     uint32_t *ranges;              // [2 * total_tiles], cleared here
     uint8_t *slot_flags;           // [cap][kSplitBwd], cleared here for positions < M
     unsigned long long cap;
@@ -281,6 +282,13 @@ __global__ __launch_bounds__(kPreprocessBlock) void k_offsets(DupArgs a) {
     }
 }
 
+#ifndef GSP_EMIT_THREADS
+#define GSP_EMIT_THREADS 256
+#endif
+constexpr int kEmitThreads = GSP_EMIT_THREADS;
+static_assert(kEmitThreads >= kSortBins && kEmitThreads <= 1024 && kEmitThreads % kWave == 0,
+              "emission block size");
+
 // Emits one (tile, view * n + i) pair per tile of each splat's rect, rows
 // outer and columns inner, at the splat's offset; a stable sort of these
 // pairs by tile then yields every tile's list in (depth, index) order.
@@ -291,24 +299,26 @@ __global__ __launch_bounds__(kPreprocessBlock) void k_offsets(DupArgs a) {
 // also clear the tile ranges and the backward's slot flags of their
 // positions, which the later stages of this forward and of its backward
 // fill in.
-__global__ __launch_bounds__(kWindowThreads) void k_emit(DupArgs a, ViewsK views, int n) {
-    static_assert(kWindowThreads == kSortBins, "one histogram bin per thread");
+__global__ __launch_bounds__(kEmitThreads) void k_emit(DupArgs a, ViewsK views, int n) {
+    static_assert(kEmitThreads % kSortBins == 0, "whole histograms per block");
     constexpr int kMaxSplats = kSortItems + 1;
     __shared__ uint32_t s_off[kMaxSplats + 1];
     __shared__ uint32_t s_idx[kMaxSplats];
     __shared__ uint2 s_rect[kMaxSplats];
     __shared__ uint32_t s_hist[kSortBins];
     const int b = blockIdx.x, t = threadIdx.x;
-    for (int i = b * kWindowThreads + t; i < 2 * a.total_tiles; i += gridDim.x * kWindowThreads)
+    for (int i = b * kEmitThreads + t; i < 2 * a.total_tiles; i += gridDim.x * kEmitThreads)
         a.ranges[i] = 0u;
-    s_hist[t] = 0u;
+    if (t < kSortBins) s_hist[t] = 0u;
+    // pstart has eblk + 1 entries; they are read before M is known (those of
+    // blocks past M are stale and unused)
+    const uint32_t kb = a.pstart[b], kn = a.pstart[b + 1];
     const uint32_t M = a.counters[kCntMEff];
     const uint32_t p0 = (uint32_t)b * kSortItems;
     if (p0 < M) {
         const uint32_t p1 = min(p0 + (uint32_t)kSortItems, M);
-        const uint32_t kb = a.pstart[b];
-        const int nk = min((int)(a.pstart[b + 1] + 1 - kb), kMaxSplats);
-        for (int j = t; j < nk; j += kWindowThreads) {
+        const int nk = min((int)(kn + 1 - kb), kMaxSplats);
+        for (int j = t; j < nk; j += kEmitThreads) {
             const uint32_t idx = a.order[kb + j];
             s_off[j] = a.offk[kb + j];
             s_idx[j] = idx;
@@ -316,7 +326,7 @@ __global__ __launch_bounds__(kWindowThreads) void k_emit(DupArgs a, ViewsK views
         }
         if (t == 0) s_off[nk] = a.offk[kb + nk];
         __syncthreads();
-        for (uint32_t e = p0 + t; e < p1; e += kWindowThreads) {
+        for (uint32_t e = p0 + t; e < p1; e += kEmitThreads) {
             // largest j with s_off[j] <= e; s_off[0] <= p0 <= e < p1 <= s_off[nk]
             int lo = 0, hi = nk;
             while (hi - lo > 1) {
@@ -332,7 +342,7 @@ __global__ __launch_bounds__(kWindowThreads) void k_emit(DupArgs a, ViewsK views
             const uint32_t key = (uint32_t)vw.tile_base + ty * (uint32_t)vw.gw + tx;
             a.keys[e] = key;
             a.vals[e] = idx;
-            atomicAdd(&s_hist[key & (kSortBins - 1)], 1u);
+            atomicAdd(&s_hist[key & a.mask0], 1u);
             if constexpr (kSplitBwd == 1) a.slot_flags[e] = 0;
             else if constexpr (kSplitBwd == 2) reinterpret_cast<uint16_t *>(a.slot_flags)[e] = 0;
             else if constexpr (kSplitBwd == 4) reinterpret_cast<uint32_t *>(a.slot_flags)[e] = 0u;
@@ -341,7 +351,7 @@ __global__ __launch_bounds__(kWindowThreads) void k_emit(DupArgs a, ViewsK views
         }
     }
     __syncthreads();
-    a.hist[(size_t)t * a.eblk + b] = s_hist[t];
+    if (t < kSortBins) a.hist[(size_t)t * a.eblk + b] = s_hist[t];
 }
 
 hipError_t launch_preprocess(const GaussiansK &g, const ViewsK &views, const float *poses,
@@ -382,6 +392,7 @@ hipError_t launch_offsets_and_duplicate(const ViewsK &views, const Layout &L, ch
     a.keys = region<uint32_t>(ws, L.keys0);
     a.vals = region<uint32_t>(ws, L.vals0);
     a.hist = region<uint32_t>(ws, L.hist);
+    a.mask0 = (1u << digit_bits(L.tile_bits)) - 1u;
     a.ranges = region<uint32_t>(ws, L.ranges);
     a.slot_flags = region<uint8_t>(ws, L.slot_flags);
     a.cap = (unsigned long long)L.cap;
@@ -395,7 +406,7 @@ hipError_t launch_offsets_and_duplicate(const ViewsK &views, const Layout &L, ch
     }
     hipLaunchKernelGGL(k_offsets, dim3(L.nblk_scan > 0 ? L.nblk_scan : 1), dim3(kPreprocessBlock),
                        0, s, a);
-    hipLaunchKernelGGL(k_emit, dim3(L.nblk_emit), dim3(kWindowThreads), 0, s, a, views, (int)L.n);
+    hipLaunchKernelGGL(k_emit, dim3(L.nblk_emit), dim3(kEmitThreads), 0, s, a, views, (int)L.n);
     return hipGetLastError();
 }
 

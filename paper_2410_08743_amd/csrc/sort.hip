@@ -34,6 +34,7 @@ struct SortPass {
     uint32_t count_val;         // element count when count_ptr is null
     int nblk;
     int shift;
+    uint32_t mask;     // digit mask of this pass (at most kSortBins - 1)
 };
 
 __device__ __forceinline__ uint32_t sort_count(const SortPass &a) {
@@ -51,7 +52,7 @@ __global__ __launch_bounds__(kSortThreads) void k_sort_hist(SortPass a) {
 #pragma unroll 4
         for (int r = 0; r < kSortRounds; r++) {
             const size_t k = base + (size_t)r * kSortThreads + t;
-            if (k < M) atomicAdd(&h[(a.keys_in[k] >> a.shift) & (kSortBins - 1)], 1u);
+            if (k < M) atomicAdd(&h[(a.keys_in[k] >> a.shift) & a.mask], 1u);
         }
     }
     __syncthreads();
@@ -112,7 +113,7 @@ __global__ __launch_bounds__(kSortThreads) void k_sort_scatter(SortPass a) {
     __syncthreads();
 #pragma unroll
     for (int r = 0; r < kSortRounds; r++) {
-        if (r * kSortThreads + t < cnt) atomicAdd(&run[(key[r] >> a.shift) & (kSortBins - 1)], 1u);
+        if (r * kSortThreads + t < cnt) atomicAdd(&run[(key[r] >> a.shift) & a.mask], 1u);
     }
     __syncthreads();
     uint32_t tot;
@@ -127,7 +128,7 @@ __global__ __launch_bounds__(kSortThreads) void k_sort_scatter(SortPass a) {
 #pragma unroll 1
     for (int r = 0; r < kSortRounds; r++) {
         const bool valid = r * kSortThreads + t < cnt;
-        const uint32_t d = (key[r] >> a.shift) & (kSortBins - 1);
+        const uint32_t d = (key[r] >> a.shift) & a.mask;
         unsigned long long peers = __ballot(valid);
 #pragma unroll
         for (int b = 0; b < kSortBits; b++) {
@@ -161,7 +162,7 @@ __global__ __launch_bounds__(kSortThreads) void k_sort_scatter(SortPass a) {
 
     for (int i = t; i < cnt; i += kSortThreads) {
         const uint32_t k = skeys[i];
-        const uint32_t d = (k >> a.shift) & (kSortBins - 1);
+        const uint32_t d = (k >> a.shift) & a.mask;
         const size_t dst = (size_t)gbase[d] + (uint32_t)(i - dstart[d]);
         a.keys_out[dst] = k;
         a.vals_out[dst] = svals[i];
@@ -179,14 +180,16 @@ int launch_sort_pairs(uint32_t *k0, uint32_t *v0, uint32_t *k1, uint32_t *v1, ui
     a.count_val = count_val;
     a.nblk = (int)((max_count + kSortItems - 1) / kSortItems);
     *err = hipSuccess;
-    const int passes = (bits + kSortBits - 1) / kSortBits;
+    const int passes = sort_passes(bits);
+    const int pbits = digit_bits(bits);
+    a.mask = (1u << pbits) - 1u;
     if (a.nblk == 0) return passes;
     for (int p = 0; p < passes; p++) {
         a.keys_in = (p & 1) ? k1 : k0;
         a.vals_in = (p & 1) ? v1 : v0;
         a.keys_out = (p & 1) ? k0 : k1;
         a.vals_out = (p & 1) ? v0 : v1;
-        a.shift = p * kSortBits;
+        a.shift = p * pbits;
         if (p > 0 || !hist0_given)
             hipLaunchKernelGGL(k_sort_hist, dim3(a.nblk), dim3(kSortThreads), 0, s, a);
         hipLaunchKernelGGL(k_sort_scan, dim3(kSortBins), dim3(kSortThreads), 0, s, a);
