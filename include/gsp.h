@@ -194,6 +194,73 @@ gsp_status gsp_pose_adam(gsp_ctx *ctx, int32_t V, float *poses, const float *dpo
                          float *m, float *v, int32_t *steps, const gsp_adam_params *params,
                          const void *guard_workspace, void *stream);
 
+/* Image loss of the joint refinement, L_RGB of Eq. (16), per view:
+ *   loss[v] = (1 - beta) mean |pred - target| + beta (1 - mean SSIM(pred, target))
+ * over the 3 x roi_h x roi_w values of view v, and grad[v] = dloss[v]/dpred[v]
+ * (the L1 part as in gsp_loss_l1).  SSIM is evaluated per channel at every
+ * pixel with an 11 x 11 Gaussian window of standard deviation 1.5 (weights
+ * normalised), C1 = 0.01^2, C2 = 0.03^2, and zero padding outside the image
+ * (the formulation of the 3DGS loss that Sec. III-C adopts).  Values are
+ * expected in [0, 1].  pred, target, grad: host arrays of V device pointers
+ * (grad may not alias pred or target).  loss: device float [V] or NULL.
+ * scratch: device memory of at least gsp_loss_rgb_scratch_bytes(V, views)
+ * bytes (the per-pixel SSIM derivatives and per-tile partial sums); it is
+ * needed with or without loss.  Losses are reduced in a fixed order
+ * (bit-reproducible), and a view's results do not depend on the other views
+ * of the call. */
+gsp_status gsp_loss_rgb(gsp_ctx *ctx, int32_t V, const gsp_view *views, const float *const *pred,
+                        const float *const *target, float *const *grad, float *loss, float beta,
+                        void *scratch, size_t scratch_bytes, void *stream);
+size_t gsp_loss_rgb_scratch_bytes(int32_t V, const gsp_view *views);
+
+/* Raw Gaussian parameters of the joint refinement (device, updated in place
+ * by gsp_gaussian_adam): means [n][3], log_scales [n][3] (scales =
+ * exp(log_scales)), quats [n][4] (raw; normalised by the renderer),
+ * logit_opacities [n] (opacities = sigmoid(logit)), sh [n][S][3]. */
+typedef struct {
+    float *means;
+    float *log_scales;
+    float *quats;
+    float *logit_opacities;
+    float *sh;
+} gsp_gaussian_params;
+
+/* Hyper-parameters of gsp_gaussian_adam (double, so that decimal values
+ * such as beta2 = 0.999 reach the update unrounded).  The means' learning
+ * rate decays
+ * log-linearly from lr_means_start at step 1 to lr_means_end at step
+ * total_steps (held after it); the SH degree-0 coefficients use lr_sh_dc,
+ * the higher ones lr_sh_rest.  aniso_r is the ratio r of Eq. (17) and
+ * aniso_weight its weight in the objective (Eq. (15): 1; 0 turns it off). */
+typedef struct {
+    double lr_means_start, lr_means_end;
+    int32_t total_steps;
+    double lr_sh_dc, lr_sh_rest, lr_opacities, lr_scales, lr_quats;
+    double beta1, beta2, eps;
+    double aniso_r, aniso_weight;
+} gsp_gaussian_adam_params;
+
+/* One Adam step (step = 1, 2, ...; bias-corrected) on the raw Gaussian
+ * parameters, given `grads` (means, scales, quats, opacities, sh all
+ * non-NULL) from gsp_render_bwd, i.e. gradients with respect to the
+ * activated parameters: the kernel applies the activations' chain rule and
+ * adds aniso_weight * dL_An/dscales (Eq. (17); for tied scales the first
+ * index is the max, resp. min).  m, v: device float arrays of n (11 + 3 S)
+ * moments each, laid out group after group in the order of
+ * gsp_gaussian_params.  scales_out [n][3], opacities_out [n]: device, receive
+ * exp(log_scales) and sigmoid(logit_opacities) after the step (the arrays a
+ * gsp_gaussians for the next render points at, with means, quats and sh
+ * taken from `params`).  aniso_loss: device float or NULL; receives L_An of
+ * the parameters before the step, and then needs scratch of
+ * gsp_gaussian_adam_scratch_bytes(n) bytes.  guard_workspace as for
+ * gsp_pose_adam (on overflow nothing is written). */
+gsp_status gsp_gaussian_adam(gsp_ctx *ctx, int64_t n, int32_t sh_degree,
+                             const gsp_gaussian_params *params, const gsp_grads *grads, float *m,
+                             float *v, int32_t step, const gsp_gaussian_adam_params *hp,
+                             float *scales_out, float *opacities_out, float *aniso_loss,
+                             void *scratch, const void *guard_workspace, void *stream);
+size_t gsp_gaussian_adam_scratch_bytes(int64_t n);
+
 /* Workspace introspection for tests: device pointer and element count of an
  * intermediate array of the last forward/backward.  Names: "geom" (float4
  * pairs per view-Gaussian: u_hi v_hi u_lo v_lo | A2 B2 C2 log2(o), with
@@ -215,7 +282,8 @@ gsp_status gsp_inspect(gsp_ctx *ctx, const gsp_gaussians *g, int32_t V, const gs
 /* Measurement modes (bit mask for gsp_profile_enable).
  * GSP_PROFILE_TIMING: every stage of gsp_render_fwd / gsp_render_bwd
  * (preprocess, duplicate, sort, ranges, raster_fwd, raster_bwd,
- * preprocess_bwd) and the gsp_loss_l1 and gsp_pose_adam kernels are
+ * preprocess_bwd) and the gsp_loss_l1, gsp_loss_rgb, gsp_pose_adam and
+ * gsp_gaussian_adam kernels are
  * bracketed by HIP events recorded on the call's stream.
  * GSP_PROFILE_COUNTS: the forward rasterizer also counts, per pixel, the
  * (pixel, splat) pairs it evaluated and blended (gsp_inspect "neval",

@@ -18,7 +18,8 @@ EXPORTS = (
     "gsp_create", "gsp_destroy", "gsp_workspace_size", "gsp_render_fwd", "gsp_render_bwd",
     "gsp_instances", "gsp_loss_l1", "gsp_loss_l1_scratch_bytes", "gsp_pose_adam",
     "gsp_inspect", "gsp_status_string", "gsp_last_error", "gsp_version",
-    "gsp_profile_enable", "gsp_profile_read",
+    "gsp_profile_enable", "gsp_profile_read", "gsp_loss_rgb", "gsp_loss_rgb_scratch_bytes",
+    "gsp_gaussian_adam", "gsp_gaussian_adam_scratch_bytes",
 )
 
 
@@ -59,6 +60,21 @@ class AdamParams(ctypes.Structure):
                 ("beta2", ctypes.c_float), ("eps", ctypes.c_float)]
 
 
+class GaussianParams(ctypes.Structure):
+    _fields_ = [("means", ctypes.c_void_p), ("log_scales", ctypes.c_void_p),
+                ("quats", ctypes.c_void_p), ("logit_opacities", ctypes.c_void_p),
+                ("sh", ctypes.c_void_p)]
+
+
+class GaussianAdamParams(ctypes.Structure):
+    _fields_ = [("lr_means_start", ctypes.c_double), ("lr_means_end", ctypes.c_double),
+                ("total_steps", ctypes.c_int32), ("lr_sh_dc", ctypes.c_double),
+                ("lr_sh_rest", ctypes.c_double), ("lr_opacities", ctypes.c_double),
+                ("lr_scales", ctypes.c_double), ("lr_quats", ctypes.c_double),
+                ("beta1", ctypes.c_double), ("beta2", ctypes.c_double), ("eps", ctypes.c_double),
+                ("aniso_r", ctypes.c_double), ("aniso_weight", ctypes.c_double)]
+
+
 _lib = None
 
 
@@ -86,6 +102,10 @@ def lib():
                          ctypes.POINTER(I64)], I32),
         "gsp_profile_enable": ([P, ctypes.c_int], I32),
         "gsp_profile_read": ([P, I32, P, P, P, ctypes.POINTER(I32)], I32),
+        "gsp_loss_rgb": ([P, I32, P, P, P, P, P, ctypes.c_float, P, SZ, P], I32),
+        "gsp_loss_rgb_scratch_bytes": ([I32, P], SZ),
+        "gsp_gaussian_adam": ([P, I64, I32, P, P, P, P, I32, P, P, P, P, P, P, P], I32),
+        "gsp_gaussian_adam_scratch_bytes": ([I64], SZ),
         "gsp_status_string": ([I32], ctypes.c_char_p),
         "gsp_last_error": ([], ctypes.c_char_p),
         "gsp_version": ([], ctypes.c_int),

@@ -4,6 +4,7 @@
 // kernels of the other files.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
@@ -554,6 +555,173 @@ gsp_status gsp_pose_adam(gsp_ctx *ctx, int32_t V, float *poses, const float *dpo
     });
     if (e != hipSuccess) return hip_fail(e, "pose adam");
     return GSP_OK;
+}
+
+namespace {
+
+// Normalised 11-tap Gaussian window of standard deviation 1.5, in double.
+void ssim_window(float out[11]) {
+    double w[11], sum = 0.0;
+    for (int k = 0; k < 11; k++) {
+        const double d = k - 5;
+        w[k] = std::exp(-d * d / (2.0 * 1.5 * 1.5));
+        sum += w[k];
+    }
+    for (int k = 0; k < 11; k++) out[k] = (float)(w[k] / sum);
+}
+
+struct RgbLayout {
+    int total_tiles;
+    int64_t total_pix;
+    size_t partial_bytes, total;
+};
+
+RgbLayout rgb_layout(int32_t V, const gsp_view *views) {
+    RgbLayout L{0, 0, 0, 0};
+    for (int v = 0; views && v < V; v++) {
+        L.total_tiles += gsp::ssim_tiles(views[v].roi_w, views[v].roi_h);
+        L.total_pix += (int64_t)views[v].roi_w * views[v].roi_h;
+    }
+    L.partial_bytes = align256((size_t)3 * (L.total_tiles > 0 ? L.total_tiles : 1) * sizeof(double2));
+    L.total = L.partial_bytes + (size_t)9 * L.total_pix * sizeof(float);
+    return L;
+}
+
+}  // namespace
+
+gsp_status gsp_loss_rgb(gsp_ctx *ctx, int32_t V, const gsp_view *views, const float *const *pred,
+                        const float *const *target, float *const *grad, float *loss, float beta,
+                        void *scratch, size_t scratch_bytes, void *stream) {
+    gsp_status s = check_device(ctx);
+    if (s != GSP_OK) return s;
+    gsp::ViewsK vk;
+    int64_t total_pix = 0;
+    s = make_views(V, views, &vk, &total_pix);
+    if (s != GSP_OK) return s;
+    if (!pred || !target || !grad) return fail(GSP_EINVAL, "null pointer array");
+    if (!scratch) return fail(GSP_EINVAL, "null scratch");
+    if (!(beta >= 0.f && beta <= 1.f)) return fail(GSP_EINVAL, "beta must lie in [0, 1]");
+    const RgbLayout L = rgb_layout(V, views);
+    if (scratch_bytes < L.total)
+        return fail(GSP_ENOMEM, "scratch of %zu bytes is smaller than the %zu needed", scratch_bytes,
+                    L.total);
+    gsp::RgbViewsK a;
+    std::memset(&a, 0, sizeof a);
+    a.V = V;
+    a.beta = beta;
+    a.total_tiles = L.total_tiles;
+    ssim_window(a.win);
+    float *maps = reinterpret_cast<float *>(static_cast<char *>(scratch) + L.partial_bytes);
+    int64_t pix = 0;
+    for (int v = 0; v < V; v++) {
+        if (!pred[v] || !target[v] || !grad[v])
+            return fail(GSP_EINVAL, "null pred, target or grad of view %d", v);
+        if (grad[v] == pred[v] || grad[v] == target[v])
+            return fail(GSP_EINVAL, "grad of view %d aliases an input", v);
+        a.pred[v] = pred[v];
+        a.target[v] = target[v];
+        a.grad[v] = grad[v];
+        a.w[v] = views[v].roi_w;
+        a.h[v] = views[v].roi_h;
+        a.tiles_x[v] = (views[v].roi_w + 63) / 64;
+        a.tile_base[v + 1] = a.tile_base[v] + gsp::ssim_tiles(views[v].roi_w, views[v].roi_h);
+        a.gmap[v] = maps + 9 * pix;
+        pix += (int64_t)views[v].roi_w * views[v].roi_h;
+    }
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    hipError_t e = stage(ctx, "loss_rgb", st, [&] {
+        return gsp::launch_loss_rgb(a, loss, static_cast<double2 *>(scratch), st);
+    });
+    if (e != hipSuccess) return hip_fail(e, "rgb loss");
+    return GSP_OK;
+}
+
+size_t gsp_loss_rgb_scratch_bytes(int32_t V, const gsp_view *views) {
+    return rgb_layout(V, views).total;
+}
+
+gsp_status gsp_gaussian_adam(gsp_ctx *ctx, int64_t n, int32_t sh_degree,
+                             const gsp_gaussian_params *params, const gsp_grads *grads, float *m,
+                             float *v, int32_t step, const gsp_gaussian_adam_params *hp,
+                             float *scales_out, float *opacities_out, float *aniso_loss,
+                             void *scratch, const void *guard_workspace, void *stream) {
+    gsp_status s = check_device(ctx);
+    if (s != GSP_OK) return s;
+    if (n < 0 || n >= (int64_t(1) << 31)) return fail(GSP_EINVAL, "bad Gaussian count");
+    if (sh_degree < 0 || sh_degree > 3) return fail(GSP_EINVAL, "sh_degree must be 0..3");
+    if (!params || !grads || !m || !v || !hp || !scales_out || !opacities_out)
+        return fail(GSP_EINVAL, "null argument");
+    if (!params->means || !params->log_scales || !params->quats || !params->logit_opacities ||
+        !params->sh)
+        return fail(GSP_EINVAL, "null parameter array");
+    if (!grads->means || !grads->scales || !grads->quats || !grads->opacities || !grads->sh)
+        return fail(GSP_EINVAL, "every Gaussian gradient is needed");
+    if (step < 1) return fail(GSP_EINVAL, "step counts from 1");
+    if (!(hp->beta1 >= 0.0 && hp->beta1 < 1.0 && hp->beta2 >= 0.0 && hp->beta2 < 1.0 &&
+          hp->eps > 0.0 && hp->total_steps >= 1 && hp->lr_means_start > 0.0 &&
+          hp->lr_means_end > 0.0 && hp->lr_sh_dc >= 0.0 && hp->lr_sh_rest >= 0.0 &&
+          hp->lr_opacities >= 0.0 && hp->lr_scales >= 0.0 && hp->lr_quats >= 0.0 &&
+          hp->aniso_r > 0.0 && hp->aniso_weight >= 0.0))
+        return fail(GSP_EINVAL, "bad Adam hyper-parameters");
+    if (aniso_loss && !scratch) return fail(GSP_EINVAL, "aniso_loss requires scratch memory");
+    const int S = (sh_degree + 1) * (sh_degree + 1);
+    gsp::GaussAdamK a;
+    std::memset(&a, 0, sizeof a);
+    a.means = params->means;
+    a.log_scales = params->log_scales;
+    a.quats = params->quats;
+    a.logits = params->logit_opacities;
+    a.sh = params->sh;
+    a.g_means = grads->means;
+    a.g_scales = grads->scales;
+    a.g_quats = grads->quats;
+    a.g_opacities = grads->opacities;
+    a.g_sh = grads->sh;
+    a.m = m;
+    a.v = v;
+    a.scales_out = scales_out;
+    a.opacities_out = opacities_out;
+    a.partial = aniso_loss ? static_cast<double *>(scratch) : nullptr;
+    a.guard = static_cast<const uint32_t *>(guard_workspace);
+    a.n = n;
+    a.S = S;
+    a.items[0] = 3 * n;
+    a.items[1] = a.items[0] + n;
+    a.items[2] = a.items[1] + 4 * n;
+    a.items[3] = a.items[2] + n;
+    a.items[4] = a.items[3] + 3 * (int64_t)S * n;
+    a.moff[0] = 0;
+    a.moff[1] = 3 * n;
+    a.moff[2] = 6 * n;
+    a.moff[3] = 10 * n;
+    a.moff[4] = 11 * n;
+    double t = 0.0;
+    if (hp->total_steps > 1)
+        t = (double)std::min(step - 1, hp->total_steps - 1) / (double)(hp->total_steps - 1);
+    a.lr_means = std::exp(std::log(hp->lr_means_start) * (1.0 - t) + std::log(hp->lr_means_end) * t);
+    a.lr_scales = hp->lr_scales;
+    a.lr_quats = hp->lr_quats;
+    a.lr_opacities = hp->lr_opacities;
+    a.lr_sh_dc = hp->lr_sh_dc;
+    a.lr_sh_rest = hp->lr_sh_rest;
+    a.b1 = hp->beta1;
+    a.b2 = hp->beta2;
+    a.c1 = 1.0 - std::pow(hp->beta1, (double)step);
+    a.c2 = 1.0 - std::pow(hp->beta2, (double)step);
+    a.eps = hp->eps;
+    a.aniso_r = hp->aniso_r;
+    a.aniso_w = hp->aniso_weight;
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    hipError_t e = stage(ctx, "gaussian_adam", st, [&] {
+        return gsp::launch_gauss_adam(a, aniso_loss, st);
+    });
+    if (e != hipSuccess) return hip_fail(e, "gaussian adam");
+    return GSP_OK;
+}
+
+size_t gsp_gaussian_adam_scratch_bytes(int64_t n) {
+    const int64_t p = gsp::gauss_adam_partials(n);
+    return (size_t)(p > 0 ? p : 1) * sizeof(double);
 }
 
 }  // extern "C"

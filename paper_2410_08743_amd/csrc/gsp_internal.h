@@ -148,6 +148,40 @@ hipError_t launch_pose_adam(int V, float *poses, const float *dpose, float *m, f
                             int32_t *steps, const gsp_adam_params &p, const uint32_t *guard,
                             hipStream_t s);
 
+// joint.hip: L_RGB (Eq. (16)) over the views of a call, and Adam over the raw
+// Gaussian parameters with the L_An hinge (Eq. (17)).
+struct RgbViewsK {
+    const float *pred[GSP_MAX_VIEWS];
+    const float *target[GSP_MAX_VIEWS];
+    float *grad[GSP_MAX_VIEWS];
+    float *gmap[GSP_MAX_VIEWS];          // scratch: 3 maps x 3 channels x h x w
+    int w[GSP_MAX_VIEWS], h[GSP_MAX_VIEWS], tiles_x[GSP_MAX_VIEWS];
+    int tile_base[GSP_MAX_VIEWS + 1];    // first SSIM tile (per channel) of each view
+    int V, total_tiles;
+    float beta;
+    float win[11];                       // normalised Gaussian window, sigma 1.5
+};
+int ssim_tiles(int w, int h);
+hipError_t launch_loss_rgb(const RgbViewsK &a, float *loss, double2 *partial, hipStream_t s);
+
+struct GaussAdamK {
+    float *means, *log_scales, *quats, *logits, *sh;      // raw parameters, updated in place
+    const float *g_means, *g_scales, *g_quats, *g_opacities, *g_sh;  // activated gradients
+    float *m, *v;                        // moments, groups one after another
+    float *scales_out, *opacities_out;   // activated values after the step
+    double *partial;                     // L_An partial sums per block, or null
+    const uint32_t *guard;               // counters of the producing render, or null
+    int64_t n;
+    int S;
+    int64_t items[5];                    // cumulative work items: means, scales, quats, opacities, sh
+    int64_t moff[5];                     // first moment of each group
+    double lr_means, lr_scales, lr_quats, lr_opacities, lr_sh_dc, lr_sh_rest;
+    double b1, b2, c1, c2, eps;
+    double aniso_r, aniso_w;
+};
+int64_t gauss_adam_partials(int64_t n);
+hipError_t launch_gauss_adam(const GaussAdamK &a, float *aniso_loss, hipStream_t s);
+
 template <typename T>
 inline T *region(char *ws, size_t off) { return reinterpret_cast<T *>(ws + off); }
 

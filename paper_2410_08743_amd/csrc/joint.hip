@@ -1,0 +1,324 @@
+// joint.hip -- the joint reconstruction and pose refinement objective beyond
+// the renderer (Sec. III-C): the image loss L_RGB = (1 - beta) L1 +
+// beta (1 - SSIM) of Eq. (16) with its gradient, and one Adam step over the
+// raw Gaussian parameters with the anisotropy hinge L_An of Eq. (17) folded
+// into the scale gradient.
+//
+// SSIM uses the 11 x 11 Gaussian window (sigma 1.5) of the 3DGS loss the
+// paper adopts, C1 = 0.01^2, C2 = 0.03^2 and zero padding outside the image.
+// It is computed in two passes over 64 x 16 pixel tiles of one channel: the
+// forward filters the five local moments separably in LDS and stores, per
+// pixel, the three partial derivatives of SSIM with respect to the filtered
+// quantities (mean, E[x^2], E[xy]); the backward filters those three maps
+// with the same (symmetric) window, which is the adjoint of the forward
+// filter, and combines them into dL/dpred together with the L1 term.  Both
+// passes are bound by HBM traffic (x, y in; three maps out; three maps, x, y
+// in; gradient out).
+#include "block_ops.h"
+#include "gsp_internal.h"
+
+namespace gsp {
+
+constexpr int kSsimR = 5;                        // window radius
+constexpr int kSsimTaps = 2 * kSsimR + 1;
+constexpr int kSsimTW = 64, kSsimTH = 16;        // output tile
+constexpr int kSsimThreads = 256;
+constexpr int kSsimLW = kSsimTW + 2 * kSsimR;    // staged tile with halo
+constexpr int kSsimLH = kSsimTH + 2 * kSsimR;
+constexpr float kSsimC1 = 0.01f * 0.01f;
+constexpr float kSsimC2 = 0.03f * 0.03f;
+
+int ssim_tiles(int w, int h) {
+    return ((w + kSsimTW - 1) / kSsimTW) * ((h + kSsimTH - 1) / kSsimTH);
+}
+
+__device__ __forceinline__ int rgb_view_of(const RgbViewsK &a, int tile) {
+    int v = 0;
+    while (v + 1 < a.V && tile >= a.tile_base[v + 1]) v++;
+    return v;
+}
+
+// partial[c * total_tiles + tile] = (sum of SSIM, sum of |x - y|) of the tile.
+__global__ __launch_bounds__(kSsimThreads) void k_ssim_fwd(RgbViewsK a, double2 *partial) {
+    __shared__ float sx[kSsimLH][kSsimLW], sy[kSsimLH][kSsimLW];
+    __shared__ float hm[5][kSsimLH][kSsimTW];
+    __shared__ double red[kSsimThreads / kWave];
+    const int tile = blockIdx.x, c = blockIdx.y;
+    const int v = rgb_view_of(a, tile);
+    const int W = a.w[v], H = a.h[v];
+    const int lt = tile - a.tile_base[v];
+    const int x0 = (lt % a.tiles_x[v]) * kSsimTW, y0 = (lt / a.tiles_x[v]) * kSsimTH;
+    const size_t plane = (size_t)W * H;
+    const float *X = a.pred[v] + c * plane, *Y = a.target[v] + c * plane;
+    const int t = threadIdx.x;
+    for (int i = t; i < kSsimLH * kSsimLW; i += kSsimThreads) {
+        const int r = i / kSsimLW, q = i - r * kSsimLW;
+        const int gy = y0 + r - kSsimR, gx = x0 + q - kSsimR;
+        const bool in = gy >= 0 && gy < H && gx >= 0 && gx < W;
+        sx[r][q] = in ? X[(size_t)gy * W + gx] : 0.f;
+        sy[r][q] = in ? Y[(size_t)gy * W + gx] : 0.f;
+    }
+    __syncthreads();
+    for (int i = t; i < kSsimLH * kSsimTW; i += kSsimThreads) {
+        const int r = i / kSsimTW, q = i - r * kSsimTW;
+        float s0 = 0.f, s1 = 0.f, s2 = 0.f, s3 = 0.f, s4 = 0.f;
+#pragma unroll
+        for (int k = 0; k < kSsimTaps; k++) {
+            const float wk = a.win[k], xv = sx[r][q + k], yv = sy[r][q + k];
+            const float wx = wk * xv, wy = wk * yv;
+            s0 += wx;
+            s1 += wy;
+            s2 = fmaf(wx, xv, s2);
+            s3 = fmaf(wy, yv, s3);
+            s4 = fmaf(wx, yv, s4);
+        }
+        hm[0][r][q] = s0;
+        hm[1][r][q] = s1;
+        hm[2][r][q] = s2;
+        hm[3][r][q] = s3;
+        hm[4][r][q] = s4;
+    }
+    __syncthreads();
+    const int tx = t % kSsimTW, ty = t / kSsimTW;
+    float *G = a.gmap[v];
+    double ssum = 0.0, l1sum = 0.0;
+#pragma unroll
+    for (int j = 0; j < kSsimTH / (kSsimThreads / kSsimTW); j++) {
+        const int r = ty + (kSsimThreads / kSsimTW) * j;
+        const int gy = y0 + r, gx = x0 + tx;
+        if (gy >= H || gx >= W) continue;
+        float mx = 0.f, my = 0.f, exx = 0.f, eyy = 0.f, exy = 0.f;
+#pragma unroll
+        for (int k = 0; k < kSsimTaps; k++) {
+            const float wk = a.win[k];
+            mx = fmaf(wk, hm[0][r + k][tx], mx);
+            my = fmaf(wk, hm[1][r + k][tx], my);
+            exx = fmaf(wk, hm[2][r + k][tx], exx);
+            eyy = fmaf(wk, hm[3][r + k][tx], eyy);
+            exy = fmaf(wk, hm[4][r + k][tx], exy);
+        }
+        const float sxx = fmaf(-mx, mx, exx), syy = fmaf(-my, my, eyy), sxy = fmaf(-mx, my, exy);
+        const float a1 = fmaf(2.f * mx, my, kSsimC1), a2 = fmaf(2.f, sxy, kSsimC2);
+        const float b1 = fmaf(mx, mx, fmaf(my, my, kSsimC1)), b2 = sxx + syy + kSsimC2;
+        const float inv = 1.f / (b1 * b2);
+        const float S = a1 * a2 * inv;
+        // dS/dmu_x, dS/dsigma_x^2, dS/dsigma_xy, then through the raw moments
+        const float ds_dmx = 2.f * my * a2 * inv - 2.f * mx * S / b1;
+        const float ds_dsxx = -S / b2;
+        const float ds_dsxy = 2.f * a1 * inv;
+        const float g_mean = ds_dmx - 2.f * mx * ds_dsxx - my * ds_dsxy;
+        const size_t o = (size_t)gy * W + gx;
+        G[(size_t)(0 + c) * plane + o] = g_mean;
+        G[(size_t)(3 + c) * plane + o] = ds_dsxx;
+        G[(size_t)(6 + c) * plane + o] = ds_dsxy;
+        ssum += (double)S;
+        l1sum += fabs((double)sx[r + kSsimR][tx + kSsimR] - (double)sy[r + kSsimR][tx + kSsimR]);
+    }
+    ssum = block_sum<double, kSsimThreads>(ssum, red);
+    l1sum = block_sum<double, kSsimThreads>(l1sum, red);
+    if (t == 0) partial[(size_t)c * a.total_tiles + tile] = make_double2(ssum, l1sum);
+}
+
+// dL/dpred = (1 - beta) sign(x - y) / N - beta / N (F g_mean + 2 x F g_exx +
+// y F g_exy), F the window filter (its own adjoint: the window is symmetric
+// and the maps are zero outside the image), N = 3 W H.
+__global__ __launch_bounds__(kSsimThreads) void k_ssim_bwd(RgbViewsK a) {
+    __shared__ float sg[3][kSsimLH][kSsimLW];
+    __shared__ float hg[3][kSsimLH][kSsimTW];
+    const int tile = blockIdx.x, c = blockIdx.y;
+    const int v = rgb_view_of(a, tile);
+    const int W = a.w[v], H = a.h[v];
+    const int lt = tile - a.tile_base[v];
+    const int x0 = (lt % a.tiles_x[v]) * kSsimTW, y0 = (lt / a.tiles_x[v]) * kSsimTH;
+    const size_t plane = (size_t)W * H;
+    const float *G = a.gmap[v];
+    const int t = threadIdx.x;
+    for (int i = t; i < kSsimLH * kSsimLW; i += kSsimThreads) {
+        const int r = i / kSsimLW, q = i - r * kSsimLW;
+        const int gy = y0 + r - kSsimR, gx = x0 + q - kSsimR;
+        const bool in = gy >= 0 && gy < H && gx >= 0 && gx < W;
+        const size_t o = (size_t)gy * W + gx;
+#pragma unroll
+        for (int m = 0; m < 3; m++) sg[m][r][q] = in ? G[(size_t)(3 * m + c) * plane + o] : 0.f;
+    }
+    __syncthreads();
+    for (int i = t; i < kSsimLH * kSsimTW; i += kSsimThreads) {
+        const int r = i / kSsimTW, q = i - r * kSsimTW;
+        float s0 = 0.f, s1 = 0.f, s2 = 0.f;
+#pragma unroll
+        for (int k = 0; k < kSsimTaps; k++) {
+            const float wk = a.win[k];
+            s0 = fmaf(wk, sg[0][r][q + k], s0);
+            s1 = fmaf(wk, sg[1][r][q + k], s1);
+            s2 = fmaf(wk, sg[2][r][q + k], s2);
+        }
+        hg[0][r][q] = s0;
+        hg[1][r][q] = s1;
+        hg[2][r][q] = s2;
+    }
+    __syncthreads();
+    const int tx = t % kSsimTW, ty = t / kSsimTW;
+    const float *X = a.pred[v] + c * plane, *Y = a.target[v] + c * plane;
+    float *D = a.grad[v] + c * plane;
+    const float invn = 1.f / (3.f * (float)plane);
+    const float wl1 = (1.f - a.beta) * invn, wss = -a.beta * invn;
+#pragma unroll
+    for (int j = 0; j < kSsimTH / (kSsimThreads / kSsimTW); j++) {
+        const int r = ty + (kSsimThreads / kSsimTW) * j;
+        const int gy = y0 + r, gx = x0 + tx;
+        if (gy >= H || gx >= W) continue;
+        float f0 = 0.f, f1 = 0.f, f2 = 0.f;
+#pragma unroll
+        for (int k = 0; k < kSsimTaps; k++) {
+            const float wk = a.win[k];
+            f0 = fmaf(wk, hg[0][r + k][tx], f0);
+            f1 = fmaf(wk, hg[1][r + k][tx], f1);
+            f2 = fmaf(wk, hg[2][r + k][tx], f2);
+        }
+        const size_t o = (size_t)gy * W + gx;
+        const float x = X[o], y = Y[o];
+        const float d = x - y;
+        const float sgn = d > 0.f ? 1.f : (d < 0.f ? -1.f : 0.f);
+        D[o] = fmaf(wss, fmaf(y, f2, fmaf(2.f * x, f1, f0)), wl1 * sgn);
+    }
+}
+
+// One block per view: the view's tile partials in a fixed order.
+__global__ __launch_bounds__(256) void k_rgb_final(RgbViewsK a, const double2 *partial,
+                                                   float *loss) {
+    __shared__ double red[256 / kWave];
+    const int v = blockIdx.x;
+    const int nt = a.tile_base[v + 1] - a.tile_base[v];
+    double s = 0.0, l = 0.0;
+    for (int i = threadIdx.x; i < 3 * nt; i += 256) {
+        const int c = i / nt, k = i - c * nt;
+        const double2 p = partial[(size_t)c * a.total_tiles + a.tile_base[v] + k];
+        s += p.x;
+        l += p.y;
+    }
+    s = block_sum<double, 256>(s, red);
+    l = block_sum<double, 256>(l, red);
+    if (threadIdx.x == 0) {
+        const double n = 3.0 * (double)a.w[v] * (double)a.h[v];
+        loss[v] = n > 0 ? (float)((1.0 - a.beta) * l / n + a.beta * (1.0 - s / n)) : 0.f;
+    }
+}
+
+hipError_t launch_loss_rgb(const RgbViewsK &a, float *loss, double2 *partial, hipStream_t s) {
+    if (a.total_tiles <= 0) return hipSuccess;
+    const dim3 grid((unsigned)a.total_tiles, 3);
+    hipLaunchKernelGGL(k_ssim_fwd, grid, dim3(kSsimThreads), 0, s, a, partial);
+    hipLaunchKernelGGL(k_ssim_bwd, grid, dim3(kSsimThreads), 0, s, a);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess || !loss) return e;
+    hipLaunchKernelGGL(k_rgb_final, dim3(a.V), dim3(256), 0, s, a, partial, loss);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Adam over the raw Gaussian parameters.  Work items: one per scalar of the
+// means, quaternions, logit opacities and SH coefficients, and one per
+// Gaussian for the log scales (all three at once, since the L_An derivative
+// of each needs the other two before any is updated).  The update runs in
+// FP64 from FP32 storage; the bias corrections and the learning rates come
+// from the host.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_gauss_adam(GaussAdamK a) {
+    __shared__ double red[256 / kWave];
+    const int64_t f = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    const bool skip = a.guard && a.guard[kCntOverflow] != 0u;
+    double lan = 0.0;
+    auto adam = [&](float *p, float *m, float *v, double g, double lr) {
+        const double mm = a.b1 * (double)*m + (1.0 - a.b1) * g;
+        const double vv = a.b2 * (double)*v + (1.0 - a.b2) * g * g;
+        const double np = (double)*p - lr * (mm / a.c1) / (sqrt(vv / a.c2) + a.eps);
+        *m = (float)mm;
+        *v = (float)vv;
+        *p = (float)np;
+        return np;
+    };
+    if (f < a.items[0]) {                       // means: one scalar
+        if (!skip) adam(a.means + f, a.m + a.moff[0] + f, a.v + a.moff[0] + f, a.g_means[f], a.lr_means);
+    } else if (f < a.items[1]) {                // log scales: one Gaussian
+        const int64_t i = f - a.items[0];
+        double s[3];
+#pragma unroll
+        for (int k = 0; k < 3; k++) s[k] = exp((double)a.log_scales[3 * i + k]);
+        int imax = 0, imin = 0;
+#pragma unroll
+        for (int k = 1; k < 3; k++) {
+            if (s[k] > s[imax]) imax = k;
+            if (s[k] < s[imin]) imin = k;
+        }
+        const double ratio = s[imax] / s[imin];
+        double gan[3] = {0.0, 0.0, 0.0};
+        if (ratio > a.aniso_r) {
+            lan = ratio - a.aniso_r;
+            gan[imax] += 1.0 / (s[imin] * (double)a.n);
+            gan[imin] -= s[imax] / (s[imin] * s[imin] * (double)a.n);
+        }
+        if (!skip) {
+#pragma unroll
+            for (int k = 0; k < 3; k++) {
+                const int64_t e = 3 * i + k;
+                const double g = ((double)a.g_scales[e] + a.aniso_w * gan[k]) * s[k];
+                const double np = adam(a.log_scales + e, a.m + a.moff[1] + e, a.v + a.moff[1] + e, g,
+                                       a.lr_scales);
+                a.scales_out[e] = (float)exp(np);
+            }
+        }
+    } else if (f < a.items[2]) {                // quaternions: one scalar
+        const int64_t e = f - a.items[1];
+        if (!skip) adam(a.quats + e, a.m + a.moff[2] + e, a.v + a.moff[2] + e, a.g_quats[e], a.lr_quats);
+    } else if (f < a.items[3]) {                // logit opacities: one scalar
+        const int64_t e = f - a.items[2];
+        if (!skip) {
+            const double o = 1.0 / (1.0 + exp(-(double)a.logits[e]));
+            const double g = (double)a.g_opacities[e] * o * (1.0 - o);
+            const double np = adam(a.logits + e, a.m + a.moff[3] + e, a.v + a.moff[3] + e, g, a.lr_opacities);
+            a.opacities_out[e] = (float)(1.0 / (1.0 + exp(-np)));
+        }
+    } else if (f < a.items[4]) {                // SH coefficients: one scalar
+        const int64_t e = f - a.items[3];
+        const int coef = (int)((e / 3) % a.S);
+        if (!skip)
+            adam(a.sh + e, a.m + a.moff[4] + e, a.v + a.moff[4] + e, a.g_sh[e],
+                 coef == 0 ? a.lr_sh_dc : a.lr_sh_rest);
+    }
+    if (a.partial) {
+        // only the blocks that hold log-scale items carry L_An terms
+        const int64_t b0 = a.items[0] / 256, b1 = (a.items[1] - 1) / 256;
+        if ((int64_t)blockIdx.x >= b0 && (int64_t)blockIdx.x <= b1) {
+            lan = block_sum<double, 256>(lan, red);
+            if (threadIdx.x == 0) a.partial[blockIdx.x - b0] = lan;
+        }
+    }
+}
+
+__global__ __launch_bounds__(256) void k_aniso_final(const double *partial, int64_t nblk, int64_t n,
+                                                     float *loss) {
+    __shared__ double red[256 / kWave];
+    double s = 0.0;
+    for (int64_t b = threadIdx.x; b < nblk; b += 256) s += partial[b];
+    s = block_sum<double, 256>(s, red);
+    if (threadIdx.x == 0) *loss = n > 0 ? (float)(s / (double)n) : 0.f;
+}
+
+int64_t gauss_adam_partials(int64_t n) {
+    if (n <= 0) return 0;
+    const int64_t items0 = 3 * n, items1 = items0 + n;
+    return (items1 - 1) / 256 - items0 / 256 + 1;
+}
+
+hipError_t launch_gauss_adam(const GaussAdamK &a, float *aniso_loss, hipStream_t s) {
+    if (a.n <= 0) return hipSuccess;
+    const int64_t blocks = (a.items[4] + 255) / 256;
+    hipLaunchKernelGGL(k_gauss_adam, dim3((unsigned)blocks), dim3(256), 0, s, a);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess || !aniso_loss) return e;
+    hipLaunchKernelGGL(k_aniso_final, dim3(1), dim3(256), 0, s, a.partial, gauss_adam_partials(a.n),
+                       a.n, aniso_loss);
+    return hipGetLastError();
+}
+
+}  // namespace gsp

@@ -66,7 +66,25 @@ def test_calls_reject_null_context(lib):
     assert lib.gsp_render_fwd(None, None, 1, None, None, None, None, None, 0, 0, None) == N.GSP_EINVAL
     assert lib.gsp_loss_l1(None, 1, None, None, None, None, None, None, None) == N.GSP_EINVAL
     assert lib.gsp_pose_adam(None, 1, None, None, None, None, None, None, None, None) == N.GSP_EINVAL
+    assert lib.gsp_loss_rgb(None, 1, None, None, None, None, None, 0.2, None, 0, None) == N.GSP_EINVAL
+    assert lib.gsp_gaussian_adam(None, 1, 0, None, None, None, None, 1, None, None, None, None,
+                                 None, None, None) == N.GSP_EINVAL
     assert lib.gsp_create(0, None) == N.GSP_EINVAL
+
+
+def test_scratch_sizes_of_the_joint_calls(lib):
+    from paper_2410_08743_amd import _native as N
+    from paper_2410_08743_amd.synthetic import Camera
+    one = N.view_array([Camera(100, 37, 90.0, 90.0, 50.0, 18.0)])
+    # two 64 x 16 tiles across, three down; per-tile sums of 3 channels + 9 floats per pixel
+    tiles = 2 * 3
+    expect = ((3 * tiles * 16 + 255) // 256) * 256 + 9 * 100 * 37 * 4
+    assert lib.gsp_loss_rgb_scratch_bytes(1, one) == expect
+    two = N.view_array([Camera(100, 37, 90.0, 90.0, 50.0, 18.0)] * 2)
+    assert lib.gsp_loss_rgb_scratch_bytes(2, two) == ((3 * 2 * tiles * 16 + 255) // 256) * 256 + 2 * 9 * 100 * 37 * 4
+    # L_An partial sums: one per 256-item block holding log-scale items (items 3n .. 4n)
+    assert lib.gsp_gaussian_adam_scratch_bytes(1000) == 8 * ((4000 - 1) // 256 - 3000 // 256 + 1)
+    assert lib.gsp_gaussian_adam_scratch_bytes(0) == 8
 
 
 def test_product_path_fails_loudly_without_library(tmp_path, monkeypatch):

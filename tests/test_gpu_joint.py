@@ -1,0 +1,247 @@
+"""GPU parity of the joint refinement pieces against the FP64 oracle
+(oracle/joint.py, oracle's renderer): the fused L1 + DSSIM loss and its
+gradient (Eq. (16)), Adam on the raw Gaussian parameters with the anisotropy
+hinge (Eq. (17)), one whole refinement step in situ, and a refinement run
+that lowers the loss and the pose error.
+
+Tolerances.  L_RGB: the GPU filters in FP32; the local variances are
+differences E[x^2] - mu^2 of O(0.3) terms whose FP32 rounding (~3e-8) is
+divided by sigma^2 + C2 >= 9e-4, so SSIM is good to ~1e-5 per pixel and
+its mean to well below that; loss |d| <= 2e-6, gradient relative L2 <= 1e-4
+and max |d| <= 1e-4 max|g|.  Adam: FP64 arithmetic on FP32 storage, so
+parameters and moments agree to FP32 rounding (relative 2e-6 per step)."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from oracle import joint as OJ
+from paper_2410_08743_amd import joint as J
+from paper_2410_08743_amd import render as R
+from paper_2410_08743_amd import synthetic as S
+
+from parity_util import rel_l2, random_case
+
+pytestmark = pytest.mark.gpu
+DEV = "cuda:0"
+
+
+def _images(seed, W, H, noise=0.15):
+    rng = np.random.default_rng(seed)
+    # smooth-ish content plus noise, in [0, 1], like rendered images
+    yy, xx = np.mgrid[0:H, 0:W]
+    base = np.stack([0.5 + 0.4 * np.sin(xx / (3.0 + c) + yy / (5.0 + c)) for c in range(3)])
+    x = np.clip(base + rng.normal(0, noise, base.shape), 0, 1).astype(np.float32)
+    y = np.clip(base + rng.normal(0, noise, base.shape), 0, 1).astype(np.float32)
+    return x, y
+
+
+def _cam(W, H):
+    return S.Camera(W, H, 0.9 * W, 0.9 * W, W / 2, H / 2)
+
+
+@pytest.mark.parametrize("W,H", [(64, 16), (100, 37), (5, 3), (130, 70), (16, 200)])
+def test_loss_rgb_matches_oracle(W, H):
+    x, y = _images(W * 1000 + H, W, H)
+    loss, grad = J.loss_rgb([_cam(W, H)], torch.tensor(x.ravel(), device=DEV),
+                            torch.tensor(y.ravel(), device=DEV))
+    ref_loss, ref_grad = OJ.rgb_loss(x, y, 0.2)
+    got = grad.cpu().numpy().reshape(3, H, W)
+    assert abs(float(loss.item()) - ref_loss) <= 2e-6, (loss.item(), ref_loss)
+    assert rel_l2(got, ref_grad) <= 1e-4
+    assert np.max(np.abs(got - ref_grad)) <= 1e-4 * np.max(np.abs(ref_grad))
+
+
+def test_loss_rgb_identical_images_and_beta_limits():
+    x, _ = _images(7, 70, 33)
+    t = torch.tensor(x.ravel(), device=DEV)
+    loss, grad = J.loss_rgb([_cam(70, 33)], t, t.clone())
+    assert abs(loss.item()) < 1e-6 and float(grad.abs().max()) < 1e-7
+    x, y = _images(8, 70, 33)
+    tx, ty = torch.tensor(x.ravel(), device=DEV), torch.tensor(y.ravel(), device=DEV)
+    l0, g0 = J.loss_rgb([_cam(70, 33)], tx, ty, beta=0.0)        # pure L1 = gsp_loss_l1
+    l1, g1 = R.loss_l1([_cam(70, 33)], tx, ty)
+    assert torch.equal(g0, g1)
+    assert abs(l0.item() - l1.item()) < 1e-6
+    l2, g2 = J.loss_rgb([_cam(70, 33)], tx, ty, beta=1.0)        # pure DSSIM
+    ref, rg = OJ.dssim(x, y)
+    assert abs(l2.item() - ref) < 2e-6 and rel_l2(g2.cpu().numpy().reshape(rg.shape), rg) < 1e-4
+
+
+def test_loss_rgb_views_are_independent():
+    sizes = [(100, 37), (64, 48), (33, 17)]
+    imgs = [_images(20 + k, W, H) for k, (W, H) in enumerate(sizes)]
+    cams = [_cam(W, H) for W, H in sizes]
+    xs = [torch.tensor(x.ravel(), device=DEV) for x, _ in imgs]
+    ys = [torch.tensor(y.ravel(), device=DEV) for _, y in imgs]
+    loss, grads = J.loss_rgb(cams, xs, ys)
+    for k in range(3):
+        lk, gk = J.loss_rgb([cams[k]], xs[k], ys[k])
+        assert torch.equal(loss[k:k + 1], lk)
+        assert torch.equal(grads[k], gk)
+
+
+def _raw_case(seed, n, deg):
+    rng = np.random.default_rng(seed)
+    S_ = (deg + 1) ** 2
+    raw = {
+        "means": rng.normal(0, 1, (n, 3)).astype(np.float32),
+        "log_scales": (rng.uniform(-4, -1, (n, 3))
+                       + np.where(rng.random((n, 1)) < 0.3, [[3.0, 0, 0]], 0.0)).astype(np.float32),
+        "quats": rng.normal(0, 1, (n, 4)).astype(np.float32),
+        "logit_opacities": rng.normal(0, 1.5, n).astype(np.float32),
+        "sh": rng.normal(0, 0.3, (n, S_, 3)).astype(np.float32),
+    }
+    return raw, rng
+
+
+def _grads(rng, n, S_):
+    return {"means": rng.normal(0, 1e-3, (n, 3)).astype(np.float32),
+            "scales": rng.normal(0, 1e-2, (n, 3)).astype(np.float32),
+            "quats": rng.normal(0, 1e-3, (n, 4)).astype(np.float32),
+            "opacities": rng.normal(0, 1e-3, n).astype(np.float32),
+            "sh": rng.normal(0, 1e-3, (n, S_, 3)).astype(np.float32)}
+
+
+def _flat_moments(d):
+    return np.concatenate([np.asarray(d[k], np.float64).ravel() for k in OJ.GROUPS])
+
+
+@pytest.mark.parametrize("n,deg", [(3001, 3), (257, 0), (1, 1)])
+def test_gaussian_adam_matches_oracle(n, deg):
+    raw, rng = _raw_case(100 + n, n, deg)
+    S_ = (deg + 1) ** 2
+    t = lambda a: torch.tensor(a, device=DEV).contiguous()
+    R_ = J.RawGaussians(t(raw["means"]), t(raw["log_scales"]), t(raw["quats"]),
+                        t(raw["logit_opacities"]), t(raw["sh"]), deg)
+    m = torch.zeros(J.moments_size(n, deg), device=DEV)
+    v = torch.zeros_like(m)
+    so = torch.empty((n, 3), device=DEV)
+    oo = torch.empty(n, device=DEV)
+    lan = torch.zeros(1, device=DEV)
+    hp = J.JointHyper()
+    om = {k: np.zeros_like(a, dtype=np.float64) for k, a in raw.items()}
+    ov = {k: np.zeros_like(a, dtype=np.float64) for k, a in raw.items()}
+    oraw = {k: a.astype(np.float64) for k, a in raw.items()}
+    for step in range(1, 4):
+        g = _grads(rng, n, S_)
+        J.gaussian_adam(R_, {k: t(a) for k, a in g.items()}, m, v, step, 30, hp, so, oo,
+                        aniso_loss=lan)
+        # the oracle starts each step from the GPU's FP32 state of the step
+        # before (set at the end of the loop), so rounding does not accumulate
+        new, om, ov, l_an = OJ.gaussian_adam(oraw, g, om, ov, step, 30)
+        got = {"means": R_.means, "log_scales": R_.log_scales, "quats": R_.quats,
+               "logit_opacities": R_.logit_opacities, "sh": R_.sh}
+        for k in OJ.GROUPS:
+            a = got[k].cpu().numpy().astype(np.float64)
+            assert np.max(np.abs(a - new[k])) <= 2e-6 * max(1.0, np.max(np.abs(new[k]))), (k, step)
+        assert abs(lan.item() - l_an) <= 1e-6 * max(1.0, abs(l_an))
+        gm = m.cpu().numpy().astype(np.float64)
+        gv = v.cpu().numpy().astype(np.float64)
+        fm, fv = _flat_moments(om), _flat_moments(ov)
+        assert np.max(np.abs(gm - fm)) <= 1e-6 * np.max(np.abs(fm))
+        assert np.max(np.abs(gv - fv)) <= 1e-6 * np.max(np.abs(fv))
+        assert np.allclose(so.cpu().numpy(), np.exp(new["log_scales"]), rtol=1e-5, atol=0)
+        assert np.allclose(oo.cpu().numpy(), OJ.sigmoid(new["logit_opacities"]), rtol=1e-5, atol=1e-7)
+        oraw = {k: got[k].cpu().numpy().astype(np.float64) for k in OJ.GROUPS}
+        om = {k: _unflatten(m, n, S_)[k] for k in OJ.GROUPS}
+        ov = {k: _unflatten(v, n, S_)[k] for k in OJ.GROUPS}
+
+
+def _unflatten(buf, n, S_):
+    a = buf.cpu().numpy().astype(np.float64)
+    sizes = {"means": (n, 3), "log_scales": (n, 3), "quats": (n, 4), "logit_opacities": (n,),
+             "sh": (n, S_, 3)}
+    out, off = {}, 0
+    for k in OJ.GROUPS:
+        c = int(np.prod(sizes[k]))
+        out[k] = a[off:off + c].reshape(sizes[k])
+        off += c
+    return out
+
+
+def test_gaussian_adam_skips_after_an_overflowing_render():
+    n, deg = 300, 1
+    raw, rng = _raw_case(5, n, deg)
+    t = lambda a: torch.tensor(a, device=DEV).contiguous()
+    R_ = J.RawGaussians(t(raw["means"]), t(raw["log_scales"]), t(raw["quats"]),
+                        t(raw["logit_opacities"]), t(raw["sh"]), deg)
+    before = {k: getattr(R_, k).clone() for k in OJ.GROUPS}
+    m = torch.zeros(J.moments_size(n, deg), device=DEV)
+    v = torch.zeros_like(m)
+    so = torch.full((n, 3), -1.0, device=DEV)
+    oo = torch.full((n,), -1.0, device=DEV)
+    guard = torch.zeros(64, dtype=torch.uint8, device=DEV)
+    guard.view(torch.int32)[2] = 1          # counters[2]: the last forward overflowed
+    g = {k: t(a) for k, a in _grads(rng, n, 4).items()}
+    J.gaussian_adam(R_, g, m, v, 1, 10, J.JointHyper(), so, oo, guard=guard)
+    for k in OJ.GROUPS:
+        assert torch.equal(getattr(R_, k), before[k])
+    assert float(m.abs().max()) == 0.0 and float(so.max()) == -1.0 and float(oo.max()) == -1.0
+
+
+def test_refinement_step_in_situ_matches_oracle():
+    """One JointRefiner step: the gradients that reach the rasterizer's
+    backward are those of the oracle's L_RGB of the same render, and the
+    Gaussian update is the oracle's Adam applied to the gradients the GPU
+    computed."""
+    sc, cam, pose = random_case(71, 1, 96, 64, 400)
+    gt_pose = S.random_pose_near_identity(72, 1.0, 0.02)
+    g_gt = R.GaussianParams.from_set(sc, DEV)
+    rast = R.Rasterizer(0)
+    target, _ = rast.forward(g_gt, [cam], torch.tensor(gt_pose[None], device=DEV))
+    target = target.clone().view(3, cam.height, cam.width)
+    raw = J.RawGaussians.from_set(sc, DEV)
+    raw0 = {k: getattr(raw, k).cpu().numpy().astype(np.float64) for k in OJ.GROUPS}
+    ref = J.JointRefiner(raw, [cam], [target], torch.tensor(pose[None], device=DEV), 10)
+    ref.step()
+    torch.cuda.synchronize()
+    # render and L_RGB gradient of the oracle at the same state
+    act = S.GaussianSet(raw0["means"], np.exp(raw0["log_scales"]), raw0["quats"],
+                        OJ.sigmoid(raw0["logit_opacities"]), raw0["sh"], 1)
+    img = oracle.render(act, cam, pose)["image"]
+    _, dl = OJ.rgb_loss(img, target.cpu().numpy().astype(np.float64), 0.2)
+    gpu_dl = ref.dl[0].cpu().numpy().reshape(3, cam.height, cam.width)
+    assert rel_l2(gpu_dl, dl) <= 1e-3
+    back = oracle.backward(act, cam, pose, dl)
+    for k in ("means", "scales", "quats", "opacities", "sh"):
+        assert rel_l2(ref.grads[k].cpu().numpy(), back[k]) <= 2e-3, k
+    gg = {k: ref.grads[k].cpu().numpy() for k in ("means", "scales", "quats", "opacities", "sh")}
+    zero = {k: np.zeros_like(a) for k, a in raw0.items()}
+    new, _, _, _ = OJ.gaussian_adam(raw0, gg, zero, zero, 1, 10)
+    for k in OJ.GROUPS:
+        a = getattr(raw, k).cpu().numpy().astype(np.float64)
+        assert np.max(np.abs(a - new[k])) <= 2e-6 * max(1.0, np.max(np.abs(new[k]))), k
+
+
+def test_refinement_lowers_loss_and_pose_error():
+    W, H = 128, 96
+    cam = S.Camera(W, H, 110.0, 110.0, W / 2, H / 2)
+    sc = S.random_scene(81, 20_000, 1, cam, depth=(2.0, 7.0),
+                        log_scale=(np.log(0.01), np.log(0.06)))
+    g_gt = R.GaussianParams.from_set(sc, DEV)
+    rast = R.Rasterizer(0)
+    K = 4
+    gts = [S.random_pose_near_identity(90 + k, 2.0, 0.05) for k in range(K)]
+    targets = []
+    for p in gts:
+        t_, _ = rast.forward(g_gt, [cam], torch.tensor(p[None], device=DEV))
+        targets.append(t_.clone().view(3, H, W))
+    rng = S.rng_for(82, 1)
+    noisy = S.GaussianSet(sc.means + rng.normal(0, 0.01, sc.means.shape).astype(np.float32),
+                          sc.scales, sc.quats, sc.opacities, sc.sh, 1)
+    init = np.stack([S.perturb_pose(p, 1.0, 0.02, rng) for p in gts]).astype(np.float32)
+    raw = J.RawGaussians.from_set(noisy, DEV)
+    steps = 120
+    ref = J.JointRefiner(raw, [cam] * K, targets, torch.tensor(init, device=DEV), steps,
+                         views_per_step=2, hp=J.JointHyper(lr_means=(1.6e-4, 1.6e-6)))
+    first = float(ref.step(with_loss=True))
+    for _ in range(steps - 2):
+        ref.step()
+    last = float(ref.step(with_loss=True))
+    assert not ref.overflowed()
+    assert last < 0.7 * first, (first, last)
+    est = ref.poses_in_input_order().cpu().numpy()
+    e0 = np.mean([S.pose_error(init[k], gts[k])[0] for k in range(K)])
+    e1 = np.mean([S.pose_error(est[k], gts[k])[0] for k in range(K)])
+    assert e1 < 0.5 * e0, (e0, e1)
