@@ -393,15 +393,19 @@ def joint_scene():
 
 
 def joint_section(args, dev):
-    """Joint reconstruction step at one GPU's share: 1M Gaussians (SH 3), 4 of
-    the 20 arc views (1008x756) per step, forward + per-view L1 + backward to
-    every Gaussian parameter and the 4 pose twists + the pose Adam step.  The
-    optimised scene is the ground-truth scene with mu += N(0, 0.01^2),
+    """Joint reconstruction and pose refinement step (Sec. III-C) at one GPU's
+    share: 1M Gaussians (SH 3), 4 of the 20 arc views (1008x756) per step:
+    forward, L_RGB = 0.8 L1 + 0.2 DSSIM with its gradient, backward to every
+    Gaussian parameter and the 4 pose twists, Adam on the raw Gaussian
+    parameters with the anisotropy hinge (r = 10), pose Adam.  The optimised
+    scene is the ground-truth scene with mu += N(0, 0.01^2),
     log s += N(0, 0.1^2) and resampled colours; targets are rendered from the
-    ground truth at the ground-truth poses."""
+    ground truth at the ground-truth poses; the views are visited in a fixed
+    random order, four at a time."""
     import numpy as np
     import torch
 
+    from paper_2410_08743_amd import joint as J
     from paper_2410_08743_amd import render as R
     from paper_2410_08743_amd import synthetic as S
 
@@ -413,68 +417,49 @@ def joint_section(args, dev):
     noisy = S.GaussianSet((sc.means + rng.normal(0, 0.01, sc.means.shape)).astype(np.float32),
                           (sc.scales * np.exp(rng.normal(0, 0.1, sc.scales.shape))).astype(np.float32),
                           sc.quats, sc.opacities, S.colour_sh(rng, sc.n, 3), 3)
-    g = R.GaussianParams.from_set(noisy, dev)
     V = 4
     nv = wl.extra["gt_poses"].shape[0]
-    perm = S.rng_for(1003, 6).permutation(nv)
+    order = S.rng_for(1003, 6).permutation(nv)
     rast = R.Rasterizer(0)
-    P = cam.width * cam.height
     targets = []
     for k in range(nv):
         t, _ = rast.forward(gt, [cam], torch.tensor(wl.extra["gt_poses"][k:k + 1], device=dev))
-        targets.append(t.clone())
-    poses = torch.tensor(wl.extra["noisy_poses"], device=dev)
-    m = torch.zeros((nv, 6), device=dev)
-    v = torch.zeros((nv, 6), device=dev)
-    st = torch.zeros(nv, dtype=torch.int32, device=dev)
-    cams = [cam] * V
-    imgs = [torch.empty(3 * P, device=dev) for _ in range(V)]
-    dls = [torch.empty(3 * P, device=dev) for _ in range(V)]
-    out = {k: torch.empty(sh, device=dev) for k, sh in
-           (("means", (g.n, 3)), ("scales", (g.n, 3)), ("quats", (g.n, 4)),
-            ("opacities", (g.n,)), ("sh", tuple(g.sh.shape)))}
-    out["pose"] = torch.empty((V, 6), device=dev)
-    # capacity for 4 views from one render of each batch's first view
-    rast.forward(g, [cam] * V, poses[perm[:V]].contiguous())
-    m0, _ = rast.instances()
-    rast.capacity = int(1.5 * m0) + 4096
-    rast.ws = None
-
-    def step(k):
-        idx = perm[(k * V + np.arange(V)) % nv]
-        pv = poses[idx].contiguous()
-        rast.forward(g, cams, pv, check=False, images=imgs)
-        R.loss_l1(cams, imgs, [targets[i] for i in idx], grad=dls, with_loss=False)
-        rast.backward(g, cams, pv, dls, out=out)
-        pm, pvv, pst = m[idx].contiguous(), v[idx].contiguous(), st[idx].contiguous()
-        R.pose_adam(pv, out["pose"], pm, pvv, pst, 1e-3, 1e-5, 1000, guard=rast.ws)
-        poses[idx] = pv
-        m[idx] = pm
-        v[idx] = pvv
-        st[idx] = pst
-
-    rast._ensure(g, R.N.view_array(cams))
-    for k in range(3):
-        step(k)
-    rast.reset_overflow()
+        targets.append(t.clone().view(3, cam.height, cam.width))
+    del rast
+    raw = J.RawGaussians.from_set(noisy, dev)
+    K = args.joint_steps
+    ref = J.JointRefiner(raw, [cam] * nv, targets, torch.tensor(wl.extra["noisy_poses"], device=dev),
+                         total_steps=3 + K, views_per_step=V, order=order)
+    P = cam.width * cam.height
+    for _ in range(3):
+        ref.step()
+    ref.rast.reset_overflow()
     torch.cuda.synchronize()
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    K = args.joint_steps
     e0.record()
-    for k in range(K):
-        step(3 + k)
+    for _ in range(K):
+        ref.step()
     e1.record()
     torch.cuda.synchronize()
     ms = e0.elapsed_time(e1) / K
-    M, ovf = rast.instances()
+    M, ovf = ref.rast.instances()
     if ovf:
         print("[bench] joint step overflowed its instance capacity", file=sys.stderr)
         return None
-    print(f"[bench] joint step: {ms:.3f} ms for {V} views ({V * P / (ms * 1e3):.1f} Mpix/s)",
+    # per-stage split from the library's own events, in a separate pass
+    R.profile_enable(0, R.PROFILE_TIMING)
+    R.profile_read(0)
+    for _ in range(5):
+        ref.step()
+    stages = {k: round(ms_ / 5, 4) for k, (c, ms_) in R.profile_read(0).items()}
+    R.profile_enable(0, 0)
+    print(f"[bench] joint step: {ms:.3f} ms for {V} views ({V * P / (ms * 1e3):.1f} Mpix/s) {stages}",
           file=sys.stderr, flush=True)
-    return {"workload": "joint-1M-4x1008x756-sh3", "gaussians": g.n, "views_per_step": V,
+    return {"workload": "joint-1M-4x1008x756-sh3", "gaussians": raw.n, "views_per_step": V,
             "steps": K, "ms_per_step": round(ms, 4), "mpix_per_s": round(V * P / (ms * 1e3), 2),
-            "instances": M, "step": "fwd+L1+bwd(all Gaussian params + 4 poses)+pose adam"}
+            "instances": M, "stages_ms_per_step": stages,
+            "step": "fwd + (0.8 L1 + 0.2 DSSIM) + bwd(all Gaussian params + 4 poses) "
+                    "+ Gaussian Adam with L_An + pose Adam"}
 
 
 def tracking_section(args, dev):
