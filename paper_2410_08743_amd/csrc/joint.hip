@@ -38,16 +38,34 @@ __device__ __forceinline__ int rgb_view_of(const RgbViewsK &a, int tile) {
     return v;
 }
 
+// Register blocking of the separable filters: a horizontal work item is a
+// run of kSsimRun outputs of one staged row (kSsimRun + 10 LDS reads instead
+// of 11 per output), a vertical one a run of kSsimRows consecutive output
+// rows of one column.  Each output is still the sum over the taps in tap
+// order.
+constexpr int kSsimRun = 8;
+constexpr int kSsimRows = kSsimTH / (kSsimThreads / kSsimTW);   // 4
+constexpr int kSsimLD = kSsimLW + 2;   // staged row stride: 16-byte aligned runs
+static_assert(kSsimLH * (kSsimTW / kSsimRun) <= kSsimThreads, "one horizontal item per thread");
+
+__device__ __forceinline__ void ssim_tile_origin(const RgbViewsK &a, int tile, int &v, int &x0,
+                                                 int &y0) {
+    v = rgb_view_of(a, tile);
+    const int lt = tile - a.tile_base[v];
+    x0 = (lt % a.tiles_x[v]) * kSsimTW;
+    y0 = (lt / a.tiles_x[v]) * kSsimTH;
+}
+
 // partial[c * total_tiles + tile] = (sum of SSIM, sum of |x - y|) of the tile.
 __global__ __launch_bounds__(kSsimThreads) void k_ssim_fwd(RgbViewsK a, double2 *partial) {
-    __shared__ float sx[kSsimLH][kSsimLW], sy[kSsimLH][kSsimLW];
+    __shared__ __align__(16) float sx[kSsimLH][kSsimLD];
+    __shared__ __align__(16) float sy[kSsimLH][kSsimLD];
     __shared__ float hm[5][kSsimLH][kSsimTW];
     __shared__ double red[kSsimThreads / kWave];
     const int tile = blockIdx.x, c = blockIdx.y;
-    const int v = rgb_view_of(a, tile);
+    int v, x0, y0;
+    ssim_tile_origin(a, tile, v, x0, y0);
     const int W = a.w[v], H = a.h[v];
-    const int lt = tile - a.tile_base[v];
-    const int x0 = (lt % a.tiles_x[v]) * kSsimTW, y0 = (lt / a.tiles_x[v]) * kSsimTH;
     const size_t plane = (size_t)W * H;
     const float *X = a.pred[v] + c * plane, *Y = a.target[v] + c * plane;
     const int t = threadIdx.x;
@@ -59,43 +77,57 @@ __global__ __launch_bounds__(kSsimThreads) void k_ssim_fwd(RgbViewsK a, double2 
         sy[r][q] = in ? Y[(size_t)gy * W + gx] : 0.f;
     }
     __syncthreads();
-    for (int i = t; i < kSsimLH * kSsimTW; i += kSsimThreads) {
-        const int r = i / kSsimTW, q = i - r * kSsimTW;
-        float s0 = 0.f, s1 = 0.f, s2 = 0.f, s3 = 0.f, s4 = 0.f;
+    if (t < kSsimLH * (kSsimTW / kSsimRun)) {
+        const int r = t / (kSsimTW / kSsimRun), q0 = (t % (kSsimTW / kSsimRun)) * kSsimRun;
+        float xv[kSsimRun + 2 * kSsimR], yv[kSsimRun + 2 * kSsimR];
 #pragma unroll
-        for (int k = 0; k < kSsimTaps; k++) {
-            const float wk = a.win[k], xv = sx[r][q + k], yv = sy[r][q + k];
-            const float wx = wk * xv, wy = wk * yv;
-            s0 += wx;
-            s1 += wy;
-            s2 = fmaf(wx, xv, s2);
-            s3 = fmaf(wy, yv, s3);
-            s4 = fmaf(wx, yv, s4);
+        for (int j = 0; j < kSsimRun + 2 * kSsimR; j++) {
+            xv[j] = sx[r][q0 + j];
+            yv[j] = sy[r][q0 + j];
         }
-        hm[0][r][q] = s0;
-        hm[1][r][q] = s1;
-        hm[2][r][q] = s2;
-        hm[3][r][q] = s3;
-        hm[4][r][q] = s4;
+#pragma unroll
+        for (int o = 0; o < kSsimRun; o++) {
+            float s0 = 0.f, s1 = 0.f, s2 = 0.f, s3 = 0.f, s4 = 0.f;
+#pragma unroll
+            for (int k = 0; k < kSsimTaps; k++) {
+                const float wk = a.win[k], xk = xv[o + k], yk = yv[o + k];
+                const float wx = wk * xk, wy = wk * yk;
+                s0 += wx;
+                s1 += wy;
+                s2 = fmaf(wx, xk, s2);
+                s3 = fmaf(wy, yk, s3);
+                s4 = fmaf(wx, yk, s4);
+            }
+            hm[0][r][q0 + o] = s0;
+            hm[1][r][q0 + o] = s1;
+            hm[2][r][q0 + o] = s2;
+            hm[3][r][q0 + o] = s3;
+            hm[4][r][q0 + o] = s4;
+        }
     }
     __syncthreads();
-    const int tx = t % kSsimTW, ty = t / kSsimTW;
+    const int tx = t % kSsimTW, r0 = (t / kSsimTW) * kSsimRows;
+    float col[5][kSsimRows + 2 * kSsimR];
+#pragma unroll
+    for (int m = 0; m < 5; m++)
+#pragma unroll
+        for (int j = 0; j < kSsimRows + 2 * kSsimR; j++) col[m][j] = hm[m][r0 + j][tx];
     float *G = a.gmap[v];
     double ssum = 0.0, l1sum = 0.0;
 #pragma unroll
-    for (int j = 0; j < kSsimTH / (kSsimThreads / kSsimTW); j++) {
-        const int r = ty + (kSsimThreads / kSsimTW) * j;
+    for (int j = 0; j < kSsimRows; j++) {
+        const int r = r0 + j;
         const int gy = y0 + r, gx = x0 + tx;
         if (gy >= H || gx >= W) continue;
         float mx = 0.f, my = 0.f, exx = 0.f, eyy = 0.f, exy = 0.f;
 #pragma unroll
         for (int k = 0; k < kSsimTaps; k++) {
             const float wk = a.win[k];
-            mx = fmaf(wk, hm[0][r + k][tx], mx);
-            my = fmaf(wk, hm[1][r + k][tx], my);
-            exx = fmaf(wk, hm[2][r + k][tx], exx);
-            eyy = fmaf(wk, hm[3][r + k][tx], eyy);
-            exy = fmaf(wk, hm[4][r + k][tx], exy);
+            mx = fmaf(wk, col[0][j + k], mx);
+            my = fmaf(wk, col[1][j + k], my);
+            exx = fmaf(wk, col[2][j + k], exx);
+            eyy = fmaf(wk, col[3][j + k], eyy);
+            exy = fmaf(wk, col[4][j + k], exy);
         }
         const float sxx = fmaf(-mx, mx, exx), syy = fmaf(-my, my, eyy), sxy = fmaf(-mx, my, exy);
         const float a1 = fmaf(2.f * mx, my, kSsimC1), a2 = fmaf(2.f, sxy, kSsimC2);
@@ -123,13 +155,12 @@ __global__ __launch_bounds__(kSsimThreads) void k_ssim_fwd(RgbViewsK a, double2 
 // y F g_exy), F the window filter (its own adjoint: the window is symmetric
 // and the maps are zero outside the image), N = 3 W H.
 __global__ __launch_bounds__(kSsimThreads) void k_ssim_bwd(RgbViewsK a) {
-    __shared__ float sg[3][kSsimLH][kSsimLW];
+    __shared__ __align__(16) float sg[3][kSsimLH][kSsimLD];
     __shared__ float hg[3][kSsimLH][kSsimTW];
     const int tile = blockIdx.x, c = blockIdx.y;
-    const int v = rgb_view_of(a, tile);
+    int v, x0, y0;
+    ssim_tile_origin(a, tile, v, x0, y0);
     const int W = a.w[v], H = a.h[v];
-    const int lt = tile - a.tile_base[v];
-    const int x0 = (lt % a.tiles_x[v]) * kSsimTW, y0 = (lt / a.tiles_x[v]) * kSsimTH;
     const size_t plane = (size_t)W * H;
     const float *G = a.gmap[v];
     const int t = threadIdx.x;
@@ -142,38 +173,44 @@ __global__ __launch_bounds__(kSsimThreads) void k_ssim_bwd(RgbViewsK a) {
         for (int m = 0; m < 3; m++) sg[m][r][q] = in ? G[(size_t)(3 * m + c) * plane + o] : 0.f;
     }
     __syncthreads();
-    for (int i = t; i < kSsimLH * kSsimTW; i += kSsimThreads) {
-        const int r = i / kSsimTW, q = i - r * kSsimTW;
-        float s0 = 0.f, s1 = 0.f, s2 = 0.f;
+    if (t < kSsimLH * (kSsimTW / kSsimRun)) {
+        const int r = t / (kSsimTW / kSsimRun), q0 = (t % (kSsimTW / kSsimRun)) * kSsimRun;
 #pragma unroll
-        for (int k = 0; k < kSsimTaps; k++) {
-            const float wk = a.win[k];
-            s0 = fmaf(wk, sg[0][r][q + k], s0);
-            s1 = fmaf(wk, sg[1][r][q + k], s1);
-            s2 = fmaf(wk, sg[2][r][q + k], s2);
+        for (int m = 0; m < 3; m++) {
+            float gv[kSsimRun + 2 * kSsimR];
+#pragma unroll
+            for (int j = 0; j < kSsimRun + 2 * kSsimR; j++) gv[j] = sg[m][r][q0 + j];
+#pragma unroll
+            for (int o = 0; o < kSsimRun; o++) {
+                float s = 0.f;
+#pragma unroll
+                for (int k = 0; k < kSsimTaps; k++) s = fmaf(a.win[k], gv[o + k], s);
+                hg[m][r][q0 + o] = s;
+            }
         }
-        hg[0][r][q] = s0;
-        hg[1][r][q] = s1;
-        hg[2][r][q] = s2;
     }
     __syncthreads();
-    const int tx = t % kSsimTW, ty = t / kSsimTW;
+    const int tx = t % kSsimTW, r0 = (t / kSsimTW) * kSsimRows;
+    float col[3][kSsimRows + 2 * kSsimR];
+#pragma unroll
+    for (int m = 0; m < 3; m++)
+#pragma unroll
+        for (int j = 0; j < kSsimRows + 2 * kSsimR; j++) col[m][j] = hg[m][r0 + j][tx];
     const float *X = a.pred[v] + c * plane, *Y = a.target[v] + c * plane;
     float *D = a.grad[v] + c * plane;
     const float invn = 1.f / (3.f * (float)plane);
     const float wl1 = (1.f - a.beta) * invn, wss = -a.beta * invn;
 #pragma unroll
-    for (int j = 0; j < kSsimTH / (kSsimThreads / kSsimTW); j++) {
-        const int r = ty + (kSsimThreads / kSsimTW) * j;
-        const int gy = y0 + r, gx = x0 + tx;
+    for (int j = 0; j < kSsimRows; j++) {
+        const int gy = y0 + r0 + j, gx = x0 + tx;
         if (gy >= H || gx >= W) continue;
         float f0 = 0.f, f1 = 0.f, f2 = 0.f;
 #pragma unroll
         for (int k = 0; k < kSsimTaps; k++) {
             const float wk = a.win[k];
-            f0 = fmaf(wk, hg[0][r + k][tx], f0);
-            f1 = fmaf(wk, hg[1][r + k][tx], f1);
-            f2 = fmaf(wk, hg[2][r + k][tx], f2);
+            f0 = fmaf(wk, col[0][j + k], f0);
+            f1 = fmaf(wk, col[1][j + k], f1);
+            f2 = fmaf(wk, col[2][j + k], f2);
         }
         const size_t o = (size_t)gy * W + gx;
         const float x = X[o], y = Y[o];

@@ -59,17 +59,21 @@ __global__ __launch_bounds__(kSortThreads) void k_sort_hist(SortPass a) {
     a.hist[(size_t)t * a.nblk + blockIdx.x] = h[t];
 }
 
-// One block per digit: exclusive scan of that digit's counts across blocks.
-__global__ __launch_bounds__(kSortThreads) void k_sort_scan(SortPass a) {
-    __shared__ uint32_t scratch[kSortThreads / kWave];
+// One block per digit: exclusive scan of that digit's counts across blocks
+// (a row of up to tens of thousands of counts for the instance sort of a
+// multi-view call, hence the wide block).
+constexpr int kSortScanThreads = 1024;
+
+__global__ __launch_bounds__(kSortScanThreads) void k_sort_scan(SortPass a) {
+    __shared__ uint32_t scratch[kSortScanThreads / kWave];
     const int t = threadIdx.x;
     uint32_t *row = a.hist + (size_t)blockIdx.x * a.nblk;
-    const int per = (a.nblk + kSortThreads - 1) / kSortThreads;
+    const int per = (a.nblk + kSortScanThreads - 1) / kSortScanThreads;
     const int begin = min(t * per, a.nblk), end = min(begin + per, a.nblk);
     uint32_t local = 0;
     for (int k = begin; k < end; k++) local += row[k];
     uint32_t total;
-    uint32_t off = block_exclusive_scan<uint32_t, kSortThreads>(local, scratch, &total);
+    uint32_t off = block_exclusive_scan<uint32_t, kSortScanThreads>(local, scratch, &total);
     for (int k = begin; k < end; k++) {
         const uint32_t x = row[k];
         row[k] = off;
@@ -192,7 +196,7 @@ int launch_sort_pairs(uint32_t *k0, uint32_t *v0, uint32_t *k1, uint32_t *v1, ui
         a.shift = p * pbits;
         if (p > 0 || !hist0_given)
             hipLaunchKernelGGL(k_sort_hist, dim3(a.nblk), dim3(kSortThreads), 0, s, a);
-        hipLaunchKernelGGL(k_sort_scan, dim3(kSortBins), dim3(kSortThreads), 0, s, a);
+        hipLaunchKernelGGL(k_sort_scan, dim3(kSortBins), dim3(kSortScanThreads), 0, s, a);
         hipLaunchKernelGGL(k_sort_scatter, dim3(a.nblk), dim3(kSortThreads), 0, s, a);
         *err = hipGetLastError();
         if (*err != hipSuccess) return passes;
