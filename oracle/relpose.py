@@ -19,9 +19,10 @@ notes):
   * Opacity starts at a constant (0.1, the 3DGS initial opacity); rotation
     is the identity quaternion.
   * Pixels whose depth is not a positive finite number still yield a
-    Gaussian (at depth 1 on the pixel's ray, opacity sigmoid(-30), scale
-    0.01), and are nobody's neighbour.  A point with fewer than three valid
-    neighbours averages over those it has (scale 0.01 with none).
+    Gaussian (at depth 1 on the pixel's ray, opacity sigmoid(-30), so that
+    it never blends) and are nobody's neighbour.  Every point's scale is the
+    mean over its three nearest valid neighbours; a point with fewer
+    averages over those it has (scale 0.01 with none).
 """
 import numpy as np
 
