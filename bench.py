@@ -99,6 +99,10 @@ def main():
     ap.add_argument("--no-joint", action="store_true", help="skip the joint-step measurement")
     ap.add_argument("--no-tiny", action="store_true", help="skip the tiny-scene measurement")
     ap.add_argument("--no-track", action="store_true", help="skip the tracking measurement")
+    ap.add_argument("--no-relpose", action="store_true",
+                    help="skip the relative-pose (two-frame) measurement")
+    ap.add_argument("--relpose-only", action="store_true",
+                    help="run only the relative-pose measurement and print its JSON")
     ap.add_argument("--track-frames", type=int, default=100)
     ap.add_argument("--joint-steps", type=int, default=20)
     ap.add_argument("--serve-rates", type=str, default="0.5,1,2",
@@ -128,6 +132,9 @@ def main():
         return
     if args.joint_only:
         print(json.dumps(joint_section(args, dev)), flush=True)
+        return
+    if args.relpose_only:
+        print(json.dumps(relpose_section(args, dev)), flush=True)
         return
     wl = S.single_view()
     cam = wl.camera
@@ -292,6 +299,9 @@ def main():
     track = None
     if not args.no_track:
         track = tracking_section(args, dev)
+    relpose = None
+    if not args.no_relpose:
+        relpose = relpose_section(args, dev)
     serving = None
     if not args.no_serve:
         serving = serving_section(args, dev, with_cpu=not args.no_cpu)
@@ -309,6 +319,7 @@ def main():
         "tiny": tiny,
         "joint": joint,
         "tracking": track,
+        "relative_pose": relpose,
         "serving": serving,
         "stages": stage_report,
         "work": {"instances": M, "evaluated_pairs": neval, "blended_pairs": nblend,
@@ -460,6 +471,70 @@ def joint_section(args, dev):
             "instances": M, "stages_ms_per_step": stages,
             "step": "fwd + (0.8 L1 + 0.2 DSSIM) + bwd(all Gaussian params + 4 poses) "
                     "+ Gaussian Adam with L_An + pose Adam"}
+
+
+def relpose_section(args, dev):
+    """Relative pose between two frames (Sec. III-D) on the tracking room
+    (500k Gaussians, SH 3, 1200x680): frames 60 and 62 of its trajectory;
+    frame 60's depth map is the expected-depth render of the scene (the
+    stand-in for a monocular estimate).  Timed: unprojection of every 4th
+    pixel with its three-nearest-neighbour scales, 100 fitting steps of the
+    frame's scene (L_RGB, Gaussian Adam), 100 masked-L1 pose steps."""
+    import numpy as np
+    import torch
+
+    from paper_2410_08743_amd import joint as J
+    from paper_2410_08743_amd import relpose as RP
+    from paper_2410_08743_amd import render as R
+    from paper_2410_08743_amd import synthetic as S
+
+    wl = S.room(n_frames=63)
+    cam = wl.camera
+    g = R.GaussianParams.from_set(wl.scene, dev)
+    traj = wl.extra["trajectory"]
+    P0, P1 = traj[60].astype(np.float64), traj[62].astype(np.float64)
+    rast = R.Rasterizer(0)
+    t0 = torch.tensor(P0[None].astype(np.float32), device=dev)
+    i0 = rast.forward(g, [cam], t0)[0].clone().view(3, cam.height, cam.width)
+    i1 = rast.forward(g, [cam], torch.tensor(P1[None].astype(np.float32), device=dev))[0].clone()
+    gz = R.GaussianParams.from_set(S.depth_coloured(wl.scene, P0), dev)
+    dimg, al = R.Rasterizer(0).forward(gz, [cam], t0, alphas=True)
+    depth = (dimg.view(3, cam.height, cam.width)[0] /
+             al.view(cam.height, cam.width).clamp_min(1e-6)).contiguous()
+    del rast, gz
+
+    def run():
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
+        ev[0].record()
+        raw = RP.unproject(cam, depth, i0, 4)
+        ev[1].record()
+        ref = J.JointRefiner(raw, [cam], [i0], RP.identity_poses(1, dev), 100, hp=RP.FIT_HYPER,
+                             optimize_poses=False)
+        for _ in range(100):
+            ref.step()
+        ev[2].record()
+        pose = R.solve_poses(ref.g, [cam], i1.reshape(-1), RP.identity_poses(1, dev), steps=100,
+                             masked=True)
+        ev[3].record()
+        torch.cuda.synchronize()
+        return raw.n, pose[0], [ev[k].elapsed_time(ev[k + 1]) for k in range(3)]
+
+    run()                                     # warm-up (allocations, first launches)
+    n, pose, (t_un, t_fit, t_pose) = run()
+    H0 = np.vstack([P0, [0, 0, 0, 1]])
+    H1 = np.vstack([P1, [0, 0, 0, 1]])
+    gt = (H1 @ np.linalg.inv(H0))[:3]
+    e0 = S.pose_error(np.hstack([np.eye(3), np.zeros((3, 1))]), gt)
+    e1 = S.pose_error(pose.cpu().numpy(), gt)
+    total = t_un + t_fit + t_pose
+    print(f"[bench] relative pose: {n} Gaussians, unproject {t_un:.2f} ms, fit {t_fit:.1f} ms, "
+          f"pose {t_pose:.1f} ms, error {e0[0]:.3f} deg / {e0[1]:.4f} -> {e1[0]:.4f} deg / "
+          f"{e1[1]:.5f}", file=sys.stderr, flush=True)
+    return {"workload": "relpose-room-1200x680-frames-60-62", "gaussians": n, "stride": 4,
+            "unproject_ms": round(t_un, 3), "fit_ms_100_steps": round(t_fit, 2),
+            "pose_ms_100_steps": round(t_pose, 2), "frame_pair_ms": round(total, 2),
+            "initial_error": [round(e0[0], 4), round(e0[1], 5)],
+            "final_error": [round(e1[0], 4), round(e1[1], 5)]}
 
 
 def tracking_section(args, dev):

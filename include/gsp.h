@@ -261,6 +261,45 @@ gsp_status gsp_gaussian_adam(gsp_ctx *ctx, int64_t n, int32_t sh_degree,
                              void *scratch, const void *guard_workspace, void *stream);
 size_t gsp_gaussian_adam_scratch_bytes(int64_t n);
 
+/* Relative pose estimation between frames t and t+1 (Sec. III-D).
+ *
+ * gsp_unproject: the scene of frame t from its depth map.  Pixels
+ * (stride i, stride j) of the view's region of interest, i < ceil(roi_w /
+ * stride), j < ceil(roi_h / stride), become Gaussian k = j * ceil(roi_w /
+ * stride) + i at the point of camera-frame depth depth[y][x] on the ray
+ * through the pixel's centre (frame t's camera is the world frame), with
+ * identity rotation, logit opacity log(opacity / (1 - opacity)), SH
+ * degree-0 coefficient (c - 1/2) / Y_0 from the pixel colour c (higher
+ * coefficients 0), and isotropic log scale log of the mean distance to its
+ * three nearest neighbours (fewer if there are fewer; 0.01 with none).  A
+ * pixel whose depth is not a positive finite number gives a Gaussian at
+ * depth 1 with logit -30 (it never blends) that is nobody's neighbour.
+ *   depth [roi_h][roi_w], image [3][roi_h][roi_w]: device FP32
+ *   out: raw parameters of gsp_unproject_count(...) Gaussians (device; sh
+ *        [n][(sh_degree+1)^2][3])
+ *   scratch: device, gsp_unproject_scratch_bytes(view, stride) bytes
+ * The neighbours are found by brute force (n^2 distance tests). */
+gsp_status gsp_unproject_count(const gsp_view *view, int32_t stride, int64_t *n);
+size_t gsp_unproject_scratch_bytes(const gsp_view *view, int32_t stride);
+gsp_status gsp_unproject(gsp_ctx *ctx, const gsp_view *view, const float *depth,
+                         const float *image, int32_t stride, float opacity, int32_t sh_degree,
+                         const gsp_gaussian_params *out, void *scratch, size_t scratch_bytes,
+                         void *stream);
+
+/* Confidence-masked L1 of Eq. (21) per view: loss[v] = sum over the pixels
+ * and channels of M |pred - target| and grad[v] = M sign(pred - target)
+ * (0 where equal), with the mask of Eq. (20) M = [alpha > 0.99], alpha the
+ * accumulated opacity 1 - T_final that gsp_render_fwd writes (decided in
+ * FP64 on the FP32 value).  pred, target, alpha, grad: host arrays of V
+ * device pointers; loss: device float [V] or NULL (then scratch may be
+ * NULL), else scratch of gsp_loss_masked_l1_scratch_bytes(V, views) bytes;
+ * fixed-order reduction. */
+gsp_status gsp_loss_masked_l1(gsp_ctx *ctx, int32_t V, const gsp_view *views,
+                              const float *const *pred, const float *const *target,
+                              const float *const *alpha, float *const *grad, float *loss,
+                              void *scratch, void *stream);
+size_t gsp_loss_masked_l1_scratch_bytes(int32_t V, const gsp_view *views);
+
 /* Workspace introspection for tests: device pointer and element count of an
  * intermediate array of the last forward/backward.  Names: "geom" (float4
  * pairs per view-Gaussian: u_hi v_hi u_lo v_lo | A2 B2 C2 log2(o), with

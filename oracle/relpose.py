@@ -16,8 +16,9 @@ notes):
     camera-frame z of each pixel; frame t's camera is the world frame.
   * Colour c of the pixel becomes the degree-0 SH coefficient
     (c - 1/2) / Y_0, Y_0 = 1 / (2 sqrt(pi)); higher coefficients are 0.
-  * Opacity starts at a constant (0.1, the 3DGS initial opacity); rotation
-    is the identity quaternion.
+  * Opacity starts at a constant, 0.5 by default (high enough that
+    overlapping neighbours reach the mask threshold of Eq. (20) where the
+    depth map has surface); rotation is the identity quaternion.
   * Pixels whose depth is not a positive finite number still yield a
     Gaussian (at depth 1 on the pixel's ray, opacity sigmoid(-30), so that
     it never blends) and are nobody's neighbour.  Every point's scale is the
@@ -60,7 +61,7 @@ def knn3_mean_distance(points, valid=None):
     return out
 
 
-def unproject(depth, image, cam, stride, opacity=0.1):
+def unproject(depth, image, cam, stride, opacity=0.5):
     """Raw Gaussian parameters (means, log_scales, quats, logit_opacities,
     sh [n, 1, 3]) of the unprojected grid.  depth [h, w], image [3, h, w]
     over the camera's region of interest."""

@@ -19,7 +19,9 @@ EXPORTS = (
     "gsp_instances", "gsp_loss_l1", "gsp_loss_l1_scratch_bytes", "gsp_pose_adam",
     "gsp_inspect", "gsp_status_string", "gsp_last_error", "gsp_version",
     "gsp_profile_enable", "gsp_profile_read", "gsp_loss_rgb", "gsp_loss_rgb_scratch_bytes",
-    "gsp_gaussian_adam", "gsp_gaussian_adam_scratch_bytes",
+    "gsp_gaussian_adam", "gsp_gaussian_adam_scratch_bytes", "gsp_unproject_count",
+    "gsp_unproject_scratch_bytes", "gsp_unproject", "gsp_loss_masked_l1",
+    "gsp_loss_masked_l1_scratch_bytes",
 )
 
 
@@ -106,6 +108,11 @@ def lib():
         "gsp_loss_rgb_scratch_bytes": ([I32, P], SZ),
         "gsp_gaussian_adam": ([P, I64, I32, P, P, P, P, I32, P, P, P, P, P, P, P], I32),
         "gsp_gaussian_adam_scratch_bytes": ([I64], SZ),
+        "gsp_unproject_count": ([P, I32, ctypes.POINTER(I64)], I32),
+        "gsp_unproject_scratch_bytes": ([P, I32], SZ),
+        "gsp_unproject": ([P, P, P, P, I32, ctypes.c_float, I32, P, P, SZ, P], I32),
+        "gsp_loss_masked_l1": ([P, I32, P, P, P, P, P, P, P, P], I32),
+        "gsp_loss_masked_l1_scratch_bytes": ([I32, P], SZ),
         "gsp_status_string": ([I32], ctypes.c_char_p),
         "gsp_last_error": ([], ctypes.c_char_p),
         "gsp_version": ([], ctypes.c_int),

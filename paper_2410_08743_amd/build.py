@@ -15,7 +15,8 @@ CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libgsp.so")
 SOURCES = ["api.hip", "preprocess.hip", "sort.hip", "raster_fwd.hip", "raster_bwd.hip",
-           "preprocess_bwd.hip", "misc.hip", "joint.hip"]
+           "preprocess_bwd.hip", "misc.hip", "joint.hip",
+           "relpose.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-Wall",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",

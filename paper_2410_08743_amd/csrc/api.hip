@@ -719,6 +719,108 @@ gsp_status gsp_gaussian_adam(gsp_ctx *ctx, int64_t n, int32_t sh_degree,
     return GSP_OK;
 }
 
+gsp_status gsp_unproject_count(const gsp_view *view, int32_t stride, int64_t *n) {
+    gsp::ViewsK vk;
+    int64_t total_pix = 0;
+    gsp_status s = make_views(1, view, &vk, &total_pix);
+    if (s != GSP_OK) return s;
+    if (stride < 1) return fail(GSP_EINVAL, "stride must be positive");
+    if (!n) return fail(GSP_EINVAL, "null output");
+    *n = (int64_t)((view->roi_w + stride - 1) / stride) * ((view->roi_h + stride - 1) / stride);
+    return GSP_OK;
+}
+
+size_t gsp_unproject_scratch_bytes(const gsp_view *view, int32_t stride) {
+    int64_t n = 0;
+    if (gsp_unproject_count(view, stride, &n) != GSP_OK) return 0;
+    return (size_t)(n > 0 ? n : 1) * sizeof(float4);
+}
+
+gsp_status gsp_unproject(gsp_ctx *ctx, const gsp_view *view, const float *depth,
+                         const float *image, int32_t stride, float opacity, int32_t sh_degree,
+                         const gsp_gaussian_params *out, void *scratch, size_t scratch_bytes,
+                         void *stream) {
+    gsp_status s = check_device(ctx);
+    if (s != GSP_OK) return s;
+    int64_t n = 0;
+    s = gsp_unproject_count(view, stride, &n);
+    if (s != GSP_OK) return s;
+    if (n >= (int64_t(1) << 31)) return fail(GSP_EINVAL, "too many points");
+    if (!depth || !image || !out || !scratch) return fail(GSP_EINVAL, "null argument");
+    if (!out->means || !out->log_scales || !out->quats || !out->logit_opacities || !out->sh)
+        return fail(GSP_EINVAL, "null parameter array");
+    if (sh_degree < 0 || sh_degree > 3) return fail(GSP_EINVAL, "sh_degree must be 0..3");
+    if (!(opacity > 0.f && opacity < 1.f)) return fail(GSP_EINVAL, "opacity must lie in (0, 1)");
+    if (scratch_bytes < gsp_unproject_scratch_bytes(view, stride))
+        return fail(GSP_ENOMEM, "scratch too small");
+    gsp::UnprojK a;
+    std::memset(&a, 0, sizeof a);
+    a.depth = depth;
+    a.image = image;
+    a.w = view->roi_w;
+    a.h = view->roi_h;
+    a.stride = stride;
+    a.nx = (view->roi_w + stride - 1) / stride;
+    a.ny = (view->roi_h + stride - 1) / stride;
+    a.S = (sh_degree + 1) * (sh_degree + 1);
+    a.roi_x = view->roi_x;
+    a.roi_y = view->roi_y;
+    a.fx = view->fx;
+    a.fy = view->fy;
+    a.cx = view->cx;
+    a.cy = view->cy;
+    a.logit = (float)std::log((double)opacity / (1.0 - (double)opacity));
+    a.means = out->means;
+    a.log_scales = out->log_scales;
+    a.quats = out->quats;
+    a.logits = out->logit_opacities;
+    a.sh = out->sh;
+    a.pts = static_cast<float4 *>(scratch);
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    hipError_t e = stage(ctx, "unproject", st, [&] { return gsp::launch_unproject(a, st); });
+    if (e != hipSuccess) return hip_fail(e, "unproject");
+    return GSP_OK;
+}
+
+gsp_status gsp_loss_masked_l1(gsp_ctx *ctx, int32_t V, const gsp_view *views,
+                              const float *const *pred, const float *const *target,
+                              const float *const *alpha, float *const *grad, float *loss,
+                              void *scratch, void *stream) {
+    gsp_status s = check_device(ctx);
+    if (s != GSP_OK) return s;
+    gsp::ViewsK vk;
+    int64_t total_pix = 0;
+    s = make_views(V, views, &vk, &total_pix);
+    if (s != GSP_OK) return s;
+    if (!pred || !target || !alpha || !grad) return fail(GSP_EINVAL, "null pointer array");
+    if (loss && !scratch) return fail(GSP_EINVAL, "loss requires scratch memory");
+    gsp::MaskViewsK a;
+    std::memset(&a, 0, sizeof a);
+    a.V = V;
+    for (int v = 0; v < V; v++) {
+        if (!pred[v] || !target[v] || !alpha[v] || !grad[v])
+            return fail(GSP_EINVAL, "null pred, target, alpha or grad of view %d", v);
+        a.pred[v] = pred[v];
+        a.target[v] = target[v];
+        a.alpha[v] = alpha[v];
+        a.grad[v] = grad[v];
+        a.pix[v] = (int64_t)views[v].roi_w * views[v].roi_h;
+        a.blk_base[v + 1] = a.blk_base[v] + gsp::masked_blocks(3 * a.pix[v]);
+    }
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    hipError_t e = stage(ctx, "loss_masked_l1", st,
+                         [&] { return gsp::launch_masked_l1(a, loss, scratch, st); });
+    if (e != hipSuccess) return hip_fail(e, "masked loss");
+    return GSP_OK;
+}
+
+size_t gsp_loss_masked_l1_scratch_bytes(int32_t V, const gsp_view *views) {
+    int64_t blocks = 0;
+    for (int v = 0; views && v < V; v++)
+        blocks += gsp::masked_blocks(3 * (int64_t)views[v].roi_w * views[v].roi_h);
+    return (size_t)(blocks > 0 ? blocks : 1) * sizeof(double);
+}
+
 size_t gsp_gaussian_adam_scratch_bytes(int64_t n) {
     const int64_t p = gsp::gauss_adam_partials(n);
     return (size_t)(p > 0 ? p : 1) * sizeof(double);

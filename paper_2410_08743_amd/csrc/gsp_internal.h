@@ -182,6 +182,29 @@ struct GaussAdamK {
 int64_t gauss_adam_partials(int64_t n);
 hipError_t launch_gauss_adam(const GaussAdamK &a, float *aniso_loss, hipStream_t s);
 
+// relpose.hip: scene of frame t from its depth map, and the masked L1
+// (Sec. III-D, Eq. (20)-(21)).
+struct UnprojK {
+    const float *depth, *image;          // [h][w], [3][h][w] over the region of interest
+    int w, h, stride, nx, ny, S, roi_x, roi_y;
+    float fx, fy, cx, cy, logit;
+    float *means, *log_scales, *quats, *logits, *sh;   // raw parameters out
+    float4 *pts;                         // scratch: (x, y, z, valid) per point
+};
+hipError_t launch_unproject(const UnprojK &a, hipStream_t s);
+
+struct MaskViewsK {
+    const float *pred[GSP_MAX_VIEWS];
+    const float *target[GSP_MAX_VIEWS];
+    const float *alpha[GSP_MAX_VIEWS];
+    float *grad[GSP_MAX_VIEWS];
+    int64_t pix[GSP_MAX_VIEWS];
+    int64_t blk_base[GSP_MAX_VIEWS + 1];
+    int V;
+};
+int64_t masked_blocks(int64_t count);
+hipError_t launch_masked_l1(const MaskViewsK &a, float *loss, void *scratch, hipStream_t s);
+
 template <typename T>
 inline T *region(char *ws, size_t off) { return reinterpret_cast<T *>(ws + off); }
 

@@ -143,8 +143,10 @@ class JointRefiner:
     def __init__(self, raw: RawGaussians, cams: Sequence, targets: Sequence[torch.Tensor],
                  init_poses: torch.Tensor, total_steps: int, views_per_step: int = 1,
                  hp: Optional[JointHyper] = None, order: Optional[Sequence[int]] = None,
-                 margin: float = 1.5, rast: Optional[Rasterizer] = None):
+                 margin: float = 1.5, rast: Optional[Rasterizer] = None,
+                 optimize_poses: bool = True):
         self.raw = raw
+        self.optimize_poses = bool(optimize_poses)
         self.hp = hp or JointHyper()
         K = len(cams)
         order = list(range(K)) if order is None else [int(i) for i in order]
@@ -204,14 +206,18 @@ class JointRefiner:
         view_losses, _ = loss_rgb(cams, imgs, self.targets[a:b], grad=dls, beta=self.hp.beta_ssim,
                                   with_loss=with_loss, scratch=self.loss_scratch)
         out = dict(self.grads)
-        out["pose"] = self.grads["pose"][:V]
-        self.rast.backward(self.g, cams, poses, dls, out=out)
+        if self.optimize_poses:
+            out["pose"] = self.grads["pose"][:V]
+        else:
+            del out["pose"]
+        self.rast.backward(self.g, cams, poses, dls, pose=self.optimize_poses, out=out)
         gaussian_adam(self.raw, self.grads, self.m, self.v, self.k, self.total_steps, self.hp,
                       self.scales, self.opacities, aniso_loss=self.aniso if with_loss else None,
                       scratch=self.adam_scratch, guard=self.rast.ws)
-        pose_adam(poses, out["pose"], self.pm[a:b], self.pv[a:b], self.psteps[a:b],
-                  self.hp.lr_pose[0], self.hp.lr_pose[1], self.pose_steps_total,
-                  self.hp.betas[0], self.hp.betas[1], self.hp.pose_eps, guard=self.rast.ws)
+        if self.optimize_poses:
+            pose_adam(poses, out["pose"], self.pm[a:b], self.pv[a:b], self.psteps[a:b],
+                      self.hp.lr_pose[0], self.hp.lr_pose[1], self.pose_steps_total,
+                      self.hp.betas[0], self.hp.betas[1], self.hp.pose_eps, guard=self.rast.ws)
         if with_loss:
             return view_losses.sum() + self.aniso[0]
         return None

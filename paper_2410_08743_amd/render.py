@@ -168,8 +168,10 @@ class Rasterizer:
 
     # -- forward / backward ------------------------------------------------
     def forward(self, g: GaussianParams, cams: Sequence, poses: torch.Tensor,
-                alphas: bool = False, check: bool = True, images=None):
-        """Renders len(cams) views; returns (images, packed alphas or None).
+                alphas=False, check: bool = True, images=None):
+        """Renders len(cams) views; returns (images, alphas or None).
+        `alphas`: False, True (a packed tensor of 1 - T_final is made) or an
+        output buffer (packed tensor or list of per-view [h, w] tensors).
         `images` is an optional output: one packed tensor or a list of
         per-view [3, h, w] tensors; by default a packed tensor is made."""
         L = N.lib()
@@ -181,7 +183,10 @@ class Rasterizer:
         dev = f"cuda:{self.device}"
         if images is None:
             images = torch.empty(3 * P, dtype=torch.float32, device=dev)
-        al = torch.empty(P, dtype=torch.float32, device=dev) if alphas else None
+        if isinstance(alphas, bool):
+            al = torch.empty(P, dtype=torch.float32, device=dev) if alphas else None
+        else:
+            al = alphas
         if self.capacity <= 0:
             self.capacity = max(1024, 8 * g.n * len(cams))
         gs = g.struct()
@@ -271,6 +276,31 @@ def loss_l1(cams: Sequence, pred, target, grad=None, with_loss: bool = True):
     return loss, grad
 
 
+def masked_l1(cams: Sequence, pred, target, alpha, grad=None, with_loss: bool = True,
+              scratch: Optional[torch.Tensor] = None):
+    """(per-view masked L1 sums [V] or None, grad) of Eq. (21) with the mask
+    of Eq. (20) from the render's accumulated opacity `alpha` (packed or a
+    list of per-view [h, w] tensors, as gsp_render_fwd writes it)."""
+    L = N.lib()
+    views = N.view_array(cams)
+    if grad is None:
+        grad = ([torch.empty_like(p) for p in pred] if isinstance(pred, (list, tuple))
+                else torch.empty_like(pred))
+    dev = (pred[0] if isinstance(pred, (list, tuple)) else pred).device
+    loss = None
+    if with_loss:
+        loss = torch.empty(len(cams), dtype=torch.float32, device=dev)
+        need = L.gsp_loss_masked_l1_scratch_bytes(len(cams), views)
+        if scratch is None or scratch.numel() < need:
+            scratch = torch.empty(need, dtype=torch.uint8, device=dev)
+    N.check(L.gsp_loss_masked_l1(context(dev.index), len(cams), views, view_ptrs(pred, cams, 3),
+                                 view_ptrs(target, cams, 3), view_ptrs(alpha, cams, 1),
+                                 view_ptrs(grad, cams, 3), _ptr(loss),
+                                 _ptr(scratch if with_loss else None), _stream()),
+            "gsp_loss_masked_l1")
+    return loss, grad
+
+
 def pose_adam(poses, dpose, m, v, steps, lr_start, lr_end, total_steps, beta1=0.9, beta2=0.999,
               eps=1e-8, guard: Optional[torch.Tensor] = None):
     """In-place tangent Adam step with left retraction on every pose; with a
@@ -324,10 +354,11 @@ def render(g: GaussianParams, cams: Sequence, poses: torch.Tensor, tau: Optional
 
 def solve_poses(g: GaussianParams, cams: Sequence, targets: torch.Tensor, init_poses: torch.Tensor,
                 steps: int = 100, lr=(1e-2, 1e-4), betas=(0.9, 0.999), eps=1e-8,
-                rast: Optional[Rasterizer] = None, history: bool = False):
+                rast: Optional[Rasterizer] = None, history: bool = False, masked: bool = False):
     """Estimates the poses of len(cams) views against packed target images by
     `steps` tangent-space Adam iterations on the L1 loss (cosine learning-rate
-    decay lr[0] -> lr[1]).  Forward, loss, backward (pose only) and the update
+    decay lr[0] -> lr[1]); with masked=True on the confidence-masked L1 of
+    Eq. (20)-(21) (pixels whose rendered opacity exceeds 0.99).  Forward, loss, backward (pose only) and the update
     all run on the device without host synchronisation; the instance capacity
     is sized from the first render and the whole solve is repeated if any
     iteration overflowed it."""
@@ -343,6 +374,9 @@ def solve_poses(g: GaussianParams, cams: Sequence, targets: torch.Tensor, init_p
         P = sum(pixel_counts(cams))
         images = torch.empty(3 * P, dtype=torch.float32, device=dev)
         dl = torch.empty_like(images)
+        alpha = torch.empty(P, dtype=torch.float32, device=dev) if masked else None
+        mscratch = (torch.empty(N.lib().gsp_loss_masked_l1_scratch_bytes(V, N.view_array(cams)),
+                                dtype=torch.uint8, device=dev) if masked and history else None)
         rast.forward(g, cams, poses, check=True, images=images)
         if rast.capacity < 1.5 * rast.instances()[0]:
             rast.capacity = int(1.5 * rast.instances()[0]) + 1024
@@ -351,8 +385,13 @@ def solve_poses(g: GaussianParams, cams: Sequence, targets: torch.Tensor, init_p
         rast.reset_overflow()
         hist = []
         for k in range(steps):
-            rast.forward(g, cams, poses, check=False, images=images)
-            loss, _ = loss_l1(cams, images, targets, grad=dl, with_loss=history)
+            if masked:
+                rast.forward(g, cams, poses, check=False, images=images, alphas=alpha)
+                loss, _ = masked_l1(cams, images, targets, alpha, grad=dl, with_loss=history,
+                                    scratch=mscratch)
+            else:
+                rast.forward(g, cams, poses, check=False, images=images)
+                loss, _ = loss_l1(cams, images, targets, grad=dl, with_loss=history)
             rast.backward(g, cams, poses, dl, want=(), pose=True, out={"pose": dpose})
             pose_adam(poses, dpose, m, v, st, lr[0], lr[1], steps, betas[0], betas[1], eps,
                       guard=rast.ws)

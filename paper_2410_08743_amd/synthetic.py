@@ -288,6 +288,36 @@ def room(seed=1004, n=500_000, n_frames=100):
     return wl
 
 
+def box_depth(cam, pose, half=(3.0, 1.5, 2.5)):
+    """Camera-frame depth [H, W] of the walls of the axis-aligned box
+    [-half, half] seen from inside it (rays through pixel centres): the
+    stand-in for a monocular depth estimate of a room frame (it knows the
+    walls, not the objects in the room)."""
+    pose = np.asarray(pose, dtype=np.float64)
+    R, t = pose[:, :3], pose[:, 3]
+    o = -R.T @ t
+    ys, xs = np.mgrid[0:cam.height, 0:cam.width]
+    dc = np.stack([(xs + 0.5 - cam.cx) / cam.fx, (ys + 0.5 - cam.cy) / cam.fy,
+                   np.ones(xs.shape)], axis=-1)
+    dw = dc @ R                       # R^T d per pixel
+    h = np.asarray(half, dtype=np.float64)
+    with np.errstate(divide="ignore", invalid="ignore"):
+        tt = np.where(dw > 0, (h - o) / dw, np.where(dw < 0, (-h - o) / dw, np.inf))
+    return tt.min(axis=-1).astype(np.float32)
+
+
+def depth_coloured(scene, pose):
+    """The scene with every Gaussian's colour set to its camera-frame depth
+    under `pose` (SH degree-0 term only): a render of it divided by its
+    accumulated opacity is the expected depth map of the view -- the
+    stand-in for a monocular depth estimate of a frame."""
+    pose = np.asarray(pose, dtype=np.float64)
+    z = (np.asarray(scene.means, dtype=np.float64) @ pose[:, :3].T + pose[:, 3])[:, 2]
+    sh = np.zeros((scene.n, 1, 3), dtype=np.float32)
+    sh[:, 0, :] = ((z - 0.5) / 0.28209479177387814)[:, None]
+    return GaussianSet(scene.means, scene.scales, scene.quats, scene.opacities, sh, 0)
+
+
 REQUEST_SIZES = ((320, 240), (640, 480), (1008, 756))
 
 
