@@ -106,11 +106,21 @@ typedef struct {
 
 /* Hyper-parameters of the tangent-space Adam step (gsp_pose_adam).  The
  * learning rate follows a cosine decay from lr_start to lr_end over
- * total_steps steps (constant when they are equal). */
+ * total_steps steps (constant when they are equal).  parametrization
+ * selects the group the step moves in: GSP_POSE_SE3 (the paper's, Sec.
+ * III-B: poses in SE(3), update retracted on the left) or GSP_POSE_T_SO3
+ * (the decoupled alternative the paper leaves to future work, Sec. IV-A:
+ * camera centre c in R^3 and rotation in SO(3) separately; the twist
+ * gradient (rho, phi) maps to dL/dc = -R^T dL/drho and dL/dphi, the step
+ * moves c <- c + delta_c and R <- Exp(delta_phi) R, i.e. rotates about the
+ * camera centre). */
+#define GSP_POSE_SE3 0
+#define GSP_POSE_T_SO3 1
 typedef struct {
     float lr_start, lr_end;
     int32_t total_steps;
     float beta1, beta2, eps;
+    int32_t parametrization;
 } gsp_adam_params;
 
 /* Creates a context on HIP device `device` (validates that it is gfx950). */

@@ -11,6 +11,7 @@ LIB_PATH = os.path.join(HERE, "libgsp.so")
 
 GSP_OK, GSP_EINVAL, GSP_ECAPACITY, GSP_ENOMEM, GSP_EHIP, GSP_EUNSUPPORTED = range(6)
 GSP_ACCUMULATE = 1
+GSP_POSE_SE3, GSP_POSE_T_SO3 = 0, 1
 GSP_MAX_VIEWS = 32
 
 # Every symbol include/gsp.h declares.
@@ -59,7 +60,8 @@ class Grads(ctypes.Structure):
 class AdamParams(ctypes.Structure):
     _fields_ = [("lr_start", ctypes.c_float), ("lr_end", ctypes.c_float),
                 ("total_steps", ctypes.c_int32), ("beta1", ctypes.c_float),
-                ("beta2", ctypes.c_float), ("eps", ctypes.c_float)]
+                ("beta2", ctypes.c_float), ("eps", ctypes.c_float),
+                ("parametrization", ctypes.c_int32)]
 
 
 class GaussianParams(ctypes.Structure):

@@ -548,6 +548,8 @@ gsp_status gsp_pose_adam(gsp_ctx *ctx, int32_t V, float *poses, const float *dpo
     if (!(params->beta1 >= 0.f && params->beta1 < 1.f && params->beta2 >= 0.f &&
           params->beta2 < 1.f && params->eps > 0.f))
         return fail(GSP_EINVAL, "bad Adam hyper-parameters");
+    if (params->parametrization != GSP_POSE_SE3 && params->parametrization != GSP_POSE_T_SO3)
+        return fail(GSP_EINVAL, "unknown pose parametrization %d", params->parametrization);
     hipStream_t st = static_cast<hipStream_t>(stream);
     hipError_t e = stage(ctx, "pose_adam", st, [&] {
         return gsp::launch_pose_adam(V, poses, dpose, m, v, steps, *params,

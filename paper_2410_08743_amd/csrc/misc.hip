@@ -103,6 +103,44 @@ __device__ void se3_retract_left(const double d[6], float *T) {
     for (int k = 0; k < 12; k++) T[k] = (float)out[k];
 }
 
+// SO(3) exponential of phi composed on the left of the rotation of T, with
+// the camera centre c kept: T = [R | -R c] -> [Exp(phi) R | -Exp(phi) R c'],
+// c' = c + dc (the T x SO(3) step).
+__device__ void tso3_step(const double dc[3], const double phi[3], float *T) {
+    const double px = phi[0], py = phi[1], pz = phi[2];
+    const double th2 = px * px + py * py + pz * pz, th = sqrt(th2);
+    double A, B;   // sin t / t, (1 - cos t) / t^2
+    if (th < 1e-4) {
+        A = 1 - th2 / 6 + th2 * th2 / 120;
+        B = 0.5 - th2 / 24 + th2 * th2 / 720;
+    } else {
+        A = sin(th) / th;
+        B = (1 - cos(th)) / th2;
+    }
+    const double K[9] = {0, -pz, py, pz, 0, -px, -py, px, 0};
+    double E[9];
+    for (int r = 0; r < 3; r++)
+        for (int c = 0; c < 3; c++) {
+            const double k2 = K[3 * r] * K[c] + K[3 * r + 1] * K[3 + c] + K[3 * r + 2] * K[6 + c];
+            E[3 * r + c] = (r == c ? 1.0 : 0.0) + A * K[3 * r + c] + B * k2;
+        }
+    double R[9], t[3];
+    for (int r = 0; r < 3; r++) {
+        for (int c = 0; c < 3; c++) R[3 * r + c] = T[4 * r + c];
+        t[r] = T[4 * r + 3];
+    }
+    double cc[3];
+    for (int k = 0; k < 3; k++) cc[k] = -(R[k] * t[0] + R[3 + k] * t[1] + R[6 + k] * t[2]) + dc[k];
+    double Rn[9];
+    for (int r = 0; r < 3; r++)
+        for (int c = 0; c < 3; c++)
+            Rn[3 * r + c] = E[3 * r] * R[c] + E[3 * r + 1] * R[3 + c] + E[3 * r + 2] * R[6 + c];
+    for (int r = 0; r < 3; r++) {
+        for (int c = 0; c < 3; c++) T[4 * r + c] = (float)Rn[3 * r + c];
+        T[4 * r + 3] = (float)(-(Rn[3 * r] * cc[0] + Rn[3 * r + 1] * cc[1] + Rn[3 * r + 2] * cc[2]));
+    }
+}
+
 // guard: the counters of the workspace whose render produced dpose, or null;
 // when that render overflowed its instance capacity the step is skipped
 // (poses, moments and step counts unchanged).
@@ -121,16 +159,29 @@ __global__ __launch_bounds__(64) void k_pose_adam(int V, float *poses, const flo
     }
     const double b1 = p.beta1, b2 = p.beta2;
     const double c1 = 1.0 - pow(b1, (double)k), c2 = 1.0 - pow(b2, (double)k);
+    const bool tso3 = p.parametrization == GSP_POSE_T_SO3;
+    double gv[6];
+    for (int e = 0; e < 6; e++) gv[e] = dpose[6 * i + e];
+    if (tso3) {   // dL/dc = -R^T dL/drho; the rotation part is unchanged
+        const float *T = poses + 12 * i;
+        double gc[3];
+        for (int k2 = 0; k2 < 3; k2++)
+            gc[k2] = -((double)T[k2] * gv[0] + (double)T[4 + k2] * gv[1] + (double)T[8 + k2] * gv[2]);
+        for (int k2 = 0; k2 < 3; k2++) gv[k2] = gc[k2];
+    }
     double delta[6];
     for (int e = 0; e < 6; e++) {
-        const double g = dpose[6 * i + e];
+        const double g = gv[e];
         const double mm = b1 * m[6 * i + e] + (1.0 - b1) * g;
         const double vv = b2 * v[6 * i + e] + (1.0 - b2) * g * g;
         m[6 * i + e] = (float)mm;
         v[6 * i + e] = (float)vv;
         delta[e] = -lr * (mm / c1) / (sqrt(vv / c2) + (double)p.eps);
     }
-    se3_retract_left(delta, poses + 12 * i);
+    if (tso3)
+        tso3_step(delta, delta + 3, poses + 12 * i);
+    else
+        se3_retract_left(delta, poses + 12 * i);
 }
 
 hipError_t launch_pose_adam(int V, float *poses, const float *dpose, float *m, float *v,

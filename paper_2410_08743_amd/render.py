@@ -301,12 +301,18 @@ def masked_l1(cams: Sequence, pred, target, alpha, grad=None, with_loss: bool = 
     return loss, grad
 
 
+PARAMETRIZATIONS = {"se3": N.GSP_POSE_SE3, "t_so3": N.GSP_POSE_T_SO3}
+
+
 def pose_adam(poses, dpose, m, v, steps, lr_start, lr_end, total_steps, beta1=0.9, beta2=0.999,
-              eps=1e-8, guard: Optional[torch.Tensor] = None):
-    """In-place tangent Adam step with left retraction on every pose; with a
-    `guard` workspace whose last render overflowed, the step is skipped."""
+              eps=1e-8, guard: Optional[torch.Tensor] = None, parametrization: str = "se3"):
+    """In-place tangent Adam step on every pose: in SE(3) with left
+    retraction (the paper's), or with parametrization="t_so3" on the camera
+    centre and the rotation separately; with a `guard` workspace whose last
+    render overflowed, the step is skipped."""
     L = N.lib()
-    prm = N.AdamParams(lr_start, lr_end, int(total_steps), beta1, beta2, eps)
+    prm = N.AdamParams(lr_start, lr_end, int(total_steps), beta1, beta2, eps,
+                       PARAMETRIZATIONS[parametrization])
     N.check(L.gsp_pose_adam(context(poses.device.index), poses.shape[0], _ptr(poses), _ptr(dpose),
                             _ptr(m), _ptr(v), _ptr(steps), ctypes.byref(prm), _ptr(guard),
                             _stream()), "gsp_pose_adam")
@@ -354,11 +360,15 @@ def render(g: GaussianParams, cams: Sequence, poses: torch.Tensor, tau: Optional
 
 def solve_poses(g: GaussianParams, cams: Sequence, targets: torch.Tensor, init_poses: torch.Tensor,
                 steps: int = 100, lr=(1e-2, 1e-4), betas=(0.9, 0.999), eps=1e-8,
-                rast: Optional[Rasterizer] = None, history: bool = False, masked: bool = False):
+                rast: Optional[Rasterizer] = None, history: bool = False, masked: bool = False,
+                parametrization: str = "se3", final_loss: bool = False):
     """Estimates the poses of len(cams) views against packed target images by
     `steps` tangent-space Adam iterations on the L1 loss (cosine learning-rate
     decay lr[0] -> lr[1]); with masked=True on the confidence-masked L1 of
-    Eq. (20)-(21) (pixels whose rendered opacity exceeds 0.99).  Forward, loss, backward (pose only) and the update
+    Eq. (20)-(21) (pixels whose rendered opacity exceeds 0.99).
+    `parametrization` is "se3" (the paper's) or "t_so3" (see pose_adam);
+    with final_loss=True the per-view loss at the final poses is returned
+    too (one more render).  Forward, loss, backward (pose only) and the update
     all run on the device without host synchronisation; the instance capacity
     is sized from the first render and the whole solve is repeated if any
     iteration overflowed it."""
@@ -394,16 +404,44 @@ def solve_poses(g: GaussianParams, cams: Sequence, targets: torch.Tensor, init_p
                 loss, _ = loss_l1(cams, images, targets, grad=dl, with_loss=history)
             rast.backward(g, cams, poses, dl, want=(), pose=True, out={"pose": dpose})
             pose_adam(poses, dpose, m, v, st, lr[0], lr[1], steps, betas[0], betas[1], eps,
-                      guard=rast.ws)
+                      guard=rast.ws, parametrization=parametrization)
             if history:
                 hist.append(loss)
+        fin = None
+        if final_loss:
+            if masked:
+                rast.forward(g, cams, poses, check=False, images=images, alphas=alpha)
+                fin, _ = masked_l1(cams, images, targets, alpha, grad=dl)
+            else:
+                rast.forward(g, cams, poses, check=False, images=images)
+                fin, _ = loss_l1(cams, images, targets, grad=dl)
         if not rast.overflowed():
+            out = (poses,)
             if history:
-                return poses, torch.cat(hist).cpu().numpy()
-            return poses
+                out += (torch.cat(hist).cpu().numpy(),)
+            if final_loss:
+                out += (fin,)
+            return out if len(out) > 1 else poses
         rast.capacity = int(rast.capacity * rast.growth) + 1024
         rast.ws = None
     raise RuntimeError("instance capacity kept overflowing during the pose solve")
+
+
+def solve_multi_hypothesis(g: GaussianParams, cam, target: torch.Tensor, inits: torch.Tensor,
+                           steps: int = 100, lr=(1e-2, 1e-4), parametrization: str = "se3",
+                           masked: bool = False, rast: Optional[Rasterizer] = None):
+    """Pose estimation of one image from H starting poses at once: the H
+    hypotheses are views of one launch (same camera, the one target image
+    shared by pointer, no copies); returns (best pose [3, 4], index of the
+    best hypothesis, final losses [H], all final poses [H, 3, 4]), best =
+    lowest final loss."""
+    H = int(inits.shape[0])
+    targets = [target.reshape(-1)] * H
+    poses, losses = solve_poses(g, [cam] * H, targets, inits.contiguous(), steps=steps, lr=lr,
+                                rast=rast, masked=masked, parametrization=parametrization,
+                                final_loss=True)
+    best = int(torch.argmin(losses).item())
+    return poses[best], best, losses, poses
 
 
 PROFILE_TIMING = 1

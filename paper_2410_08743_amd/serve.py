@@ -99,7 +99,7 @@ class PoseServer:
         self.v = torch.zeros((B, 6), dtype=torch.float32, device=self.dev)
         self.steps = torch.zeros(B, dtype=torch.int32, device=self.dev)
         self.dpose = torch.zeros((B, 6), dtype=torch.float32, device=self.dev)
-        self.adam = N.AdamParams(lr[0], lr[1], self.iters, betas[0], betas[1], eps)
+        self.adam = N.AdamParams(lr[0], lr[1], self.iters, betas[0], betas[1], eps, N.GSP_POSE_SE3)
 
     # -- sizing ------------------------------------------------------------
     @staticmethod
