@@ -89,7 +89,7 @@ def main():
     ap.add_argument("--steps", type=int, default=100)
     ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
-    ap.add_argument("--cpu-reps", type=int, default=3)
+    ap.add_argument("--cpu-reps", type=int, default=15)
     ap.add_argument("--no-serve", action="store_true", help="skip the serving measurement")
     ap.add_argument("--serve-only", action="store_true",
                     help="run only the serving measurement and print its JSON (for profiling)")
@@ -302,6 +302,7 @@ def main():
     relpose = None
     if not args.no_relpose:
         relpose = relpose_section(args, dev)
+    hypotheses = multi_hypothesis_section(g, cam, target, wl, dev)
     serving = None
     if not args.no_serve:
         serving = serving_section(args, dev, with_cpu=not args.no_cpu)
@@ -320,6 +321,7 @@ def main():
         "joint": joint,
         "tracking": track,
         "relative_pose": relpose,
+        "multi_hypothesis": hypotheses,
         "serving": serving,
         "stages": stage_report,
         "work": {"instances": M, "evaluated_pairs": neval, "blended_pairs": nblend,
@@ -330,6 +332,38 @@ def main():
                        "final_error": [round(rot_err, 4), round(trans_err, 5)]},
     }
     print(json.dumps(line), flush=True)
+
+
+def multi_hypothesis_section(g, cam, target, wl, dev):
+    """Eight starting poses of the benchmark image solved at once (100
+    steps, the hypotheses are the views of each launch), in SE(3) and in
+    T x SO(3): the given start (5 deg / 0.1 off) and seven more, 10 deg /
+    0.2 off in random directions; the best final loss picks the answer."""
+    import numpy as np
+    import torch
+
+    from paper_2410_08743_amd import render as R
+    from paper_2410_08743_amd import synthetic as S
+
+    rng = S.rng_for(1002, 9)
+    inits = [wl.init_pose.astype(np.float64)] + [S.perturb_pose(wl.pose, 10.0, 0.2, rng)
+                                                 for _ in range(7)]
+    inits = torch.tensor(np.stack(inits).astype(np.float32), device=dev)
+    out = {"hypotheses": 8, "steps": 100}
+    for param in ("se3", "t_so3"):
+        R.solve_multi_hypothesis(g, cam, target, inits, steps=10, parametrization=param)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        best, idx, losses, _ = R.solve_multi_hypothesis(g, cam, target, inits, steps=100,
+                                                        parametrization=param)
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - t0) * 1e3
+        e = S.pose_error(best.cpu().numpy(), wl.pose)
+        out[param] = {"ms": round(ms, 1), "best": idx, "final_error": [round(e[0], 4), round(e[1], 5)]}
+    print(f"[bench] multi-hypothesis (8 starts, 100 steps): se3 {out['se3']['ms']} ms, "
+          f"t_so3 {out['t_so3']['ms']} ms, errors {out['se3']['final_error']} / "
+          f"{out['t_so3']['final_error']}", file=sys.stderr, flush=True)
+    return out
 
 
 def tiny_section(args, dev):
