@@ -114,8 +114,9 @@ def main():
                     help="run warmup + timed steps only (for rocprofv3), no JSON extras")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "
-              "(the multi-GPU layout is described in DESIGN.md)", file=sys.stderr)
+        print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported: the "
+              "path runs on one GPU (how it would shard across GPUs is a design note, not code)",
+              file=sys.stderr)
         sys.exit(2)
 
     import numpy as np
