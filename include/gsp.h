@@ -288,7 +288,8 @@ size_t gsp_gaussian_adam_scratch_bytes(int64_t n);
  *   out: raw parameters of gsp_unproject_count(...) Gaussians (device; sh
  *        [n][(sh_degree+1)^2][3])
  *   scratch: device, gsp_unproject_scratch_bytes(view, stride) bytes
- * The neighbours are found by brute force (n^2 distance tests). */
+ * The neighbours are found by brute force (n^2 distance tests), so n is
+ * limited to 2^18 points (GSP_EINVAL beyond: choose a larger stride). */
 gsp_status gsp_unproject_count(const gsp_view *view, int32_t stride, int64_t *n);
 size_t gsp_unproject_scratch_bytes(const gsp_view *view, int32_t stride);
 gsp_status gsp_unproject(gsp_ctx *ctx, const gsp_view *view, const float *depth,

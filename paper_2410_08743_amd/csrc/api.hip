@@ -747,7 +747,9 @@ gsp_status gsp_unproject(gsp_ctx *ctx, const gsp_view *view, const float *depth,
     int64_t n = 0;
     s = gsp_unproject_count(view, stride, &n);
     if (s != GSP_OK) return s;
-    if (n >= (int64_t(1) << 31)) return fail(GSP_EINVAL, "too many points");
+    if (n > gsp::kMaxUnprojectPoints)
+        return fail(GSP_EINVAL, "%lld points exceed the %d the brute-force neighbour search takes; "
+                    "use a larger stride", (long long)n, gsp::kMaxUnprojectPoints);
     if (!depth || !image || !out || !scratch) return fail(GSP_EINVAL, "null argument");
     if (!out->means || !out->log_scales || !out->quats || !out->logit_opacities || !out->sh)
         return fail(GSP_EINVAL, "null parameter array");

@@ -184,6 +184,7 @@ hipError_t launch_gauss_adam(const GaussAdamK &a, float *aniso_loss, hipStream_t
 
 // relpose.hip: scene of frame t from its depth map, and the masked L1
 // (Sec. III-D, Eq. (20)-(21)).
+constexpr int kMaxUnprojectPoints = 1 << 18;   // n^2 neighbour tests: ~2 s at the limit
 struct UnprojK {
     const float *depth, *image;          // [h][w], [3][h][w] over the region of interest
     int w, h, stride, nx, ny, S, roi_x, roi_y;
