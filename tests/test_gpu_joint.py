@@ -245,3 +245,46 @@ def test_refinement_lowers_loss_and_pose_error():
     e0 = np.mean([S.pose_error(init[k], gts[k])[0] for k in range(K)])
     e1 = np.mean([S.pose_error(est[k], gts[k])[0] for k in range(K)])
     assert e1 < 0.5 * e0, (e0, e1)
+
+
+def test_joint_workload_full_size_step():
+    """The joint workload at its full size, in the launch configuration the
+    benchmark times (1M Gaussians SH 3, 4 views of 1008x756 per step): one
+    JointRefiner step; for the batch's first view, the rendered image
+    against the oracle's render, the L_RGB gradient against the oracle's
+    loss gradient of the oracle's image, and the view's pose twist gradient
+    against the oracle's backward of that loss gradient."""
+    from parity_util import f32_camera
+    wl = S.joint()
+    cam = f32_camera(wl.camera)
+    sc = wl.scene
+    gt_poses = wl.extra["gt_poses"]
+    noisy = wl.extra["noisy_poses"]
+    g_gt = R.GaussianParams.from_set(sc, DEV)
+    rast = R.Rasterizer(0)
+    order = [3, 11, 7, 16]
+    targets = []
+    for k in order:
+        t_, _ = rast.forward(g_gt, [cam], torch.tensor(gt_poses[k:k + 1], device=DEV))
+        targets.append(t_.clone().view(3, cam.height, cam.width))
+    del rast
+    raw = J.RawGaussians.from_set(sc, DEV)
+    ref = J.JointRefiner(raw, [cam] * 4, targets, torch.tensor(noisy[order], device=DEV), 10,
+                         views_per_step=4)
+    # the activated parameters the renderer receives in this step
+    act = S.GaussianSet(sc.means, ref.scales.cpu().numpy(), sc.quats,
+                        ref.opacities.cpu().numpy(), sc.sh, 3)
+    ref.step()
+    torch.cuda.synchronize()
+    pose0 = noisy[order[0]]
+    out = oracle.render(act, cam, pose0)
+    img = ref.images[0].cpu().numpy().reshape(3, cam.height, cam.width)
+    strad = out["straddle"]
+    err = np.abs(img - out["image"]).max(axis=0)
+    assert strad.mean() <= 2e-3 and float(err[~strad].max()) <= 1e-4
+    _, dl = OJ.rgb_loss(out["image"], targets[0].cpu().numpy().astype(np.float64), 0.2)
+    gpu_dl = ref.dl[0].cpu().numpy().reshape(3, cam.height, cam.width)
+    assert rel_l2(gpu_dl, dl) <= 1e-3
+    back = oracle.backward(act, cam, pose0, dl)
+    gp = ref.grads["pose"][0].cpu().numpy()
+    assert rel_l2(gp[:3], back["pose"][:3]) <= 1e-3 and rel_l2(gp[3:], back["pose"][3:]) <= 1e-3
