@@ -175,8 +175,13 @@ class JointRefiner:
                       "quats": torch.empty((n, 4), device=dev), "opacities": torch.empty(n, device=dev),
                       "sh": torch.empty((n, S, 3), device=dev),
                       "pose": torch.empty((self.V, 6), device=dev)}
-        self.images = [torch.empty(3 * c.width * c.height, device=dev) for c in self.cams[:self.V]]
-        self.dl = [torch.empty_like(im) for im in self.images]
+        # one buffer per position in a batch, large enough for every view
+        # that takes that position (views may differ in size)
+        npix = lambda c: 3 * (c.roi[2] * c.roi[3] if getattr(c, "roi", None) else c.width * c.height)
+        sizes = [max(npix(self.cams[a + j]) for a, b in self.batches if a + j < b)
+                 for j in range(self.V)]
+        self.images = [torch.empty(n, device=dev) for n in sizes]
+        self.dl = [torch.empty(n, device=dev) for n in sizes]
         self.aniso = torch.zeros(1, device=dev)
         self.loss = torch.zeros(self.V, device=dev)
         L = N.lib()
@@ -191,7 +196,8 @@ class JointRefiner:
             cap = max(cap, self.rast.instances()[0])
         self.rast.capacity = int(margin * cap) + 4096
         self.rast.ws = None
-        self.rast._ensure(self.g, N.view_array(self.cams[:self.V]))
+        for a, b in self.batches:     # room for the largest batch
+            self.rast._ensure(self.g, N.view_array(self.cams[a:b]))
         self.k = 0
 
     def step(self, with_loss: bool = False):
@@ -201,7 +207,9 @@ class JointRefiner:
         cams = self.cams[a:b]
         V = b - a
         poses = self.poses[a:b]
-        imgs, dls = self.images[:V], self.dl[:V]
+        npix = lambda c: 3 * (c.roi[2] * c.roi[3] if getattr(c, "roi", None) else c.width * c.height)
+        imgs = [self.images[j][:npix(c)] for j, c in enumerate(cams)]
+        dls = [self.dl[j][:npix(c)] for j, c in enumerate(cams)]
         self.rast.forward(self.g, cams, poses, check=False, images=imgs)
         view_losses, _ = loss_rgb(cams, imgs, self.targets[a:b], grad=dls, beta=self.hp.beta_ssim,
                                   with_loss=with_loss, scratch=self.loss_scratch)

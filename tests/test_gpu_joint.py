@@ -288,3 +288,24 @@ def test_joint_workload_full_size_step():
     back = oracle.backward(act, cam, pose0, dl)
     gp = ref.grads["pose"][0].cpu().numpy()
     assert rel_l2(gp[:3], back["pose"][:3]) <= 1e-3 and rel_l2(gp[3:], back["pose"][3:]) <= 1e-3
+
+
+def test_refiner_with_views_of_different_sizes():
+    """Batches may mix view sizes: every step renders and differentiates each
+    view at its own size (the same as a refiner of that view alone)."""
+    sc, cam, pose = random_case(73, 0, 96, 64, 800)
+    cam2 = S.Camera(64, 48, 60.0, 60.0, 32.0, 24.0)
+    g = R.GaussianParams.from_set(sc, DEV)
+    rast = R.Rasterizer(0)
+    cams = [cam, cam2, cam2, cam]
+    ps = torch.tensor(np.stack([pose] * 4), device=DEV)
+    targets = []
+    for c in cams:
+        t_, _ = rast.forward(g, [c], ps[:1])
+        targets.append(t_.clone().view(3, c.height, c.width))
+    raw = J.RawGaussians.from_set(sc, DEV)
+    ref = J.JointRefiner(raw, cams, targets, ps, 4, views_per_step=3)
+    for _ in range(4):
+        ref.step()
+    assert not ref.overflowed()
+    assert all(torch.isfinite(getattr(raw, k)).all() for k in OJ.GROUPS)
