@@ -371,7 +371,8 @@ def tiny_section(args, dev):
     """The tiny correctness workload (1000 Gaussians, SH 0, 128x128): forward,
     L1 against the target pose's render, backward to every Gaussian
     parameter and the pose, Adam -- once with one view per launch (launch
-    latency bound) and once with 32 copies of the view in one launch."""
+    latency bound) and once with 32 copies of the view in one launch, each
+    launched eagerly and as a replayed HIP graph of one step."""
     import numpy as np
     import torch
 
@@ -420,10 +421,26 @@ def tiny_section(args, dev):
         e1.record()
         torch.cuda.synchronize()
         ms = e0.elapsed_time(e1) / K
-        out[f"views_{V}"] = {"ms_per_step": round(ms, 4), "mpix_per_s": round(V * P / (ms * 1e3), 2)}
-    print(f"[bench] tiny: {out['views_1']['ms_per_step']:.3f} ms/step (1 view), "
-          f"{out['views_32']['ms_per_step']:.3f} ms/step (32 views, "
-          f"{out['views_32']['mpix_per_s']:.0f} Mpix/s)", file=sys.stderr, flush=True)
+        side = torch.cuda.Stream()
+        side.wait_stream(torch.cuda.current_stream())
+        cg = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(cg, stream=side):
+            step()
+        for _ in range(10):
+            cg.replay()
+        torch.cuda.synchronize()
+        e0.record()
+        for _ in range(K):
+            cg.replay()
+        e1.record()
+        torch.cuda.synchronize()
+        ms_g = e0.elapsed_time(e1) / K
+        out[f"views_{V}"] = {"ms_per_step": round(ms, 4), "mpix_per_s": round(V * P / (ms * 1e3), 2),
+                             "graph_ms_per_step": round(ms_g, 4)}
+    print(f"[bench] tiny: {out['views_1']['ms_per_step']:.3f} ms/step (1 view; graph "
+          f"{out['views_1']['graph_ms_per_step']:.3f}), {out['views_32']['ms_per_step']:.3f} "
+          f"ms/step (32 views, {out['views_32']['mpix_per_s']:.0f} Mpix/s; graph "
+          f"{out['views_32']['graph_ms_per_step']:.3f})", file=sys.stderr, flush=True)
     return out
 
 

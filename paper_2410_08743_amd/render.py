@@ -361,7 +361,7 @@ def render(g: GaussianParams, cams: Sequence, poses: torch.Tensor, tau: Optional
 def solve_poses(g: GaussianParams, cams: Sequence, targets: torch.Tensor, init_poses: torch.Tensor,
                 steps: int = 100, lr=(1e-2, 1e-4), betas=(0.9, 0.999), eps=1e-8,
                 rast: Optional[Rasterizer] = None, history: bool = False, masked: bool = False,
-                parametrization: str = "se3", final_loss: bool = False):
+                parametrization: str = "se3", final_loss: bool = False, graph: bool = False):
     """Estimates the poses of len(cams) views against packed target images by
     `steps` tangent-space Adam iterations on the L1 loss (cosine learning-rate
     decay lr[0] -> lr[1]); with masked=True on the confidence-masked L1 of
@@ -371,7 +371,12 @@ def solve_poses(g: GaussianParams, cams: Sequence, targets: torch.Tensor, init_p
     too (one more render).  Forward, loss, backward (pose only) and the update
     all run on the device without host synchronisation; the instance capacity
     is sized from the first render and the whole solve is repeated if any
-    iteration overflowed it."""
+    iteration overflowed it.  With graph=True one iteration is captured in a
+    HIP graph and replayed `steps` times (no per-launch host work; the Adam
+    step count and learning rate live on the device, so every replay is the
+    next iteration); history is not available then."""
+    if graph and history:
+        raise ValueError("history is not recorded by a graph-replayed solve")
     rast = rast or Rasterizer()
     V = len(cams)
     dev = init_poses.device
@@ -394,7 +399,8 @@ def solve_poses(g: GaussianParams, cams: Sequence, targets: torch.Tensor, init_p
         rast._ensure(g, N.view_array(cams))
         rast.reset_overflow()
         hist = []
-        for k in range(steps):
+
+        def iteration():
             if masked:
                 rast.forward(g, cams, poses, check=False, images=images, alphas=alpha)
                 loss, _ = masked_l1(cams, images, targets, alpha, grad=dl, with_loss=history,
@@ -405,8 +411,21 @@ def solve_poses(g: GaussianParams, cams: Sequence, targets: torch.Tensor, init_p
             rast.backward(g, cams, poses, dl, want=(), pose=True, out={"pose": dpose})
             pose_adam(poses, dpose, m, v, st, lr[0], lr[1], steps, betas[0], betas[1], eps,
                       guard=rast.ws, parametrization=parametrization)
-            if history:
-                hist.append(loss)
+            return loss
+
+        if graph:
+            side = torch.cuda.Stream(device=dev)
+            side.wait_stream(torch.cuda.current_stream(dev))
+            cg = torch.cuda.CUDAGraph()
+            with torch.cuda.graph(cg, stream=side):
+                iteration()                 # recorded, not run
+            for k in range(steps):
+                cg.replay()
+        else:
+            for k in range(steps):
+                loss = iteration()
+                if history:
+                    hist.append(loss)
         fin = None
         if final_loss:
             if masked:

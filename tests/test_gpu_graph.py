@@ -67,3 +67,21 @@ def test_graph_replays_match_eager_steps():
         # eager work between replays must not disturb the graph's buffers
         _ = (st["img"] * 2).sum().item()
     assert not st["rast"].overflowed()
+
+
+@pytest.mark.parametrize("views,masked", [(1, False), (3, False), (2, True)])
+def test_graph_replayed_solve_equals_eager_solve(views, masked):
+    wl = S.tiny()
+    cam = wl.camera
+    g = R.GaussianParams.from_set(wl.scene, DEV)
+    rast = R.Rasterizer(0)
+    tgt, _ = rast.forward(g, [cam], torch.tensor(wl.pose[None], device=DEV))
+    targets = [tgt.clone()] * views
+    rng = S.rng_for(31, 1)
+    inits = torch.tensor(np.stack([wl.init_pose] + [S.perturb_pose(wl.pose, 3.0, 0.05, rng)
+                                                    for _ in range(views - 1)]).astype(np.float32),
+                         device=DEV)
+    eager = R.solve_poses(g, [cam] * views, targets, inits, steps=30, masked=masked)
+    graphed = R.solve_poses(g, [cam] * views, targets, inits, steps=30, masked=masked, graph=True)
+    assert torch.equal(eager, graphed)
+    assert not torch.equal(eager, inits)
