@@ -79,3 +79,25 @@ def test_pose_gradient_of_crops_by_central_differences():
         assert rel_l2(got, an) <= 1e-3, (k, got, an)
         checked += 1
     assert checked >= 6
+
+
+def test_full_frame_matches_the_oracle(room):
+    """A whole 1200x680 frame of the tracking workload (the size the
+    tracking benchmark renders): image and pose gradient of the L1 loss's
+    upstream gradient against the oracle."""
+    g = R.GaussianParams.from_set(room.scene, DEV)
+    cam = f32_camera(room.camera)
+    pose = room.extra["trajectory"][60]
+    rast = R.Rasterizer(0)
+    img, _ = rast.forward(g, [cam], torch.tensor(pose[None], device=DEV))
+    ref = oracle.render(room.scene, cam, pose)
+    got = img.cpu().numpy().reshape(3, cam.height, cam.width)
+    strad = ref["straddle"]
+    err = np.abs(got - ref["image"]).max(axis=0)
+    assert strad.mean() <= 2e-3 and float(err[~strad].max()) <= 1e-4
+    W = S.upstream(760, (3, cam.height, cam.width))
+    gr = rast.backward(g, [cam], torch.tensor(pose[None], device=DEV),
+                       torch.tensor(W.ravel(), device=DEV), want=())
+    back = oracle.backward(room.scene, cam, pose, W)
+    gp = gr["pose"][0].cpu().numpy()
+    assert rel_l2(gp[:3], back["pose"][:3]) <= 1e-3 and rel_l2(gp[3:], back["pose"][3:]) <= 1e-3
