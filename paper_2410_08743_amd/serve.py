@@ -305,6 +305,43 @@ class PoseServer:
         return [results[r.rid] for r in requests]
 
 
+def serve_hypotheses(server: PoseServer, requests: Sequence[PoseRequest], clock: str = "wall"):
+    """Multi-hypothesis pose estimation through the server: a request whose
+    init_pose is [H, 3, 4] is served as H requests (one per start, sharing the
+    target tensor) in the continuous batch, and its answer is the start whose
+    final L1 is lowest (evaluated in renders of up to GSP_MAX_VIEWS results
+    per launch).  Returns (one PoseResult per request -- the chosen
+    hypothesis, completed when its last hypothesis completed -- and the index
+    of the chosen start of each request)."""
+    expanded, owner = [], []
+    for q, r in enumerate(requests):
+        inits = r.init_pose.reshape(-1, 3, 4)
+        for h in range(inits.shape[0]):
+            expanded.append(PoseRequest(r.camera, r.target, inits[h].contiguous(), r.arrival,
+                                        len(expanded)))
+            owner.append(q)
+    res = server.run(expanded, clock=clock)
+    losses = np.zeros(len(res))
+    rast = R.Rasterizer(server.device)
+    for a in range(0, len(res), N.GSP_MAX_VIEWS):
+        idx = list(range(a, min(a + N.GSP_MAX_VIEWS, len(res))))
+        cams = [expanded[k].camera for k in idx]
+        poses = torch.tensor(np.stack([res[k].pose for k in idx]), device=server.dev)
+        imgs, _ = rast.forward(server.g, cams, poses)
+        loss, _ = R.loss_l1(cams, R.split_images(imgs, cams), [expanded[k].target for k in idx])
+        losses[idx] = loss.cpu().numpy()
+    out, chosen = [], []
+    for q, r in enumerate(requests):
+        ks = [k for k, o in enumerate(owner) if o == q]
+        best = min(ks, key=lambda k: (losses[k], k))
+        done = max(res[k].completed for k in ks)
+        b = res[best]
+        out.append(PoseResult(r.rid, b.pose, r.arrival, min(res[k].admitted for k in ks), done,
+                              done - r.arrival, b.iterations, b.batch_sizes))
+        chosen.append(best - ks[0])
+    return out, chosen
+
+
 def latency_stats(results: Sequence[PoseResult]):
     lat = np.array([r.latency for r in results], dtype=np.float64)
     span = max(r.completed for r in results) - min(r.arrival for r in results)

@@ -88,3 +88,22 @@ def test_batched_solve_converges():
         e0 = S.pose_error(r.init_pose.cpu().numpy(), gt)
         e1 = S.pose_error(out.pose, gt)
         assert e1[0] < 0.5 * e0[0] and e1[1] < 0.5 * e0[1], (e0, e1)
+
+
+def test_multi_hypothesis_requests_match_the_batched_solve():
+    g, reqs = _setup(seed=541, n_req=2)
+    iters = 30
+    hyp = []
+    for k, r in enumerate(reqs):
+        rng = S.rng_for(600 + k, 1)
+        base = r.init_pose.cpu().numpy().astype(np.float64)
+        starts = np.stack([base] + [S.perturb_pose(base, 8.0, 0.2, rng) for _ in range(3)])
+        hyp.append(SV.PoseRequest(r.camera, r.target, torch.tensor(starts.astype(np.float32), device=DEV),
+                                  r.arrival, r.rid))
+    res, chosen = SV.serve_hypotheses(SV.PoseServer(g, iters=iters, max_batch=8), hyp,
+                                      clock="iterations")
+    for r, out, c in zip(hyp, res, chosen):
+        best, idx, losses, poses = R.solve_multi_hypothesis(g, r.camera, r.target, r.init_pose,
+                                                            steps=iters)
+        assert c == idx, (c, idx, losses.cpu().numpy())
+        assert np.array_equal(out.pose, best.cpu().numpy())
