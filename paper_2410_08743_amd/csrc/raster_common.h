@@ -30,7 +30,7 @@ namespace gsp {
 constexpr int kRasterThreads = 64;
 constexpr int kBatch = 64;          // list entries staged in LDS at a time
 #ifndef GSP_FWD_UNROLL
-#define GSP_FWD_UNROLL 4
+#define GSP_FWD_UNROLL 2
 #endif
 constexpr int kUnroll = GSP_FWD_UNROLL;   // entries per step of the inner loop
 
