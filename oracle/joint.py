@@ -39,7 +39,8 @@ SSIM_C2 = 0.03 ** 2
 
 
 def ssim_window(size=SSIM_SIZE, sigma=SSIM_SIGMA):
-    """Normalised 1D Gaussian window; the 2D window is its outer product."""
+    """Normalised 1D Gaussian window of the SSIM in the DSSIM term of
+    Eq. (16); the 2D window is its outer product."""
     k = np.arange(size, dtype=np.float64) - (size // 2)
     w = np.exp(-(k * k) / (2.0 * sigma * sigma))
     return w / w.sum()
@@ -86,7 +87,8 @@ def _moments(x, y, w2):
 
 
 def ssim_map(x, y):
-    """SSIM at every pixel of each channel; x, y: [C, H, W]."""
+    """SSIM at every pixel of each channel (the DSSIM term of Eq. (16));
+    x, y: [C, H, W]."""
     x = np.asarray(x, dtype=np.float64)
     y = np.asarray(y, dtype=np.float64)
     w = ssim_window()
@@ -101,7 +103,7 @@ def ssim_map(x, y):
 
 
 def dssim(x, y):
-    """(1 - mean SSIM, its gradient with respect to x)."""
+    """L_DSSIM of Eq. (16): (1 - mean SSIM, its gradient with respect to x)."""
     x = np.asarray(x, dtype=np.float64)
     y = np.asarray(y, dtype=np.float64)
     w = ssim_window()
@@ -132,7 +134,7 @@ def dssim(x, y):
 
 
 def l1(x, y):
-    """(mean |x - y|, its gradient; 0 where equal)."""
+    """L_L1 of Eq. (16): (mean |x - y|, its gradient; 0 where equal)."""
     x = np.asarray(x, dtype=np.float64)
     y = np.asarray(y, dtype=np.float64)
     return np.abs(x - y).mean(), np.sign(x - y) / x.size
@@ -171,7 +173,8 @@ def sigmoid(x):
 
 
 def means_lr(step, total_steps, lr_start, lr_end):
-    """Log-linear decay: lr_start at step 1, lr_end at step total_steps."""
+    """The means' learning rate of Sec. IV-A (exponential decay): log-linear
+    from lr_start at step 1 to lr_end at step total_steps."""
     if total_steps <= 1:
         return lr_start
     t = min(step - 1, total_steps - 1) / (total_steps - 1)
@@ -185,7 +188,8 @@ def gaussian_adam(raw, grads, m, v, step, total_steps, lr_means=(1.6e-2, 1.6e-4)
                   lr_sh_dc=2.5e-3, lr_sh_rest=2.5e-3 / 20, lr_opacity=5e-2, lr_scales=5e-3,
                   lr_quats=1e-3, beta1=0.9, beta2=0.999, eps=1e-15, aniso_r=10.0,
                   aniso_weight=1.0):
-    """One Adam step on the raw Gaussian parameters.
+    """One Adam step on the raw Gaussian parameters, for the objective
+    L = L_RGB + L_An of Eq. (15) (Sec. III-C; rates of Sec. IV-A).
 
     raw:   dict GROUPS -> arrays ([N,3], [N,3], [N,4], [N], [N,S,3])
     grads: dict of the gradients with respect to the ACTIVATED parameters

@@ -17,7 +17,7 @@ import numpy as np
 
 
 def so3_exp(phi):
-    """Rodrigues' formula."""
+    """Rodrigues' formula: the SO(3) exponential of the rotation update."""
     phi = np.asarray(phi, dtype=np.float64)
     th = np.linalg.norm(phi)
     K = np.array([[0.0, -phi[2], phi[1]], [phi[2], 0.0, -phi[0]], [-phi[1], phi[0], 0.0]])
@@ -27,7 +27,8 @@ def so3_exp(phi):
 
 
 def txso3_gradient(pose, g):
-    """(dL/dc, dL/dphi) from the left-twist gradient g = (rho, phi)."""
+    """(dL/dc, dL/dphi) from the left-twist gradient g = (rho, phi) of
+    Sec. III-B (Eq. (7)-(13)), for the T x SO(3) alternative of Sec. IV-A."""
     R = np.asarray(pose, dtype=np.float64)[:, :3]
     g = np.asarray(g, dtype=np.float64)
     return np.concatenate([-R.T @ g[:3], g[3:]])

@@ -37,8 +37,8 @@ def grid_shape(roi_w, roi_h, stride):
 
 
 def knn3_mean_distance(points, valid=None):
-    """Mean Euclidean distance of each point to its three nearest valid
-    neighbours (itself excluded), by brute force."""
+    """The scale of Sec. III-D: mean Euclidean distance of each point to its
+    three nearest valid neighbours (itself excluded), by brute force."""
     p = np.asarray(points, dtype=np.float64)
     n = p.shape[0]
     valid = np.ones(n, dtype=bool) if valid is None else np.asarray(valid, dtype=bool)
@@ -62,7 +62,8 @@ def knn3_mean_distance(points, valid=None):
 
 
 def unproject(depth, image, cam, stride, opacity=0.5):
-    """Raw Gaussian parameters (means, log_scales, quats, logit_opacities,
+    """The unprojection of Sec. III-D.  Raw Gaussian parameters (means,
+    log_scales, quats, logit_opacities,
     sh [n, 1, 3]) of the unprojected grid.  depth [h, w], image [3, h, w]
     over the camera's region of interest."""
     depth = np.asarray(depth, dtype=np.float64)
