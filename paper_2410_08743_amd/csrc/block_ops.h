@@ -10,6 +10,10 @@ namespace gsp {
 
 constexpr int kWave = 64;
 
+// Wave-wide vote on a lane predicate, straight from the compare's lane mask
+// (no round trip of the predicate through a vector register).
+__device__ __forceinline__ bool wave_any(bool p) { return __builtin_amdgcn_ballot_w64(p) != 0; }
+
 template <typename T>
 __device__ __forceinline__ T wave_sum(T v) {
 #pragma unroll
@@ -87,9 +91,12 @@ constexpr int kDppQuadXor2 = 0x4E;     // quad_perm [2,3,0,1]
 constexpr int kDppRowHalfMirror = 0x141;
 constexpr int kDppRowMirror = 0x140;
 
+// x + x[permuted lane]; every permutation used here reads a lane inside the
+// row, so bound_ctrl (zero for out-of-range sources) never applies and lets
+// the compiler fold the move into the add (v_add_f32_dpp).
 template <int CTRL>
 __device__ __forceinline__ float dpp_add(float x) {
-    return x + __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), CTRL, 0xF, 0xF, false));
+    return x + __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), CTRL, 0xF, 0xF, true));
 }
 
 // Sum over the 16 lanes of each row; every lane of the row receives it.

@@ -189,7 +189,7 @@ __global__ __launch_bounds__(kRasterThreads) __attribute__((amdgpu_waves_per_eu(
                     any |= cand[q];
                 }
                 float x0 = 0.f, x1 = 0.f, x2 = 0.f;
-                if (__any(any)) {
+                if (wave_any(any)) {
                     const float col3[3] = {t.r, t.g, ew[u].b};
                     // Per lane, dx is the same for all its pixels, so the
                     // conic and centre gradients need only the moments
@@ -201,7 +201,7 @@ __global__ __launch_bounds__(kRasterThreads) __attribute__((amdgpu_waves_per_eu(
                     // adding exact zeros.
 #pragma unroll
                     for (int q = 0; q < kPixPerLane; q++) {
-                        if (!__any(cand[q])) continue;
+                        if (!wave_any(cand[q])) continue;
                         const float dy = s.v - fy[q];
                         const float apre = splat_alpha_pre(p2[q], t.lo);
                         const float alpha = fminf(kAlphaMax, apre);

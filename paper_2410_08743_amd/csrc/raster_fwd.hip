@@ -81,7 +81,7 @@ __device__ __forceinline__ bool any_active(const float (&fy)[N]) {
     bool a = false;
 #pragma unroll
     for (int q = 0; q < N; q++) a |= fy[q] != kInactiveRow;
-    return __any(a);
+    return wave_any(a);
 }
 
 // STATS = true is a measurement variant that also counts, per pixel, the
@@ -191,7 +191,7 @@ __global__ __launch_bounds__(kRasterThreads) __attribute__((amdgpu_waves_per_eu(
                     any |= cand[q];
                 }
                 // no pixel of this part can reach 1/255: nothing to do
-                if (!__any(any)) continue;
+                if (!wave_any(any)) continue;
 #pragma unroll
                 for (int q = 0; q < kPixPerLane; q++) {
                     const float alpha = fminf(kAlphaMax, splat_alpha_pre(p2[q], et[u2].lo));
