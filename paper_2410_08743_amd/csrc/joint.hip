@@ -79,24 +79,28 @@ __global__ __launch_bounds__(kSsimThreads) void k_ssim_fwd(RgbViewsK a, double2 
     __syncthreads();
     if (t < kSsimLH * (kSsimTW / kSsimRun)) {
         const int r = t / (kSsimTW / kSsimRun), q0 = (t % (kSsimTW / kSsimRun)) * kSsimRun;
+        // the run's values and their squares and products, once each
         float xv[kSsimRun + 2 * kSsimR], yv[kSsimRun + 2 * kSsimR];
+        float xx[kSsimRun + 2 * kSsimR], yy[kSsimRun + 2 * kSsimR], xy[kSsimRun + 2 * kSsimR];
 #pragma unroll
         for (int j = 0; j < kSsimRun + 2 * kSsimR; j++) {
             xv[j] = sx[r][q0 + j];
             yv[j] = sy[r][q0 + j];
+            xx[j] = xv[j] * xv[j];
+            yy[j] = yv[j] * yv[j];
+            xy[j] = xv[j] * yv[j];
         }
 #pragma unroll
         for (int o = 0; o < kSsimRun; o++) {
             float s0 = 0.f, s1 = 0.f, s2 = 0.f, s3 = 0.f, s4 = 0.f;
 #pragma unroll
             for (int k = 0; k < kSsimTaps; k++) {
-                const float wk = a.win[k], xk = xv[o + k], yk = yv[o + k];
-                const float wx = wk * xk, wy = wk * yk;
-                s0 += wx;
-                s1 += wy;
-                s2 = fmaf(wx, xk, s2);
-                s3 = fmaf(wy, yk, s3);
-                s4 = fmaf(wx, yk, s4);
+                const float wk = a.win[k];
+                s0 = fmaf(wk, xv[o + k], s0);
+                s1 = fmaf(wk, yv[o + k], s1);
+                s2 = fmaf(wk, xx[o + k], s2);
+                s3 = fmaf(wk, yy[o + k], s3);
+                s4 = fmaf(wk, xy[o + k], s4);
             }
             hm[0][r][q0 + o] = s0;
             hm[1][r][q0 + o] = s1;
@@ -132,11 +136,12 @@ __global__ __launch_bounds__(kSsimThreads) void k_ssim_fwd(RgbViewsK a, double2 
         const float sxx = fmaf(-mx, mx, exx), syy = fmaf(-my, my, eyy), sxy = fmaf(-mx, my, exy);
         const float a1 = fmaf(2.f * mx, my, kSsimC1), a2 = fmaf(2.f, sxy, kSsimC2);
         const float b1 = fmaf(mx, mx, fmaf(my, my, kSsimC1)), b2 = sxx + syy + kSsimC2;
+        // one division: 1 / b1 = b2 inv and 1 / b2 = b1 inv
         const float inv = 1.f / (b1 * b2);
         const float S = a1 * a2 * inv;
         // dS/dmu_x, dS/dsigma_x^2, dS/dsigma_xy, then through the raw moments
-        const float ds_dmx = 2.f * my * a2 * inv - 2.f * mx * S / b1;
-        const float ds_dsxx = -S / b2;
+        const float ds_dmx = 2.f * my * a2 * inv - 2.f * mx * S * (b2 * inv);
+        const float ds_dsxx = -S * (b1 * inv);
         const float ds_dsxy = 2.f * a1 * inv;
         const float g_mean = ds_dmx - 2.f * mx * ds_dsxx - my * ds_dsxy;
         const size_t o = (size_t)gy * W + gx;
