@@ -127,8 +127,13 @@ __global__ __launch_bounds__(kWindowThreads) void k_slot_reduce(const uint32_t *
     }
 }
 
+// Two waves per SIMD: with every Gaussian gradient wanted the kernel would
+// otherwise take all 256 registers and run one wave per SIMD, exposing the
+// latency of its FP64 chains; the cap costs a few spilled registers and
+// measured 0.95 -> 0.72 ms per joint step (1M Gaussians, 4 views).  3 or 4
+// waves spill too much (1.24, 0.88 ms).
 template <int D, bool WANT_GAUSS>
-__global__ __launch_bounds__(kPoseReduceBlock) void k_preprocess_bwd(PbArgs a, ViewsK views) {
+__global__ __launch_bounds__(kPoseReduceBlock) __attribute__((amdgpu_waves_per_eu(2))) void k_preprocess_bwd(PbArgs a, ViewsK views) {
     constexpr int S = (D + 1) * (D + 1);
     __shared__ double red[kPoseReduceBlock / kWave];
     const int n = a.g.n;
@@ -172,9 +177,14 @@ __global__ __launch_bounds__(kPoseReduceBlock) void k_preprocess_bwd(PbArgs a, V
 
     // gradients summed over views
     double gmu[3] = {0, 0, 0}, gSig[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0}, gop = 0;
-    float gsh[WANT_GAUSS ? S * 3 : 1];
+    // SH gradient accumulators in LDS ([coefficient][thread], conflict-free),
+    // not registers: 3 S floats per thread would cap the kernel at one wave
+    // per SIMD
+    __shared__ float s_gsh[WANT_GAUSS ? S * 3 : 1][kPoseReduceBlock];
+    if constexpr (WANT_GAUSS) {
 #pragma unroll
-    for (int k = 0; k < (WANT_GAUSS ? S * 3 : 1); k++) gsh[k] = 0.f;
+        for (int k = 0; k < S * 3; k++) s_gsh[k][threadIdx.x] = 0.f;
+    }
 
     for (int v = 0; v < views.count; v++) {
         const ViewK &vw = views.v[v];
@@ -303,7 +313,8 @@ __global__ __launch_bounds__(kPoseReduceBlock) void k_preprocess_bwd(PbArgs a, V
 #pragma unroll
                 for (int k = 0; k < S; k++) {
                     wgt[k] = fmaf(gc, sh[3 * k + ch], wgt[k]);
-                    if constexpr (WANT_GAUSS) gsh[3 * k + ch] = fmaf(gc, Y[k], gsh[3 * k + ch]);
+                    if constexpr (WANT_GAUSS)
+                        s_gsh[3 * k + ch][threadIdx.x] = fmaf(gc, Y[k], s_gsh[3 * k + ch][threadIdx.x]);
                 }
             }
             float gdf[3];
@@ -330,19 +341,25 @@ __global__ __launch_bounds__(kPoseReduceBlock) void k_preprocess_bwd(PbArgs a, V
     }
 
     if constexpr (WANT_GAUSS) {
-        if (!valid) return;
         const gsp_grads &o = a.out;
         const bool acc = a.accumulate;
+        if (o.sh) {
+            // the block's SH gradients are one contiguous range: coalesced
+            __syncthreads();
+            const int i0 = blockIdx.x * kPoseReduceBlock;
+            const int cnt = min(kPoseReduceBlock, n - i0) * (S * 3);
+            float *dst = o.sh + (size_t)i0 * (S * 3);
+            for (int e = threadIdx.x; e < cnt; e += kPoseReduceBlock) {
+                const float gv = s_gsh[e % (S * 3)][e / (S * 3)];
+                dst[e] = (acc ? dst[e] : 0.f) + gv;
+            }
+        }
+        if (!valid) return;
         if (o.means) {
 #pragma unroll
             for (int k = 0; k < 3; k++) o.means[3 * i + k] = (acc ? o.means[3 * i + k] : 0.f) + (float)gmu[k];
         }
         if (o.opacities) o.opacities[i] = (acc ? o.opacities[i] : 0.f) + (float)gop;
-        if (o.sh) {
-#pragma unroll
-            for (int k = 0; k < S * 3; k++)
-                o.sh[(size_t)i * (S * 3) + k] = (acc ? o.sh[(size_t)i * (S * 3) + k] : 0.f) + gsh[k];
-        }
         if (o.scales || o.quats) {
             // Sigma = M M^T with M = R_q diag(s): dL/dM = 2 dL/dSigma M (dL/dSigma symmetric)
             double GM[9];
