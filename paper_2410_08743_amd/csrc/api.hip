@@ -233,6 +233,13 @@ Layout make_layout(int64_t n, int32_t sh_degree, int32_t V, const ViewsK &views,
     L.digit_tot = take((size_t)kSortBins * 4);
     L.ranges = take((size_t)L.total_tiles * 8);
     L.tile_order = take((size_t)L.total_tiles * 4);
+    // Every chunk in front of a cut holds kChunk entries, so there are at
+    // most cap / kChunk cuts and one work item per tile more than that; a
+    // cut at sorted position p < cap has record p / kChunk.
+    L.max_items = (int64_t)L.total_tiles + (int64_t)(capz / kChunk);
+    L.items = take((size_t)L.max_items * 4);
+    L.ckpt = take((capz + kChunk - 1) / kChunk * kTile * kTile * 16);
+    L.cfinal = take((size_t)pix * 12);
     L.tfinal = take((size_t)pix * 4);
     L.ncontrib = take((size_t)pix * 4);
     L.stats = take((size_t)pix * 8);

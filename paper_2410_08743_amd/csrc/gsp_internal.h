@@ -63,6 +63,24 @@ constexpr int kWindowThreads = 256;
 #endif
 constexpr int kSplitFwd = GSP_SPLIT_FWD;
 constexpr int kSplitBwd = GSP_SPLIT_BWD;
+// Backward work items: a tile's list longer than kChunk entries is cut at
+// multiples of kChunk into at most kMaxChunks chunks (the last one takes the
+// rest), each walked by its own workgroups, so that no work item is long
+// enough to run alone at the end of the launch (a 1008 x 756 view has 3024
+// tiles of some 500 entries on average, for 4096 backward workgroup slots).
+// The length is fixed, so a view is cut the same way alone or batched with
+// others.  The forward records, per pixel, the transmittance and the
+// accumulated colour at every cut, from which the backward of the chunk in
+// front of the cut starts.  The cut at position p of the sorted instances
+// has record p / kChunk: cuts are kChunk apart inside a list and more than
+// that across lists, so no two share a record, and p < cap keeps the
+// records below ceil(cap / kChunk).
+constexpr int kChunk = 256;              // a multiple of the rasterizers' 64-entry batch
+constexpr int kMaxChunks = 8;
+__host__ __device__ inline int chunks_of(int len) {
+    const int c = (len + kChunk - 1) / kChunk;
+    return c < 1 ? 1 : (c > kMaxChunks ? kMaxChunks : c);
+}
 
 // Per-view constants, computed on the host once per call.
 struct ViewK {
@@ -92,16 +110,19 @@ struct Layout {
     size_t geom, color, rect, depth, tiles, offsets, offk, wstart, pstart, blocksum, counters;
     size_t dkeys0, dkeys1, dvals0, dvals1;
     size_t keys0, keys1, vals0, vals1, hist, digit_tot, ranges, tile_order;
+    size_t items, ckpt, cfinal;   // backward work items, states at the cuts, final colours
+    int64_t max_items;
     size_t tfinal, ncontrib, stats, slots, slot_flags, grad2d, posepart;
     size_t total;
 };
 
 // Counters at the start of the counters region.
 // kCntSticky keeps the OR of every overflow since the workspace was zeroed;
-// kCntWin is the number of work windows of this call.
+// kCntWin is the number of work windows of this call; kCntItems the number of
+// backward work items.
 enum Counter : int {
     kCntMLo = 0, kCntMHi = 1, kCntOverflow = 2, kCntMEff = 3, kCntSticky = 4, kCntWin = 5,
-    kCntCount = 16
+    kCntItems = 6, kCntCount = 16
 };
 
 Layout make_layout(int64_t n, int32_t sh_degree, int32_t V, const ViewsK &views, int64_t cap);

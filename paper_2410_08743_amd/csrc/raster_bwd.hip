@@ -10,12 +10,16 @@
 //   dpower/du = -(A dx + B dy), dpower/dv = -(C dy + B dx),
 //   dpower/dA = -dx^2/2, dpower/dB = -dx dy, dpower/dC = -dy^2/2.
 //
-// MI355X design: nothing per pixel is stored by the forward beyond T_final
-// and the contributor count.  kSplit wavefronts per tile, each a strip of
-// rows, walk the tile's list back to front from the largest contributor
-// count of their pixels, recovering T_i = T_{i+1} / (1 - alpha_i) with the
-// forward's exact evaluation, and skip (per lane-parallel bound, as in the
-// forward) the entries that reach 1/255 nowhere in their rows.  Each lane
+// MI355X design: nothing per pixel is stored by the forward beyond T_final,
+// the contributor count and, for lists that are cut, the final colour and
+// (T, accumulated colour) at every cut.  The work items are (tile, chunk)
+// pairs, so that no workgroup walks more than a chunk of a list that is cut
+// (the longest lists would otherwise run alone at the end of the launch);
+// kSplit wavefronts per item, each a strip of rows, walk the chunk back to
+// front from the largest contributor count of their pixels inside it,
+// recovering T_i = T_{i+1} / (1 - alpha_i) with the forward's exact
+// evaluation, and skip (per lane-parallel bound, as in the forward) the
+// entries that reach 1/255 nowhere in their rows.  Each lane
 // sums its pixels in registers; the nine sums are reduced over the 64 lanes
 // by a reduce-scatter butterfly (v_permlane32_swap, v_permlane16_swap, then
 // DPP inside rows: about 30 VALU operations for nine values), and nine lanes
@@ -32,7 +36,11 @@ constexpr int kSplit = kSplitBwd;
 constexpr int kPixPerLane = 4 / kSplit;   // pixels per lane, one column
 
 struct BwdArgs {
-    const uint32_t *order;   // launch order of the tiles (longest lists first)
+    const uint32_t *items;   // work items tile * kMaxChunks + chunk, longest first
+    const uint32_t *counters;
+    const float4 *ckpt;
+    const float *cfinal;
+    int total_pix;
     const uint2 *ranges;
     const uint32_t *vals;
     const float4 *geom;
@@ -43,7 +51,6 @@ struct BwdArgs {
     const uint32_t *ncontrib;
     float *slots;          // [cap][kSplit][9]
     uint8_t *slot_flags;   // [cap][kSplit]: 1 where this kernel wrote the slot
-    int total_tiles;
 };
 
 constexpr uint32_t kNoSlot = 0xffffffffu;
@@ -67,8 +74,9 @@ __global__ __launch_bounds__(kRasterThreads) __attribute__((amdgpu_waves_per_eu(
     __shared__ float sL[kBatch];   // candidate limit kLog2AlphaMinLoose - lo
     int rank, part;
     part_of_block<kSplit>(blockIdx.x, rank, part);
-    if (rank >= a.total_tiles) return;
-    const int tile = (int)a.order[rank];
+    if ((uint32_t)rank >= a.counters[kCntItems]) return;
+    const uint32_t item = a.items[rank];
+    const int tile = (int)(item / kMaxChunks), chunk = (int)(item % kMaxChunks);
     const ViewK &vw = views.v[view_of_tile(views, tile)];
     const int lt = tile - vw.tile_base;
     const int tx = lt % vw.gw, ty = lt / vw.gw;
@@ -92,6 +100,17 @@ __global__ __launch_bounds__(kRasterThreads) __attribute__((amdgpu_waves_per_eu(
 
     // GS = G . S: the upstream gradient dotted with the colour behind the
     // current splat, which is all that dL/dalpha needs of S.
+    // This chunk holds list positions [clo, chi).  A pixel that composited
+    // past chi starts at chi from the state the forward recorded at that
+    // cut; the others start from their final state at their contributor
+    // count, as in an unsplit walk.
+    const uint2 rg = a.ranges[tile];
+    const int len = (int)(rg.y - rg.x);
+    const int nch = chunks_of(len);
+    const int clo = chunk * kChunk, chi = chunk == nch - 1 ? len : clo + kChunk;
+    const float4 *const ck =
+        chunk < nch - 1 ? a.ckpt + (size_t)((rg.x + (uint32_t)chi) / kChunk) * (kTile * kTile)
+                        : nullptr;
     float T[kPixPerLane], G[kPixPerLane][3], GS[kPixPerLane], fy[kPixPerLane];
     int last[kPixPerLane];
     int maxlast = 0;
@@ -108,16 +127,26 @@ __global__ __launch_bounds__(kRasterThreads) __attribute__((amdgpu_waves_per_eu(
         G[q][0] = in ? dl[pix] : 0.f;
         G[q][1] = in ? dl[(size_t)P + pix] : 0.f;
         G[q][2] = in ? dl[2 * (size_t)P + pix] : 0.f;
-        GS[q] = G[q][0] * vw.bg[0] + G[q][1] * vw.bg[1] + G[q][2] * vw.bg[2];
+        float S0 = vw.bg[0], S1 = vw.bg[1], S2 = vw.bg[2];
+        if (last[q] > chi) {   // only when this chunk ends at a cut
+            // final colour = colour in front of the cut + T_cut * colour behind it
+            const float4 c = ck[ryl * kTile + lx];
+            const size_t pf = (size_t)vw.pix_base + pix;
+            const float inv = 1.f / c.x;
+            T[q] = c.x;
+            S0 = (a.cfinal[pf] - c.y) * inv;
+            S1 = (a.cfinal[(size_t)a.total_pix + pf] - c.z) * inv;
+            S2 = (a.cfinal[2 * (size_t)a.total_pix + pf] - c.w) * inv;
+            last[q] = chi;
+        }
+        GS[q] = G[q][0] * S0 + G[q][1] * S1 + G[q][2] * S2;
         maxlast = max(maxlast, last[q]);
     }
     maxlast = wave_max(maxlast);
     const float fxl = (float)lx;
 
-    const uint2 rg = a.ranges[tile];
-    const int len = (int)(rg.y - rg.x);
     // batches of 64 entries ending at hi, walked back to front; positions
-    // below 0 are absent.  Records are gathered one batch ahead.
+    // below clo are absent.  Records are gathered one batch ahead.
     float4 g0, g1, gc;
     uint32_t gslot;
     auto gather = [&](int k) {
@@ -125,7 +154,7 @@ __global__ __launch_bounds__(kRasterThreads) __attribute__((amdgpu_waves_per_eu(
         g1 = make_float4(-1.f, 0.f, -1.f, -INFINITY);
         gc = make_float4(0.f, 0.f, 0.f, 0.f);
         gslot = kNoSlot;
-        if (k >= 0) {
+        if (k >= clo) {
             const uint32_t id = a.vals[rg.x + k];
             g0 = a.geom[2 * (size_t)id];
             g1 = a.geom[2 * (size_t)id + 1];
@@ -133,8 +162,8 @@ __global__ __launch_bounds__(kRasterThreads) __attribute__((amdgpu_waves_per_eu(
             gslot = slot_of(a, id, tx, ty);
         }
     };
-    if (maxlast > 0) gather(maxlast - kBatch + lane);
-    for (int hi = maxlast; hi > 0; hi -= kBatch) {
+    if (maxlast > clo) gather(maxlast - kBatch + lane);
+    for (int hi = maxlast; hi > clo; hi -= kBatch) {
         const int lo = hi - kBatch;
         // Stage, in list order, the entries that can reach 1/255 somewhere in
         // this part's rows; a dropped entry blends nowhere there, and its slot
@@ -159,7 +188,7 @@ __global__ __launch_bounds__(kRasterThreads) __attribute__((amdgpu_waves_per_eu(
             sL[lane] = INFINITY;
         }
         __syncthreads();
-        if (lo > 0) gather(lo - kBatch + lane);
+        if (lo > clo) gather(lo - kBatch + lane);
         for (int j0 = nkr - kBwdUnroll; j0 >= 0; j0 -= kBwdUnroll) {
             StagedA es[kBwdUnroll];
             StagedB et[kBwdUnroll];
@@ -252,7 +281,11 @@ hipError_t launch_raster_bwd(const ViewsK &views, const Layout &L, char *ws, con
                              hipStream_t s) {
     if (L.total_tiles == 0) return hipSuccess;
     BwdArgs a;
-    a.order = region<uint32_t>(ws, L.tile_order);
+    a.items = region<uint32_t>(ws, L.items);
+    a.counters = region<uint32_t>(ws, L.counters);
+    a.ckpt = region<float4>(ws, L.ckpt);
+    a.cfinal = region<float>(ws, L.cfinal);
+    a.total_pix = (int)L.total_pix;
     a.ranges = region<uint2>(ws, L.ranges);
     a.vals = vals;
     a.geom = region<float4>(ws, L.geom);
@@ -263,12 +296,13 @@ hipError_t launch_raster_bwd(const ViewsK &views, const Layout &L, char *ws, con
     a.ncontrib = region<uint32_t>(ws, L.ncontrib);
     a.slots = region<float>(ws, L.slots);
     a.slot_flags = region<uint8_t>(ws, L.slot_flags);
-    a.total_tiles = L.total_tiles;
     // Slots that no entry writes keep the flag 0 that the forward's emission
     // stored and count as zero.  The set of written slots depends only on the
     // forward's state, so repeated backwards of one forward agree on it.
-    hipLaunchKernelGGL(k_raster_bwd, dim3(raster_blocks<kSplit>(L.total_tiles)), dim3(kRasterThreads), 0, s,
-                       a, views);
+    // one workgroup per part of each possible work item; those past the
+    // item count of this call exit at once
+    hipLaunchKernelGGL(k_raster_bwd, dim3(raster_blocks<kSplit>((int)L.max_items)),
+                       dim3(kRasterThreads), 0, s, a, views);
     return hipGetLastError();
 }
 

@@ -29,6 +29,7 @@ namespace gsp {
 // and stops for its own rows.
 constexpr int kRasterThreads = 64;
 constexpr int kBatch = 64;          // list entries staged in LDS at a time
+static_assert(kChunk % kBatch == 0, "the backward's chunks start at batch boundaries");
 #ifndef GSP_FWD_UNROLL
 #define GSP_FWD_UNROLL 2
 #endif

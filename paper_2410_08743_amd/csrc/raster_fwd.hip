@@ -36,31 +36,96 @@ __global__ __launch_bounds__(256) void k_ranges(const uint32_t *keys, const uint
 
 // Launch order of the tiles: longest lists first (in buckets of 16
 // entries), so that the longest tiles do not start last and leave a tail.
-// The order only decides which workgroup takes which tile; every tile's
+// The same kernel lists the backward work items (tile, chunk), also longest
+// first by chunk length; their count goes to counters[kCntItems].  The
+// orders only decide which workgroup takes which tile or chunk; every
 // result is the same in any order.
 constexpr int kOrderBuckets = 64;
+constexpr int kOrderThreads = 1024;
+constexpr int kOrderRounds = 8;   // tiles per thread whose ranges are loaded together
 
-__global__ __launch_bounds__(1024) void k_tile_order(const uint2 *ranges, int total_tiles,
-                                                     uint32_t *order) {
-    __shared__ uint32_t cnt[kOrderBuckets], base[kOrderBuckets];
-    const int t = threadIdx.x;
-    if (t < kOrderBuckets) cnt[t] = 0;
+__host__ __device__ constexpr int order_bucket(int len) {
+    return kOrderBuckets - 1 - ((len >> 4) < kOrderBuckets - 1 ? (len >> 4) : kOrderBuckets - 1);
+}
+
+__global__ __launch_bounds__(kOrderThreads) void k_tile_order(const uint2 *ranges, int total_tiles,
+                                                             uint32_t *order, uint32_t *items,
+                                                             uint32_t *counters) {
+    // Full chunks all fall into one bucket; a wave adds its tiles' full
+    // chunks there with one atomic (same-address LDS atomics serialise).
+    constexpr int kFull = order_bucket(kChunk);
+    __shared__ uint32_t cnt[2][kOrderBuckets], base[2][kOrderBuckets];
+    const int t = threadIdx.x, lane = t & (kWave - 1);
+    if (t < kOrderBuckets) cnt[0][t] = cnt[1][t] = 0;
     __syncthreads();
-    auto bucket = [&](int tile) {
-        const uint2 r = ranges[tile];
-        return kOrderBuckets - 1 - (int)min((r.y - r.x) >> 4, (uint32_t)(kOrderBuckets - 1));
-    };
-    for (int k = t; k < total_tiles; k += 1024) atomicAdd(&cnt[bucket(k)], 1u);
-    __syncthreads();
-    if (t == 0) {
-        uint32_t acc = 0;
-        for (int b = 0; b < kOrderBuckets; b++) {
-            base[b] = acc;
-            acc += cnt[b];
+    constexpr int kStep = kOrderThreads * kOrderRounds;
+    // lengths of this thread's tiles in the round at k0 (-1 past the last tile)
+    auto load = [&](int k0, int (&len)[kOrderRounds]) {
+#pragma unroll
+        for (int r = 0; r < kOrderRounds; r++) {
+            const int k = k0 + r * kOrderThreads + t;
+            const uint2 rg = k < total_tiles ? ranges[k] : make_uint2(1u, 0u);
+            len[r] = (int)(rg.y - rg.x);
         }
+    };
+    const int wave0 = t - lane;   // first thread of this wave
+    for (int k0 = 0; k0 < total_tiles; k0 += kStep) {
+        int len[kOrderRounds];
+        load(k0, len);
+        uint32_t full = 0;   // this thread's full chunks in the round
+#pragma unroll
+        for (int r = 0; r < kOrderRounds; r++) {
+            if (k0 + r * kOrderThreads + wave0 >= total_tiles) break;   // whole wave past the end
+            if (len[r] < 0) continue;
+            const int nch = chunks_of(len[r]);
+            atomicAdd(&cnt[0][order_bucket(len[r])], 1u);
+            atomicAdd(&cnt[1][order_bucket(len[r] - (nch - 1) * kChunk)], 1u);
+            full += (uint32_t)(nch - 1);
+        }
+        const uint32_t wfull = wave_sum(full);
+        if (lane == 0 && wfull > 0) atomicAdd(&cnt[1][kFull], wfull);
     }
     __syncthreads();
-    for (int k = t; k < total_tiles; k += 1024) order[atomicAdd(&base[bucket(k)], 1u)] = (uint32_t)k;
+    if (t < 2) {
+        uint32_t acc = 0;
+        for (int b = 0; b < kOrderBuckets; b++) {
+            base[t][b] = acc;
+            acc += cnt[t][b];
+        }
+        if (t == 1) counters[kCntItems] = acc;
+    }
+    __syncthreads();
+    for (int k0 = 0; k0 < total_tiles; k0 += kStep) {
+        int len[kOrderRounds];
+        load(k0, len);
+        uint32_t full = 0;
+#pragma unroll
+        for (int r = 0; r < kOrderRounds; r++) full += len[r] >= 0 ? (uint32_t)(chunks_of(len[r]) - 1) : 0u;
+        const uint32_t wfull = wave_sum(full);
+        uint32_t wb = 0;
+        if (lane == 0 && wfull > 0) wb = atomicAdd(&base[1][kFull], wfull);
+        wb = __shfl(wb, 0, kWave);   // the wave's first full-chunk item
+        const unsigned long long below = (1ull << lane) - 1ull;
+#pragma unroll
+        for (int r = 0; r < kOrderRounds; r++) {
+            if (k0 + r * kOrderThreads + wave0 >= total_tiles) break;
+            const uint32_t k = (uint32_t)(k0 + r * kOrderThreads + t);
+            const int nch = len[r] >= 0 ? chunks_of(len[r]) : 1;
+            if (len[r] >= 0) {
+                order[atomicAdd(&base[0][order_bucket(len[r])], 1u)] = k;
+                items[atomicAdd(&base[1][order_bucket(len[r] - (nch - 1) * kChunk)], 1u)] =
+                    k * kMaxChunks + (uint32_t)(nch - 1);
+            }
+            // full chunks j of the wave's tiles, compacted by ballot so that
+            // each store covers consecutive items
+            for (int j = 0; j < kMaxChunks - 1; j++) {
+                const unsigned long long m = __ballot(j < nch - 1);
+                if (m == 0ull) break;
+                if (j < nch - 1) items[wb + (uint32_t)__popcll(m & below)] = k * kMaxChunks + (uint32_t)j;
+                wb += (uint32_t)__popcll(m);
+            }
+        }
+    }
 }
 
 struct FwdArgs {
@@ -73,6 +138,9 @@ struct FwdArgs {
     uint32_t *ncontrib;
     uint32_t *neval;    // STATS only: entries evaluated per pixel (up to the stop)
     uint32_t *nblend;   // STATS only: entries blended per pixel
+    float4 *ckpt;       // per cut and tile pixel: (T, colour in front of the cut)
+    float *cfinal;      // [3][total_pix]: final colour, for tiles with cuts
+    int total_pix;
     int total_tiles;
 };
 
@@ -140,9 +208,32 @@ __global__ __launch_bounds__(kRasterThreads) __attribute__((amdgpu_waves_per_eu(
             gc = a.color[id];
         }
     };
+    // Cuts of the list for the backward's chunks (at multiples of kChunk):
+    // at each cut the transmittance and accumulated colour of the pixels
+    // still compositing are recorded, and the pixels that blend past the
+    // first cut also store their final colour; the backward reads them only
+    // for pixels that blend past the cut that ends its chunk.
+    const int ncut = chunks_of(len) - 1;
+    int cuts_done = 0;
     gather(lane);
     for (int b0 = 0; b0 < len; b0 += kBatch) {
         if (!any_active(fy)) break;
+        if (cuts_done < ncut && b0 == (cuts_done + 1) * kChunk) {
+            // The lane index is read here, not reused from the kernel's
+            // start, so that no per-lane record address stays live through
+            // the compositing loop (it would cost the kernel a resident wave
+            // per SIMD).
+            uint32_t ln;
+            asm volatile("v_mbcnt_lo_u32_b32 %0, -1, 0\n\tv_mbcnt_hi_u32_b32 %0, -1, %0" : "=v"(ln));
+#pragma unroll
+            for (int q = 0; q < kPixPerLane; q++) {
+                const int ryl = row0 + (int)(ln >> 4) + 4 * q;
+                if (fy[q] != kInactiveRow)   // still compositing (so inside the region)
+                    a.ckpt[(size_t)((rg.x + (uint32_t)b0) / kChunk) * (kTile * kTile) +
+                           (uint32_t)(ryl * kTile) + (ln & 15)] = make_float4(T[q], cr[q], cg[q], cb[q]);
+            }
+            cuts_done++;
+        }
         // Stage the entries that can reach 1/255 somewhere in this part's
         // rows, in list order; the others cannot change any of its pixels.
         const float u = rel_coord(g0.x, g0.z, px0), v = rel_coord(g0.y, g0.w, py0);
@@ -226,9 +317,16 @@ __global__ __launch_bounds__(kRasterThreads) __attribute__((amdgpu_waves_per_eu(
         const size_t pix = (size_t)ry * vw.roi_w + rx;
         const float Tf = T[q];
         float *img = vw.img;
-        img[pix] = cr[q] + Tf * vw.bg[0];
-        img[(size_t)P + pix] = cg[q] + Tf * vw.bg[1];
-        img[2 * (size_t)P + pix] = cb[q] + Tf * vw.bg[2];
+        const float fr = cr[q] + Tf * vw.bg[0], fg = cg[q] + Tf * vw.bg[1],
+                    fb = cb[q] + Tf * vw.bg[2];
+        img[pix] = fr;
+        img[(size_t)P + pix] = fg;
+        img[2 * (size_t)P + pix] = fb;
+        if (last[q] > kChunk) {   // the backward's chunks derive the colour behind a cut from it
+            a.cfinal[vw.pix_base + pix] = fr;
+            a.cfinal[(size_t)a.total_pix + vw.pix_base + pix] = fg;
+            a.cfinal[2 * (size_t)a.total_pix + vw.pix_base + pix] = fb;
+        }
         a.tfinal[vw.pix_base + pix] = Tf;
         a.ncontrib[vw.pix_base + pix] = (uint32_t)last[q];
         if (vw.alpha) vw.alpha[pix] = 1.f - Tf;
@@ -247,8 +345,9 @@ hipError_t launch_ranges(const Layout &L, char *ws, const uint32_t *keys, hipStr
                        region<uint32_t>(ws, L.counters), ranges);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess || L.total_tiles == 0) return e;
-    hipLaunchKernelGGL(k_tile_order, dim3(1), dim3(1024), 0, s, ranges, L.total_tiles,
-                       region<uint32_t>(ws, L.tile_order));
+    hipLaunchKernelGGL(k_tile_order, dim3(1), dim3(kOrderThreads), 0, s, ranges, L.total_tiles,
+                       region<uint32_t>(ws, L.tile_order), region<uint32_t>(ws, L.items),
+                       region<uint32_t>(ws, L.counters));
     return hipGetLastError();
 }
 
@@ -265,6 +364,9 @@ hipError_t launch_raster_fwd(const ViewsK &views, const Layout &L, char *ws, con
     a.ncontrib = region<uint32_t>(ws, L.ncontrib);
     a.neval = region<uint32_t>(ws, L.stats);
     a.nblend = a.neval + L.total_pix;
+    a.ckpt = region<float4>(ws, L.ckpt);
+    a.cfinal = region<float>(ws, L.cfinal);
+    a.total_pix = (int)L.total_pix;
     a.total_tiles = L.total_tiles;
     const dim3 grid(raster_blocks<kSplit>(L.total_tiles));
     if (stats)

@@ -45,10 +45,22 @@ def _case(name):
         sc.scales[idx, (k + 1) % 3] *= np.float32(3.0)
         sc.opacities[:] = rng.uniform(0.005, 0.99, sc.n).astype(np.float32)
         return sc, cam, pose
+    if name == "sh2-deep":
+        # tile lists of 1000-1200 entries, pixels compositing past several
+        # cuts: the backward's chunks start from the forward's cut states
+        return random_case(17, 2, 64, 48, 9000, depth=(1.0, 8.0))
+    if name == "sh2-deeper":
+        # lists of ~2500 entries: more than kMaxChunks chunks' worth, so the
+        # last chunk of every tile is longer than the others
+        return random_case(17, 2, 64, 48, 20000, depth=(1.0, 8.0))
     raise KeyError(name)
 
 
-CASES = ["tiny", "sh0", "sh1-ragged", "sh2-near", "sh3-roi", "sh3-dense", "sh1-thin"]
+CASES = ["tiny", "sh0", "sh1-ragged", "sh2-near", "sh3-roi", "sh3-dense", "sh1-thin", "sh2-deep",
+         "sh2-deeper"]
+# chunk length of the backward's work items
+CHUNK = 256
+MAX_CHUNKS = 8
 
 
 def _gpu(sc, cams, poses, up=None, cap=0, want=("means", "scales", "quats", "opacities", "sh")):
@@ -64,6 +76,11 @@ def _gpu(sc, cams, poses, up=None, cap=0, want=("means", "scales", "quats", "opa
         out.update({k: v.cpu().numpy() for k, v in gr.items()})
     torch.cuda.synchronize()
     return out
+
+
+def _tiles(cam):
+    gw, gh = oracle.tiles_of(cam)
+    return range(gw * gh)
 
 
 def _upstream(seed, cam):
@@ -195,6 +212,23 @@ def test_backward_parity(name):
         assert v <= 1e-3, f"{k}: relative L2 {v:.2e}"
 
 
+@pytest.mark.parametrize("name", ["sh2-deep", "sh2-deeper"])
+def test_long_lists_are_cut(name):
+    """The deep cases exercise what they are for: lists longer than a chunk
+    (and, for the deeper one, than kMaxChunks chunks), with pixels that
+    composite past a cut."""
+    sc, cam, pose = _case(name)
+    ref = oracle.preprocess(sc, cam, pose)
+    gw, gh = oracle.tiles_of(cam)
+    rkeys, _ = oracle.bin_sort([ref], [(gw, gh)])
+    ln = np.diff(oracle.tile_ranges(rkeys, gw * gh), axis=1).ravel()
+    assert (ln > CHUNK).all()
+    if name == "sh2-deeper":
+        assert (ln > MAX_CHUNKS * CHUNK).all()
+    nc = oracle.render(sc, cam, pose)["n_contrib"]
+    assert (nc > 2 * CHUNK).mean() > 0.2   # past two cuts
+
+
 def test_multiview_batch_equals_single_views():
     sc, cam0, pose0 = random_case(31, 3, 96, 64, 800)
     cam1 = f32_camera(S.Camera(80, 48, 75.0, 70.0, 40.5, 23.75, roi=(16, 0, 50, 48)))
@@ -213,6 +247,39 @@ def test_multiview_batch_equals_single_views():
             sums[key] = sums[key] + one[key].astype(np.float64)
     for key in sums:
         assert rel_l2(both[key], sums[key]) <= 1e-6
+
+
+def test_batched_views_with_and_without_long_lists():
+    """One launch holding a view with millions of instances (lists of
+    thousands of entries, cut into chunks) and a small one gives each view
+    the image and pose gradient it gets alone, bit for bit."""
+    wl = S.joint()
+    big = wl.camera
+    small = S.Camera(1008, 756, 815.0, 815.0, 504.0, 378.0, roi=(400, 304, 160, 128))
+    cams = [big, small]
+    poses = [wl.extra["noisy_poses"][0], wl.extra["noisy_poses"][3]]
+    g = R.GaussianParams.from_set(wl.scene, DEV)
+    ups = [_upstream(60 + k, c) for k, c in enumerate(cams)]
+
+    def run(cs, ps, us):
+        P = torch.tensor(np.stack(ps), device=DEV, dtype=torch.float32)
+        rast = R.Rasterizer(0)
+        img, _ = rast.forward(g, cs, P)
+        M, ovf = rast.instances()
+        assert not ovf
+        dl = torch.tensor(np.concatenate([u.ravel() for u in us]), device=DEV)
+        gr = rast.backward(g, cs, P, dl, want=(), pose=True)
+        torch.cuda.synchronize()
+        return [t.cpu().numpy() for t in R.split_images(img, cs)], gr["pose"].cpu().numpy(), M
+
+    imgs, pose, _ = run(cams, poses, ups)
+    Ms = []
+    for k in range(2):
+        i1, p1, M1 = run([cams[k]], [poses[k]], [ups[k]])
+        Ms.append(M1)
+        assert np.array_equal(imgs[k], i1[0])
+        assert np.array_equal(pose[k], p1[0])
+    assert Ms[0] > 1000 * len(_tiles(big)) and Ms[1] < Ms[0] // 10
 
 
 def test_roi_equals_full_image_crop():
