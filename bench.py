@@ -52,8 +52,8 @@ PEAK_FP32_TFLOPS = 78.6
 FWD_FLOPS_EVAL, FWD_FLOPS_BLEND = 19, 7
 BWD_FLOPS_EVAL, BWD_FLOPS_BLEND = 16, 49
 KERNEL_SOURCES = {
-    "raster_fwd": ["raster_fwd.hip", "raster_common.h"],
-    "raster_bwd": ["raster_bwd.hip", "raster_common.h"],
+    "raster_fwd": ["raster_fwd.hip", "raster_common.h", "gsp_internal.h"],
+    "raster_bwd": ["raster_bwd.hip", "raster_common.h", "gsp_internal.h"],
     "preprocess": ["preprocess.hip"],
     "depth_sort": ["sort.hip"],
     "tile_sort": ["sort.hip"],

@@ -67,16 +67,22 @@ constexpr int kSplitBwd = GSP_SPLIT_BWD;
 // multiples of kChunk into at most kMaxChunks chunks (the last one takes the
 // rest), each walked by its own workgroups, so that no work item is long
 // enough to run alone at the end of the launch (a 1008 x 756 view has 3024
-// tiles of some 500 entries on average, for 4096 backward workgroup slots).
-// The length is fixed, so a view is cut the same way alone or batched with
-// others.  The forward records, per pixel, the transmittance and the
-// accumulated colour at every cut, from which the backward of the chunk in
-// front of the cut starts.  The cut at position p of the sorted instances
-// has record p / kChunk: cuts are kChunk apart inside a list and more than
-// that across lists, so no two share a record, and p < cap keeps the
-// records below ceil(cap / kChunk).
-constexpr int kChunk = 256;              // a multiple of the rasterizers' 64-entry batch
-constexpr int kMaxChunks = 8;
+// tiles of some 500 entries on average, for 4096 backward workgroup slots;
+// 128 measured best among 64 .. 384).  The length is fixed, so a view is cut
+// the same way alone or batched with others.  The forward records, per
+// pixel, the transmittance and the accumulated colour at every cut, from
+// which the backward of the chunk in front of the cut starts.  The cut at
+// position p of the sorted instances has record p / kChunk: cuts are kChunk
+// apart inside a list and more than that across lists, so no two share a
+// record, and p < cap keeps the records below ceil(cap / kChunk).
+#ifndef GSP_CHUNK
+#define GSP_CHUNK 128
+#endif
+constexpr int kChunk = GSP_CHUNK;        // a multiple of the rasterizers' 64-entry batch
+#ifndef GSP_MAX_CHUNKS
+#define GSP_MAX_CHUNKS 16
+#endif
+constexpr int kMaxChunks = GSP_MAX_CHUNKS;
 __host__ __device__ inline int chunks_of(int len) {
     const int c = (len + kChunk - 1) / kChunk;
     return c < 1 ? 1 : (c > kMaxChunks ? kMaxChunks : c);
