@@ -15,8 +15,9 @@
 // (T, accumulated colour) at every cut.  The work items are (tile, chunk)
 // pairs, so that no workgroup walks more than a chunk of a list that is cut
 // (the longest lists would otherwise run alone at the end of the launch);
-// kSplit wavefronts per item, each a strip of rows, walk the chunk back to
-// front from the largest contributor count of their pixels inside it,
+// kSplit wavefronts per item (one by default, the whole tile), each a strip
+// of rows, walk the chunk back to front from the largest contributor count
+// of their pixels inside it,
 // recovering T_i = T_{i+1} / (1 - alpha_i) with the forward's exact
 // evaluation, and skip (per lane-parallel bound, as in the forward) the
 // entries that reach 1/255 nowhere in their rows.  Each lane
@@ -56,7 +57,7 @@ struct BwdArgs {
 constexpr uint32_t kNoSlot = 0xffffffffu;
 
 #ifndef GSP_BWD_UNROLL
-#define GSP_BWD_UNROLL 4
+#define GSP_BWD_UNROLL 2
 #endif
 constexpr int kBwdUnroll = GSP_BWD_UNROLL;   // entries whose LDS records are read ahead
 
@@ -67,7 +68,10 @@ __device__ __forceinline__ uint32_t slot_of(const BwdArgs &a, uint32_t id, int t
     return a.offsets[id] + (uint32_t)((ty - y0) * (x1 - x0) + (tx - x0));
 }
 
-__global__ __launch_bounds__(kRasterThreads) __attribute__((amdgpu_waves_per_eu(4))) void k_raster_bwd(BwdArgs a, ViewsK views) {
+#ifndef GSP_BWD_WAVES
+#define GSP_BWD_WAVES 4
+#endif
+__global__ __launch_bounds__(kRasterThreads) __attribute__((amdgpu_waves_per_eu(GSP_BWD_WAVES))) void k_raster_bwd(BwdArgs a, ViewsK views) {
     __shared__ StagedA sA[kBatch];
     __shared__ StagedB sB[kBatch];
     __shared__ StagedC sC[kBatch];
