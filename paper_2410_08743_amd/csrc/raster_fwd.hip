@@ -59,7 +59,7 @@ __global__ __launch_bounds__(kOrderThreads) void k_tile_order(const uint2 *range
     if (t < kOrderBuckets) cnt[0][t] = cnt[1][t] = 0;
     __syncthreads();
     constexpr int kStep = kOrderThreads * kOrderRounds;
-    // lengths of this thread's tiles in the round at k0 (-1 past the last tile)
+    // lengths of this thread's tiles in the group starting at k0 (-1 past the last tile)
     auto load = [&](int k0, int (&len)[kOrderRounds]) {
 #pragma unroll
         for (int r = 0; r < kOrderRounds; r++) {
