@@ -51,14 +51,16 @@ FIT_HYPER = JointHyper(lr_means=(1.6e-4, 1.6e-6))
 
 
 def relative_pose(cam, image_t: torch.Tensor, depth_t: torch.Tensor, image_t1: torch.Tensor,
-                  stride: int = 4, fit_steps: int = 100, pose_steps: int = 100,
-                  lr=(1e-2, 1e-4), hp: Optional[JointHyper] = None, init=None,
+                  stride: int = 4, fit_steps: int = 100, pose_steps: int = 200,
+                  lr=(1e-3, 1e-4), hp: Optional[JointHyper] = None, init=None,
                   opacity: float = 0.5):
     """(pose of frame t+1 relative to frame t [3, 4], fitted raw scene of
     frame t).  Frame t's camera is the world frame.  The fit of frame t's
-    scene keeps the means nearly in place (FIT_HYPER: 1.6e-4 -> 1.6e-6) so
-    that the geometry stays the depth map's; the pose solve runs on the
-    masked L1 with the camera rate of Sec. IV (1e-2 -> 1e-4)."""
+    scene (100 steps, Sec. IV) keeps the means nearly in place (FIT_HYPER:
+    1.6e-4 -> 1.6e-6) so that the geometry stays the depth map's; the pose
+    solve runs on the masked L1 for 200 steps at a learning rate decaying
+    from 1e-3 to 1e-4 on a cosine schedule, the settings Sec. IV gives for
+    the relative pose between consecutive frames."""
     dev = image_t.device
     hp = hp or FIT_HYPER
     raw = unproject(cam, depth_t, image_t, stride, opacity=opacity)

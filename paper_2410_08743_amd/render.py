@@ -134,7 +134,10 @@ class Rasterizer:
         self.capacity = int(capacity)
         self.growth = float(growth)
         self.ws = None
-        self._key = None
+        # incremented by every forward: an autograd context remembers the
+        # generation of its forward and refuses to back-propagate once the
+        # workspace holds another forward's state
+        self.generation = 0
 
     # -- workspace ---------------------------------------------------------
     def _ws_bytes(self, n, degree, views, cap):
@@ -204,7 +207,7 @@ class Rasterizer:
                 break
             self.capacity = int(m * self.growth) + 1024
             self.ws = None       # reallocated (zeroed) at the larger size
-        self._key = (g.n, g.sh_degree, tuple(pixel_counts(cams)))
+        self.generation += 1
         return images, al
 
     def backward(self, g: GaussianParams, cams: Sequence, poses: torch.Tensor,
@@ -324,13 +327,18 @@ class _RenderFn(torch.autograd.Function):
         g = GaussianParams(means.contiguous(), scales.contiguous(), quats.contiguous(),
                            opacities.contiguous(), sh.contiguous(), sh_degree)
         images, _ = rast.forward(g, cams, poses.detach(), check=check)
-        ctx.g, ctx.cams, ctx.rast = g, cams, rast
+        ctx.g, ctx.cams, ctx.rast, ctx.generation = g, cams, rast, rast.generation
         ctx.save_for_backward(poses)
         return images
 
     @staticmethod
     def backward(ctx, dl):
         (poses,) = ctx.saved_tensors
+        if ctx.rast.generation != ctx.generation:
+            raise RuntimeError(
+                "the Rasterizer rendered again after this forward, so its workspace no longer "
+                "holds this forward's state; give each render whose backward is still pending "
+                "its own Rasterizer")
         names = ("means", "scales", "quats", "opacities", "sh")
         want = tuple(k for k, need in zip(names, ctx.needs_input_grad[:5]) if need)
         need_pose = ctx.needs_input_grad[5]

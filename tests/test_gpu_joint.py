@@ -20,7 +20,7 @@ from paper_2410_08743_amd import joint as J
 from paper_2410_08743_amd import render as R
 from paper_2410_08743_amd import synthetic as S
 
-from parity_util import rel_l2, random_case
+from parity_util import assert_grad_close, rel_l2, random_case
 
 pytestmark = pytest.mark.gpu
 DEV = "cuda:0"
@@ -203,9 +203,14 @@ def test_refinement_step_in_situ_matches_oracle():
     _, dl = OJ.rgb_loss(img, target.cpu().numpy().astype(np.float64), 0.2)
     gpu_dl = ref.dl[0].cpu().numpy().reshape(3, cam.height, cam.width)
     assert rel_l2(gpu_dl, dl) <= 1e-3
-    back = oracle.backward(act, cam, pose, dl)
+    # the rasterizer's backward judged alone: the oracle's backward of the
+    # very image gradient the GPU's loss produced
+    back = oracle.backward(act, cam, pose, gpu_dl)
     for k in ("means", "scales", "quats", "opacities", "sh"):
-        assert rel_l2(ref.grads[k].cpu().numpy(), back[k]) <= 2e-3, k
+        assert_grad_close(ref.grads[k].cpu().numpy(), back[k], k)
+    gp = ref.grads["pose"][0].cpu().numpy()
+    assert_grad_close(gp[:3], back["pose"][:3], "rho")
+    assert_grad_close(gp[3:], back["pose"][3:], "phi")
     gg = {k: ref.grads[k].cpu().numpy() for k in ("means", "scales", "quats", "opacities", "sh")}
     zero = {k: np.zeros_like(a) for k, a in raw0.items()}
     new, _, _, _ = OJ.gaussian_adam(raw0, gg, zero, zero, 1, 10)
@@ -250,10 +255,12 @@ def test_refinement_lowers_loss_and_pose_error():
 def test_joint_workload_full_size_step():
     """The joint workload at its full size, in the launch configuration the
     benchmark times (1M Gaussians SH 3, 4 views of 1008x756 per step): one
-    JointRefiner step; for the batch's first view, the rendered image
-    against the oracle's render, the L_RGB gradient against the oracle's
-    loss gradient of the oracle's image, and the view's pose twist gradient
-    against the oracle's backward of that loss gradient."""
+    JointRefiner step.  For the batch's first view, the rendered image
+    against the oracle's render and the L_RGB gradient against the oracle's
+    loss gradient of the oracle's image; for all four views, each view's
+    pose twist gradient and the Gaussian gradients summed over the views
+    (Eq. (14)) against the oracle's backward of the image gradient the GPU's
+    loss produced for that view (the rasterizer judged alone)."""
     from parity_util import f32_camera
     wl = S.joint()
     cam = f32_camera(wl.camera)
@@ -285,9 +292,25 @@ def test_joint_workload_full_size_step():
     _, dl = OJ.rgb_loss(out["image"], targets[0].cpu().numpy().astype(np.float64), 0.2)
     gpu_dl = ref.dl[0].cpu().numpy().reshape(3, cam.height, cam.width)
     assert rel_l2(gpu_dl, dl) <= 1e-3
-    back = oracle.backward(act, cam, pose0, dl)
-    gp = ref.grads["pose"][0].cpu().numpy()
-    assert rel_l2(gp[:3], back["pose"][:3]) <= 1e-3 and rel_l2(gp[3:], back["pose"][3:]) <= 1e-3
+    del out
+    names = ("means", "scales", "quats", "opacities", "sh")
+    total = None
+    for j, k in enumerate(order):
+        dl_j = ref.dl[j].cpu().numpy().reshape(3, cam.height, cam.width)
+        back = oracle.backward(act, cam, noisy[k], dl_j)
+        print(f"view {j} (pose {k}): oracle backward done", flush=True)
+        gp = ref.grads["pose"][j].cpu().numpy()
+        assert_grad_close(gp[:3], back["pose"][:3], f"view {j} rho")
+        assert_grad_close(gp[3:], back["pose"][3:], f"view {j} phi")
+        if total is None:
+            total = {n: back[n] for n in names}
+        else:
+            for n in names:
+                total[n] += back[n]
+        del back
+    for n in names:
+        r, e = assert_grad_close(ref.grads[n].cpu().numpy(), total[n], n)
+        print(f"{n}: relative L2 {r:.2e}, max element {e:.2e}")
 
 
 def test_refiner_with_views_of_different_sizes():

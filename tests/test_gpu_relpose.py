@@ -82,13 +82,15 @@ def test_masked_l1_views_are_independent():
 
 
 def test_relative_pose_between_room_frames():
-    """Frames 60 and 62 of the room trajectory (a clear view of the room),
-    frame 60's depth map from the expected-depth render of the scene."""
+    """Consecutive frames 60 and 61 of the room trajectory (a clear view of
+    the room), frame 60's depth map from the expected-depth render of the
+    scene; the solve at the settings of Sec. IV (200 masked-L1 steps,
+    1e-3 -> 1e-4)."""
     wl = S.room(n=150_000, n_frames=63)
     cam = S.Camera(320, 180, 160.0, 160.0, 160.0, 90.0)
     g = R.GaussianParams.from_set(wl.scene, DEV)
     traj = wl.extra["trajectory"]
-    P0, P1 = traj[60].astype(np.float64), traj[62].astype(np.float64)
+    P0, P1 = traj[60].astype(np.float64), traj[61].astype(np.float64)
     rast = R.Rasterizer(0)
     t0 = torch.tensor(P0[None].astype(np.float32), device=DEV)
     i0, _ = rast.forward(g, [cam], t0)
@@ -98,7 +100,7 @@ def test_relative_pose_between_room_frames():
     gz = R.GaussianParams.from_set(S.depth_coloured(wl.scene, P0), DEV)
     dimg, al = R.Rasterizer(0).forward(gz, [cam], t0, alphas=True)
     depth = (dimg.view(3, 180, 320)[0] / al.view(180, 320).clamp_min(1e-6)).contiguous()
-    rel, raw = RP.relative_pose(cam, i0, depth, i1, stride=2, fit_steps=100, pose_steps=150)
+    rel, raw = RP.relative_pose(cam, i0, depth, i1, stride=2)
     # ground truth: frame t+1's world->camera composed with frame t's camera->world
     H0 = np.vstack([P0, [0, 0, 0, 1]])
     H1 = np.vstack([P1, [0, 0, 0, 1]])

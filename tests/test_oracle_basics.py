@@ -157,6 +157,69 @@ def test_l1_definition():
     assert np.all(grad[1::3][(a - b)[1::3] == 0] == 0)
 
 
+def _stack_at_pixel(opacities):
+    """Gaussians one behind the other on the optical axis of a 16 x 16
+    camera whose pixel (8, 8) they hit dead centre (power = 0 there, so
+    alpha = min(0.99, o) exactly), front to back in the given order."""
+    from paper_2410_08743_amd import synthetic as S
+    n = len(opacities)
+    means = np.zeros((n, 3), np.float32)
+    means[:, 2] = 1.0 + 0.25 * np.arange(n)
+    sc = S.GaussianSet(means, np.full((n, 3), 0.05, np.float32),
+                       np.tile(np.float32([1, 0, 0, 0]), (n, 1)),
+                       np.asarray(opacities, np.float32), np.zeros((n, 1, 3), np.float32), 0)
+    cam = S.Camera(16, 16, 16.0, 16.0, 8.5, 8.5)
+    pose = np.concatenate([np.eye(3), np.zeros((3, 1))], 1)
+    return sc, cam, pose
+
+
+# (front-to-back opacities, the accumulated opacity sum_i alpha_i T_i of the
+# centre pixel worked out by hand, the mask of Eq. (20) for it)
+_MASK_CASES = [
+    ([0.5], 0.5, 0),
+    # one splat clamped at alpha = 0.99: the sum is exactly 0.99, which is not
+    # above the threshold (a ">=" reading would set the mask)
+    ([0.99], 0.99, 0),
+    # 0.99 in front, then alpha = 0.01 (float32) behind: 0.99 + 0.01 a2 > 0.99
+    ([0.99, 0.01], 0.99 + 0.01 * float(np.float32(0.01)), 1),
+    # six and seven halvings: 63/64 (below) and 127/128 (above), exact
+    ([0.5] * 6, 63 / 64, 0),
+    ([0.5] * 7, 127 / 128, 1),
+]
+
+
+def test_masked_l1_mask_at_the_threshold():
+    """Eq. (20)-(21) on hand-computed pixels around the 0.99 threshold.  The
+    accumulated opacity is read from the compositing trace itself (the sum of
+    the blended weights alpha_i T_i, the quantity Eq. (20) thresholds), and
+    the masked L1 is checked on residuals whose masked sum is known."""
+    T_final, weights = [], []
+    for opac, acc, _ in _MASK_CASES:
+        sc, cam, pose = _stack_at_pixel(opac)
+        tr = oracle.pixel_trace(sc, cam, pose, 8, 8)
+        bl = tr[tr["blended"] == 1]
+        assert len(bl) == len(opac)
+        w = float(np.sum(bl["alpha"] * bl["T_before"]))
+        assert abs(w - acc) <= 1e-15, (opac, w, acc)
+        Tf = oracle.render(sc, cam, pose)["T_final"][8, 8]
+        assert abs((1.0 - Tf) - w) <= 1e-15
+        T_final.append(Tf)
+        weights.append(w)
+    assert weights[1] == 0.99      # exactly at the threshold
+    mask = np.array([m for _, _, m in _MASK_CASES])
+    # residuals r = a - b per pixel and channel, sum of |r| over the masked
+    # pixels (2 and 4): |-0.5| + 0.25 + 0 + 2 + |-0.125| + 1 = 3.875
+    r = np.array([[1.0, -0.5, -0.5, 3.0, 2.0],
+                  [-2.0, 0.25, 0.25, 1.0, -0.125],
+                  [0.5, 4.0, 0.0, -1.0, 1.0]])
+    b = np.arange(15, dtype=np.float64).reshape(3, 5) / 8
+    val, grad = oracle.masked_l1(b + r, b, np.array(T_final))
+    assert val == 3.875
+    assert np.array_equal(grad, np.sign(r) * mask[None])
+    assert np.array_equal(grad[:, 0], np.zeros(3)) and np.array_equal(grad[:, 1], np.zeros(3))
+    assert np.array_equal(grad[:, 2], [-1.0, 1.0, 0.0])
+
+
 def test_masked_l1_definition():
     rng = np.random.default_rng(11)
     h, w = 20, 30
