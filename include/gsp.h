@@ -191,6 +191,23 @@ gsp_status gsp_loss_l1(gsp_ctx *ctx, int32_t V, const gsp_view *views, const flo
                        void *scratch, void *stream);
 size_t gsp_loss_l1_scratch_bytes(int32_t V, const gsp_view *views);
 
+/* gsp_loss_l1 for callers that cannot allocate device memory (code under HIP
+ * graph capture, tight serving loops, harnesses that forbid allocation): the
+ * same computation and results, bit for bit, without the scratch argument.
+ * The per-block partial sums of the losses go to a fixed array inside the
+ * library (GSP_NOALLOC_SCRATCH_BYTES per GPU, held by each GPU the library
+ * runs on until the process ends), so with `loss` non-NULL the views of a
+ * call may total at most 2^15 blocks of 4096 values (134,217,728 values, e.g.
+ * 32 views of 2048 x 2048); larger calls return GSP_EINVAL before anything is
+ * enqueued (without `loss` there is no limit).  Every call on a GPU shares
+ * that GPU's array: calls that overlap on one GPU (other streams, threads or
+ * contexts) race on it and must be serialised by the caller.  The call
+ * allocates nothing. */
+#define GSP_NOALLOC_SCRATCH_BYTES (256 * 1024)
+gsp_status gsp_loss_l1_noalloc(gsp_ctx *ctx, int32_t V, const gsp_view *views,
+                               const float *const *pred, const float *const *target,
+                               float *const *grad, float *loss, void *stream);
+
 /* One tangent-space Adam step per view (Sec. III-B: pose T = Exp(tau) with
  * the update retracted on the left): for each v, steps[v] += 1,
  * m, v moments updated with dpose[v], delta = -lr mhat / (sqrt(vhat) + eps),

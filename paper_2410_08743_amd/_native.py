@@ -22,7 +22,7 @@ EXPORTS = (
     "gsp_profile_enable", "gsp_profile_read", "gsp_loss_rgb", "gsp_loss_rgb_scratch_bytes",
     "gsp_gaussian_adam", "gsp_gaussian_adam_scratch_bytes", "gsp_unproject_count",
     "gsp_unproject_scratch_bytes", "gsp_unproject", "gsp_loss_masked_l1",
-    "gsp_loss_masked_l1_scratch_bytes",
+    "gsp_loss_masked_l1_scratch_bytes", "gsp_loss_l1_noalloc",
 )
 
 
@@ -101,6 +101,7 @@ def lib():
         "gsp_instances": ([P, P, P, ctypes.POINTER(I64), ctypes.POINTER(I32)], I32),
         "gsp_loss_l1": ([P, I32, P, P, P, P, P, P, P], I32),
         "gsp_loss_l1_scratch_bytes": ([I32, P], SZ),
+        "gsp_loss_l1_noalloc": ([P, I32, P, P, P, P, P, P], I32),
         "gsp_pose_adam": ([P, I32, P, P, P, P, P, P, P, P], I32),
         "gsp_inspect": ([P, P, I32, P, P, SZ, I64, ctypes.c_char_p, ctypes.POINTER(P),
                          ctypes.POINTER(I64)], I32),

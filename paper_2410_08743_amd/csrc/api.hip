@@ -28,6 +28,7 @@ struct StageSum {
 
 struct gsp_ctx {
     int device;
+    void *noalloc_scratch = nullptr;   // device address of the library's fixed L1 scratch
     bool profiling = false;   // stage timing
     bool stats = false;       // per-pixel work counters in the forward
     std::vector<StageRec> pending;
@@ -285,9 +286,13 @@ gsp_status gsp_create(int device, gsp_ctx **out) {
     if (std::strncmp(prop.gcnArchName, "gfx950", 6) != 0)
         return fail(GSP_EUNSUPPORTED, "device %d is %s; this library is built for gfx950", device,
                     prop.gcnArchName);
+    void *scratch = nullptr;
+    e = gsp::noalloc_scratch_init(device, &scratch);
+    if (e != hipSuccess) return hip_fail(e, "hipGetSymbolAddress of the fixed scratch");
     gsp_ctx *ctx = new (std::nothrow) gsp_ctx;
     if (!ctx) return fail(GSP_ENOMEM, "out of host memory");
     ctx->device = device;
+    ctx->noalloc_scratch = scratch;
     *out = ctx;
     return GSP_OK;
 }
@@ -534,6 +539,44 @@ gsp_status gsp_loss_l1(gsp_ctx *ctx, int32_t V, const gsp_view *views, const flo
     }
     hipStream_t st = static_cast<hipStream_t>(stream);
     hipError_t e = stage(ctx, "loss_l1", st, [&] { return gsp::launch_loss_l1(lv, loss, scratch, st); });
+    if (e != hipSuccess) return hip_fail(e, "loss");
+    return GSP_OK;
+}
+
+gsp_status gsp_loss_l1_noalloc(gsp_ctx *ctx, int32_t V, const gsp_view *views,
+                               const float *const *pred, const float *const *target,
+                               float *const *grad, float *loss, void *stream) {
+    gsp_status s = check_device(ctx);
+    if (s != GSP_OK) return s;
+    if (!ctx->noalloc_scratch) return fail(GSP_EHIP, "fixed scratch of this device not set up");
+    gsp::ViewsK vk;
+    int64_t total_pix = 0;
+    s = make_views(V, views, &vk, &total_pix);
+    if (s != GSP_OK) return s;
+    if (!pred || !target || !grad) return fail(GSP_EINVAL, "null pointer array");
+    gsp::LossViewsK lv;
+    std::memset(&lv, 0, sizeof lv);
+    lv.V = V;
+    lv.blk_base[0] = 0;
+    for (int v = 0; v < V; v++) {
+        if (!pred[v] || !target[v] || !grad[v])
+            return fail(GSP_EINVAL, "null pred, target or grad of view %d", v);
+        lv.pred[v] = pred[v];
+        lv.target[v] = target[v];
+        lv.grad[v] = grad[v];
+        lv.count[v] = 3 * (int64_t)views[v].roi_w * views[v].roi_h;
+        lv.blk_base[v + 1] = lv.blk_base[v] + gsp::loss_blocks(lv.count[v]);
+    }
+    const size_t need = (size_t)lv.blk_base[V] * sizeof(double);
+    if (loss && need > gsp::kNoAllocScratchBytes)
+        return fail(GSP_EINVAL,
+                    "%lld loss blocks need %zu bytes of partial sums, more than the %zu of the "
+                    "fixed scratch (at most %zu values over the views of a call)",
+                    (long long)lv.blk_base[V], need, gsp::kNoAllocScratchBytes,
+                    gsp::kNoAllocScratchBytes / sizeof(double) * gsp::kLossItems);
+    // not bracketed by profiling events: this entry point creates nothing
+    hipError_t e = gsp::launch_loss_l1(lv, loss, ctx->noalloc_scratch,
+                                       static_cast<hipStream_t>(stream));
     if (e != hipSuccess) return hip_fail(e, "loss");
     return GSP_OK;
 }

@@ -173,8 +173,13 @@ struct LossViewsK {
     int64_t blk_base[GSP_MAX_VIEWS + 1];   // first loss block of each view
     int V;
 };
+constexpr int kLossItems = 4096;   // elements per loss block
 int64_t loss_blocks(int64_t count);
-hipError_t launch_loss_l1(const LossViewsK &lv, float *loss, void *scratch, hipStream_t s);
+hipError_t launch_loss_l1(const LossViewsK &lv, float *loss, void *partial_buf, hipStream_t s);
+// Fixed per-device scratch of gsp_loss_l1_noalloc (bytes), and its device
+// address on `device` (looked up once per device; thread-safe).
+constexpr size_t kNoAllocScratchBytes = GSP_NOALLOC_SCRATCH_BYTES;
+hipError_t noalloc_scratch_init(int device, void **ptr);
 hipError_t launch_pose_adam(int V, float *poses, const float *dpose, float *m, float *v,
                             int32_t *steps, const gsp_adam_params &p, const uint32_t *guard,
                             hipStream_t s);

@@ -2,12 +2,12 @@
 // photometric loss with its gradient (the L1 part of Eq. (16)), and the
 // tangent-space Adam step with left retraction on each pose (Sec. III-B:
 // T = Exp(tau), gradients taken on tau).
+#include <mutex>
+
 #include "block_ops.h"
 #include "gsp_internal.h"
 
 namespace gsp {
-
-constexpr int kLossItems = 4096;   // elements per loss block
 
 int64_t loss_blocks(int64_t count) { return (count + kLossItems - 1) / kLossItems; }
 
@@ -50,10 +50,45 @@ __global__ __launch_bounds__(256) void k_l1_final(LossViewsK lv, const double *p
     if (threadIdx.x == 0) loss[v] = (float)(s / (double)lv.count[v]);
 }
 
-hipError_t launch_loss_l1(const LossViewsK &lv, float *loss, void *scratch, hipStream_t s) {
+// Scratch of gsp_loss_l1_noalloc: the per-block partial sums of the loss,
+// in a fixed array of the library instead of caller memory.  Each device
+// that loads the library holds its own copy until the process ends.  Host
+// code must not pass the array's name to a kernel (on the host it is only a
+// stand-in for the device symbol): its device address comes from
+// hipGetSymbolAddress, taken once per device by noalloc_scratch_init.
+static __device__ __align__(256) unsigned char scratch[kNoAllocScratchBytes];
+
+namespace {
+constexpr int kMaxDevices = 64;
+void *g_noalloc_ptr[kMaxDevices];
+bool g_noalloc_done[kMaxDevices];
+std::mutex g_noalloc_mutex;
+}  // namespace
+
+hipError_t noalloc_scratch_init(int device, void **ptr) {
+    if (device < 0 || device >= kMaxDevices) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lock(g_noalloc_mutex);
+    if (!g_noalloc_done[device]) {
+        int prev = 0;
+        hipError_t e = hipGetDevice(&prev);
+        if (e != hipSuccess) return e;
+        if ((e = hipSetDevice(device)) != hipSuccess) return e;
+        void *p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        const hipError_t e2 = hipSetDevice(prev);
+        if (e != hipSuccess) return e;
+        if (e2 != hipSuccess) return e2;
+        g_noalloc_ptr[device] = p;
+        g_noalloc_done[device] = true;
+    }
+    *ptr = g_noalloc_ptr[device];
+    return hipSuccess;
+}
+
+hipError_t launch_loss_l1(const LossViewsK &lv, float *loss, void *partial_buf, hipStream_t s) {
     const int64_t nblk = lv.blk_base[lv.V];
     if (nblk <= 0) return hipSuccess;
-    double *partial = loss ? static_cast<double *>(scratch) : nullptr;
+    double *partial = loss ? static_cast<double *>(partial_buf) : nullptr;
     hipLaunchKernelGGL(k_l1, dim3((unsigned)nblk), dim3(256), 0, s, lv, partial);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess || !loss) return e;
