@@ -22,12 +22,12 @@ Serving (`serving` in the JSON line, skipped with --no-serve): a resident
 1M-Gaussian SH-3 scene (the joint-reconstruction scene) and pose-estimation
 requests of mixed sizes {320x240, 640x480, 1008x756}, starting errors
 U(1, 5) deg / U(0.02, 0.1), 50 Adam iterations each, targets rendered at the
-ground-truth poses.  The requests are first solved one at a time (the
-sequential baseline: its rate mu_seq and per-request service times), then
-served with continuous batching at Poisson arrival rates of 0.5, 1 and 2 x
-mu_seq; latency = completion - arrival.  The sequential server's latencies at
-the same arrival times follow from its measured service times (first come,
-first served).  Final poses of the two are compared bit for bit.
+ground-truth poses.  The sequential rate mu_seq is measured on the first
+100 requests solved one at a time, back to back; then, for Poisson arrival
+rates of 0.5, 1 and 2 x mu_seq, the same arrival trace of all requests (500
+by default) is served live twice: by the sequential server (one request at a
+time, first come first served) and with continuous batching; latency =
+completion - arrival.  Final poses of the two are compared bit for bit.
 """
 import argparse
 import hashlib
@@ -95,7 +95,7 @@ def main():
                     help="run only the serving measurement and print its JSON (for profiling)")
     ap.add_argument("--joint-only", action="store_true",
                     help="run only the joint-step measurement and print its JSON (for profiling)")
-    ap.add_argument("--serve-requests", type=int, default=48)
+    ap.add_argument("--serve-requests", type=int, default=500)
     ap.add_argument("--no-joint", action="store_true", help="skip the joint-step measurement")
     ap.add_argument("--no-tiny", action="store_true", help="skip the tiny-scene measurement")
     ap.add_argument("--no-track", action="store_true", help="skip the tracking measurement")
@@ -103,7 +103,11 @@ def main():
                     help="skip the relative-pose (two-frame) measurement")
     ap.add_argument("--relpose-only", action="store_true",
                     help="run only the relative-pose measurement and print its JSON")
+    ap.add_argument("--track-only", action="store_true",
+                    help="run only the tracking measurement and print its JSON")
     ap.add_argument("--track-frames", type=int, default=100)
+    ap.add_argument("--track-frames-stored", type=int, default=10,
+                    help="frames of the tracking run repeated with stored per-pixel lists")
     ap.add_argument("--joint-steps", type=int, default=20)
     ap.add_argument("--serve-rates", type=str, default="0.5,1,2",
                     help="arrival rates as multiples of the sequential rate")
@@ -130,6 +134,9 @@ def main():
     dev = "cuda:0"
     if args.serve_only:
         print(json.dumps(serving_section(args, dev, with_cpu=False)), flush=True)
+        return
+    if args.track_only:
+        print(json.dumps(tracking_section(args, dev)), flush=True)
         return
     if args.joint_only:
         print(json.dumps(joint_section(args, dev)), flush=True)
@@ -597,10 +604,12 @@ def tracking_section(args, dev):
     frame's estimate (frame 0 from the ground truth turned by 1 deg and moved
     by 0.02) and running 50 pose-only Adam iterations on the L1 loss; the
     render and its backward are the library's, the loss and its gradient are
-    torch's autograd.  Peak HBM of this recompute design is measured; the
-    per-pixel state a store-the-lists design would add (an id and an alpha
-    per blended pair, 8 B each pair) is computed from the contributor
-    counts."""
+    torch's autograd.  The whole trajectory runs with the recomputing
+    backward; then its first frames run again with stored per-pixel lists
+    (GSP_STORE_LISTS: 12 B per blended pair).  For both, the peak HBM above
+    what the scene and the target images hold is measured
+    (torch.cuda.max_memory_allocated), as are the time per iteration and
+    the pose errors."""
     import numpy as np
     import torch
 
@@ -613,58 +622,99 @@ def tracking_section(args, dev):
     g = R.GaussianParams.from_set(wl.scene, dev)
     rast = R.Rasterizer(0)
     targets = []
-    stored_pairs = []
+    m0 = 0
     for k in range(len(traj)):
         t, _ = rast.forward(g, [cam], torch.tensor(traj[k:k + 1], device=dev))
         targets.append(t.clone())
-        stored_pairs.append(int(rast.inspect(g, [cam], "ncontrib", torch.int32)
-                                .to(torch.int64).sum().item()))
-    m0, _ = rast.instances()
-    rast.capacity = int(1.5 * m0) + 4096
-    rast.ws = None
-    rast._ensure(g, R.N.view_array([cam]))
+        m0 = max(m0, rast.instances()[0])
+    del rast
     iters = 50
-    pose = torch.tensor(S.perturb_pose(traj[0], 1.0, 0.02, S.rng_for(1004, 2))[None]
-                        .astype(np.float32), device=dev)
-    errs = []
-    torch.cuda.synchronize()
-    torch.cuda.reset_peak_memory_stats()
-    t0 = time.perf_counter()
-    for k in range(len(traj)):
-        m = torch.zeros((1, 6), device=dev)
-        v = torch.zeros((1, 6), device=dev)
-        st = torch.zeros(1, dtype=torch.int32, device=dev)
-        for _ in range(iters):
-            tau = torch.zeros((1, 6), device=dev, requires_grad=True)
-            img = R.render(g, [cam], pose, tau=tau, rast=rast, check=False)
-            loss = (img - targets[k]).abs().mean()
-            loss.backward()
-            R.pose_adam(pose, tau.grad, m, v, st, 1e-2, 1e-4, iters, guard=rast.ws)
-        errs.append(S.pose_error(pose[0].cpu().numpy(), traj[k]))
-    torch.cuda.synchronize()
-    sec = time.perf_counter() - t0
-    peak = torch.cuda.max_memory_allocated()
-    if rast.overflowed():
+    P = cam.width * cam.height
+    start = S.perturb_pose(traj[0], 1.0, 0.02, S.rng_for(1004, 2))[None].astype(np.float32)
+
+    def track(frames, store):
+        rast = R.Rasterizer(0, capacity=int(1.5 * m0) + 4096, store_lists=store)
+        pose = torch.tensor(start, device=dev)
+        rast.forward(g, [cam], pose)             # sizes the buffers (and the pair capacity)
+        if store:
+            rast.pair_capacity = int(1.5 * rast.list_pairs()[0]) + 4096
+            rast.lists = None
+            rast.forward(g, [cam], pose)
+        rast.reset_overflow()
+        errs, pairs = [], 0
+        torch.cuda.synchronize()
+        base = torch.cuda.memory_allocated()
+        torch.cuda.reset_peak_memory_stats()
+        t0 = time.perf_counter()
+        for k in range(frames):
+            m = torch.zeros((1, 6), device=dev)
+            v = torch.zeros((1, 6), device=dev)
+            st = torch.zeros(1, dtype=torch.int32, device=dev)
+            for _ in range(iters):
+                tau = torch.zeros((1, 6), device=dev, requires_grad=True)
+                img = R.render(g, [cam], pose, tau=tau, rast=rast, check=False)
+                loss = (img - targets[k]).abs().mean()
+                loss.backward()
+                R.pose_adam(pose, tau.grad, m, v, st, 1e-2, 1e-4, iters, guard=rast.ws)
+            errs.append(S.pose_error(pose[0].cpu().numpy(), traj[k]))
+            if store:
+                pairs = max(pairs, rast.list_pairs()[0])
+        torch.cuda.synchronize()
+        sec = time.perf_counter() - t0
+        peak = torch.cuda.max_memory_allocated()
+        if rast.overflowed():
+            return None
+        ws = rast.ws.numel()
+        lists = rast.lists.numel() if store else 0
+        # the pose estimates feed the next frames: the stored run ends at
+        # the recomputing run's errors up to FP32 rounding
+        return {"seconds": sec, "ms_per_iteration": 1e3 * sec / (frames * iters),
+                "errors": np.array(errs), "peak_above_scene_and_targets": int(peak - base),
+                "peak_hbm_bytes": int(peak), "workspace_bytes": int(ws), "list_bytes": int(lists),
+                "max_pairs": int(pairs)}
+
+    rec = track(len(traj), False)
+    if rec is None:
         print("[bench] tracking overflowed its instance capacity", file=sys.stderr)
         return None
-    e = np.array(errs)
-    P = cam.width * cam.height
+    nst = min(args.track_frames_stored, len(traj))
+    sto = track(nst, True)
+    e = rec["errors"]
+    sec = rec["seconds"]
     n_it = len(traj) * iters
     print(f"[bench] tracking: {len(traj)} frames x {iters} iterations in {sec:.2f} s "
-          f"({1e3 * sec / n_it:.3f} ms/iteration); median error {np.median(e[:, 0]):.3f} deg / "
-          f"{np.median(e[:, 1]):.4f}", file=sys.stderr, flush=True)
-    return {"workload": wl.name, "gaussians": g.n, "frames": len(traj),
-            "iterations_per_frame": iters, "seconds": round(sec, 3),
-            "ms_per_iteration": round(1e3 * sec / n_it, 4),
-            "mpix_per_s": round(P * n_it / sec / 1e6, 2),
-            "error_deg_median": round(float(np.median(e[:, 0])), 4),
-            "error_deg_max": round(float(np.max(e[:, 0])), 4),
-            "error_trans_median": round(float(np.median(e[:, 1])), 5),
-            "error_trans_max": round(float(np.max(e[:, 1])), 5),
-            "peak_hbm_bytes_recompute": int(peak),
-            "per_pixel_state_bytes_recompute": 8 * P,
-            "per_pixel_state_bytes_stored_lists_mean": int(8 * np.mean(stored_pairs)) + 8 * P,
-            "note": "loss and its gradient in torch autograd; render, backward and Adam in the library"}
+          f"({rec['ms_per_iteration']:.3f} ms/iteration); median error {np.median(e[:, 0]):.3f} deg / "
+          f"{np.median(e[:, 1]):.4f}; state above scene+targets {rec['peak_above_scene_and_targets'] / 1e9:.3f} GB",
+          file=sys.stderr, flush=True)
+    out = {"workload": wl.name, "gaussians": g.n, "frames": len(traj),
+           "iterations_per_frame": iters, "seconds": round(sec, 3),
+           "ms_per_iteration": round(rec["ms_per_iteration"], 4),
+           "mpix_per_s": round(P * n_it / sec / 1e6, 2),
+           "error_deg_median": round(float(np.median(e[:, 0])), 4),
+           "error_deg_max": round(float(np.max(e[:, 0])), 4),
+           "error_trans_median": round(float(np.median(e[:, 1])), 5),
+           "error_trans_max": round(float(np.max(e[:, 1])), 5),
+           "peak_hbm_bytes_recompute": rec["peak_hbm_bytes"],
+           "state_bytes_recompute": rec["peak_above_scene_and_targets"],
+           "workspace_bytes_recompute": rec["workspace_bytes"],
+           "per_pixel_state_bytes_recompute": 8 * P,
+           "note": "loss and its gradient in torch autograd; render, backward and Adam in the library"}
+    if sto is not None:
+        es = sto["errors"]
+        same = float(np.max(np.abs(es - e[:nst])))
+        print(f"[bench] tracking, stored lists: {nst} frames, {sto['ms_per_iteration']:.3f} ms/iteration, "
+              f"state above scene+targets {sto['peak_above_scene_and_targets'] / 1e9:.3f} GB "
+              f"(lists {sto['list_bytes'] / 1e9:.3f} GB, {sto['max_pairs']} pairs); "
+              f"max |error difference| to the recomputing run {same:.2e}", file=sys.stderr, flush=True)
+        out["stored_lists"] = {
+            "frames": nst, "ms_per_iteration": round(sto["ms_per_iteration"], 4),
+            "peak_hbm_bytes": sto["peak_hbm_bytes"],
+            "state_bytes": sto["peak_above_scene_and_targets"],
+            "list_bytes": sto["list_bytes"], "max_pairs_per_frame": sto["max_pairs"],
+            "max_abs_error_difference_to_recompute": same,
+            "ms_per_iteration_recompute_same_frames": round(
+                1e3 * rec["seconds"] / n_it, 4)}
+    return out
 
 
 def serving_section(args, dev, with_cpu=True):
@@ -691,57 +741,66 @@ def serving_section(args, dev, with_cpu=True):
     print(f"[bench] serving: {g.n} Gaussians resident, {len(reqs)} requests", file=sys.stderr,
           flush=True)
 
-    # sequential baseline: one request at a time, back to back
+    # sequential rate: one request at a time, back to back, on the first
+    # requests of the trace
     seq_srv = SV.PoseServer(g, iters=iters, max_batch=1)
     seq_srv.run(reqs[:2])            # warm-up (calibration, allocations)
-    seq = seq_srv.run(reqs)
-    done = [r.completed for r in seq]
-    service = [done[0]] + [b - a for a, b in zip(done, done[1:])]
-    mu_seq = len(seq) / done[-1]
-    print(f"[bench] sequential: {mu_seq:.2f} requests/s", file=sys.stderr, flush=True)
+    n_cal = min(len(reqs), 100)
+    cal = seq_srv.run(reqs[:n_cal])
+    mu_seq = n_cal / cal[-1].completed
+    print(f"[bench] sequential: {mu_seq:.2f} requests/s back to back", file=sys.stderr, flush=True)
 
     def errors(results):
         e = np.array([S.pose_error(r.pose, sp["gt_pose"]) for r, sp in zip(results, specs)])
+        e0 = np.array([S.pose_error(sp["init_pose"], sp["gt_pose"]) for sp in specs])
         return {"rot_deg_p50": float(np.percentile(e[:, 0], 50)),
                 "rot_deg_p99": float(np.percentile(e[:, 0], 99)),
                 "trans_p50": float(np.percentile(e[:, 1], 50)),
-                "trans_p99": float(np.percentile(e[:, 1], 99))}
+                "trans_p99": float(np.percentile(e[:, 1], 99)),
+                "initial_rot_deg_p50": float(np.percentile(e0[:, 0], 50)),
+                "initial_trans_p50": float(np.percentile(e0[:, 1], 50))}
+
+    def stats(res):
+        st = SV.latency_stats(res)
+        return {"requests_per_s": round(st["requests_per_s"], 3),
+                "p50_ms": round(st["p50_ms"], 2), "p99_ms": round(st["p99_ms"], 2),
+                "mean_batch": round(st["mean_batch"], 2)}
 
     gaps = np.array([sp["gap"] for sp in specs])
     rates = []
     srv = SV.PoseServer(g, iters=iters)
     srv.run(reqs[:4])                # warm-up
+    seq_final = None
     for rel in [float(x) for x in args.serve_rates.split(",")]:
         lam = rel * mu_seq
         arr = np.cumsum(gaps) / lam
         arr -= arr[0]
-        batched = srv.run([SV.PoseRequest(r.camera, r.target, r.init_pose, float(a), r.rid)
-                           for r, a in zip(reqs, arr)])
-        st = SV.latency_stats(batched)
-        comp = SV.fifo_latencies(arr, service)
-        lat_seq = np.array(comp) - arr
+        trace = [SV.PoseRequest(r.camera, r.target, r.init_pose, float(a), r.rid)
+                 for r, a in zip(reqs, arr)]
+        # both servers live on the same arrival trace
+        seq = seq_srv.run(trace)
+        batched = srv.run(trace)
+        sb, ss = stats(batched), stats(seq)
         same = sum(bool(np.array_equal(a.pose, b.pose)) for a, b in zip(batched, seq))
+        seq_final = seq
         rates.append({
             "arrival_rate_rel": rel, "arrival_rate": round(lam, 3),
-            "batched": {"requests_per_s": round(st["requests_per_s"], 3),
-                        "p50_ms": round(st["p50_ms"], 2), "p99_ms": round(st["p99_ms"], 2),
-                        "mean_batch": round(st["mean_batch"], 2)},
-            "sequential": {"requests_per_s": round(len(comp) / (comp[-1] - arr[0]), 3),
-                           "p50_ms": round(float(np.percentile(lat_seq, 50)) * 1e3, 2),
-                           "p99_ms": round(float(np.percentile(lat_seq, 99)) * 1e3, 2)},
+            "batched": sb, "sequential": ss,
+            "batched_final_error": errors(batched), "sequential_final_error": errors(seq),
             "identical_final_poses": f"{same}/{len(batched)}",
         })
-        print(f"[bench] rate {rel} x mu_seq: batched {st['requests_per_s']:.2f} req/s "
-              f"p50 {st['p50_ms']:.1f} ms p99 {st['p99_ms']:.1f} ms; identical {same}/{len(batched)}",
+        print(f"[bench] rate {rel} x mu_seq ({len(trace)} requests): batched {sb['requests_per_s']:.2f} "
+              f"req/s p50 {sb['p50_ms']:.1f} ms p99 {sb['p99_ms']:.1f} ms (mean batch "
+              f"{sb['mean_batch']:.1f}); sequential {ss['requests_per_s']:.2f} req/s p50 "
+              f"{ss['p50_ms']:.1f} ms p99 {ss['p99_ms']:.1f} ms; identical {same}/{len(batched)}",
               file=sys.stderr, flush=True)
 
     out = {
         "workload": "serve-1M-sh3-mixed-320x240-640x480-1008x756",
         "gaussians": g.n, "requests": len(reqs), "iterations_per_request": iters,
-        "sequential_requests_per_s": round(mu_seq, 3),
-        "sequential_service_ms_p50": round(float(np.percentile(service, 50)) * 1e3, 2),
+        "sequential_requests_per_s_back_to_back": round(mu_seq, 3),
         "rates": rates,
-        "final_error": errors(seq),
+        "final_error": errors(seq_final),
     }
     if with_cpu:
         import oracle

@@ -15,7 +15,8 @@
  *    the call reads before returning.  The caller owns every buffer.  The
  *    library allocates no device memory after gsp_create.
  *  - Work is enqueued on the given HIP stream (NULL = the default stream) and
- *    calls return without synchronising, except gsp_instances.
+ *    calls return without synchronising, except gsp_instances and
+ *    gsp_list_pairs.
  *  - Every call returns a gsp_status.  Argument errors return GSP_EINVAL
  *    before anything is enqueued; gsp_last_error() then describes the
  *    problem (thread-local, valid until the next call on the same thread).
@@ -167,6 +168,50 @@ gsp_status gsp_render_bwd(gsp_ctx *ctx, const gsp_gaussians *g, int32_t V, const
                           const float *poses, const float *const *dl_dimages,
                           void *workspace, size_t ws_bytes, int64_t instance_capacity,
                           const gsp_grads *grads, uint32_t flags, void *stream);
+
+/* Stored-list mode (the alternative to recomputation in the backward).
+ * The backward of Eq. (3)-(4) needs, for every pixel, the alpha_i of its
+ * blended splats and the transmittance T_i in front of each.  gsp_render_bwd
+ * recomputes them back to front from T_final (T_i = T_{i+1} / (1 - alpha_i)),
+ * which keeps only 8 bytes of per-pixel state.  This mode stores them
+ * instead: gsp_render_fwd_store renders exactly as gsp_render_fwd and then
+ * writes, for each pixel and each blended splat front to back, a 12-byte
+ * record (list position in the pixel's tile, alpha_i negated when the 0.99
+ * clamp is active, T_i) into a caller buffer `lists`; gsp_render_bwd_stored
+ * is gsp_render_bwd reading those records instead of recomputing them
+ * (same outputs, to FP32 rounding of the recovered transmittances).
+ *   lists          device, lists_bytes >= gsp_lists_bytes(V, views,
+ *                  pair_capacity); the same buffer and capacity must reach
+ *                  the backward.  Layout: a 64-byte header (uint32 [0], [1]
+ *                  low and high words of the number of stored pairs of the
+ *                  last forward, [2] nonzero when it exceeded pair_capacity,
+ *                  [3] nonzero when any forward did since the caller zeroed
+ *                  the buffer), then per-pixel counts and offsets and the
+ *                  records.
+ *   pair_capacity  records the buffer holds (0 .. 2^32 - 2).
+ * When a forward's pairs exceed pair_capacity its records are not written
+ * and the stored backward of it produces zero gradients; gsp_list_pairs
+ * reports the overflow and the count needed.  Errors as gsp_render_fwd /
+ * gsp_render_bwd, plus GSP_EINVAL for a NULL `lists` and GSP_ENOMEM for a
+ * buffer smaller than gsp_lists_bytes.  gsp_lists_bytes returns 0 for
+ * invalid views or capacity. */
+size_t gsp_lists_bytes(int32_t V, const gsp_view *views, int64_t pair_capacity);
+gsp_status gsp_render_fwd_store(gsp_ctx *ctx, const gsp_gaussians *g, int32_t V,
+                                const gsp_view *views, const float *poses, float *const *images,
+                                float *const *alphas, void *workspace, size_t ws_bytes,
+                                int64_t instance_capacity, void *lists, size_t lists_bytes,
+                                int64_t pair_capacity, void *stream);
+gsp_status gsp_render_bwd_stored(gsp_ctx *ctx, const gsp_gaussians *g, int32_t V,
+                                 const gsp_view *views, const float *poses,
+                                 const float *const *dl_dimages, void *workspace, size_t ws_bytes,
+                                 int64_t instance_capacity, const void *lists, size_t lists_bytes,
+                                 int64_t pair_capacity, const gsp_grads *grads, uint32_t flags,
+                                 void *stream);
+/* Synchronises `stream` and reports the pairs stored by the last forward in
+ * `lists` and whether that or any earlier forward (since the caller zeroed
+ * the buffer) exceeded its pair capacity. */
+gsp_status gsp_list_pairs(gsp_ctx *ctx, const void *lists, void *stream, int64_t *pairs_out,
+                          int32_t *overflow_out);
 
 /* Synchronises `stream` and reports the instance count M of the last forward
  * in `workspace`, and whether that forward or any earlier one on the same

@@ -22,7 +22,8 @@ EXPORTS = (
     "gsp_profile_enable", "gsp_profile_read", "gsp_loss_rgb", "gsp_loss_rgb_scratch_bytes",
     "gsp_gaussian_adam", "gsp_gaussian_adam_scratch_bytes", "gsp_unproject_count",
     "gsp_unproject_scratch_bytes", "gsp_unproject", "gsp_loss_masked_l1",
-    "gsp_loss_masked_l1_scratch_bytes", "gsp_loss_l1_noalloc",
+    "gsp_loss_masked_l1_scratch_bytes", "gsp_loss_l1_noalloc", "gsp_render_fwd_store",
+    "gsp_render_bwd_stored", "gsp_lists_bytes", "gsp_list_pairs",
 )
 
 
@@ -116,6 +117,11 @@ def lib():
         "gsp_unproject": ([P, P, P, P, I32, ctypes.c_float, I32, P, P, SZ, P], I32),
         "gsp_loss_masked_l1": ([P, I32, P, P, P, P, P, P, P, P], I32),
         "gsp_loss_masked_l1_scratch_bytes": ([I32, P], SZ),
+        "gsp_render_fwd_store": ([P, P, I32, P, P, P, P, P, SZ, I64, P, SZ, I64, P], I32),
+        "gsp_render_bwd_stored": ([P, P, I32, P, P, P, P, SZ, I64, P, SZ, I64, P, ctypes.c_uint32,
+                                   P], I32),
+        "gsp_lists_bytes": ([I32, P, I64], SZ),
+        "gsp_list_pairs": ([P, P, P, ctypes.POINTER(I64), ctypes.POINTER(I32)], I32),
         "gsp_status_string": ([I32], ctypes.c_char_p),
         "gsp_last_error": ([], ctypes.c_char_p),
         "gsp_version": ([], ctypes.c_int),

@@ -14,7 +14,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libgsp.so")
-SOURCES = ["api.hip", "preprocess.hip", "sort.hip", "raster_fwd.hip", "raster_bwd.hip",
+SOURCES = ["api.hip", "preprocess.hip", "sort.hip", "raster_fwd.hip", "raster_bwd.hip", "lists.hip",
            "preprocess_bwd.hip", "misc.hip", "joint.hip",
            "relpose.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")

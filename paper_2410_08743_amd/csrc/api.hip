@@ -374,10 +374,24 @@ gsp_status gsp_workspace_size(int64_t n, int32_t sh_degree, int32_t V, const gsp
     return GSP_OK;
 }
 
-gsp_status gsp_render_fwd(gsp_ctx *ctx, const gsp_gaussians *g, int32_t V, const gsp_view *views,
-                          const float *poses, float *const *images, float *const *alphas,
-                          void *workspace, size_t ws_bytes, int64_t instance_capacity,
-                          void *stream) {
+namespace {
+
+gsp_status check_lists(const gsp::Layout &L, const void *lists, size_t lists_bytes,
+                       int64_t pair_capacity, gsp::ListLayout *Q) {
+    if (!lists) return fail(GSP_EINVAL, "null list buffer");
+    if (pair_capacity < 0 || pair_capacity >= (1ll << 32) - 1)
+        return fail(GSP_EINVAL, "pair capacity %lld outside 0..2^32-2", (long long)pair_capacity);
+    *Q = gsp::make_list_layout(L, pair_capacity);
+    if (lists_bytes < Q->total)
+        return fail(GSP_ENOMEM, "list buffer of %zu bytes is smaller than the %zu needed",
+                    lists_bytes, Q->total);
+    return GSP_OK;
+}
+
+gsp_status render_fwd(gsp_ctx *ctx, const gsp_gaussians *g, int32_t V, const gsp_view *views,
+                      const float *poses, float *const *images, float *const *alphas,
+                      void *workspace, size_t ws_bytes, int64_t instance_capacity, void *lists,
+                      size_t lists_bytes, int64_t pair_capacity, void *stream) {
     gsp_status s = check_device(ctx);
     if (s != GSP_OK) return s;
     Prepared p;
@@ -392,6 +406,9 @@ gsp_status gsp_render_fwd(gsp_ctx *ctx, const gsp_gaussians *g, int32_t V, const
     if (ws_bytes < p.L.total)
         return fail(GSP_ENOMEM, "workspace of %zu bytes is smaller than the %zu needed", ws_bytes,
                     p.L.total);
+    gsp::ListLayout Q;
+    std::memset(&Q, 0, sizeof Q);
+    if (lists && (s = check_lists(p.L, lists, lists_bytes, pair_capacity, &Q)) != GSP_OK) return s;
     hipStream_t st = static_cast<hipStream_t>(stream);
     char *ws = static_cast<char *>(workspace);
     const gsp::GaussiansK gk = kernel_gaussians(g);
@@ -419,13 +436,67 @@ gsp_status gsp_render_fwd(gsp_ctx *ctx, const gsp_gaussians *g, int32_t V, const
              return gsp::launch_raster_fwd(p.views, p.L, ws, vals, ctx->stats, st);
          })) != hipSuccess)
         return hip_fail(e, "raster forward");
+    if (lists) {
+        if ((e = stage(ctx, "store_lists", st, [&] {
+                 return gsp::launch_store_lists(p.views, p.L, ws, vals, Q, static_cast<char *>(lists),
+                                                st);
+             })) != hipSuccess)
+            return hip_fail(e, "store lists");
+    }
     return GSP_OK;
 }
 
-gsp_status gsp_render_bwd(gsp_ctx *ctx, const gsp_gaussians *g, int32_t V, const gsp_view *views,
-                          const float *poses, const float *const *dl_dimages, void *workspace,
-                          size_t ws_bytes, int64_t instance_capacity, const gsp_grads *grads,
-                          uint32_t flags, void *stream) {
+}  // namespace
+
+gsp_status gsp_render_fwd(gsp_ctx *ctx, const gsp_gaussians *g, int32_t V, const gsp_view *views,
+                          const float *poses, float *const *images, float *const *alphas,
+                          void *workspace, size_t ws_bytes, int64_t instance_capacity,
+                          void *stream) {
+    return render_fwd(ctx, g, V, views, poses, images, alphas, workspace, ws_bytes,
+                      instance_capacity, nullptr, 0, 0, stream);
+}
+
+gsp_status gsp_render_fwd_store(gsp_ctx *ctx, const gsp_gaussians *g, int32_t V,
+                                const gsp_view *views, const float *poses, float *const *images,
+                                float *const *alphas, void *workspace, size_t ws_bytes,
+                                int64_t instance_capacity, void *lists, size_t lists_bytes,
+                                int64_t pair_capacity, void *stream) {
+    if (!lists) return fail(GSP_EINVAL, "null list buffer");
+    return render_fwd(ctx, g, V, views, poses, images, alphas, workspace, ws_bytes,
+                      instance_capacity, lists, lists_bytes, pair_capacity, stream);
+}
+
+size_t gsp_lists_bytes(int32_t V, const gsp_view *views, int64_t pair_capacity) {
+    gsp::ViewsK vk;
+    int64_t total_pix = 0;
+    if (make_views(V, views, &vk, &total_pix) != GSP_OK) return 0;
+    if (pair_capacity < 0 || pair_capacity >= (1ll << 32) - 1) return 0;
+    const gsp::Layout L = gsp::make_layout(0, 0, V, vk, 0);
+    return gsp::make_list_layout(L, pair_capacity).total;
+}
+
+gsp_status gsp_list_pairs(gsp_ctx *ctx, const void *lists, void *stream, int64_t *pairs_out,
+                          int32_t *overflow_out) {
+    gsp_status s = check_device(ctx);
+    if (s != GSP_OK) return s;
+    if (!lists) return fail(GSP_EINVAL, "null list buffer");
+    hipError_t e = hipStreamSynchronize(static_cast<hipStream_t>(stream));
+    if (e != hipSuccess) return hip_fail(e, "hipStreamSynchronize");
+    uint32_t c[gsp::kListHdrCount];
+    e = hipMemcpy(c, lists, sizeof c, hipMemcpyDeviceToHost);
+    if (e != hipSuccess) return hip_fail(e, "hipMemcpy");
+    if (pairs_out) *pairs_out = (int64_t)(((uint64_t)c[gsp::kListPairsHi] << 32) | c[gsp::kListPairsLo]);
+    if (overflow_out) *overflow_out = (int32_t)(c[gsp::kListOverflow] | c[gsp::kListSticky]);
+    return GSP_OK;
+}
+
+namespace {
+
+gsp_status render_bwd(gsp_ctx *ctx, const gsp_gaussians *g, int32_t V, const gsp_view *views,
+                      const float *poses, const float *const *dl_dimages, void *workspace,
+                      size_t ws_bytes, int64_t instance_capacity, const void *lists,
+                      size_t lists_bytes, int64_t pair_capacity, const gsp_grads *grads,
+                      uint32_t flags, void *stream) {
     gsp_status s = check_device(ctx);
     if (s != GSP_OK) return s;
     Prepared p;
@@ -441,12 +512,17 @@ gsp_status gsp_render_bwd(gsp_ctx *ctx, const gsp_gaussians *g, int32_t V, const
     if (ws_bytes < p.L.total)
         return fail(GSP_ENOMEM, "workspace of %zu bytes is smaller than the %zu needed", ws_bytes,
                     p.L.total);
+    gsp::ListLayout Q;
+    std::memset(&Q, 0, sizeof Q);
+    if (lists && (s = check_lists(p.L, lists, lists_bytes, pair_capacity, &Q)) != GSP_OK) return s;
     hipStream_t st = static_cast<hipStream_t>(stream);
     char *ws = static_cast<char *>(workspace);
     const uint32_t *vals = gsp::region<uint32_t>(ws, gsp::sorted_vals(p.L));
     hipError_t e;
     if ((e = stage(ctx, "raster_bwd", st, [&] {
-             return gsp::launch_raster_bwd(p.views, p.L, ws, vals, st);
+             return lists ? gsp::launch_raster_bwd_stored(p.views, p.L, ws, vals, Q,
+                                                          static_cast<const char *>(lists), st)
+                          : gsp::launch_raster_bwd(p.views, p.L, ws, vals, st);
          })) != hipSuccess)
         return hip_fail(e, "raster backward");
     if ((e = stage(ctx, "preprocess_bwd", st, [&] {
@@ -455,6 +531,27 @@ gsp_status gsp_render_bwd(gsp_ctx *ctx, const gsp_gaussians *g, int32_t V, const
          })) != hipSuccess)
         return hip_fail(e, "preprocess backward");
     return GSP_OK;
+}
+
+}  // namespace
+
+gsp_status gsp_render_bwd(gsp_ctx *ctx, const gsp_gaussians *g, int32_t V, const gsp_view *views,
+                          const float *poses, const float *const *dl_dimages, void *workspace,
+                          size_t ws_bytes, int64_t instance_capacity, const gsp_grads *grads,
+                          uint32_t flags, void *stream) {
+    return render_bwd(ctx, g, V, views, poses, dl_dimages, workspace, ws_bytes, instance_capacity,
+                      nullptr, 0, 0, grads, flags, stream);
+}
+
+gsp_status gsp_render_bwd_stored(gsp_ctx *ctx, const gsp_gaussians *g, int32_t V,
+                                 const gsp_view *views, const float *poses,
+                                 const float *const *dl_dimages, void *workspace, size_t ws_bytes,
+                                 int64_t instance_capacity, const void *lists, size_t lists_bytes,
+                                 int64_t pair_capacity, const gsp_grads *grads, uint32_t flags,
+                                 void *stream) {
+    if (!lists) return fail(GSP_EINVAL, "null list buffer");
+    return render_bwd(ctx, g, V, views, poses, dl_dimages, workspace, ws_bytes, instance_capacity,
+                      lists, lists_bytes, pair_capacity, grads, flags, stream);
 }
 
 gsp_status gsp_instances(gsp_ctx *ctx, const void *workspace, void *stream, int64_t *m_out,

@@ -145,6 +145,25 @@ struct GaussiansK {
     int n, sh_degree;
 };
 
+// lists.hip: the stored per-pixel state (GSP_STORE_LISTS).  A separate
+// caller buffer: header | per-pixel counts | per-pixel offsets (+1) | scan
+// block sums | pair records.
+struct PairRec {
+    uint32_t pos;     // list position in the tile
+    float alpha;      // alpha_i, negated when clamped at 0.99
+    float T;          // transmittance in front of i
+};
+constexpr int kPairBytes = 12;
+static_assert(sizeof(PairRec) == kPairBytes, "pair record layout");
+enum ListCounter : int {
+    kListPairsLo = 0, kListPairsHi = 1, kListOverflow = 2, kListSticky = 3, kListHdrCount = 16
+};
+struct ListLayout {
+    int64_t cap;
+    int nblk;
+    size_t hdr, count, offsets, blocksum, pairs, total;
+};
+
 // preprocess.hip
 hipError_t launch_preprocess(const GaussiansK &g, const ViewsK &views, const float *poses,
                              const Layout &L, char *ws, hipStream_t s);
@@ -157,9 +176,17 @@ hipError_t launch_tile_sort(const Layout &L, char *ws, hipStream_t s);
 hipError_t launch_ranges(const Layout &L, char *ws, const uint32_t *keys, hipStream_t s);
 hipError_t launch_raster_fwd(const ViewsK &views, const Layout &L, char *ws,
                              const uint32_t *vals, bool stats, hipStream_t s);
-// raster_bwd.hip
+// raster_bwd.hip; with `lists` the stored-list variant (one workgroup per
+// tile, alpha and T read from the pair records)
 hipError_t launch_raster_bwd(const ViewsK &views, const Layout &L, char *ws,
                              const uint32_t *vals, hipStream_t s);
+hipError_t launch_raster_bwd_stored(const ViewsK &views, const Layout &L, char *ws,
+                                    const uint32_t *vals, const ListLayout &Q, const char *lists,
+                                    hipStream_t s);
+// lists.hip
+ListLayout make_list_layout(const Layout &L, int64_t pair_capacity);
+hipError_t launch_store_lists(const ViewsK &views, const Layout &L, char *ws, const uint32_t *vals,
+                              const ListLayout &Q, char *lists, hipStream_t s);
 // preprocess_bwd.hip
 hipError_t launch_preprocess_bwd(const GaussiansK &g, const ViewsK &views, const float *poses,
                                  const Layout &L, char *ws, const gsp_grads &grads,

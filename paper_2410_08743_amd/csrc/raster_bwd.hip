@@ -28,6 +28,8 @@
 // own slot (its position in emission order), flagging it written.  No
 // atomics: the per-splat sum over its slots happens later in a fixed order,
 // so gradients are bit-reproducible.
+#include <cstring>
+
 #include "block_ops.h"
 #include "raster_common.h"
 
@@ -52,6 +54,12 @@ struct BwdArgs {
     const uint32_t *ncontrib;
     float *slots;          // [cap][kSplit][9]
     uint8_t *slot_flags;   // [cap][kSplit]: 1 where this kernel wrote the slot
+    // stored-list variant only
+    const uint32_t *order;     // tiles, longest list first
+    const uint32_t *loff;      // [total_pix + 1] first pair of each pixel
+    const PairRec *pairs;
+    const uint32_t *lhdr;      // list header (overflow flag)
+    int total_tiles;
 };
 
 constexpr uint32_t kNoSlot = 0xffffffffu;
@@ -71,6 +79,18 @@ __device__ __forceinline__ uint32_t slot_of(const BwdArgs &a, uint32_t id, int t
 #ifndef GSP_BWD_WAVES
 #define GSP_BWD_WAVES 4
 #endif
+// Pixel with no stored pair left, and the list position of padding records
+// (never a pixel's next pair; below every pixel's count as a signed int, and
+// the padding's infinite candidate limit rejects it in the recomputing walk).
+constexpr uint32_t kNoPos = 0xffffffffu;
+constexpr uint32_t kPadPos = 0xfffffffeu;
+
+// STORED = false: the recomputing backward over (tile, chunk) work items.
+// STORED = true: one workgroup per whole tile; each pixel's blended entries,
+// with their alpha and the transmittance in front of them, come from the
+// pair records the forward stored (GSP_STORE_LISTS); the walk, the
+// culling, the gradient formulas and the reduction are the same.
+template <bool STORED>
 __global__ __launch_bounds__(kRasterThreads) __attribute__((amdgpu_waves_per_eu(GSP_BWD_WAVES))) void k_raster_bwd(BwdArgs a, ViewsK views) {
     __shared__ StagedA sA[kBatch];
     __shared__ StagedB sB[kBatch];
@@ -78,8 +98,14 @@ __global__ __launch_bounds__(kRasterThreads) __attribute__((amdgpu_waves_per_eu(
     __shared__ float sL[kBatch];   // candidate limit kLog2AlphaMinLoose - lo
     int rank, part;
     part_of_block<kSplit>(blockIdx.x, rank, part);
-    if ((uint32_t)rank >= a.counters[kCntItems]) return;
-    const uint32_t item = a.items[rank];
+    uint32_t item;
+    if (STORED) {
+        if (rank >= a.total_tiles || a.lhdr[kListOverflow]) return;
+        item = a.order[rank] * kMaxChunks;   // chunk 0 of an uncut walk
+    } else {
+        if ((uint32_t)rank >= a.counters[kCntItems]) return;
+        item = a.items[rank];
+    }
     const int tile = (int)(item / kMaxChunks), chunk = (int)(item % kMaxChunks);
     const ViewK &vw = views.v[view_of_tile(views, tile)];
     const int lt = tile - vw.tile_base;
@@ -110,13 +136,17 @@ __global__ __launch_bounds__(kRasterThreads) __attribute__((amdgpu_waves_per_eu(
     // count, as in an unsplit walk.
     const uint2 rg = a.ranges[tile];
     const int len = (int)(rg.y - rg.x);
-    const int nch = chunks_of(len);
+    const int nch = STORED ? 1 : chunks_of(len);
     const int clo = chunk * kChunk, chi = chunk == nch - 1 ? len : clo + kChunk;
     const float4 *const ck =
         chunk < nch - 1 ? a.ckpt + (size_t)((rg.x + (uint32_t)chi) / kChunk) * (kTile * kTile)
                         : nullptr;
     float T[kPixPerLane], G[kPixPerLane][3], GS[kPixPerLane], fy[kPixPerLane];
     int last[kPixPerLane];
+    // stored lists: the pixel's next pair back to front (position, alpha, T)
+    // and its index; pbase is the pixel's first pair
+    uint32_t npos[kPixPerLane], pidx[kPixPerLane], pbase[kPixPerLane];
+    float nal[kPixPerLane];
     int maxlast = 0;
 #pragma unroll
     for (int q = 0; q < kPixPerLane; q++) {
@@ -125,14 +155,31 @@ __global__ __launch_bounds__(kRasterThreads) __attribute__((amdgpu_waves_per_eu(
         const bool in = rx < vw.roi_w && ry < vw.roi_h;
         const size_t pix = (size_t)ry * vw.roi_w + rx;
         fy[q] = (float)ryl;
-        T[q] = in ? a.tfinal[vw.pix_base + pix] : 1.f;
-        last[q] = in ? (int)a.ncontrib[vw.pix_base + pix] : 0;
+        if (STORED) {
+            npos[q] = kNoPos;
+            nal[q] = 0.f;
+            T[q] = 1.f;
+            pbase[q] = in ? a.loff[vw.pix_base + pix] : 0u;
+            pidx[q] = in ? a.loff[vw.pix_base + pix + 1] : 0u;   // one past the last pair
+            last[q] = 0;
+            if (pidx[q] > pbase[q]) {
+                pidx[q]--;
+                const PairRec r = a.pairs[pidx[q]];
+                npos[q] = r.pos;
+                nal[q] = r.alpha;
+                T[q] = r.T;
+                last[q] = (int)r.pos + 1;
+            }
+        } else {
+            T[q] = in ? a.tfinal[vw.pix_base + pix] : 1.f;
+            last[q] = in ? (int)a.ncontrib[vw.pix_base + pix] : 0;
+        }
         const float *dl = vw.dl;
         G[q][0] = in ? dl[pix] : 0.f;
         G[q][1] = in ? dl[(size_t)P + pix] : 0.f;
         G[q][2] = in ? dl[2 * (size_t)P + pix] : 0.f;
         float S0 = vw.bg[0], S1 = vw.bg[1], S2 = vw.bg[2];
-        if (last[q] > chi) {   // only when this chunk ends at a cut
+        if (!STORED && last[q] > chi) {   // only when this chunk ends at a cut
             // final colour = colour in front of the cut + T_cut * colour behind it
             const float4 c = ck[ryl * kTile + lx];
             const size_t pf = (size_t)vw.pix_base + pix;
@@ -188,7 +235,7 @@ __global__ __launch_bounds__(kRasterThreads) __attribute__((amdgpu_waves_per_eu(
         if (lane >= nk && lane < nkr) {   // padding up to the unroll width
             sA[lane] = StagedA{0.f, 0.f, -1.f, 0.f};
             sB[lane] = StagedB{-1.f, -INFINITY, 0.f, 0.f};
-            sC[lane] = StagedC{0.f, 0.f, kNoSlot, 0u};
+            sC[lane] = StagedC{0.f, 0.f, kNoSlot, kPadPos};
             sL[lane] = INFINITY;
         }
         __syncthreads();
@@ -217,8 +264,13 @@ __global__ __launch_bounds__(kRasterThreads) __attribute__((amdgpu_waves_per_eu(
                 bool any = false;
 #pragma unroll
                 for (int q = 0; q < kPixPerLane; q++) {
-                    p2[q] = splat_p2(ct, t.C2, s.v - fy[q]);
-                    cand[q] = (pos < last[q]) & (p2[q] <= 0.f) & (p2[q] >= lim);
+                    if (STORED) {
+                        p2[q] = 0.f;
+                        cand[q] = npos[q] == (uint32_t)pos;
+                    } else {
+                        p2[q] = splat_p2(ct, t.C2, s.v - fy[q]);
+                        cand[q] = (pos < last[q]) & (p2[q] <= 0.f) & (p2[q] >= lim);
+                    }
                     any |= cand[q];
                 }
                 float x0 = 0.f, x1 = 0.f, x2 = 0.f;
@@ -236,19 +288,41 @@ __global__ __launch_bounds__(kRasterThreads) __attribute__((amdgpu_waves_per_eu(
                     for (int q = 0; q < kPixPerLane; q++) {
                         if (!wave_any(cand[q])) continue;
                         const float dy = s.v - fy[q];
-                        const float apre = splat_alpha_pre(p2[q], t.lo);
-                        const float alpha = fminf(kAlphaMax, apre);
-                        const bool valid = cand[q] && alpha >= kAlphaMin;
-                        const float Tn = T[q] * __builtin_amdgcn_rcpf(1.f - alpha);
-                        T[q] = valid ? Tn : T[q];
-                        const float wgt = valid ? alpha * T[q] : 0.f;
+                        float alpha, wgt;
+                        bool valid, unclamped;
+                        if (STORED) {
+                            // alpha and T_i of this pair as the forward left them
+                            valid = cand[q];
+                            alpha = valid ? fabsf(nal[q]) : 0.f;
+                            unclamped = nal[q] >= 0.f;
+                            wgt = valid ? alpha * T[q] : 0.f;
+                        } else {
+                            const float apre = splat_alpha_pre(p2[q], t.lo);
+                            alpha = fminf(kAlphaMax, apre);
+                            valid = cand[q] && alpha >= kAlphaMin;
+                            unclamped = apre <= kAlphaMax;
+                            const float Tn = T[q] * __builtin_amdgcn_rcpf(1.f - alpha);
+                            T[q] = valid ? Tn : T[q];
+                            wgt = valid ? alpha * T[q] : 0.f;
+                        }
                         const float Gc = fmaf(G[q][2], col3[2], fmaf(G[q][1], col3[1], G[q][0] * col3[0]));
                         const float diff = Gc - GS[q];
 #pragma unroll
                         for (int ch = 0; ch < 3; ch++) gc[ch] = fmaf(G[q][ch], wgt, gc[ch]);
                         GS[q] = valid ? fmaf(alpha, diff, GS[q]) : GS[q];
                         // dL/dpower; zero where alpha is clamped at 0.99
-                        const float dp = apre <= kAlphaMax ? wgt * diff : 0.f;
+                        const float dp = unclamped ? wgt * diff : 0.f;
+                        if (STORED && valid) {
+                            // step to the pixel's previous pair (if any)
+                            npos[q] = kNoPos;
+                            if (pidx[q] > pbase[q]) {
+                                pidx[q]--;
+                                const PairRec r = a.pairs[pidx[q]];
+                                npos[q] = r.pos;
+                                nal[q] = r.alpha;
+                                T[q] = r.T;
+                            }
+                        }
                         const float dpy = dp * dy;
                         m0 += dp;
                         my += dpy;
@@ -285,6 +359,7 @@ hipError_t launch_raster_bwd(const ViewsK &views, const Layout &L, char *ws, con
                              hipStream_t s) {
     if (L.total_tiles == 0) return hipSuccess;
     BwdArgs a;
+    std::memset(&a, 0, sizeof a);
     a.items = region<uint32_t>(ws, L.items);
     a.counters = region<uint32_t>(ws, L.counters);
     a.ckpt = region<float4>(ws, L.ckpt);
@@ -305,7 +380,35 @@ hipError_t launch_raster_bwd(const ViewsK &views, const Layout &L, char *ws, con
     // forward's state, so repeated backwards of one forward agree on it.
     // one workgroup per part of each possible work item; those past the
     // item count of this call exit at once
-    hipLaunchKernelGGL(k_raster_bwd, dim3(raster_blocks<kSplit>((int)L.max_items)),
+    hipLaunchKernelGGL(k_raster_bwd<false>, dim3(raster_blocks<kSplit>((int)L.max_items)),
+                       dim3(kRasterThreads), 0, s, a, views);
+    return hipGetLastError();
+}
+
+hipError_t launch_raster_bwd_stored(const ViewsK &views, const Layout &L, char *ws,
+                                    const uint32_t *vals, const ListLayout &Q, const char *lists,
+                                    hipStream_t s) {
+    if (L.total_tiles == 0) return hipSuccess;
+    BwdArgs a;
+    std::memset(&a, 0, sizeof a);
+    a.counters = region<uint32_t>(ws, L.counters);
+    a.total_pix = (int)L.total_pix;
+    a.ranges = region<uint2>(ws, L.ranges);
+    a.vals = vals;
+    a.geom = region<float4>(ws, L.geom);
+    a.color = region<float4>(ws, L.color);
+    a.rect = region<uint2>(ws, L.rect);
+    a.offsets = region<uint32_t>(ws, L.offsets);
+    a.slots = region<float>(ws, L.slots);
+    a.slot_flags = region<uint8_t>(ws, L.slot_flags);
+    a.order = region<uint32_t>(ws, L.tile_order);
+    char *lw = const_cast<char *>(lists);
+    a.loff = region<uint32_t>(lw, Q.offsets);
+    a.pairs = region<PairRec>(lw, Q.pairs);
+    a.lhdr = region<uint32_t>(lw, Q.hdr);
+    a.total_tiles = L.total_tiles;
+    // one workgroup per part of each tile, in the forward's launch order
+    hipLaunchKernelGGL(k_raster_bwd<true>, dim3(raster_blocks<kSplit>(L.total_tiles)),
                        dim3(kRasterThreads), 0, s, a, views);
     return hipGetLastError();
 }

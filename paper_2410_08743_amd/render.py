@@ -127,12 +127,22 @@ class Rasterizer:
     instance count and re-runs with a larger capacity on overflow; with
     check=False nothing synchronises and `overflowed()` tells afterwards
     whether any forward since the workspace was allocated ran out of room.
+
+    With store_lists=True (GSP_STORE_LISTS) every forward also stores each
+    pixel's blended entries (list position, alpha, transmittance in front;
+    12 bytes per blended pair, in a second buffer sized for `pair_capacity`
+    pairs and grown like the workspace), and the backward reads them instead
+    of recomputing the compositing.
     """
 
-    def __init__(self, device: Optional[int] = None, capacity: int = 0, growth: float = 1.5):
+    def __init__(self, device: Optional[int] = None, capacity: int = 0, growth: float = 1.5,
+                 store_lists: bool = False, pair_capacity: int = 0):
         self.device = torch.cuda.current_device() if device is None else int(device)
         self.capacity = int(capacity)
         self.growth = float(growth)
+        self.store_lists = bool(store_lists)
+        self.pair_capacity = int(pair_capacity)
+        self.lists = None
         self.ws = None
         # incremented by every forward: an autograd context remembers the
         # generation of its forward and refuses to back-propagate once the
@@ -153,9 +163,22 @@ class Rasterizer:
             self.ws = torch.zeros(nbytes, dtype=torch.uint8, device=f"cuda:{self.device}")
         return nbytes
 
+    def _lists_bytes(self, views):
+        return N.lib().gsp_lists_bytes(len(views), views, self.pair_capacity)
+
+    def _ensure_lists(self, views):
+        nbytes = self._lists_bytes(views)
+        if nbytes == 0:
+            raise ValueError("bad views or pair capacity for the stored lists")
+        if self.lists is None or self.lists.numel() < nbytes:
+            self.lists = torch.zeros(nbytes, dtype=torch.uint8, device=f"cuda:{self.device}")
+        return nbytes
+
     def reset_overflow(self):
         if self.ws is not None:
             self.ws[:64].zero_()
+        if self.lists is not None:
+            self.lists[:64].zero_()
 
     def instances(self):
         """(M of the last forward, overflow flag); synchronises the stream."""
@@ -166,8 +189,21 @@ class Rasterizer:
                                 ctypes.byref(o)), "gsp_instances")
         return m.value, bool(o.value)
 
+    def list_pairs(self):
+        """(stored pairs of the last forward, overflow flag of the pair
+        capacity); store_lists mode only; synchronises the stream."""
+        L = N.lib()
+        q = ctypes.c_int64()
+        o = ctypes.c_int32()
+        N.check(L.gsp_list_pairs(context(self.device), _ptr(self.lists), _stream(),
+                                 ctypes.byref(q), ctypes.byref(o)), "gsp_list_pairs")
+        return q.value, bool(o.value)
+
     def overflowed(self):
-        return self.instances()[1]
+        ovf = self.instances()[1]
+        if self.store_lists and self.lists is not None:
+            ovf = ovf or self.list_pairs()[1]
+        return ovf
 
     # -- forward / backward ------------------------------------------------
     def forward(self, g: GaussianParams, cams: Sequence, poses: torch.Tensor,
@@ -192,21 +228,38 @@ class Rasterizer:
             al = alphas
         if self.capacity <= 0:
             self.capacity = max(1024, 8 * g.n * len(cams))
+        if self.store_lists and self.pair_capacity <= 0:
+            self.pair_capacity = 32 * P + 1024
         gs = g.struct()
         img_ptrs = view_ptrs(images, cams, 3)
         al_ptrs = view_ptrs(al, cams, 1)
         for _ in range(8):
             nbytes = self._ensure(g, views)
-            N.check(L.gsp_render_fwd(context(self.device), ctypes.byref(gs), len(cams), views,
-                                     _ptr(poses), img_ptrs, al_ptrs, _ptr(self.ws), nbytes,
-                                     self.capacity, _stream()), "gsp_render_fwd")
+            if self.store_lists:
+                lbytes = self._ensure_lists(views)
+                N.check(L.gsp_render_fwd_store(context(self.device), ctypes.byref(gs), len(cams),
+                                               views, _ptr(poses), img_ptrs, al_ptrs, _ptr(self.ws),
+                                               nbytes, self.capacity, _ptr(self.lists), lbytes,
+                                               self.pair_capacity, _stream()),
+                        "gsp_render_fwd_store")
+            else:
+                N.check(L.gsp_render_fwd(context(self.device), ctypes.byref(gs), len(cams), views,
+                                         _ptr(poses), img_ptrs, al_ptrs, _ptr(self.ws), nbytes,
+                                         self.capacity, _stream()), "gsp_render_fwd")
             if not check:
                 break
             m, ovf = self.instances()
-            if not ovf:
-                break
-            self.capacity = int(m * self.growth) + 1024
-            self.ws = None       # reallocated (zeroed) at the larger size
+            if ovf:
+                self.capacity = int(m * self.growth) + 1024
+                self.ws = None       # reallocated (zeroed) at the larger size
+                continue
+            if self.store_lists:
+                q, lovf = self.list_pairs()
+                if lovf:
+                    self.pair_capacity = int(q * self.growth) + 1024
+                    self.lists = None
+                    continue
+            break
         self.generation += 1
         return images, al
 
@@ -231,11 +284,20 @@ class Rasterizer:
                        for k in ("means", "scales", "quats", "opacities", "sh", "pose")])
         gs = g.struct()
         nbytes = self._ws_bytes(g.n, g.sh_degree, views, self.capacity)
-        N.check(L.gsp_render_bwd(context(self.device), ctypes.byref(gs), len(cams), views,
-                                 _ptr(poses.contiguous()), view_ptrs(dl_dimages, cams, 3),
-                                 _ptr(self.ws), nbytes, self.capacity, ctypes.byref(gr),
-                                 N.GSP_ACCUMULATE if accumulate else 0, _stream()),
-                "gsp_render_bwd")
+        flags = N.GSP_ACCUMULATE if accumulate else 0
+        if self.store_lists:
+            N.check(L.gsp_render_bwd_stored(context(self.device), ctypes.byref(gs), len(cams),
+                                            views, _ptr(poses.contiguous()),
+                                            view_ptrs(dl_dimages, cams, 3), _ptr(self.ws), nbytes,
+                                            self.capacity, _ptr(self.lists),
+                                            self._lists_bytes(views), self.pair_capacity,
+                                            ctypes.byref(gr), flags, _stream()),
+                    "gsp_render_bwd_stored")
+        else:
+            N.check(L.gsp_render_bwd(context(self.device), ctypes.byref(gs), len(cams), views,
+                                     _ptr(poses.contiguous()), view_ptrs(dl_dimages, cams, 3),
+                                     _ptr(self.ws), nbytes, self.capacity, ctypes.byref(gr), flags,
+                                     _stream()), "gsp_render_bwd")
         return out
 
     def inspect(self, g: GaussianParams, cams: Sequence, name: str, dtype=torch.float32):
