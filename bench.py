@@ -199,6 +199,21 @@ def main():
     rot0, trans0 = S.pose_error(wl.init_pose, wl.pose)
     print(f"[bench] {K} steps: {ms_step:.3f} ms/step, {value:.1f} Mpix/s; pose error "
           f"{rot0:.2f} deg/{trans0:.3f} -> {rot_err:.3f} deg/{trans_err:.4f}", file=sys.stderr, flush=True)
+    # the 100-step solve of the workload, whatever --steps is
+    s100 = new_state()
+    torch.cuda.synchronize()
+    e0.record()
+    for _ in range(100):
+        step(s100, 100)
+    e1.record()
+    torch.cuda.synchronize()
+    ms100 = e0.elapsed_time(e1)
+    rot100, trans100 = S.pose_error(s100["pose"][0].cpu().numpy(), wl.pose)
+    if rast.instances()[1]:
+        print("[bench] instance capacity overflowed during the 100-step solve", file=sys.stderr)
+        sys.exit(3)
+    print(f"[bench] 100-step solve: {ms100:.1f} ms, error {rot0:.2f} deg/{trans0:.3f} -> "
+          f"{rot100:.4f} deg/{trans100:.5f}", file=sys.stderr, flush=True)
     if args.profile_only:
         if args.calibrate_copy > 0:
             n = args.calibrate_copy << 18
@@ -279,24 +294,23 @@ def main():
     roof["avg_launch_ms"] = round(dms, 4)
     roof["algorithmic_per_launch"] = amount
     roof["traffic"] = traffic_from_profiles(dominant, "pose-200k-1008x756")
+    if kind == "alu":
+        roof["peak_note"] = ("unpacked FP32 FMA rate, 256 CU x 64 lanes x 2 flops x 2.4 GHz; the "
+                             "published 157.3 TFLOP/s counts packed FP32 instructions, which this "
+                             "build disables")
+        roof["frac_of_published_157_3"] = round(ach / 157.3, 4)
+    # roofline-bound time of the whole step: each stage at its own bound
+    t_roof = 0.0
+    for k, ms in stage_ms.items():
+        kind_k, amt = work.get(k, ("hbm", 0))
+        t_roof += amt / (PEAK_FP32_TFLOPS * 1e12) if kind_k == "alu" else amt / (PEAK_HBM_GBS * 1e9)
+    step_roof = {"t_roof_ms": round(t_roof * 1e3, 4),
+                 "rate_at_roof_mpix_s": round(P / t_roof / 1e6, 1) if t_roof > 0 else None,
+                 "frac": round(t_roof * 1e3 / ms_step, 4)}
 
     cpu = None
     if not args.no_cpu:
-        import oracle
-        ts = []
-        for _ in range(args.cpu_reps):
-            t0 = time.perf_counter()
-            oracle.render(wl.scene, cam, wl.init_pose)
-            up = np.zeros((3, cam.height, cam.width))
-            oracle.backward(wl.scene, cam, wl.init_pose, up)
-            ts.append(time.perf_counter() - t0)
-        t = float(np.median(ts))
-        cpu = {"value": round(P / t / 1e6, 4), "unit": "Mpix/s", "cores": oracle.max_threads(),
-               "kind": "oracle",
-               "sample": f"one fwd render + one bwd (pose and Gaussian grads) of the full "
-                         f"{cam.width}x{cam.height} view of the 200k-Gaussian scene at the "
-                         f"starting pose, FP64, median of {args.cpu_reps}",
-               "seconds": round(t, 3)}
+        cpu = cpu_baseline(args, wl)
 
     tiny = None
     if not args.no_tiny:
@@ -324,6 +338,7 @@ def main():
                    "width": cam.width, "height": cam.height, "views_per_step": 1,
                    "step": "fwd+L1+bwd(pose)+adam", "parallelism": "single GPU"},
         "roofline": roof,
+        "step_roofline": step_roof,
         "cpu_baseline": cpu,
         "tiny": tiny,
         "joint": joint,
@@ -334,10 +349,10 @@ def main():
         "stages": stage_report,
         "work": {"instances": M, "evaluated_pairs": neval, "blended_pairs": nblend,
                  "backward_pairs": ncontrib, **lockstep},
-        "pose_solve": {"steps": K, "seconds": round(total_ms * 1e-3, 4),
-                       "sequential_requests_per_s": round(1e3 / total_ms, 3),
+        "pose_solve": {"steps": 100, "seconds": round(ms100 * 1e-3, 4),
                        "initial_error": [round(rot0, 3), round(trans0, 4)],
-                       "final_error": [round(rot_err, 4), round(trans_err, 5)]},
+                       "final_error": [round(rot100, 4), round(trans100, 5)],
+                       "timed_steps_final_error": [round(rot_err, 4), round(trans_err, 5)]},
     }
     print(json.dumps(line), flush=True)
 
@@ -371,6 +386,69 @@ def multi_hypothesis_section(g, cam, target, wl, dev):
     print(f"[bench] multi-hypothesis (8 starts, 100 steps): se3 {out['se3']['ms']} ms, "
           f"t_so3 {out['t_so3']['ms']} ms, errors {out['se3']['final_error']} / "
           f"{out['t_so3']['final_error']}", file=sys.stderr, flush=True)
+    return out
+
+
+def cpu_baseline(args, wl):
+    """The FP64 CPU oracle timed on this host (a baseline, not the target):
+    one forward render + one backward (every Gaussian gradient and the pose
+    twist) of a seeded random upstream gradient.  `value` is the benchmark
+    view (200k Gaussians, 1008x756) on all of the oracle's OpenMP threads;
+    the same view on one thread, the tiny workload (1k Gaussians, 128x128)
+    on all threads and on one, and one frame of the tracking room (500k
+    Gaussians, 1200x680) on all threads are reported beside it.  Median of
+    `cpu_reps` runs (of 3 for the room frame, 1 for the single-threaded
+    benchmark view)."""
+    import numpy as np
+
+    import oracle
+    from paper_2410_08743_amd import synthetic as S
+
+    model = "unknown"
+    try:
+        with open("/proc/cpuinfo") as f:
+            for ln in f:
+                if ln.startswith("model name"):
+                    model = ln.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    threads = oracle.max_threads()
+
+    def timed(scene, cam, pose, reps, seed):
+        h, w = cam.region()[3], cam.region()[2]
+        up = S.upstream(seed, (3, h, w))
+        ts = []
+        for _ in range(reps):
+            t0 = time.perf_counter()
+            oracle.render(scene, cam, pose)
+            oracle.backward(scene, cam, pose, up)
+            ts.append(time.perf_counter() - t0)
+        t = float(np.median(ts))
+        return {"mpix_per_s": round(h * w / t / 1e6, 4), "seconds": round(t, 3), "runs": reps}
+
+    cam = wl.camera
+    main = timed(wl.scene, cam, wl.init_pose, args.cpu_reps, 111)
+    tiny = S.tiny()
+    out = {"value": main["mpix_per_s"], "unit": "Mpix/s", "cores": threads, "kind": "oracle",
+           "sample": f"one fwd render + one bwd (pose and every Gaussian gradient, seeded random "
+                     f"upstream gradient) of the full {cam.width}x{cam.height} view of the "
+                     f"200k-Gaussian scene at the starting pose, FP64, median of {args.cpu_reps}",
+           "seconds": main["seconds"], "cpu_model": model,
+           "tiny_1k_128x128": timed(tiny.scene, tiny.camera, tiny.pose, 5, 112)}
+    room = S.room(n_frames=61)
+    out["room_500k_1200x680_frame"] = timed(room.scene, room.camera,
+                                            room.extra["trajectory"][60], 3, 113)
+    oracle.set_threads(1)
+    try:
+        out["single_thread"] = {
+            "benchmark_view": timed(wl.scene, cam, wl.init_pose, 1, 111),
+            "tiny_1k_128x128": timed(tiny.scene, tiny.camera, tiny.pose, 3, 112)}
+    finally:
+        oracle.set_threads(threads)
+    print(f"[bench] cpu oracle ({model}, {threads} threads): {main['mpix_per_s']} Mpix/s; one "
+          f"thread {out['single_thread']['benchmark_view']['mpix_per_s']} Mpix/s",
+          file=sys.stderr, flush=True)
     return out
 
 
@@ -525,11 +603,66 @@ def joint_section(args, dev):
     R.profile_enable(0, 0)
     print(f"[bench] joint step: {ms:.3f} ms for {V} views ({V * P / (ms * 1e3):.1f} Mpix/s) {stages}",
           file=sys.stderr, flush=True)
+    # work counters of one step (the forward's per-pixel evaluated and
+    # blended pairs, the contributor counts, the instances)
+    R.profile_enable(0, R.PROFILE_COUNTS)
+    a, b = ref.batches[ref.k % len(ref.batches)]
+    ref.step()
+    R.profile_enable(0, 0)
+    cams = ref.cams[a:b]
+    cnt = lambda name: int(ref.rast.inspect(ref.g, cams, name, torch.int32).to(torch.int64).sum().item())
+    neval, nblend, ncontrib = cnt("neval"), cnt("nblend"), cnt("ncontrib")
+    Mj, _ = ref.rast.instances()
+    n, S3 = raw.n, 16
+    pb = 4 * (11 + 3 * S3)
+    tiles = V * ((cam.width + 15) // 16) * ((cam.height + 15) // 16)
+    work = {
+        "preprocess": ("hbm", pb * n + 64 * V * n),
+        "depth_sort": ("hbm", 16 * V * n),
+        "duplicate": ("hbm", 20 * V * n + 12 * Mj),
+        "tile_sort": ("hbm", 16 * Mj),
+        "ranges": ("hbm", 8 * Mj + 8 * tiles),
+        "raster_fwd": ("alu", FWD_FLOPS_EVAL * neval + FWD_FLOPS_BLEND * nblend),
+        "loss_rgb": ("hbm", 44 * 3 * P * V),
+        "raster_bwd": ("alu", BWD_FLOPS_EVAL * ncontrib + BWD_FLOPS_BLEND * nblend),
+        "preprocess_bwd": ("hbm", (pb - 4) * n + 36 * Mj + 8 * V * n + pb * n),
+        "gaussian_adam": ("hbm", 28 * (pb // 4) * n + 16 * n),
+        "pose_adam": ("hbm", 0),
+    }
+    report, t_roof = roofline_table(stages, work)
+    dominant = max(stages, key=stages.get)
     return {"workload": "joint-1M-4x1008x756-sh3", "gaussians": raw.n, "views_per_step": V,
             "steps": K, "ms_per_step": round(ms, 4), "mpix_per_s": round(V * P / (ms * 1e3), 2),
-            "instances": M, "stages_ms_per_step": stages,
+            "instances": M, "stages": report,
+            "work": {"instances": Mj, "evaluated_pairs": neval, "blended_pairs": nblend,
+                     "backward_pairs": ncontrib},
+            "roofline": {"kernel": dominant, **report[dominant]},
+            "step_roofline": {"t_roof_ms": round(t_roof * 1e3, 4),
+                              "rate_at_roof_mpix_s": round(V * P / t_roof / 1e6, 1),
+                              "frac": round(t_roof * 1e3 / ms, 4)},
             "step": "fwd + (0.8 L1 + 0.2 DSSIM) + bwd(all Gaussian params + 4 poses) "
                     "+ Gaussian Adam with L_An + pose Adam"}
+
+
+def roofline_table(stage_ms, work):
+    """Per stage: achieved rate of its algorithmic work (bytes for HBM-bound
+    stages, flops for ALU-bound ones) against its peak; and the roofline-
+    bound time of all stages, each at its own bound (seconds)."""
+    report, t_roof = {}, 0.0
+    for k, ms in stage_ms.items():
+        kind, amount = work.get(k, ("hbm", 0))
+        if kind == "hbm":
+            ach = amount / (ms * 1e-3) / 1e9
+            report[k] = {"ms": round(ms, 4), "bound": "hbm", "achieved": round(ach, 1),
+                         "peak": PEAK_HBM_GBS, "unit": "GB/s", "frac": round(ach / PEAK_HBM_GBS, 4)}
+            t_roof += amount / (PEAK_HBM_GBS * 1e9)
+        else:
+            ach = amount / (ms * 1e-3) / 1e12
+            report[k] = {"ms": round(ms, 4), "bound": "alu", "achieved": round(ach, 2),
+                         "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
+                         "frac": round(ach / PEAK_FP32_TFLOPS, 4)}
+            t_roof += amount / (PEAK_FP32_TFLOPS * 1e12)
+    return report, t_roof
 
 
 def relpose_section(args, dev):

@@ -266,6 +266,20 @@ gsp_status gsp_pose_adam(gsp_ctx *ctx, int32_t V, float *poses, const float *dpo
                          float *m, float *v, int32_t *steps, const gsp_adam_params *params,
                          const void *guard_workspace, void *stream);
 
+/* The pose a twist moves to, and the gradient on the twist itself (Sec.
+ * III-B: T(tau) = Exp(tau) T with the left perturbation, tau = (rho, phi)).
+ * gsp_twist_apply: out[v] = Exp(tau[v]) poses[v] (tau [V][6], poses and out
+ * [V][12] world->camera, device; out may alias poses).  gsp_twist_chain:
+ * given dpose[v], the twist gradient that gsp_render_bwd returns at the pose
+ * Exp(tau[v]) poses[v], writes dtau[v] = dL/dtau[v] = J(tau[v])^T dpose[v],
+ * J the left Jacobian of SE(3) (Exp(tau + delta) = Exp(J delta) Exp(tau) to
+ * first order; J = I at tau = 0); dtau must not alias dpose.  V >= 1; FP64
+ * inside, FP32 stored. */
+gsp_status gsp_twist_apply(gsp_ctx *ctx, int32_t V, const float *tau, const float *poses,
+                           float *out, void *stream);
+gsp_status gsp_twist_chain(gsp_ctx *ctx, int32_t V, const float *tau, const float *dpose,
+                           float *dtau, void *stream);
+
 /* Image loss of the joint refinement, L_RGB of Eq. (16), per view:
  *   loss[v] = (1 - beta) mean |pred - target| + beta (1 - mean SSIM(pred, target))
  * over the 3 x roi_h x roi_w values of view v, and grad[v] = dloss[v]/dpred[v]

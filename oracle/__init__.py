@@ -19,7 +19,7 @@ __all__ = [
     "load", "SPLAT_DTYPE", "TRACE_DTYPE", "sh_basis", "quat_to_rotmat",
     "se3_exp", "se3_retract", "preprocess", "count_instances", "bin_sort",
     "tile_ranges", "render", "render_brute", "pixel_trace", "backward", "l1",
-    "masked_l1", "pose_adam", "TILE", "tiles_of", "max_threads",
+    "masked_l1", "pose_adam", "TILE", "tiles_of", "max_threads", "set_threads",
 ]
 
 TILE = 16
@@ -74,6 +74,7 @@ def load():
     lib = ctypes.CDLL(LIB)
     P = ctypes.c_void_p
     lib.gso_max_threads.restype = ctypes.c_int
+    lib.gso_set_threads.argtypes = [ctypes.c_int]
     lib.gso_sh_basis.argtypes = [ctypes.c_int, P, P, P]
     lib.gso_quat_to_rotmat.argtypes = [P, P]
     lib.gso_se3_exp.argtypes = [P, P]
@@ -143,6 +144,11 @@ def _pose(pose):
 
 def max_threads():
     return int(load().gso_max_threads())
+
+
+def set_threads(n):
+    """Number of OpenMP threads of later oracle calls."""
+    load().gso_set_threads(int(n))
 
 
 def tiles_of(cam):

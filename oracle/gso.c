@@ -47,6 +47,15 @@ int gso_max_threads(void)
 #endif
 }
 
+void gso_set_threads(int n)
+{
+#ifdef _OPENMP
+    if (n >= 1) omp_set_num_threads(n);
+#else
+    (void)n;
+#endif
+}
+
 /* ------------------------------------------------------------------------ */
 /* Real spherical harmonics, degree <= 3 (Sec. III-A: c = SH(f, d)).          */
 /* ------------------------------------------------------------------------ */

@@ -110,6 +110,8 @@ int gso_version(void);
 
 /* OpenMP threads the oracle's parallel loops use. */
 int gso_max_threads(void);
+/* Sets the number of OpenMP threads later calls use (n >= 1). */
+void gso_set_threads(int n);
 
 /* Real spherical harmonics up to degree 3 (Condon-Shortley phase, order
  * m = -l..l) at direction d; writes (degree+1)^2 values and, if grad is not

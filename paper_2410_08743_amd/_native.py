@@ -23,7 +23,8 @@ EXPORTS = (
     "gsp_gaussian_adam", "gsp_gaussian_adam_scratch_bytes", "gsp_unproject_count",
     "gsp_unproject_scratch_bytes", "gsp_unproject", "gsp_loss_masked_l1",
     "gsp_loss_masked_l1_scratch_bytes", "gsp_loss_l1_noalloc", "gsp_render_fwd_store",
-    "gsp_render_bwd_stored", "gsp_lists_bytes", "gsp_list_pairs",
+    "gsp_render_bwd_stored", "gsp_lists_bytes", "gsp_list_pairs", "gsp_twist_apply",
+    "gsp_twist_chain",
 )
 
 
@@ -122,6 +123,8 @@ def lib():
                                    P], I32),
         "gsp_lists_bytes": ([I32, P, I64], SZ),
         "gsp_list_pairs": ([P, P, P, ctypes.POINTER(I64), ctypes.POINTER(I32)], I32),
+        "gsp_twist_apply": ([P, I32, P, P, P, P], I32),
+        "gsp_twist_chain": ([P, I32, P, P, P, P], I32),
         "gsp_status_string": ([I32], ctypes.c_char_p),
         "gsp_last_error": ([], ctypes.c_char_p),
         "gsp_version": ([], ctypes.c_int),

@@ -685,6 +685,29 @@ size_t gsp_loss_l1_scratch_bytes(int32_t V, const gsp_view *views) {
     return (size_t)(blocks > 0 ? blocks : 1) * sizeof(double);
 }
 
+gsp_status gsp_twist_apply(gsp_ctx *ctx, int32_t V, const float *tau, const float *poses,
+                           float *out, void *stream) {
+    gsp_status s = check_device(ctx);
+    if (s != GSP_OK) return s;
+    if (V < 1) return fail(GSP_EINVAL, "view count must be positive");
+    if (!tau || !poses || !out) return fail(GSP_EINVAL, "null argument");
+    hipError_t e = gsp::launch_twist_apply(V, tau, poses, out, static_cast<hipStream_t>(stream));
+    if (e != hipSuccess) return hip_fail(e, "twist apply");
+    return GSP_OK;
+}
+
+gsp_status gsp_twist_chain(gsp_ctx *ctx, int32_t V, const float *tau, const float *dpose,
+                           float *dtau, void *stream) {
+    gsp_status s = check_device(ctx);
+    if (s != GSP_OK) return s;
+    if (V < 1) return fail(GSP_EINVAL, "view count must be positive");
+    if (!tau || !dpose || !dtau) return fail(GSP_EINVAL, "null argument");
+    if (dpose == dtau) return fail(GSP_EINVAL, "dtau may not alias dpose");
+    hipError_t e = gsp::launch_twist_chain(V, tau, dpose, dtau, static_cast<hipStream_t>(stream));
+    if (e != hipSuccess) return hip_fail(e, "twist chain");
+    return GSP_OK;
+}
+
 gsp_status gsp_pose_adam(gsp_ctx *ctx, int32_t V, float *poses, const float *dpose, float *m,
                          float *v, int32_t *steps, const gsp_adam_params *params,
                          const void *guard_workspace, void *stream) {

@@ -207,6 +207,9 @@ hipError_t launch_loss_l1(const LossViewsK &lv, float *loss, void *partial_buf, 
 // address on `device` (looked up once per device; thread-safe).
 constexpr size_t kNoAllocScratchBytes = GSP_NOALLOC_SCRATCH_BYTES;
 hipError_t noalloc_scratch_init(int device, void **ptr);
+hipError_t launch_twist_apply(int V, const float *tau, const float *poses, float *out,
+                              hipStream_t s);
+hipError_t launch_twist_chain(int V, const float *tau, const float *g, float *out, hipStream_t s);
 hipError_t launch_pose_adam(int V, float *poses, const float *dpose, float *m, float *v,
                             int32_t *steps, const gsp_adam_params &p, const uint32_t *guard,
                             hipStream_t s);

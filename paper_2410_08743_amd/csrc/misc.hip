@@ -228,4 +228,100 @@ hipError_t launch_pose_adam(int V, float *poses, const float *dpose, float *m, f
     return hipGetLastError();
 }
 
+// T' = Exp(tau) T per view: the pose a twist tau moves the world->camera
+// pose T to under the left perturbation of Sec. III-B (FP64, stored FP32).
+__global__ __launch_bounds__(64) void k_twist_apply(int V, const float *tau, const float *poses,
+                                                    float *out) {
+    const int v = blockIdx.x * 64 + threadIdx.x;
+    if (v >= V) return;
+    double d[6];
+    for (int k = 0; k < 6; k++) d[k] = tau[6 * v + k];
+    float T[12];
+    for (int k = 0; k < 12; k++) T[k] = poses[12 * v + k];
+    se3_retract_left(d, T);
+    for (int k = 0; k < 12; k++) out[12 * v + k] = T[k];
+}
+
+// dL/dtau at tau from the twist gradient g at T' = Exp(tau) T: since
+// Exp(tau + delta) = Exp(J(tau) delta) Exp(tau) to first order, with J the
+// left Jacobian of SE(3) for tau = (rho, phi),
+//   J = [[Jr, Q], [0, Jr]],  Jr = I + b [phi]x + c [phi]x^2,
+//   Q = 1/2 [rho]x + c (P R + R P + P R P) + e (P P R + R P P - 3 P R P)
+//       + f (P R P P + P P R P),   P = [phi]x, R = [rho]x,
+// b = (1 - cos t) / t^2, c = (t - sin t) / t^3, e = (t^2/2 + cos t - 1) / t^4,
+// f = (e + 3 (t - sin t - t^3/6) / t^5) / 2, t = |phi| (series below 1e-2),
+// the gradient is J^T g: (Jr^T g_rho, Q^T g_rho + Jr^T g_phi).
+__device__ void mat3_mul_d(const double *A, const double *B, double *C) {
+    for (int r = 0; r < 3; r++)
+        for (int c = 0; c < 3; c++)
+            C[3 * r + c] = A[3 * r] * B[c] + A[3 * r + 1] * B[3 + c] + A[3 * r + 2] * B[6 + c];
+}
+
+__global__ __launch_bounds__(64) void k_twist_chain(int V, const float *tau, const float *g,
+                                                    float *out) {
+    const int v = blockIdx.x * 64 + threadIdx.x;
+    if (v >= V) return;
+    const double r0 = tau[6 * v], r1 = tau[6 * v + 1], r2 = tau[6 * v + 2];
+    const double p0 = tau[6 * v + 3], p1 = tau[6 * v + 4], p2 = tau[6 * v + 5];
+    const double t2 = p0 * p0 + p1 * p1 + p2 * p2, t = sqrt(t2);
+    double b, c, e, f;
+    if (t < 1e-2) {
+        b = 0.5 - t2 / 24 + t2 * t2 / 720;
+        c = 1.0 / 6 - t2 / 120 + t2 * t2 / 5040;
+        e = 1.0 / 24 - t2 / 720 + t2 * t2 / 40320;
+        const double h = -1.0 / 120 + t2 / 5040 - t2 * t2 / 362880;   // (t - sin t - t^3/6) / t^5
+        f = 0.5 * (e + 3.0 * h);
+    } else {
+        const double st = sin(t), ct = cos(t);
+        b = (1 - ct) / t2;
+        c = (t - st) / (t2 * t);
+        e = (0.5 * t2 + ct - 1) / (t2 * t2);
+        f = 0.5 * (e + 3.0 * (t - st - t2 * t / 6) / (t2 * t2 * t));
+    }
+    const double P[9] = {0, -p2, p1, p2, 0, -p0, -p1, p0, 0};
+    const double R[9] = {0, -r2, r1, r2, 0, -r0, -r1, r0, 0};
+    double PP[9], PR[9], RP[9], PRP[9], PPR[9], RPP[9], PRPP[9], PPRP[9];
+    mat3_mul_d(P, P, PP);
+    mat3_mul_d(P, R, PR);
+    mat3_mul_d(R, P, RP);
+    mat3_mul_d(PR, P, PRP);
+    mat3_mul_d(PP, R, PPR);
+    mat3_mul_d(RP, P, RPP);
+    mat3_mul_d(PRP, P, PRPP);
+    mat3_mul_d(PP, RP, PPRP);
+    double Jr[9], Q[9];
+    for (int k = 0; k < 9; k++) {
+        Jr[k] = (k % 4 == 0 ? 1.0 : 0.0) + b * P[k] + c * PP[k];
+        Q[k] = 0.5 * R[k] + c * (PR[k] + RP[k] + PRP[k]) + e * (PPR[k] + RPP[k] - 3.0 * PRP[k]) +
+               f * (PRPP[k] + PPRP[k]);
+    }
+    double gr[3], gp[3];
+    for (int k = 0; k < 3; k++) {
+        gr[k] = g[6 * v + k];
+        gp[k] = g[6 * v + 3 + k];
+    }
+    for (int k = 0; k < 3; k++) {
+        double a = 0, q = 0;
+        for (int i = 0; i < 3; i++) {
+            a += Jr[3 * i + k] * gr[i];
+            q += Q[3 * i + k] * gr[i] + Jr[3 * i + k] * gp[i];
+        }
+        out[6 * v + k] = (float)a;
+        out[6 * v + 3 + k] = (float)q;
+    }
+}
+
+hipError_t launch_twist_apply(int V, const float *tau, const float *poses, float *out,
+                              hipStream_t s) {
+    if (V <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_twist_apply, dim3((V + 63) / 64), dim3(64), 0, s, V, tau, poses, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_twist_chain(int V, const float *tau, const float *g, float *out, hipStream_t s) {
+    if (V <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_twist_chain, dim3((V + 63) / 64), dim3(64), 0, s, V, tau, g, out);
+    return hipGetLastError();
+}
+
 }  // namespace gsp

@@ -61,27 +61,42 @@ __global__ __launch_bounds__(kSortThreads) void k_sort_hist(SortPass a) {
 
 // One block per digit: exclusive scan of that digit's counts across blocks
 // (a row of up to tens of thousands of counts for the instance sort of a
-// multi-view call, hence the wide block).
+// multi-view call).  The row is scanned in chunks of 4 x 1024 counts: each
+// thread loads four consecutive counts of the chunk (the wave's loads cover
+// 1 KB contiguously), the block scans the per-thread sums, and the running
+// total carries from chunk to chunk.
 constexpr int kSortScanThreads = 1024;
+constexpr int kSortScanChunk = 4 * kSortScanThreads;
 
 __global__ __launch_bounds__(kSortScanThreads) void k_sort_scan(SortPass a) {
     __shared__ uint32_t scratch[kSortScanThreads / kWave];
     const int t = threadIdx.x;
     uint32_t *row = a.hist + (size_t)blockIdx.x * a.nblk;
-    const int per = (a.nblk + kSortScanThreads - 1) / kSortScanThreads;
-    const int begin = min(t * per, a.nblk), end = min(begin + per, a.nblk);
-    uint32_t local = 0;
-    for (int k = begin; k < end; k++) local += row[k];
-    uint32_t total;
-    uint32_t off = block_exclusive_scan<uint32_t, kSortScanThreads>(local, scratch, &total);
-    for (int k = begin; k < end; k++) {
-        const uint32_t x = row[k];
-        row[k] = off;
-        off += x;
+    uint32_t carry = 0;
+    for (int c0 = 0; c0 < a.nblk; c0 += kSortScanChunk) {
+        const int k0 = c0 + 4 * t;
+        uint32_t x[4];
+#pragma unroll
+        for (int j = 0; j < 4; j++) x[j] = k0 + j < a.nblk ? row[k0 + j] : 0u;
+        const uint32_t local = x[0] + x[1] + x[2] + x[3];
+        uint32_t total;
+        uint32_t off = carry + block_exclusive_scan<uint32_t, kSortScanThreads>(local, scratch, &total);
+#pragma unroll
+        for (int j = 0; j < 4; j++) {
+            if (k0 + j < a.nblk) row[k0 + j] = off;
+            off += x[j];
+        }
+        carry += total;
     }
-    if (t == 0) a.digit_tot[blockIdx.x] = total;
+    if (t == 0) a.digit_tot[blockIdx.x] = carry;
 }
 
+// With few blocks the scatter scans the histogram itself (FUSED): thread d
+// sums row d of the unscanned counts over the blocks in front of its own and
+// over all blocks, which saves the scan's launch.
+constexpr int kFusedScanMaxBlocks = 256;
+
+template <bool FUSED>
 __global__ __launch_bounds__(kSortThreads) void k_sort_scatter(SortPass a) {
     constexpr int NW = kSortThreads / kWave;
     __shared__ uint32_t skeys[kSortItems];
@@ -122,10 +137,33 @@ __global__ __launch_bounds__(kSortThreads) void k_sort_scatter(SortPass a) {
     __syncthreads();
     uint32_t tot;
     const uint32_t excl = block_exclusive_scan<uint32_t, kSortThreads>(run[t], scratch, &tot);
-    const uint32_t dex = block_exclusive_scan<uint32_t, kSortThreads>(a.digit_tot[t], scratch, &tot);
+    uint32_t digit_total, before;
+    if (FUSED) {
+        const uint32_t *row = a.hist + (size_t)t * a.nblk;
+        uint32_t s0 = 0, s1 = 0, b0 = 0, b1 = 0;
+        const int me = (int)blockIdx.x;
+        int k = 0;
+        for (; k + 1 < a.nblk; k += 2) {
+            const uint32_t x0 = row[k], x1 = row[k + 1];
+            s0 += x0;
+            s1 += x1;
+            b0 += k < me ? x0 : 0u;
+            b1 += k + 1 < me ? x1 : 0u;
+        }
+        if (k < a.nblk) {
+            s0 += row[k];
+            b0 += k < me ? row[k] : 0u;
+        }
+        digit_total = s0 + s1;
+        before = b0 + b1;
+    } else {
+        digit_total = a.digit_tot[t];
+        before = a.hist[(size_t)t * a.nblk + blockIdx.x];
+    }
+    const uint32_t dex = block_exclusive_scan<uint32_t, kSortThreads>(digit_total, scratch, &tot);
     dstart[t] = excl;
     run[t] = excl;
-    gbase[t] = dex + a.hist[(size_t)t * a.nblk + blockIdx.x];
+    gbase[t] = dex + before;
     __syncthreads();
 
     // stable ranking, round by round, wave by wave, lane by lane
@@ -196,8 +234,12 @@ int launch_sort_pairs(uint32_t *k0, uint32_t *v0, uint32_t *k1, uint32_t *v1, ui
         a.shift = p * pbits;
         if (p > 0 || !hist0_given)
             hipLaunchKernelGGL(k_sort_hist, dim3(a.nblk), dim3(kSortThreads), 0, s, a);
-        hipLaunchKernelGGL(k_sort_scan, dim3(kSortBins), dim3(kSortScanThreads), 0, s, a);
-        hipLaunchKernelGGL(k_sort_scatter, dim3(a.nblk), dim3(kSortThreads), 0, s, a);
+        if (a.nblk <= kFusedScanMaxBlocks) {
+            hipLaunchKernelGGL(k_sort_scatter<true>, dim3(a.nblk), dim3(kSortThreads), 0, s, a);
+        } else {
+            hipLaunchKernelGGL(k_sort_scan, dim3(kSortBins), dim3(kSortScanThreads), 0, s, a);
+            hipLaunchKernelGGL(k_sort_scatter<false>, dim3(a.nblk), dim3(kSortThreads), 0, s, a);
+        }
         *err = hipGetLastError();
         if (*err != hipSuccess) return passes;
     }

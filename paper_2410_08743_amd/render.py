@@ -383,19 +383,46 @@ def pose_adam(poses, dpose, m, v, steps, lr_start, lr_end, total_steps, beta1=0.
                             _stream()), "gsp_pose_adam")
 
 
+def twist_apply(tau: torch.Tensor, poses: torch.Tensor, out: Optional[torch.Tensor] = None):
+    """Exp(tau) poses per view (left perturbation; tau [V, 6] = (rho, phi),
+    poses [V, 3, 4] world->camera)."""
+    tau = tau.contiguous()
+    poses = poses.contiguous()
+    out = torch.empty_like(poses) if out is None else out
+    N.check(N.lib().gsp_twist_apply(context(poses.device.index), poses.shape[0], _ptr(tau),
+                                    _ptr(poses), _ptr(out), _stream()), "gsp_twist_apply")
+    return out
+
+
+def twist_chain(tau: torch.Tensor, dpose: torch.Tensor):
+    """dL/dtau from the twist gradient at Exp(tau) poses: J(tau)^T dpose,
+    J the left Jacobian of SE(3)."""
+    tau = tau.contiguous()
+    dpose = dpose.contiguous()
+    out = torch.empty_like(dpose)
+    N.check(N.lib().gsp_twist_chain(context(dpose.device.index), dpose.shape[0], _ptr(tau),
+                                    _ptr(dpose), _ptr(out), _stream()), "gsp_twist_chain")
+    return out
+
+
 class _RenderFn(torch.autograd.Function):
     @staticmethod
-    def forward(ctx, means, scales, quats, opacities, sh, tau, poses, cams, sh_degree, rast, check):
+    def forward(ctx, means, scales, quats, opacities, sh, tau, poses, cams, sh_degree, rast, check,
+                apply_tau):
         g = GaussianParams(means.contiguous(), scales.contiguous(), quats.contiguous(),
                            opacities.contiguous(), sh.contiguous(), sh_degree)
-        images, _ = rast.forward(g, cams, poses.detach(), check=check)
+        at = poses.detach().contiguous()
+        if apply_tau:
+            at = twist_apply(tau.detach(), at)
+        images, _ = rast.forward(g, cams, at, check=check)
         ctx.g, ctx.cams, ctx.rast, ctx.generation = g, cams, rast, rast.generation
-        ctx.save_for_backward(poses)
+        ctx.apply_tau = apply_tau
+        ctx.save_for_backward(at, tau.detach() if apply_tau else None)
         return images
 
     @staticmethod
     def backward(ctx, dl):
-        (poses,) = ctx.saved_tensors
+        at, tau = ctx.saved_tensors
         if ctx.rast.generation != ctx.generation:
             raise RuntimeError(
                 "the Rasterizer rendered again after this forward, so its workspace no longer "
@@ -404,10 +431,12 @@ class _RenderFn(torch.autograd.Function):
         names = ("means", "scales", "quats", "opacities", "sh")
         want = tuple(k for k, need in zip(names, ctx.needs_input_grad[:5]) if need)
         need_pose = ctx.needs_input_grad[5]
-        out = ctx.rast.backward(ctx.g, ctx.cams, poses.detach(), dl.contiguous(), want=want,
-                                pose=need_pose)
+        out = ctx.rast.backward(ctx.g, ctx.cams, at, dl.contiguous(), want=want, pose=need_pose)
         grads = [out.get(k) for k in names]
-        return (*grads, out.get("pose"), None, None, None, None, None)
+        dtau = out.get("pose")
+        if dtau is not None and ctx.apply_tau:
+            dtau = twist_chain(tau, dtau)
+        return (*grads, dtau, None, None, None, None, None, None)
 
 
 def render(g: GaussianParams, cams: Sequence, poses: torch.Tensor, tau: Optional[torch.Tensor] = None,
@@ -416,16 +445,20 @@ def render(g: GaussianParams, cams: Sequence, poses: torch.Tensor, tau: Optional
 
     `params` (optional) is a tuple (means, scales, quats, opacities, sh) of
     tensors that require grad; by default the tensors of `g` are used.  `tau`
-    ([V, 6], zeros) receives dL/dtau, the left se(3) twist gradient at the
-    given poses (tau is a tangent at `poses` and is not applied to them).
-    With check=False nothing synchronises; `rast.overflowed()` then tells
-    afterwards whether any render ran out of instance capacity.
+    ([V, 6], (rho, phi) per view, optional) moves the poses: the views are
+    rendered at Exp(tau) poses (the left perturbation of Sec. III-B), and
+    tau.grad receives dL/dtau at the given tau (at tau = 0, the left se(3)
+    twist gradient at `poses`; elsewhere chained through the left Jacobian of
+    SE(3)), so tau may be optimised directly.  `poses` itself receives no
+    gradient.  With check=False nothing synchronises; `rast.overflowed()`
+    then tells afterwards whether any render ran out of instance capacity.
     """
     rast = rast or Rasterizer()
+    apply_tau = tau is not None
     if tau is None:
         tau = torch.zeros((len(cams), 6), dtype=torch.float32, device=poses.device)
     p = params or (g.means, g.scales, g.quats, g.opacities, g.sh)
-    return _RenderFn.apply(*p, tau, poses, list(cams), g.sh_degree, rast, check)
+    return _RenderFn.apply(*p, tau, poses, list(cams), g.sh_degree, rast, check, apply_tau)
 
 
 def solve_poses(g: GaussianParams, cams: Sequence, targets: torch.Tensor, init_poses: torch.Tensor,

@@ -463,3 +463,46 @@ def test_autograd_refuses_a_stale_forward():
         img1.sum().backward()
     img2.sum().backward()      # the latest forward still back-propagates
     assert torch.isfinite(params[0].grad).all()
+
+
+def _se3_hat(t):
+    X = np.zeros((4, 4))
+    r, p = t[:3], t[3:]
+    X[:3, :3] = [[0, -p[2], p[1]], [p[2], 0, -p[0]], [-p[1], p[0], 0]]
+    X[:3, 3] = r
+    return X
+
+
+def test_render_applies_a_nonzero_twist():
+    """render() with a nonzero tau renders at Exp(tau) T and returns dL/dtau
+    at that tau: the left twist gradient at the moved pose chained through
+    the left Jacobian of SE(3), here taken by central differences of
+    scipy's matrix exponential and logarithm."""
+    import scipy.linalg as sl
+    sc, cam, pose = random_case(104, 2, 64, 48, 400)
+    g = R.GaussianParams.from_set(sc, DEV)
+    tau0 = (np.random.default_rng(5).standard_normal(6) * 0.05).astype(np.float32)
+    tau = torch.tensor(tau0[None], device=DEV, requires_grad=True)
+    W = _upstream(105, cam)
+    img = R.render(g, [cam], torch.tensor(pose[None], device=DEV), tau=tau)
+    (img * torch.tensor(W.ravel(), device=DEV)).sum().backward()
+    H = np.vstack([pose.astype(np.float64), [0, 0, 0, 1]])
+    moved = (sl.expm(_se3_hat(tau0.astype(np.float64))) @ H)[:3].astype(np.float32)
+    ref = _gpu(sc, [cam], [moved], up=[W])
+    assert np.max(np.abs(img.detach().cpu().numpy().reshape(ref["images"][0].shape)
+                         - ref["images"][0])) <= 1e-4
+    E = sl.expm(_se3_hat(tau0.astype(np.float64)))
+    Ei = np.linalg.inv(E)
+    vee = lambda X: np.array([X[0, 3], X[1, 3], X[2, 3], X[2, 1], X[0, 2], X[1, 0]])
+    J = np.zeros((6, 6))
+    for j in range(6):
+        d = np.zeros(6)
+        d[j] = 1e-6
+        Jp = vee(sl.logm(sl.expm(_se3_hat(tau0 + d)) @ Ei).real)
+        Jm = vee(sl.logm(sl.expm(_se3_hat(tau0 - d)) @ Ei).real)
+        J[:, j] = (Jp - Jm) / 2e-6
+    expect = J.T @ ref["pose"][0].astype(np.float64)
+    got = tau.grad.cpu().numpy()[0]
+    print("tau grad", got, "expected", expect)
+    assert rel_l2(got, expect) <= 1e-4
+    assert rel_l2(got, ref["pose"][0]) > 1e-3    # the chain rule is not the identity here
