@@ -55,8 +55,8 @@ KERNEL_SOURCES = {
     "raster_fwd": ["raster_fwd.hip", "raster_common.h", "gsp_internal.h"],
     "raster_bwd": ["raster_bwd.hip", "raster_common.h", "gsp_internal.h"],
     "preprocess": ["preprocess.hip"],
-    "depth_sort": ["sort.hip"],
     "tile_sort": ["sort.hip"],
+    "depth_order": ["sort.hip"],
     "preprocess_bwd": ["preprocess_bwd.hip"],
 }
 
@@ -260,9 +260,9 @@ def main():
     work = {
         "preprocess": ("hbm", (param_bytes + 64) * n),
         "duplicate": ("hbm", 20 * n + 12 * M),
-        "depth_sort": ("hbm", 16 * n),
         "tile_sort": ("hbm", 16 * M),
         "ranges": ("hbm", 8 * M + 8 * ((cam.width + 15) // 16) * ((cam.height + 15) // 16)),
+        "depth_order": ("hbm", 12 * M),
         "raster_fwd": ("alu", FWD_FLOPS_EVAL * neval + FWD_FLOPS_BLEND * nblend),
         "loss_l1": ("hbm", 12 * 3 * P),
         "raster_bwd": ("alu", BWD_FLOPS_EVAL * ncontrib + BWD_FLOPS_BLEND * nblend),
@@ -618,10 +618,10 @@ def joint_section(args, dev):
     tiles = V * ((cam.width + 15) // 16) * ((cam.height + 15) // 16)
     work = {
         "preprocess": ("hbm", pb * n + 64 * V * n),
-        "depth_sort": ("hbm", 16 * V * n),
         "duplicate": ("hbm", 20 * V * n + 12 * Mj),
         "tile_sort": ("hbm", 16 * Mj),
         "ranges": ("hbm", 8 * Mj + 8 * tiles),
+        "depth_order": ("hbm", 12 * Mj),
         "raster_fwd": ("alu", FWD_FLOPS_EVAL * neval + FWD_FLOPS_BLEND * nblend),
         "loss_rgb": ("hbm", 44 * 3 * P * V),
         "raster_bwd": ("alu", BWD_FLOPS_EVAL * ncontrib + BWD_FLOPS_BLEND * nblend),

@@ -393,10 +393,10 @@ size_t gsp_loss_masked_l1_scratch_bytes(int32_t V, const gsp_view *views);
  * the conic [[A, B], [B, C]] stored as (A2, B2, C2) = -log2(e) (A/2, B, C/2)),
  * "color" (float4),
  * "rect" (uint16 x0 y0 x1 y1), "depth" (uint32 float bits), "tiles"
- * (uint32 count), "offsets" (uint32 first instance of each view-Gaussian),
+ * (uint32 count), "offsets" (uint32 first emission position, i.e. gradient
+ * slot, of each view-Gaussian, in index order),
  * "keys" (uint32 global tile id of each sorted instance; the depth part of
  * the 64-bit key is "depth" of its value), "values" (uint32 sorted),
- * "depth_order" (uint32 view-Gaussians in (depth, index) order),
  * "ranges" (uint32 pairs per tile), "tfinal" (float per pixel),
  * "ncontrib" (uint32 per pixel), "neval", "nblend" (uint32 per pixel, see
  * GSP_PROFILE_COUNTS), "grad2d" (float [V*n][9]: du dv dA dB dC
@@ -407,7 +407,7 @@ gsp_status gsp_inspect(gsp_ctx *ctx, const gsp_gaussians *g, int32_t V, const gs
 
 /* Measurement modes (bit mask for gsp_profile_enable).
  * GSP_PROFILE_TIMING: every stage of gsp_render_fwd / gsp_render_bwd
- * (preprocess, duplicate, sort, ranges, raster_fwd, raster_bwd,
+ * (preprocess, duplicate, tile_sort, ranges, depth_order, raster_fwd, raster_bwd,
  * preprocess_bwd) and the gsp_loss_l1, gsp_loss_rgb, gsp_pose_adam and
  * gsp_gaussian_adam kernels are
  * bracketed by HIP events recorded on the call's stream.

@@ -198,8 +198,7 @@ Layout make_layout(int64_t n, int32_t sh_degree, int32_t V, const ViewsK &views,
     L.total_pix = pix;
     L.nblk_pre = (int)((n + kPreprocessBlock - 1) / kPreprocessBlock);
     L.nblk_scan = (int)((L.vn + kScanItems - 1) / kScanItems);
-    const int64_t max_sorted = L.cap > L.vn ? L.cap : L.vn;
-    L.nblk_sort = (int)((max_sorted + kSortItems - 1) / kSortItems);
+    L.nblk_sort = (int)((L.cap + kSortItems - 1) / kSortItems);
     L.nblk_emit = (int)((L.cap + kSortItems - 1) / kSortItems);   // blocks of the instance sort
     L.tile_bits = tile_bits_for(views.total_tiles);
     L.tile_passes = sort_passes(L.tile_bits);
@@ -217,15 +216,13 @@ Layout make_layout(int64_t n, int32_t sh_degree, int32_t V, const ViewsK &views,
     L.rect = take(vn * 8);
     L.depth = take(vn * 4);
     L.tiles = take(vn * 4);
-    L.offsets = take(vn * 4);
-    L.offk = take((vn + 1) * 4);
+    L.offsets = take((vn + 1) * 4);
+    L.vis = take(vn * 4);
+    L.offv = take((vn + 1) * 4);
     L.wstart = take(((size_t)L.nwin_max + 1) * 4);
     L.pstart = take(((size_t)L.nblk_emit + 1) * 4);
     L.blocksum = take((size_t)L.nblk_scan * 8 + 8);
-    L.dkeys0 = take(vn * 4);
-    L.dkeys1 = take(vn * 4);
-    L.dvals0 = take(vn * 4);
-    L.dvals1 = take(vn * 4);
+    L.blockvis = take((size_t)L.nblk_scan * 4 + 4);
     L.keys0 = take(capz * 4);
     L.keys1 = take(capz * 4);
     L.vals0 = take(capz * 4);
@@ -417,9 +414,6 @@ gsp_status render_fwd(gsp_ctx *ctx, const gsp_gaussians *g, int32_t V, const gsp
              return gsp::launch_preprocess(gk, p.views, poses, p.L, ws, st);
          })) != hipSuccess)
         return hip_fail(e, "preprocess");
-    if ((e = stage(ctx, "depth_sort", st, [&] { return gsp::launch_depth_sort(p.L, ws, st); })) !=
-        hipSuccess)
-        return hip_fail(e, "depth sort");
     if ((e = stage(ctx, "duplicate", st, [&] {
              return gsp::launch_offsets_and_duplicate(p.views, p.L, ws, st);
          })) != hipSuccess)
@@ -432,6 +426,9 @@ gsp_status render_fwd(gsp_ctx *ctx, const gsp_gaussians *g, int32_t V, const gsp
     if ((e = stage(ctx, "ranges", st, [&] { return gsp::launch_ranges(p.L, ws, keys, st); })) !=
         hipSuccess)
         return hip_fail(e, "ranges");
+    if ((e = stage(ctx, "depth_order", st, [&] { return gsp::launch_tile_depth_sort(p.L, ws, st); })) !=
+        hipSuccess)
+        return hip_fail(e, "depth order");
     if ((e = stage(ctx, "raster_fwd", st, [&] {
              return gsp::launch_raster_fwd(p.views, p.L, ws, vals, ctx->stats, st);
          })) != hipSuccess)
@@ -591,7 +588,6 @@ gsp_status gsp_inspect(gsp_ctx *ctx, const gsp_gaussians *g, int32_t V, const gs
         {"offsets", L.offsets, L.vn},
         {"keys", gsp::sorted_keys(L), L.cap},
         {"values", gsp::sorted_vals(L), L.cap},
-        {"depth_order", L.dvals0, L.vn},
         {"ranges", L.ranges, L.total_tiles},
         {"tfinal", L.tfinal, L.total_pix},
         {"ncontrib", L.ncontrib, L.total_pix},

@@ -117,8 +117,8 @@ struct Layout {
     int64_t n, vn, cap, total_pix;
     int32_t V, S, total_tiles, nblk_pre, nblk_scan, nblk_sort, nblk_emit, tile_bits, tile_passes,
         nwin_max;
-    size_t geom, color, rect, depth, tiles, offsets, offk, wstart, pstart, blocksum, counters;
-    size_t dkeys0, dkeys1, dvals0, dvals1;
+    size_t geom, color, rect, depth, tiles, offsets, vis, offv, wstart, pstart, blocksum, blockvis,
+        counters;
     size_t keys0, keys1, vals0, vals1, hist, digit_tot, ranges, tile_order;
     size_t items, ckpt, cfinal;   // backward work items, states at the cuts, final colours
     int64_t max_items;
@@ -170,8 +170,8 @@ hipError_t launch_preprocess(const GaussiansK &g, const ViewsK &views, const flo
 hipError_t launch_offsets_and_duplicate(const ViewsK &views, const Layout &L, char *ws,
                                         hipStream_t s);
 // sort.hip
-hipError_t launch_depth_sort(const Layout &L, char *ws, hipStream_t s);
 hipError_t launch_tile_sort(const Layout &L, char *ws, hipStream_t s);
+hipError_t launch_tile_depth_sort(const Layout &L, char *ws, hipStream_t s);
 // raster_fwd.hip
 hipError_t launch_ranges(const Layout &L, char *ws, const uint32_t *keys, hipStream_t s);
 hipError_t launch_raster_fwd(const ViewsK &views, const Layout &L, char *ws,

@@ -1,5 +1,5 @@
 // preprocess.hip -- projection of every Gaussian into every view of a call,
-// and duplication of each projected splat into (tile | depth) sort keys.
+// and duplication of each projected splat into its tile instances.
 //
 // Sec. III-A: Sigma = R(q) diag(s)^2 R(q)^T (Eq. (1)); mu_hat = pi(K T mu);
 // Sigma_hat = [J R_c Sigma R_c^T J^T]_2x2 (Eq. (2)) plus a 0.3 px^2
@@ -28,8 +28,6 @@ struct PreArgs {
     uint2 *rect;                   // [vn]: x0 | y0 << 16, x1 | y1 << 16
     uint32_t *depth;               // [vn]: float bits of the key depth
     uint32_t *tiles;               // [vn]: tiles touched
-    uint32_t *dkeys;               // [vn]: depth-sort key (depth bits; ~0 when not drawn)
-    uint32_t *dvals;               // [vn]: view * n + i
 };
 
 template <int D>
@@ -174,37 +172,43 @@ __global__ __launch_bounds__(kPreprocessBlock) void k_preprocess(PreArgs a, View
             a.rect[idx] = rect;
             a.depth[idx] = __float_as_uint(zkey);
             a.tiles[idx] = cnt;
-            a.dkeys[idx] = cnt > 0 ? __float_as_uint(zkey) : 0xffffffffu;
-            a.dvals[idx] = (uint32_t)idx;
         }
     }
 }
 
-// Per-block sums of the tile counts, taken in depth order (kScanItems
-// splats per block, kScanPerThread consecutive ones per thread).
-__global__ __launch_bounds__(kPreprocessBlock) void k_sorted_blocksums(const uint32_t *order,
-                                                                       const uint32_t *tiles,
-                                                                       unsigned long long *bs,
-                                                                       int vn) {
+// Per-block sums of the tile counts of the view-Gaussians in index order
+// (kScanItems per block, kScanPerThread consecutive ones per thread), and
+// the number of them with at least one instance.
+__global__ __launch_bounds__(kPreprocessBlock) void k_blocksums(const uint32_t *tiles,
+                                                                unsigned long long *bs,
+                                                                uint32_t *bvis, int vn) {
     __shared__ unsigned long long red[kPreprocessBlock / kWave];
     const int k0 = blockIdx.x * kScanItems + kScanPerThread * threadIdx.x;
-    unsigned long long cnt = 0;
+    unsigned long long cnt = 0, vis = 0;
 #pragma unroll
-    for (int j = 0; j < kScanPerThread; j++)
-        if (k0 + j < vn) cnt += tiles[order[k0 + j]];
+    for (int j = 0; j < kScanPerThread; j++) {
+        const uint32_t c = k0 + j < vn ? tiles[k0 + j] : 0u;
+        cnt += c;
+        vis += c > 0 ? 1ull : 0ull;
+    }
     const unsigned long long s = block_sum<unsigned long long, kPreprocessBlock>(cnt, red);
-    if (threadIdx.x == 0) bs[blockIdx.x] = s;
+    const unsigned long long v = block_sum<unsigned long long, kPreprocessBlock>(vis, red);
+    if (threadIdx.x == 0) {
+        bs[blockIdx.x] = s;
+        bvis[blockIdx.x] = (uint32_t)v;
+    }
 }
 
 struct DupArgs {
-    const uint32_t *order;         // [vn] view * n + i in (depth, index) order
     const uint2 *rect;
     const uint32_t *tiles;
-    uint32_t *offsets;             // [vn] by splat: first emission position
-    uint32_t *offk;                // [vn + 1] by depth rank: first emission position, then M
-    uint32_t *wstart;              // [windows + 1] first depth rank of each work window
-    uint32_t *pstart;              // [emission blocks + 1] depth rank owning each block's start
-    const unsigned long long *blocksum;  // [nblk] per-block tile counts in depth order
+    uint32_t *offsets;             // [vn + 1] first emission position of each view-Gaussian, then M
+    uint32_t *vis;                 // [vn] the view-Gaussians with instances, in index order
+    uint32_t *offv;                // [vn + 1] first emission position of each of those, then M
+    uint32_t *wstart;              // [windows + 1] first view-Gaussian of each work window
+    uint32_t *pstart;              // [emission blocks + 1] rank in vis owning each block's start
+    const unsigned long long *blocksum;  // [nblk] per-block tile counts in index order
+    const uint32_t *blockvis;      // [nblk] per-block counts of view-Gaussians with instances
     uint32_t *counters;
     uint32_t *keys;
     uint32_t *vals;
@@ -216,26 +220,34 @@ struct DupArgs {
     int vn, nblk, eblk, total_tiles;
 };
 
-// Exclusive offsets of the splats' instance runs in depth order, the work
+// Exclusive offsets of the splats' instance runs in index order (the
+// emission positions, which are also the backward's gradient slots), the
+// list of the splats with instances (vis, with their offsets offv), the work
 // windows and the emission blocks.  Each block first sums the block sums
 // before it (and all of them, for M and the overflow flag; block 0 writes
-// the counters).  Splat k's entry sits at position h = k + offk[k] of the
+// the counters).  Splat k's entry sits at position h = k + offsets[k] of the
 // sequence (splat, its instances, next splat, ...), the next at h + 1 + cnt;
 // window b starts at the first splat whose entry is at or after b * kWindow.
 // Emission block p covers instance positions [p, p + 1) * kSortItems and
-// starts at the splat whose run holds position p * kSortItems; entry
-// ceil(M / kSortItems) is the last splat with instances.
+// starts at the splat of vis whose run holds position p * kSortItems; entry
+// ceil(M / kSortItems) is the last of vis.  The emission works on vis, not
+// on all splats: the positions of one block then belong to at most
+// kSortItems + 1 splats, however many culled splats lie between them.
 __global__ __launch_bounds__(kPreprocessBlock) void k_offsets(DupArgs a) {
     __shared__ unsigned long long scratch[kPreprocessBlock / kWave];
     const int t = threadIdx.x;
-    unsigned long long before = 0, all = 0;
+    unsigned long long before = 0, all = 0, vbefore = 0;
     for (int j = t; j < a.nblk; j += kPreprocessBlock) {
         const unsigned long long x = a.blocksum[j];
         all += x;
-        before += j < (int)blockIdx.x ? x : 0ull;
+        if (j < (int)blockIdx.x) {
+            before += x;
+            vbefore += a.blockvis[j];
+        }
     }
     before = block_sum<unsigned long long, kPreprocessBlock>(before, scratch);
     all = block_sum<unsigned long long, kPreprocessBlock>(all, scratch);
+    vbefore = block_sum<unsigned long long, kPreprocessBlock>(vbefore, scratch);
     const bool ovf = all > a.cap;
     if (blockIdx.x == 0 && t == 0) {
         a.counters[kCntMLo] = (uint32_t)(all & 0xffffffffull);
@@ -246,36 +258,45 @@ __global__ __launch_bounds__(kPreprocessBlock) void k_offsets(DupArgs a) {
         if (a.vn == 0) a.counters[kCntWin] = 0u;
     }
     const int k0 = blockIdx.x * kScanItems + kScanPerThread * t;
-    uint32_t idx[kScanPerThread], cnt[kScanPerThread];
-    unsigned long long local = 0;
+    uint32_t cnt[kScanPerThread];
+    unsigned long long local = 0, vlocal = 0;
 #pragma unroll
     for (int j = 0; j < kScanPerThread; j++) {
-        idx[j] = k0 + j < a.vn ? a.order[k0 + j] : 0u;
-        cnt[j] = k0 + j < a.vn ? a.tiles[idx[j]] : 0u;
+        cnt[j] = k0 + j < a.vn ? a.tiles[k0 + j] : 0u;
         local += cnt[j];
+        vlocal += cnt[j] > 0 ? 1ull : 0ull;
     }
     unsigned long long total;
     unsigned long long excl =
         block_exclusive_scan<unsigned long long, kPreprocessBlock>(local, scratch, &total) + before;
+    unsigned long long vexcl =
+        block_exclusive_scan<unsigned long long, kPreprocessBlock>(vlocal, scratch, &total) + vbefore;
     if (ovf) return;
 #pragma unroll
     for (int j = 0; j < kScanPerThread; j++) {
         const int k = k0 + j;
         if (k >= a.vn) break;
-        a.offsets[idx[j]] = (uint32_t)excl;
-        a.offk[k] = (uint32_t)excl;
+        a.offsets[k] = (uint32_t)excl;
         const unsigned long long h = (unsigned long long)k + excl, h1 = h + 1 + cnt[j];
         if (k == 0) a.wstart[0] = 0u;
         for (unsigned long long b = h / kWindow + 1; b * kWindow <= h1; b++)
             a.wstart[b] = (uint32_t)k + 1;
         const unsigned long long e1 = excl + cnt[j];
-        for (unsigned long long p = (excl + kSortItems - 1) / kSortItems; p * kSortItems < e1; p++)
-            a.pstart[p] = (uint32_t)k;
-        if (cnt[j] > 0 && e1 == all) a.pstart[(all + kSortItems - 1) / kSortItems] = (uint32_t)k;
+        if (cnt[j] > 0) {
+            a.vis[vexcl] = (uint32_t)k;
+            a.offv[vexcl] = (uint32_t)excl;
+            for (unsigned long long p = (excl + kSortItems - 1) / kSortItems; p * kSortItems < e1; p++)
+                a.pstart[p] = (uint32_t)vexcl;
+            if (e1 == all) {
+                a.pstart[(all + kSortItems - 1) / kSortItems] = (uint32_t)vexcl;
+                a.offv[vexcl + 1] = (uint32_t)all;
+            }
+            vexcl++;
+        }
         if (k == a.vn - 1) {
             const unsigned long long nwin = (h1 + kWindow - 1) / kWindow;
             if (nwin * kWindow > h1) a.wstart[nwin] = (uint32_t)a.vn;
-            a.offk[a.vn] = (uint32_t)e1;
+            a.offsets[a.vn] = (uint32_t)e1;
             a.counters[kCntWin] = (uint32_t)nwin;
         }
         excl = e1;
@@ -291,7 +312,8 @@ static_assert(kEmitThreads >= kSortBins && kEmitThreads <= 1024 && kEmitThreads 
 
 // Emits one (tile, view * n + i) pair per tile of each splat's rect, rows
 // outer and columns inner, at the splat's offset; a stable sort of these
-// pairs by tile then yields every tile's list in (depth, index) order.
+// pairs by tile then yields every tile's list in index order, which the
+// per-tile depth sort turns into (depth, index) order.
 // Block p writes instance positions [p, p + 1) * kSortItems, which are the
 // keys of block p of the first pass of that sort, so it also writes their
 // low-digit histogram (zeros past M); each thread finds the splat owning a
@@ -319,12 +341,12 @@ __global__ __launch_bounds__(kEmitThreads) void k_emit(DupArgs a, ViewsK views, 
         const uint32_t p1 = min(p0 + (uint32_t)kSortItems, M);
         const int nk = min((int)(kn + 1 - kb), kMaxSplats);
         for (int j = t; j < nk; j += kEmitThreads) {
-            const uint32_t idx = a.order[kb + j];
-            s_off[j] = a.offk[kb + j];
+            const uint32_t idx = a.vis[kb + j];
+            s_off[j] = a.offv[kb + j];
             s_idx[j] = idx;
             s_rect[j] = a.rect[idx];
         }
-        if (t == 0) s_off[nk] = a.offk[kb + nk];
+        if (t == 0) s_off[nk] = a.offv[kb + nk];
         __syncthreads();
         for (uint32_t e = p0 + t; e < p1; e += kEmitThreads) {
             // largest j with s_off[j] <= e; s_off[0] <= p0 <= e < p1 <= s_off[nk]
@@ -365,8 +387,6 @@ hipError_t launch_preprocess(const GaussiansK &g, const ViewsK &views, const flo
     a.rect = region<uint2>(ws, L.rect);
     a.depth = region<uint32_t>(ws, L.depth);
     a.tiles = region<uint32_t>(ws, L.tiles);
-    a.dkeys = region<uint32_t>(ws, L.dkeys0);
-    a.dvals = region<uint32_t>(ws, L.dvals0);
     dim3 grid(L.nblk_pre), block(kPreprocessBlock);
     switch (g.sh_degree) {
         case 0: hipLaunchKernelGGL(k_preprocess<0>, grid, block, 0, s, a, views); break;
@@ -380,11 +400,12 @@ hipError_t launch_preprocess(const GaussiansK &g, const ViewsK &views, const flo
 hipError_t launch_offsets_and_duplicate(const ViewsK &views, const Layout &L, char *ws,
                                         hipStream_t s) {
     DupArgs a;
-    a.order = region<uint32_t>(ws, L.dvals0);   // depth sort: 4 passes, even
     a.rect = region<uint2>(ws, L.rect);
     a.tiles = region<uint32_t>(ws, L.tiles);
     a.offsets = region<uint32_t>(ws, L.offsets);
-    a.offk = region<uint32_t>(ws, L.offk);
+    a.vis = region<uint32_t>(ws, L.vis);
+    a.offv = region<uint32_t>(ws, L.offv);
+    a.blockvis = region<uint32_t>(ws, L.blockvis);
     a.wstart = region<uint32_t>(ws, L.wstart);
     a.pstart = region<uint32_t>(ws, L.pstart);
     a.blocksum = region<unsigned long long>(ws, L.blocksum);
@@ -401,8 +422,9 @@ hipError_t launch_offsets_and_duplicate(const ViewsK &views, const Layout &L, ch
     a.eblk = L.nblk_emit;
     a.total_tiles = L.total_tiles;
     if (a.vn > 0) {
-        hipLaunchKernelGGL(k_sorted_blocksums, dim3(L.nblk_scan), dim3(kPreprocessBlock), 0, s,
-                           a.order, a.tiles, region<unsigned long long>(ws, L.blocksum), a.vn);
+        hipLaunchKernelGGL(k_blocksums, dim3(L.nblk_scan), dim3(kPreprocessBlock), 0, s, a.tiles,
+                           region<unsigned long long>(ws, L.blocksum),
+                           region<uint32_t>(ws, L.blockvis), a.vn);
     }
     hipLaunchKernelGGL(k_offsets, dim3(L.nblk_scan > 0 ? L.nblk_scan : 1), dim3(kPreprocessBlock),
                        0, s, a);

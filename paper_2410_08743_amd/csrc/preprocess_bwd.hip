@@ -65,8 +65,7 @@ __device__ __forceinline__ void rot_vjp(double w, double x, double y, double z, 
 constexpr int kSlotFloats = 9 * kSplitBwd;   // one 9-float slot per backward part
 constexpr int kSlotPerThread = kWindow * kSlotFloats / kWindowThreads;
 
-__global__ __launch_bounds__(kWindowThreads) void k_slot_reduce(const uint32_t *order,
-                                                                const uint32_t *offk,
+__global__ __launch_bounds__(kWindowThreads) void k_slot_reduce(const uint32_t *offk,
                                                                 const uint32_t *wstart,
                                                                 const uint32_t *counters,
                                                                 const float *slots,
@@ -123,7 +122,7 @@ __global__ __launch_bounds__(kWindowThreads) void k_slot_reduce(const uint32_t *
                 d += fsrc[kSplitBwd * (size_t)e + p] ? v : 0.f;
             }
         }
-        grad2d[9 * (size_t)order[kb + j] + c] = d;
+        grad2d[9 * ((size_t)kb + j) + c] = d;
     }
 }
 
@@ -433,7 +432,7 @@ hipError_t launch_preprocess_bwd(const GaussiansK &g, const ViewsK &views, const
     a.accumulate = accumulate;
     if (L.vn > 0) {
         hipLaunchKernelGGL(k_slot_reduce, dim3(L.nwin_max), dim3(kWindowThreads), 0, s,
-                           region<uint32_t>(ws, L.dvals0), region<uint32_t>(ws, L.offk),
+                           region<uint32_t>(ws, L.offsets),
                            region<uint32_t>(ws, L.wstart), a.counters, a.slots,
                            region<uint8_t>(ws, L.slot_flags), a.grad2d,
                            (int)L.vn);

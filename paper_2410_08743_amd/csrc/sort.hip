@@ -1,12 +1,12 @@
-// sort.hip -- stable LSD radix sort of (uint32 key, uint32 value) pairs.
+// sort.hip -- the (tile, depth, index) order of the instances.
 //
-// The (tile | depth) order of the instances is produced in two stable sorts
-// that together equal one stable sort on the 64-bit key (tile << 32 | depth):
-// the splats are first sorted by their float32 depth bits (all 32 bits, ties
-// keep index order), instances are then emitted splat by splat in that order,
-// and the instances are stably sorted by tile id alone (ceil(log2 tiles)
-// bits).  The instance sort moves 8-byte pairs over 2 passes at a 1008x756
-// view instead of 12-byte pairs over 6.
+// The order of one stable sort on the 64-bit key (tile << 32 | depth) is
+// produced in two steps: the instances, emitted splat by splat in index
+// order, are stably sorted by tile id alone (ceil(log2 tiles) bits, 2 passes
+// at a 1008x756 view; 8-byte pairs), and then each tile's run, now in index
+// order, is sorted stably by depth inside one workgroup (k_tile_depth_sort,
+// at the end of this file).  Sorting the depth per tile in LDS replaces a
+// global depth sort of all splats (4 passes of 3 launches each).
 //
 // Each pass is reduce-then-scan: per-block digit histograms, a per-digit
 // scan across blocks, then a scatter in which every block ranks its
@@ -91,12 +91,6 @@ __global__ __launch_bounds__(kSortScanThreads) void k_sort_scan(SortPass a) {
     if (t == 0) a.digit_tot[blockIdx.x] = carry;
 }
 
-// With few blocks the scatter scans the histogram itself (FUSED): thread d
-// sums row d of the unscanned counts over the blocks in front of its own and
-// over all blocks, which saves the scan's launch.
-constexpr int kFusedScanMaxBlocks = 256;
-
-template <bool FUSED>
 __global__ __launch_bounds__(kSortThreads) void k_sort_scatter(SortPass a) {
     constexpr int NW = kSortThreads / kWave;
     __shared__ uint32_t skeys[kSortItems];
@@ -137,29 +131,8 @@ __global__ __launch_bounds__(kSortThreads) void k_sort_scatter(SortPass a) {
     __syncthreads();
     uint32_t tot;
     const uint32_t excl = block_exclusive_scan<uint32_t, kSortThreads>(run[t], scratch, &tot);
-    uint32_t digit_total, before;
-    if (FUSED) {
-        const uint32_t *row = a.hist + (size_t)t * a.nblk;
-        uint32_t s0 = 0, s1 = 0, b0 = 0, b1 = 0;
-        const int me = (int)blockIdx.x;
-        int k = 0;
-        for (; k + 1 < a.nblk; k += 2) {
-            const uint32_t x0 = row[k], x1 = row[k + 1];
-            s0 += x0;
-            s1 += x1;
-            b0 += k < me ? x0 : 0u;
-            b1 += k + 1 < me ? x1 : 0u;
-        }
-        if (k < a.nblk) {
-            s0 += row[k];
-            b0 += k < me ? row[k] : 0u;
-        }
-        digit_total = s0 + s1;
-        before = b0 + b1;
-    } else {
-        digit_total = a.digit_tot[t];
-        before = a.hist[(size_t)t * a.nblk + blockIdx.x];
-    }
+    const uint32_t digit_total = a.digit_tot[t];
+    const uint32_t before = a.hist[(size_t)t * a.nblk + blockIdx.x];
     const uint32_t dex = block_exclusive_scan<uint32_t, kSortThreads>(digit_total, scratch, &tot);
     dstart[t] = excl;
     run[t] = excl;
@@ -234,25 +207,12 @@ int launch_sort_pairs(uint32_t *k0, uint32_t *v0, uint32_t *k1, uint32_t *v1, ui
         a.shift = p * pbits;
         if (p > 0 || !hist0_given)
             hipLaunchKernelGGL(k_sort_hist, dim3(a.nblk), dim3(kSortThreads), 0, s, a);
-        if (a.nblk <= kFusedScanMaxBlocks) {
-            hipLaunchKernelGGL(k_sort_scatter<true>, dim3(a.nblk), dim3(kSortThreads), 0, s, a);
-        } else {
-            hipLaunchKernelGGL(k_sort_scan, dim3(kSortBins), dim3(kSortScanThreads), 0, s, a);
-            hipLaunchKernelGGL(k_sort_scatter<false>, dim3(a.nblk), dim3(kSortThreads), 0, s, a);
-        }
+        hipLaunchKernelGGL(k_sort_scan, dim3(kSortBins), dim3(kSortScanThreads), 0, s, a);
+        hipLaunchKernelGGL(k_sort_scatter, dim3(a.nblk), dim3(kSortThreads), 0, s, a);
         *err = hipGetLastError();
         if (*err != hipSuccess) return passes;
     }
     return passes;
-}
-
-hipError_t launch_depth_sort(const Layout &L, char *ws, hipStream_t s) {
-    hipError_t e;
-    launch_sort_pairs(region<uint32_t>(ws, L.dkeys0), region<uint32_t>(ws, L.dvals0),
-                      region<uint32_t>(ws, L.dkeys1), region<uint32_t>(ws, L.dvals1),
-                      region<uint32_t>(ws, L.hist), region<uint32_t>(ws, L.digit_tot), nullptr,
-                      (uint32_t)L.vn, L.vn, 32, false, s, &e);
-    return e;
 }
 
 hipError_t launch_tile_sort(const Layout &L, char *ws, hipStream_t s) {
@@ -263,6 +223,322 @@ hipError_t launch_tile_sort(const Layout &L, char *ws, hipStream_t s) {
                       region<uint32_t>(ws, L.counters) + kCntMEff, 0u, L.cap, L.tile_bits, true, s,
                       &e);
     return e;
+}
+
+
+// ---------------------------------------------------------------------------
+// Depth order inside each tile.  The instances leave the tile sort grouped by
+// tile, each tile's run in index order (they are emitted splat by splat in
+// index order and the tile sort is stable).  Each tile's run is then sorted
+// stably by the splat's depth key (the float32 bits of its camera-frame z):
+// equal depths keep index order, so every run ends in (depth, index) order,
+// which is the order of a stable sort of all instances on the 64-bit key
+// (tile << 32 | depth).  Only the values (view * n + i) move.
+//
+// One wavefront per tile (a 64-thread workgroup, so that its barriers cost
+// nothing and many tiles are in flight per CU); workgroup b takes tile b, so
+// that its first load is its range.  The keys are taken relative to the
+// run's smallest (an order-preserving shift that leaves some 25 significant
+// bits for depths in 1.5 .. 8) and sorted LSD over kTdBits-bit digits,
+// skipping every pass whose digit is the same for the whole run.  A pass is a
+// stable counting sort: rounds of 64 items, each lane ranked among the
+// round's lanes with the same digit (found through a per-digit lane mask in
+// LDS) on top of a running per-digit count, then the digit counts' exclusive
+// scan added to those ranks.  Runs of up to CAP entries stay in registers
+// and LDS (CAP is picked per launch from the mean list length the instance
+// capacity allows: 1024 or 2048); longer runs (histograms from one read
+// first) move, CAP entries at a time with every load of a chunk in flight,
+// between the sorted arrays and the tile sort's other key and value buffers,
+// the relative keys carried beside the values (the key array's tile ids are
+// restored afterwards).
+#ifndef GSP_TD_BITS
+#define GSP_TD_BITS 8
+#endif
+constexpr int kTdBits = GSP_TD_BITS;
+constexpr int kTdBins = 1 << kTdBits;
+constexpr int kTdPasses = (32 + kTdBits - 1) / kTdBits;
+constexpr int kTdPerLane = kTdBins / kWave;
+
+struct TileDepthArgs {
+    const uint2 *ranges;
+    const uint32_t *depth;      // [vn] depth key of each view-Gaussian
+    uint32_t *keys;             // sorted tile ids (scratch for long runs, then restored)
+    uint32_t *vals;             // sorted values, put in depth order per tile in place
+    uint32_t *akeys, *avals;    // [cap] the tile sort's other buffers (scratch)
+};
+
+__device__ __forceinline__ uint32_t wave_min_u32(uint32_t v) {
+#pragma unroll
+    for (int off = kWave / 2; off > 0; off >>= 1) v = min(v, (uint32_t)__shfl_xor((int)v, off, kWave));
+    return v;
+}
+
+__device__ __forceinline__ uint32_t wave_max_u32(uint32_t v) {
+#pragma unroll
+    for (int off = kWave / 2; off > 0; off >>= 1) v = max(v, (uint32_t)__shfl_xor((int)v, off, kWave));
+    return v;
+}
+
+// Rank of the lane's item among the lanes of its round with the same digit,
+// plus run[d], the count of d in earlier rounds.  The lanes with digit d find
+// each other through msk[d]: each ORs its lane bit in, then reads the mask
+// back (a wavefront's LDS accesses take effect in program order, so every OR
+// lands before any read); the lowest of them advances run[d] and clears
+// msk[d] for the next round.  msk must be zero on entry and is zero again on
+// return.
+__device__ __forceinline__ uint32_t td_rank(bool valid, uint32_t d, uint32_t *run,
+                                            unsigned long long *msk) {
+    const int lane = threadIdx.x;
+    const unsigned long long lt = (1ull << lane) - 1ull;
+    if (valid) atomicOr(&msk[d], 1ull << lane);
+    const unsigned long long peers = valid ? msk[d] : 0ull;
+    const uint32_t below = __popcll(peers & lt);
+    const uint32_t base = valid ? run[d] : 0u;
+    if (valid && below == 0) {
+        run[d] = base + (uint32_t)__popcll(peers);
+        msk[d] = 0ull;
+    }
+    return base + below;
+}
+
+// run[] (digit counts) -> exclusive starts, in place.
+__device__ __forceinline__ void td_scan(uint32_t *run) {
+    const int lane = threadIdx.x;
+    uint32_t c[kTdPerLane], s = 0;
+#pragma unroll
+    for (int j = 0; j < kTdPerLane; j++) {
+        c[j] = run[kTdPerLane * lane + j];
+        s += c[j];
+    }
+    uint32_t e = wave_inclusive_scan(s) - s;
+#pragma unroll
+    for (int j = 0; j < kTdPerLane; j++) {
+        run[kTdPerLane * lane + j] = e;
+        e += c[j];
+    }
+    __syncthreads();
+}
+
+__device__ __forceinline__ void td_zero(uint32_t *run) {
+#pragma unroll
+    for (int j = 0; j < kTdPerLane; j++) run[kTdPerLane * threadIdx.x + j] = 0u;
+}
+
+// An overflowing forward emits no instance and leaves every range empty, so
+// the kernel needs no overflow test.
+template <int CAP>
+__global__ __launch_bounds__(kWave) void k_tile_depth_sort(TileDepthArgs a) {
+    constexpr int kTdCap = CAP;
+    constexpr int kTdRounds = kTdCap / kWave;
+    // sk, sv: the run (long runs: the histograms of all passes instead)
+    __shared__ uint32_t buf[2 * kTdCap];
+    __shared__ uint32_t run[kTdBins];
+    __shared__ unsigned long long msk[kTdBins];
+    static_assert(kTdPasses * kTdBins <= 2 * kTdCap, "histograms of a long run fit in buf");
+    uint32_t *const sk = buf, *const sv = buf + kTdCap;
+    const uint32_t tile = blockIdx.x;
+    const uint2 rg = a.ranges[tile];
+    const int L = (int)(rg.y - rg.x);
+    if (L <= 1) return;
+    const int lane = threadIdx.x;
+    uint32_t key[kTdRounds], val[kTdRounds];
+    uint32_t *const kf = a.keys + rg.x, *const vf = a.vals + rg.x;
+#pragma unroll
+    for (int j = 0; j < kTdPerLane; j++) msk[kTdPerLane * lane + j] = 0ull;
+
+    if (L <= kTdCap) {
+#pragma unroll
+        for (int r = 0; r < kTdRounds; r++) {
+            const int k = r * kWave + lane;
+            val[r] = k < L ? vf[k] : 0u;
+        }
+        uint32_t kmin = 0xffffffffu;
+#pragma unroll
+        for (int r = 0; r < kTdRounds; r++) {
+            const int k = r * kWave + lane;
+            key[r] = k < L ? a.depth[val[r]] : 0xffffffffu;
+            kmin = min(kmin, key[r]);
+        }
+        kmin = wave_min_u32(kmin);
+#pragma unroll
+        for (int r = 0; r < kTdRounds; r++) key[r] -= kmin;   // past L: stays above every key
+        bool moved = false;
+        for (int p = 0; p < kTdPasses; p++) {
+            const int sh = kTdBits * p;
+            uint32_t dlo = kTdBins, dhi = 0;
+#pragma unroll
+            for (int r = 0; r < kTdRounds; r++) {
+                if (r * kWave + lane < L) {
+                    const uint32_t d = (key[r] >> sh) & (kTdBins - 1);
+                    dlo = min(dlo, d);
+                    dhi = max(dhi, d);
+                }
+            }
+            if (wave_min_u32(dlo) == wave_max_u32(dhi)) continue;   // one digit: nothing moves
+            moved = true;
+            td_zero(run);
+            __syncthreads();
+            uint32_t rk[kTdRounds];
+#pragma unroll
+            for (int r = 0; r < kTdRounds; r++) {
+                rk[r] = 0u;
+                if (r * kWave >= L) continue;   // uniform
+                const bool valid = r * kWave + lane < L;
+                rk[r] = td_rank(valid, (key[r] >> sh) & (kTdBins - 1), run, msk);
+            }
+            __syncthreads();
+            td_scan(run);
+#pragma unroll
+            for (int r = 0; r < kTdRounds; r++) {
+                if (r * kWave + lane < L) {
+                    const uint32_t pos = run[(key[r] >> sh) & (kTdBins - 1)] + rk[r];
+                    sk[pos] = key[r];
+                    sv[pos] = val[r];
+                }
+            }
+            __syncthreads();
+#pragma unroll
+            for (int r = 0; r < kTdRounds; r++) {
+                const int k = r * kWave + lane;
+                if (k < L) {
+                    key[r] = sk[k];
+                    val[r] = sv[k];
+                }
+            }
+            __syncthreads();
+        }
+        if (moved) {
+#pragma unroll
+            for (int r = 0; r < kTdRounds; r++) {
+                const int k = r * kWave + lane;
+                if (k < L) vf[k] = val[r];
+            }
+        }
+        return;
+    }
+
+    // Long run.  The smallest key, then the histograms of every pass of the
+    // relative keys, from two reads of the run (keys gathered).
+    uint32_t kmin = 0xffffffffu;
+    for (int c0 = 0; c0 < L; c0 += kTdCap) {
+#pragma unroll
+        for (int r = 0; r < kTdRounds; r++) {
+            const int k = c0 + r * kWave + lane;
+            val[r] = k < L ? vf[k] : 0u;
+        }
+#pragma unroll
+        for (int r = 0; r < kTdRounds; r++) {
+            const int k = c0 + r * kWave + lane;
+            if (k < L) kmin = min(kmin, a.depth[val[r]]);
+        }
+    }
+    kmin = wave_min_u32(kmin);
+    uint32_t *const hist = buf;   // [kTdPasses][kTdBins]
+    for (int i = lane; i < kTdPasses * kTdBins; i += kWave) hist[i] = 0u;
+    __syncthreads();
+    for (int c0 = 0; c0 < L; c0 += kTdCap) {
+#pragma unroll
+        for (int r = 0; r < kTdRounds; r++) {
+            const int k = c0 + r * kWave + lane;
+            val[r] = k < L ? vf[k] : 0u;
+        }
+#pragma unroll
+        for (int r = 0; r < kTdRounds; r++) {
+            const int k = c0 + r * kWave + lane;
+            if (k < L) {
+                const uint32_t kk = a.depth[val[r]] - kmin;
+#pragma unroll
+                for (int p = 0; p < kTdPasses; p++)
+                    atomicAdd(&hist[p * kTdBins + ((kk >> (kTdBits * p)) & (kTdBins - 1))], 1u);
+            }
+        }
+    }
+    __syncthreads();
+    // source of the next pass: (keys gathered | skey, sval), destination (dkey, dval)
+    uint32_t *skey = nullptr, *sval = vf, *dkey = a.akeys + rg.x, *dval = a.avals + rg.x;
+    bool kf_used = false;
+    for (int p = 0; p < kTdPasses; p++) {
+        const int sh = kTdBits * p;
+        bool full = false;
+#pragma unroll
+        for (int j = 0; j < kTdPerLane; j++) {
+            const uint32_t c = hist[p * kTdBins + kTdPerLane * lane + j];
+            full |= c == (uint32_t)L;
+            run[kTdPerLane * lane + j] = c;
+        }
+        if (wave_any(full)) continue;   // one digit: nothing moves
+        __syncthreads();
+        td_scan(run);
+        for (int c0 = 0; c0 < L; c0 += kTdCap) {
+#pragma unroll
+            for (int r = 0; r < kTdRounds; r++) {
+                const int k = c0 + r * kWave + lane;
+                val[r] = k < L ? sval[k] : 0u;
+                key[r] = k < L && skey ? skey[k] : 0u;
+            }
+            if (!skey) {
+#pragma unroll
+                for (int r = 0; r < kTdRounds; r++) {
+                    const int k = c0 + r * kWave + lane;
+                    key[r] = k < L ? a.depth[val[r]] - kmin : 0u;
+                }
+            }
+#pragma unroll
+            for (int r = 0; r < kTdRounds; r++) {
+                if (c0 + r * kWave >= L) break;   // uniform
+                const bool valid = c0 + r * kWave + lane < L;
+                const uint32_t pos = td_rank(valid, (key[r] >> sh) & (kTdBins - 1), run, msk);
+                if (valid) {
+                    dkey[pos] = key[r];
+                    dval[pos] = val[r];
+                }
+            }
+        }
+        // the next pass reads what every lane wrote
+        __syncthreads();
+        kf_used |= dkey == kf;
+        uint32_t *const nk = dkey == kf ? a.akeys + rg.x : kf;
+        uint32_t *const nv = dval == vf ? a.avals + rg.x : vf;
+        skey = dkey;
+        sval = dval;
+        dkey = nk;
+        dval = nv;
+    }
+    if (sval != vf) {
+        for (int c0 = 0; c0 < L; c0 += kTdCap) {
+#pragma unroll
+            for (int r = 0; r < kTdRounds; r++) {
+                const int k = c0 + r * kWave + lane;
+                val[r] = k < L ? sval[k] : 0u;
+            }
+#pragma unroll
+            for (int r = 0; r < kTdRounds; r++) {
+                const int k = c0 + r * kWave + lane;
+                if (k < L) vf[k] = val[r];
+            }
+        }
+    }
+    if (kf_used)
+        for (int k = lane; k < L; k += kWave) kf[k] = tile;
+}
+
+hipError_t launch_tile_depth_sort(const Layout &L, char *ws, hipStream_t s) {
+    if (L.total_tiles == 0) return hipSuccess;
+    TileDepthArgs a;
+    const bool odd = sorted_vals(L) == L.vals1;
+    a.ranges = region<uint2>(ws, L.ranges);
+    a.depth = region<uint32_t>(ws, L.depth);
+    a.keys = region<uint32_t>(ws, sorted_keys(L));
+    a.vals = region<uint32_t>(ws, sorted_vals(L));
+    a.akeys = region<uint32_t>(ws, odd ? L.keys0 : L.keys1);
+    a.avals = region<uint32_t>(ws, odd ? L.vals0 : L.vals1);
+    // lists longer than 1024 on average (at the 1.5x capacity margin) take the
+    // 2048-entry variant, whose larger LDS share lowers the waves per CU
+    if (L.cap > (int64_t)1536 * L.total_tiles)
+        hipLaunchKernelGGL(k_tile_depth_sort<2048>, dim3(L.total_tiles), dim3(kWave), 0, s, a);
+    else
+        hipLaunchKernelGGL(k_tile_depth_sort<1024>, dim3(L.total_tiles), dim3(kWave), 0, s, a);
+    return hipGetLastError();
 }
 
 }  // namespace gsp

@@ -140,6 +140,32 @@ def test_keys_sort_and_ranges_bit_exact(name):
         assert np.array_equal(ranges.reshape(-1, 2), oracle.tile_ranges(rkeys, gw * gh))
 
 
+def test_depth_ties_and_long_runs_bit_exact():
+    """Tile runs several times longer than the per-tile depth sort keeps in
+    LDS (its chunked global-memory path), with depth ties everywhere: 25000
+    Gaussians at three depths only, seen at the identity pose, so that the
+    camera-frame z of each is its mean's z exactly and equal keys must come
+    out in index order."""
+    sc, cam, _ = random_case(18, 0, 48, 32, 25000, depth=(2.0, 5.0))
+    z = np.array([2.0, 3.0, 4.5], np.float32)[S.rng_for(18, 5).integers(0, 3, sc.n)]
+    sc.means[:, :2] *= (z / sc.means[:, 2])[:, None]
+    sc.means[:, 2] = z
+    pose = S.identity_pose()
+    run = _gpu(sc, [cam], [pose])
+    rast, g = run["rast"], run["g"]
+    ref = oracle.preprocess(sc, cam, pose)
+    gw, gh = oracle.tiles_of(cam)
+    rkeys, rvals = oracle.bin_sort([ref], [(gw, gh)])
+    M, ovf = rast.instances()
+    assert not ovf
+    keys, vals = _sorted_instances(rast, g, [cam], M)
+    tile_len = np.bincount((rkeys >> np.uint64(32)).astype(np.int64), minlength=gw * gh)
+    assert tile_len.max() > 2 * 2048
+    assert len(np.unique(ref["depth_key"])) <= 3
+    fragile = np.nonzero(ref["fragile"])[0].astype(np.uint32)
+    assert_sorted_match(keys, vals, rkeys, rvals, fragile)
+
+
 def test_keys_bit_exact_two_views():
     sc, cam0, pose0 = random_case(16, 2, 96, 64, 700)
     cam1 = f32_camera(S.Camera(80, 48, 75.0, 70.0, 40.5, 23.75, roi=(16, 16, 50, 32)))
