@@ -121,31 +121,26 @@ __device__ __forceinline__ float pair_sum16(float a, float b) {
     return __uint_as_float(r[0]) + __uint_as_float(r[1]);
 }
 
-// Wave-wide sums of nine values with a reduce-scatter butterfly: 32-lane and
-// 16-lane swaps halve the data at each step, then DPP finishes inside rows.
-// Totals land in every lane of a row:
-//   x0 rows 0..3 = v0, v2, v1, v3;  x1 rows 0..3 = v4, v6, v5, v7;  x2 = v8.
-__device__ __forceinline__ void wave_sum9(const float v[9], float &x0, float &x1, float &x2) {
+// The first two levels of a reduce-scatter of nine values over the wave: a
+// 32-lane and a 16-lane swap halve the data at each step, leaving each value
+// as 16 partial sums (of the four lanes l, l + 16, l + 32, l + 48 of column
+// l) in one 16-lane row:
+//   a rows 0..3 = v0, v2, v1, v3;  b rows 0..3 = v4, v6, v5, v7;  c row 0 = v8.
+__device__ __forceinline__ void wave_sum9_rows(const float v[9], float &a, float &b, float &c) {
     const float w0 = pair_sum32(v[0], v[1]);
     const float w1 = pair_sum32(v[2], v[3]);
     const float w2 = pair_sum32(v[4], v[5]);
     const float w3 = pair_sum32(v[6], v[7]);
     const float w4 = pair_sum32(v[8], v[8]);
-    float a = pair_sum16(w0, w1), b = pair_sum16(w2, w3), c = pair_sum16(w4, w4);
-    // the three row butterflies interleaved, so that no DPP step waits on the
-    // one just issued
-    a = dpp_add<kDppQuadXor1>(a);
-    b = dpp_add<kDppQuadXor1>(b);
-    c = dpp_add<kDppQuadXor1>(c);
-    a = dpp_add<kDppQuadXor2>(a);
-    b = dpp_add<kDppQuadXor2>(b);
-    c = dpp_add<kDppQuadXor2>(c);
-    a = dpp_add<kDppRowHalfMirror>(a);
-    b = dpp_add<kDppRowHalfMirror>(b);
-    c = dpp_add<kDppRowHalfMirror>(c);
-    x0 = dpp_add<kDppRowMirror>(a);
-    x1 = dpp_add<kDppRowMirror>(b);
-    x2 = dpp_add<kDppRowMirror>(c);
+    a = pair_sum16(w0, w1);
+    b = pair_sum16(w2, w3);
+    c = pair_sum16(w4, w4);
+}
+
+// Row of the 16-lane row partials that hold value k (register k >> 2 for
+// k < 8, register 2 for k = 8).
+__host__ __device__ constexpr int sum9_row(int k) {
+    return k == 8 ? 0 : ((k & 3) == 1 ? 2 : ((k & 3) == 2 ? 1 : (k & 3)));
 }
 
 }  // namespace gsp

@@ -22,12 +22,13 @@
 // evaluation, and skip (per lane-parallel bound, as in the forward) the
 // entries that reach 1/255 nowhere in their rows.  Each lane
 // sums its pixels in registers; the nine sums are reduced over the 64 lanes
-// by a reduce-scatter butterfly (v_permlane32_swap, v_permlane16_swap, then
-// DPP inside rows: about 30 VALU operations for nine values), and nine lanes
-// store the (strip, splat) partial into the strip's part of the instance's
-// own slot (its position in emission order), flagging it written.  No
-// atomics: the per-splat sum over its slots happens later in a fixed order,
-// so gradients are bit-reproducible.
+// in two steps: v_permlane32_swap and v_permlane16_swap leave each as 16
+// partial sums in one row of lanes (16 VALU operations for the nine), which
+// wait in LDS; every kPend entries, 63 lanes each add up the 16 partials of
+// one (entry, component) in a fixed order and store it into the strip's part
+// of the instance's own slot (its position in emission order), flagging it
+// written.  No atomics: the per-splat sum over its slots happens later in a
+// fixed order, so gradients are bit-reproducible.
 #include <cstring>
 
 #include "block_ops.h"
@@ -96,6 +97,18 @@ __global__ __launch_bounds__(kRasterThreads) __attribute__((amdgpu_waves_per_eu(
     __shared__ StagedB sB[kBatch];
     __shared__ StagedC sC[kBatch];
     __shared__ float sL[kBatch];   // candidate limit kLog2AlphaMinLoose - lo
+    __shared__ uint32_t sM[kBatch];   // bands the entry may reach (band_mask)
+    // Row partials of the nine sums of up to kPend entries (wave_sum9_rows),
+    // register-major, rows kRowStride floats apart so that the 63 lanes of a
+    // flush, each reading its own row, spread over the banks; and the slot
+    // and 1/o of each pending entry.
+    constexpr int kPend = 7;
+    constexpr int kRowStride = 17;
+    constexpr int kRegStride = 4 * kRowStride;
+    constexpr int kEntryStride = 3 * kRegStride;
+    __shared__ float sP[kPend * kEntryStride];
+    __shared__ uint32_t sPs[kPend];
+    __shared__ float sPi[kPend];
     int rank, part;
     part_of_block<kSplit>(blockIdx.x, rank, part);
     uint32_t item;
@@ -119,14 +132,34 @@ __global__ __launch_bounds__(kRasterThreads) __attribute__((amdgpu_waves_per_eu(
     float *const pslots = a.slots + 9 * part;   // this part's slot of each instance
     uint8_t *const pflags = a.slot_flags + part;
 
-    // Which reduced value this lane stores, and its scale (see wave_sum9 and
-    // the base-2 conic of raster_common.h).
-    const int row = lane >> 4, col = lane & 15;
-    const int c0 = row == 1 ? 2 : (row == 2 ? 1 : row);
-    const int comp = col == 0 ? c0 : (col == 1 ? 4 + c0 : (col == 2 && row == 0 ? 8 : -1));
-    const float scale = comp == 0 || comp == 1 ? kLn2
-                      : comp == 2 || comp == 4 ? -0.5f
-                      : comp == 3 ? -1.f : 1.f;
+    // In a flush, lane k < 9 kPend sums component pc of pending entry pe,
+    // whose row partials start at poff within the entry's area; pscale is
+    // the component's scale (see the base-2 conic of raster_common.h; the
+    // opacity's 1/o comes with the entry).
+    const int pe = lane / 9, pc = lane % 9;
+    const int poff = ((pc == 8 ? 2 : pc >> 2) * 4 + sum9_row(pc)) * kRowStride;
+    const float pscale = pc == 0 || pc == 1 ? kLn2 : pc == 2 || pc == 4 ? -0.5f : pc == 3 ? -1.f : 1.f;
+    int npend = 0;
+    auto flush = [&]() {
+        __syncthreads();   // one wavefront: orders the stashing stores before these loads
+        if (lane < 9 * npend) {
+            const float *src = sP + pe * kEntryStride + poff;
+            float t[8];
+#pragma unroll
+            for (int i = 0; i < 8; i++) t[i] = src[i] + src[8 + i];
+#pragma unroll
+            for (int i = 0; i < 4; i++) t[i] += t[4 + i];
+            const float sum = (t[0] + t[2]) + (t[1] + t[3]);
+            const uint32_t slot = sPs[pe];
+            if (slot != kNoSlot) {
+                const float f = pc == 5 ? sPi[pe] : pscale;
+                pslots[9 * kSplit * (size_t)slot + pc] = sum * f;
+                if (pc == 0) pflags[kSplit * (size_t)slot] = 1;
+            }
+        }
+        __syncthreads();   // before the next entries overwrite the area
+        npend = 0;
+    };
 
     // GS = G . S: the upstream gradient dotted with the colour behind the
     // current splat, which is all that dL/dalpha needs of S.
@@ -194,6 +227,11 @@ __global__ __launch_bounds__(kRasterThreads) __attribute__((amdgpu_waves_per_eu(
         maxlast = max(maxlast, last[q]);
     }
     maxlast = wave_max(maxlast);
+    // largest contributor count of each band: an entry at or past it has no
+    // candidate pixel in the band
+    int blast[kPixPerLane];
+#pragma unroll
+    for (int q = 0; q < kPixPerLane; q++) blast[q] = __builtin_amdgcn_readfirstlane(wave_max(last[q]));
     const float fxl = (float)lx;
 
     // batches of 64 entries ending at hi, walked back to front; positions
@@ -230,13 +268,15 @@ __global__ __launch_bounds__(kRasterThreads) __attribute__((amdgpu_waves_per_eu(
             sB[r] = StagedB{g1.z, g1.w, gc.x, gc.y};
             sC[r] = StagedC{gc.z, __builtin_amdgcn_exp2f(-g1.w), gslot, (uint32_t)(lo + lane)};
             sL[r] = kLog2AlphaMinLoose - g1.w;
+            sM[r] = mask;
         }
         const int nkr = (nk + kBwdUnroll - 1) & ~(kBwdUnroll - 1);
-        if (lane >= nk && lane < nkr) {   // padding up to the unroll width
+        if (lane >= nk && lane < nkr) {   // padding up to the unroll width: reaches no band
             sA[lane] = StagedA{0.f, 0.f, -1.f, 0.f};
             sB[lane] = StagedB{-1.f, -INFINITY, 0.f, 0.f};
             sC[lane] = StagedC{0.f, 0.f, kNoSlot, kPadPos};
             sL[lane] = INFINITY;
+            sM[lane] = 0u;
         }
         __syncthreads();
         if (lo > clo) gather(lo - kBatch + lane);
@@ -245,89 +285,99 @@ __global__ __launch_bounds__(kRasterThreads) __attribute__((amdgpu_waves_per_eu(
             StagedB et[kBwdUnroll];
             StagedC ew[kBwdUnroll];
             float el[kBwdUnroll];
+            uint32_t em[kBwdUnroll];
 #pragma unroll
             for (int u = 0; u < kBwdUnroll; u++) {
                 es[u] = sA[j0 + u];
                 et[u] = sB[j0 + u];
                 ew[u] = sC[j0 + u];
                 el[u] = sL[j0 + u];
+                em[u] = sM[j0 + u];
             }
 #pragma unroll
             for (int u = kBwdUnroll - 1; u >= 0; u--) {
-                const int pos = (int)ew[u].pm;   // list position
+                // the bands this entry may reach that still have pixels
+                // compositing at its list position (wave-uniform)
+                const int pos = __builtin_amdgcn_readfirstlane((int)ew[u].pm);
+                uint32_t bands = __builtin_amdgcn_readfirstlane(em[u]);
+#pragma unroll
+                for (int q = 0; q < kPixPerLane; q++)
+                    if (pos >= blast[q]) bands &= ~(1u << q);
+                if (bands == 0u) continue;
                 const StagedA &s = es[u];
                 const StagedB &t = et[u];
                 const ColTerms ct = col_terms(s, fxl);
                 const float lim = el[u];
-                float p2[kPixPerLane];
-                bool cand[kPixPerLane];
-                bool any = false;
+                const float col3[3] = {t.r, t.g, ew[u].b};
+                // Per lane, dx is the same for all its pixels, so the conic
+                // and centre gradients need only the moments sum dp, sum dp dy,
+                // sum dp dy^2 of dL/dpower over them.
+                float m0 = 0.f, my = 0.f, myy = 0.f, gc[3] = {0.f, 0.f, 0.f};
+                bool blended = false;
+                // q-th pixels of all lanes form a 16 x 4 band of the tile: a
+                // band with no candidate pixel is skipped as a whole; inside a
+                // band the update is branch-free, pixels that do not blend
+                // adding exact zeros.
 #pragma unroll
                 for (int q = 0; q < kPixPerLane; q++) {
+                    if (!((bands >> q) & 1u)) continue;
+                    const float dy = s.v - fy[q];
+                    float p2;
+                    bool cand;
                     if (STORED) {
-                        p2[q] = 0.f;
-                        cand[q] = npos[q] == (uint32_t)pos;
+                        p2 = 0.f;
+                        cand = npos[q] == (uint32_t)pos;
                     } else {
-                        p2[q] = splat_p2(ct, t.C2, s.v - fy[q]);
-                        cand[q] = (pos < last[q]) & (p2[q] <= 0.f) & (p2[q] >= lim);
+                        p2 = splat_p2(ct, t.C2, dy);
+                        cand = (pos < last[q]) & (p2 <= 0.f) & (p2 >= lim);
                     }
-                    any |= cand[q];
+                    if (__builtin_amdgcn_ballot_w64(cand) == 0ull) continue;
+                    blended = true;
+                    float alpha, wgt;
+                    bool valid, unclamped;
+                    if (STORED) {
+                        // alpha and T_i of this pair as the forward left them
+                        valid = cand;
+                        alpha = valid ? fabsf(nal[q]) : 0.f;
+                        unclamped = nal[q] >= 0.f;
+                        wgt = valid ? alpha * T[q] : 0.f;
+                    } else {
+                        // A pixel that does not blend takes alpha = 0, which
+                        // leaves T (times rcp(1) = 1), G.S (plus 0 * diff)
+                        // and the sums (plus 0) exactly as they are.
+                        const float apre = splat_alpha_pre(p2, t.lo);
+                        const float a0 = fminf(kAlphaMax, apre);
+                        valid = cand && a0 >= kAlphaMin;
+                        alpha = valid ? a0 : 0.f;
+                        unclamped = apre <= kAlphaMax;
+                        T[q] = T[q] * __builtin_amdgcn_rcpf(1.f - alpha);
+                        wgt = alpha * T[q];
+                    }
+                    const float Gc = fmaf(G[q][2], col3[2], fmaf(G[q][1], col3[1], G[q][0] * col3[0]));
+                    const float diff = Gc - GS[q];
+#pragma unroll
+                    for (int ch = 0; ch < 3; ch++) gc[ch] = fmaf(G[q][ch], wgt, gc[ch]);
+                    GS[q] = STORED ? (valid ? fmaf(alpha, diff, GS[q]) : GS[q]) : fmaf(alpha, diff, GS[q]);
+                    // dL/dpower; zero where alpha is clamped at 0.99
+                    const float dp = unclamped ? wgt * diff : 0.f;
+                    if (STORED && valid) {
+                        // step to the pixel's previous pair (if any)
+                        npos[q] = kNoPos;
+                        if (pidx[q] > pbase[q]) {
+                            pidx[q]--;
+                            const PairRec r = a.pairs[pidx[q]];
+                            npos[q] = r.pos;
+                            nal[q] = r.alpha;
+                            T[q] = r.T;
+                        }
+                    }
+                    const float dpy = dp * dy;
+                    m0 += dp;
+                    my += dpy;
+                    myy = fmaf(dpy, dy, myy);
                 }
-                float x0 = 0.f, x1 = 0.f, x2 = 0.f;
-                if (wave_any(any)) {
-                    const float col3[3] = {t.r, t.g, ew[u].b};
-                    // Per lane, dx is the same for all its pixels, so the
-                    // conic and centre gradients need only the moments
-                    // sum dp, sum dp dy, sum dp dy^2 of dL/dpower over them.
-                    float m0 = 0.f, my = 0.f, myy = 0.f, gc[3] = {0.f, 0.f, 0.f};
-                    // q-th pixels of all lanes form a 16 x 4 band of the tile:
-                    // a band with no candidate is skipped as a whole; inside a
-                    // band the update is branch-free, pixels that do not blend
-                    // adding exact zeros.
-#pragma unroll
-                    for (int q = 0; q < kPixPerLane; q++) {
-                        if (!wave_any(cand[q])) continue;
-                        const float dy = s.v - fy[q];
-                        float alpha, wgt;
-                        bool valid, unclamped;
-                        if (STORED) {
-                            // alpha and T_i of this pair as the forward left them
-                            valid = cand[q];
-                            alpha = valid ? fabsf(nal[q]) : 0.f;
-                            unclamped = nal[q] >= 0.f;
-                            wgt = valid ? alpha * T[q] : 0.f;
-                        } else {
-                            const float apre = splat_alpha_pre(p2[q], t.lo);
-                            alpha = fminf(kAlphaMax, apre);
-                            valid = cand[q] && alpha >= kAlphaMin;
-                            unclamped = apre <= kAlphaMax;
-                            const float Tn = T[q] * __builtin_amdgcn_rcpf(1.f - alpha);
-                            T[q] = valid ? Tn : T[q];
-                            wgt = valid ? alpha * T[q] : 0.f;
-                        }
-                        const float Gc = fmaf(G[q][2], col3[2], fmaf(G[q][1], col3[1], G[q][0] * col3[0]));
-                        const float diff = Gc - GS[q];
-#pragma unroll
-                        for (int ch = 0; ch < 3; ch++) gc[ch] = fmaf(G[q][ch], wgt, gc[ch]);
-                        GS[q] = valid ? fmaf(alpha, diff, GS[q]) : GS[q];
-                        // dL/dpower; zero where alpha is clamped at 0.99
-                        const float dp = unclamped ? wgt * diff : 0.f;
-                        if (STORED && valid) {
-                            // step to the pixel's previous pair (if any)
-                            npos[q] = kNoPos;
-                            if (pidx[q] > pbase[q]) {
-                                pidx[q]--;
-                                const PairRec r = a.pairs[pidx[q]];
-                                npos[q] = r.pos;
-                                nal[q] = r.alpha;
-                                T[q] = r.T;
-                            }
-                        }
-                        const float dpy = dp * dy;
-                        m0 += dp;
-                        my += dpy;
-                        myy = fmaf(dpy, dy, myy);
-                    }
+                if (!blended) continue;
+                {
                     // dpower/du = -(A dx + B dy), dpower/dv = -(C dy + B dx),
                     // dpower/d(A, B, C) = -(dx^2 / 2, dx dy, dy^2 / 2), in the
                     // base-2 conic and before the per-component scale below
@@ -341,18 +391,23 @@ __global__ __launch_bounds__(kRasterThreads) __attribute__((amdgpu_waves_per_eu(
                     acc[6] = gc[0];
                     acc[7] = gc[1];
                     acc[8] = gc[2];
-                    wave_sum9(acc, x0, x1, x2);
-                    if (comp >= 0 && ew[u].slot != kNoSlot) {
-                        const float val = col == 0 ? x0 : (col == 1 ? x1 : x2);
-                        const float f = comp == 5 ? ew[u].inv_o : scale;
-                        pslots[9 * kSplit * (size_t)ew[u].slot + comp] = val * f;
-                        if (comp == 0) pflags[kSplit * (size_t)ew[u].slot] = 1;
+                    float ra, rb, rc;
+                    wave_sum9_rows(acc, ra, rb, rc);
+                    float *const dst = sP + npend * kEntryStride + (lane >> 4) * kRowStride + (lane & 15);
+                    dst[0] = ra;
+                    dst[kRegStride] = rb;
+                    dst[2 * kRegStride] = rc;
+                    if (lane == 0) {
+                        sPs[npend] = ew[u].slot;
+                        sPi[npend] = ew[u].inv_o;
                     }
+                    if (++npend == kPend) flush();
                 }
             }
         }
         __syncthreads();
     }
+    if (npend > 0) flush();
 }
 
 hipError_t launch_raster_bwd(const ViewsK &views, const Layout &L, char *ws, const uint32_t *vals,
