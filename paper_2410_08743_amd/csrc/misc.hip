@@ -184,8 +184,20 @@ __global__ __launch_bounds__(64) void k_pose_adam(int V, float *poses, const flo
                                                   const uint32_t *guard) {
     const int i = blockIdx.x * 64 + threadIdx.x;
     if (i >= V) return;
-    if (guard && guard[kCntOverflow] != 0u) return;
+    // every load first (one round of memory latency), then the guard test
+    const uint32_t ovf = guard ? guard[kCntOverflow] : 0u;
     const int k = steps[i] + 1;
+    double gv[6], m0[6], v0[6];
+    float T0[12];
+#pragma unroll
+    for (int e = 0; e < 6; e++) {
+        gv[e] = dpose[6 * i + e];
+        m0[e] = m[6 * i + e];
+        v0[e] = v[6 * i + e];
+    }
+#pragma unroll
+    for (int e = 0; e < 12; e++) T0[e] = poses[12 * i + e];
+    if (ovf != 0u) return;
     steps[i] = k;
     double lr = p.lr_start;
     if (p.total_steps > 1) {
@@ -195,10 +207,8 @@ __global__ __launch_bounds__(64) void k_pose_adam(int V, float *poses, const flo
     const double b1 = p.beta1, b2 = p.beta2;
     const double c1 = 1.0 - pow(b1, (double)k), c2 = 1.0 - pow(b2, (double)k);
     const bool tso3 = p.parametrization == GSP_POSE_T_SO3;
-    double gv[6];
-    for (int e = 0; e < 6; e++) gv[e] = dpose[6 * i + e];
     if (tso3) {   // dL/dc = -R^T dL/drho; the rotation part is unchanged
-        const float *T = poses + 12 * i;
+        const float *T = T0;
         double gc[3];
         for (int k2 = 0; k2 < 3; k2++)
             gc[k2] = -((double)T[k2] * gv[0] + (double)T[4 + k2] * gv[1] + (double)T[8 + k2] * gv[2]);
@@ -207,16 +217,18 @@ __global__ __launch_bounds__(64) void k_pose_adam(int V, float *poses, const flo
     double delta[6];
     for (int e = 0; e < 6; e++) {
         const double g = gv[e];
-        const double mm = b1 * m[6 * i + e] + (1.0 - b1) * g;
-        const double vv = b2 * v[6 * i + e] + (1.0 - b2) * g * g;
+        const double mm = b1 * m0[e] + (1.0 - b1) * g;
+        const double vv = b2 * v0[e] + (1.0 - b2) * g * g;
         m[6 * i + e] = (float)mm;
         v[6 * i + e] = (float)vv;
         delta[e] = -lr * (mm / c1) / (sqrt(vv / c2) + (double)p.eps);
     }
     if (tso3)
-        tso3_step(delta, delta + 3, poses + 12 * i);
+        tso3_step(delta, delta + 3, T0);
     else
-        se3_retract_left(delta, poses + 12 * i);
+        se3_retract_left(delta, T0);
+#pragma unroll
+    for (int e = 0; e < 12; e++) poses[12 * i + e] = T0[e];
 }
 
 hipError_t launch_pose_adam(int V, float *poses, const float *dpose, float *m, float *v,

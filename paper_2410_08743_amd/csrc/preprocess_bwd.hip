@@ -393,16 +393,37 @@ __global__ __launch_bounds__(kPoseReduceBlock) __attribute__((amdgpu_waves_per_e
 }
 
 // One block per view adds the per-block pose partials in a fixed order.
-__global__ __launch_bounds__(256) void k_pose_final(const double *posepart, int nblk, float *dpose,
-                                                    bool accumulate) {
-    __shared__ double red[256 / kWave];
-    const int v = blockIdx.x;
-    for (int c = 0; c < 6; c++) {
-        double s = 0;
-        for (int b = threadIdx.x; b < nblk; b += 256) s += posepart[((size_t)v * nblk + b) * 6 + c];
-        s = block_sum<double, 256>(s, red);
-        if (threadIdx.x == 0) dpose[6 * v + c] = (accumulate ? dpose[6 * v + c] : 0.f) + (float)s;
+// dL/dtau of each view: the sum of the preprocess blocks' FP64 partials in a
+// fixed order.  One 64-lane wave per view; every load is issued before the
+// first add, so that the kernel costs one round of memory latency.
+constexpr int kPoseFinalPer = 16;   // partial rows per lane held in flight
+
+__global__ __launch_bounds__(kWave) void k_pose_final(const double *posepart, int nblk, float *dpose,
+                                                      bool accumulate) {
+    const int v = blockIdx.x, lane = threadIdx.x;
+    const double *src = posepart + (size_t)v * nblk * 6;
+    double s[6] = {0, 0, 0, 0, 0, 0};
+    for (int b0 = 0; b0 < nblk; b0 += kWave * kPoseFinalPer) {
+        double x[kPoseFinalPer][6];
+#pragma unroll
+        for (int r = 0; r < kPoseFinalPer; r++) {
+            const int b = b0 + r * kWave + lane;
+#pragma unroll
+            for (int c = 0; c < 6; c++) x[r][c] = b < nblk ? src[(size_t)b * 6 + c] : 0.0;
+        }
+#pragma unroll
+        for (int r = 0; r < kPoseFinalPer; r++)
+#pragma unroll
+            for (int c = 0; c < 6; c++) s[c] += x[r][c];
     }
+    float prev[6];
+#pragma unroll
+    for (int c = 0; c < 6; c++) prev[c] = accumulate && lane == 0 ? dpose[6 * v + c] : 0.f;
+#pragma unroll
+    for (int c = 0; c < 6; c++) s[c] = wave_sum(s[c]);
+    if (lane == 0)
+#pragma unroll
+        for (int c = 0; c < 6; c++) dpose[6 * v + c] = prev[c] + (float)s[c];
 }
 
 template <int D>
@@ -450,7 +471,7 @@ hipError_t launch_preprocess_bwd(const GaussiansK &g, const ViewsK &views, const
         if (e != hipSuccess) return e;
     }
     if (grads.pose) {
-        hipLaunchKernelGGL(k_pose_final, dim3(L.V), dim3(256), 0, s, a.posepart, L.nblk_pre,
+        hipLaunchKernelGGL(k_pose_final, dim3(L.V), dim3(kWave), 0, s, a.posepart, L.nblk_pre,
                            grads.pose, accumulate);
         return hipGetLastError();
     }
