@@ -10,7 +10,8 @@ seeded (they stand in for the paper's LLFF pose-estimation scenes); the
 target is rendered at the ground-truth pose.
 
 A step is one pass of the whole hot path: preprocess, binning, radix sort,
-tile ranges, forward rasterizer, L1 loss, backward rasterizer,
+tile ranges, per-tile depth order, forward rasterizer with the L1 loss
+gradient in its epilogue (gsp_render_fwd_l1), backward rasterizer,
 preprocess-backward with the pose reduction, and the tangent Adam update.
 `--steps K` steps of one pose solve are timed with HIP events on the stream
 the kernels run on, inputs already resident in HBM.
@@ -159,8 +160,7 @@ def main():
     m0, _ = rast.instances()
     rast.capacity = int(1.5 * m0) + 4096
     rast.ws = None
-    images = torch.empty(3 * P, dtype=torch.float32, device=dev)
-    dl = torch.empty_like(images)
+    dl = torch.empty(3 * P, dtype=torch.float32, device=dev)
     K = args.steps
 
     def new_state():
@@ -170,8 +170,8 @@ def main():
                 "dpose": torch.zeros((1, 6), device=dev)}
 
     def step(s, total):
-        rast.forward(g, [cam], s["pose"], check=False, images=images)
-        R.loss_l1([cam], images, target, grad=dl, with_loss=False)
+        # render and L1 gradient in one pass (gsp_render_fwd_l1)
+        rast.forward_l1(g, [cam], s["pose"], target, grad=dl, check=False)
         rast.backward(g, [cam], s["pose"], dl, want=(), pose=True, out={"pose": s["dpose"]})
         R.pose_adam(s["pose"], s["dpose"], s["m"], s["v"], s["st"], 1e-2, 1e-4, total, guard=rast.ws)
 
@@ -264,7 +264,6 @@ def main():
         "ranges": ("hbm", 8 * M + 8 * ((cam.width + 15) // 16) * ((cam.height + 15) // 16)),
         "depth_order": ("hbm", 12 * M),
         "raster_fwd": ("alu", FWD_FLOPS_EVAL * neval + FWD_FLOPS_BLEND * nblend),
-        "loss_l1": ("hbm", 12 * 3 * P),
         "raster_bwd": ("alu", BWD_FLOPS_EVAL * ncontrib + BWD_FLOPS_BLEND * nblend),
         "preprocess_bwd": ("hbm", (param_bytes - 4) * n + 36 * M + 8 * n),
         "pose_adam": ("hbm", 0),

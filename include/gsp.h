@@ -169,6 +169,26 @@ gsp_status gsp_render_bwd(gsp_ctx *ctx, const gsp_gaussians *g, int32_t V, const
                           void *workspace, size_t ws_bytes, int64_t instance_capacity,
                           const gsp_grads *grads, uint32_t flags, void *stream);
 
+/* Render and L1 photometric loss in one pass (the pose-estimation objective
+ * of Sec. III-B with the L1 term of Eq. (16)): renders exactly as
+ * gsp_render_fwd, and in place of each image writes into dl_dimages[v] the
+ * gradient gsp_loss_l1 would compute from that image and targets[v]:
+ * sign(image - target) / (3 roi_h roi_w), 0 where equal -- bit for bit the
+ * same.  The images themselves are not stored.  The workspace then holds
+ * this forward for gsp_render_bwd exactly as after gsp_render_fwd.
+ *   targets, dl_dimages  host arrays of V device pointers, CHW FP32 like
+ *                        the images (targets read, dl_dimages written)
+ *   loss                 device float [V] or NULL: mean |image - target| of
+ *                        each view, summed in FP64 in a fixed order (tile by
+ *                        tile; bit-reproducible, though its last bits may
+ *                        differ from gsp_loss_l1's block order)
+ * Other arguments and errors as gsp_render_fwd. */
+gsp_status gsp_render_fwd_l1(gsp_ctx *ctx, const gsp_gaussians *g, int32_t V,
+                             const gsp_view *views, const float *poses,
+                             const float *const *targets, float *const *dl_dimages,
+                             float *const *alphas, float *loss, void *workspace, size_t ws_bytes,
+                             int64_t instance_capacity, void *stream);
+
 /* Stored-list mode (the alternative to recomputation in the backward).
  * The backward of Eq. (3)-(4) needs, for every pixel, the alpha_i of its
  * blended splats and the transmittance T_i in front of each.  gsp_render_bwd

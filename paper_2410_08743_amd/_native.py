@@ -23,6 +23,7 @@ EXPORTS = (
     "gsp_gaussian_adam", "gsp_gaussian_adam_scratch_bytes", "gsp_unproject_count",
     "gsp_unproject_scratch_bytes", "gsp_unproject", "gsp_loss_masked_l1",
     "gsp_loss_masked_l1_scratch_bytes", "gsp_loss_l1_noalloc", "gsp_render_fwd_store",
+    "gsp_render_fwd_l1",
     "gsp_render_bwd_stored", "gsp_lists_bytes", "gsp_list_pairs", "gsp_twist_apply",
     "gsp_twist_chain",
 )
@@ -119,6 +120,7 @@ def lib():
         "gsp_loss_masked_l1": ([P, I32, P, P, P, P, P, P, P, P], I32),
         "gsp_loss_masked_l1_scratch_bytes": ([I32, P], SZ),
         "gsp_render_fwd_store": ([P, P, I32, P, P, P, P, P, SZ, I64, P, SZ, I64, P], I32),
+        "gsp_render_fwd_l1": ([P, P, I32, P, P, P, P, P, P, P, SZ, I64, P], I32),
         "gsp_render_bwd_stored": ([P, P, I32, P, P, P, P, SZ, I64, P, SZ, I64, P, ctypes.c_uint32,
                                    P], I32),
         "gsp_lists_bytes": ([I32, P, I64], SZ),

@@ -245,6 +245,7 @@ Layout make_layout(int64_t n, int32_t sh_degree, int32_t V, const ViewsK &views,
     L.slot_flags = take(((size_t)kSplitBwd * capz + 3) & ~size_t(3));
     L.grad2d = take(9 * vn * 4);
     L.posepart = take((size_t)V * L.nblk_pre * 6 * 8);
+    L.l1part = take((size_t)L.total_tiles * kSplitFwd * 8);
     L.total = off;
     return L;
 }
@@ -385,10 +386,14 @@ gsp_status check_lists(const gsp::Layout &L, const void *lists, size_t lists_byt
     return GSP_OK;
 }
 
+// With targets, the forward writes dL/dimage of the per-view L1 loss into
+// `images` (the gradient buffers) instead of the images, and the losses into
+// `loss` when it is given.
 gsp_status render_fwd(gsp_ctx *ctx, const gsp_gaussians *g, int32_t V, const gsp_view *views,
                       const float *poses, float *const *images, float *const *alphas,
                       void *workspace, size_t ws_bytes, int64_t instance_capacity, void *lists,
-                      size_t lists_bytes, int64_t pair_capacity, void *stream) {
+                      size_t lists_bytes, int64_t pair_capacity, void *stream,
+                      const float *const *targets = nullptr, float *loss = nullptr) {
     gsp_status s = check_device(ctx);
     if (s != GSP_OK) return s;
     Prepared p;
@@ -399,6 +404,10 @@ gsp_status render_fwd(gsp_ctx *ctx, const gsp_gaussians *g, int32_t V, const gsp
         if (!images[v]) return fail(GSP_EINVAL, "null image pointer of view %d", v);
         p.views.v[v].img = images[v];
         p.views.v[v].alpha = alphas ? alphas[v] : nullptr;
+        if (targets) {
+            if (!targets[v]) return fail(GSP_EINVAL, "null target pointer of view %d", v);
+            p.views.v[v].dl = targets[v];   // the forward reads the target through dl
+        }
     }
     if (ws_bytes < p.L.total)
         return fail(GSP_ENOMEM, "workspace of %zu bytes is smaller than the %zu needed", ws_bytes,
@@ -430,7 +439,8 @@ gsp_status render_fwd(gsp_ctx *ctx, const gsp_gaussians *g, int32_t V, const gsp
         hipSuccess)
         return hip_fail(e, "depth order");
     if ((e = stage(ctx, "raster_fwd", st, [&] {
-             return gsp::launch_raster_fwd(p.views, p.L, ws, vals, ctx->stats, st);
+             return gsp::launch_raster_fwd(p.views, p.L, ws, vals, ctx->stats, st, targets != nullptr,
+                                           loss);
          })) != hipSuccess)
         return hip_fail(e, "raster forward");
     if (lists) {
@@ -451,6 +461,16 @@ gsp_status gsp_render_fwd(gsp_ctx *ctx, const gsp_gaussians *g, int32_t V, const
                           void *stream) {
     return render_fwd(ctx, g, V, views, poses, images, alphas, workspace, ws_bytes,
                       instance_capacity, nullptr, 0, 0, stream);
+}
+
+gsp_status gsp_render_fwd_l1(gsp_ctx *ctx, const gsp_gaussians *g, int32_t V,
+                             const gsp_view *views, const float *poses,
+                             const float *const *targets, float *const *dl_dimages,
+                             float *const *alphas, float *loss, void *workspace, size_t ws_bytes,
+                             int64_t instance_capacity, void *stream) {
+    if (!targets || !dl_dimages) return fail(GSP_EINVAL, "null targets or gradients");
+    return render_fwd(ctx, g, V, views, poses, dl_dimages, alphas, workspace, ws_bytes,
+                      instance_capacity, nullptr, 0, 0, stream, targets, loss);
 }
 
 gsp_status gsp_render_fwd_store(gsp_ctx *ctx, const gsp_gaussians *g, int32_t V,

@@ -122,7 +122,7 @@ struct Layout {
     size_t keys0, keys1, vals0, vals1, hist, digit_tot, ranges, tile_order;
     size_t items, ckpt, cfinal;   // backward work items, states at the cuts, final colours
     int64_t max_items;
-    size_t tfinal, ncontrib, stats, slots, slot_flags, grad2d, posepart;
+    size_t tfinal, ncontrib, stats, slots, slot_flags, grad2d, posepart, l1part;
     size_t total;
 };
 
@@ -174,8 +174,11 @@ hipError_t launch_tile_sort(const Layout &L, char *ws, hipStream_t s);
 hipError_t launch_tile_depth_sort(const Layout &L, char *ws, hipStream_t s);
 // raster_fwd.hip
 hipError_t launch_ranges(const Layout &L, char *ws, const uint32_t *keys, hipStream_t s);
+// l1: each view's img receives dL/dimage of the L1 loss against the target
+// its dl points to; with `loss`, the loss of each view goes there as well.
 hipError_t launch_raster_fwd(const ViewsK &views, const Layout &L, char *ws,
-                             const uint32_t *vals, bool stats, hipStream_t s);
+                             const uint32_t *vals, bool stats, hipStream_t s, bool l1 = false,
+                             float *loss = nullptr);
 // raster_bwd.hip; with `lists` the stored-list variant (one workgroup per
 // tile, alpha and T read from the pair records)
 hipError_t launch_raster_bwd(const ViewsK &views, const Layout &L, char *ws,

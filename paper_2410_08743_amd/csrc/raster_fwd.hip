@@ -140,8 +140,14 @@ struct FwdArgs {
     uint32_t *nblend;   // STATS only: entries blended per pixel
     float4 *ckpt;       // per cut and tile pixel: (T, colour in front of the cut)
     float *cfinal;      // [3][total_pix]: final colour, for tiles with cuts
+    // L1-fused forward: each view's img holds dL/dimage of the mean absolute
+    // error against the target its dl points to (instead of the image), and
+    // with l1part each wave leaves its FP64 sum of |image - target| at
+    // [tile * kSplit + part]
+    double *l1part;
     int total_pix;
     int total_tiles;
+    bool l1;
 };
 
 template <int N>
@@ -310,6 +316,9 @@ __global__ __launch_bounds__(kRasterThreads) __attribute__((amdgpu_waves_per_eu(
     }
 
     const int P = vw.roi_w * vw.roi_h;
+    // L1-fused: sign(image - target) / (3 P), as gsp_loss_l1 writes it
+    const float l1_inv = 1.0f / (float)(3 * (int64_t)P);
+    double l1sum = 0.0;
 #pragma unroll
     for (int q = 0; q < kPixPerLane; q++) {
         const int ry = kTile * ty + row0 + ly + 4 * q;
@@ -319,9 +328,20 @@ __global__ __launch_bounds__(kRasterThreads) __attribute__((amdgpu_waves_per_eu(
         float *img = vw.img;
         const float fr = cr[q] + Tf * vw.bg[0], fg = cg[q] + Tf * vw.bg[1],
                     fb = cb[q] + Tf * vw.bg[2];
-        img[pix] = fr;
-        img[(size_t)P + pix] = fg;
-        img[2 * (size_t)P + pix] = fb;
+        if (a.l1) {
+            const float *tg = vw.dl;
+            const float c3[3] = {fr, fg, fb};
+#pragma unroll
+            for (int ch = 0; ch < 3; ch++) {
+                const float d = c3[ch] - tg[(size_t)ch * P + pix];
+                img[(size_t)ch * P + pix] = d > 0.f ? l1_inv : (d < 0.f ? -l1_inv : 0.f);
+                l1sum += fabs((double)d);
+            }
+        } else {
+            img[pix] = fr;
+            img[(size_t)P + pix] = fg;
+            img[2 * (size_t)P + pix] = fb;
+        }
         if (last[q] > kChunk) {   // the backward's chunks derive the colour behind a cut from it
             a.cfinal[vw.pix_base + pix] = fr;
             a.cfinal[(size_t)a.total_pix + vw.pix_base + pix] = fg;
@@ -336,6 +356,23 @@ __global__ __launch_bounds__(kRasterThreads) __attribute__((amdgpu_waves_per_eu(
             a.nblend[vw.pix_base + pix] = nb[q];
         }
     }
+    if (a.l1part) {
+        l1sum = wave_sum(l1sum);
+        if (lane == 0) a.l1part[(size_t)tile * kSplit + part] = l1sum;
+    }
+}
+
+// Loss of an L1-fused forward: per view, the waves' partial sums in tile and
+// strip order, over the view's 3 x roi_h x roi_w values.
+__global__ __launch_bounds__(256) void k_l1_fused_final(ViewsK views, const double *l1part,
+                                                        float *loss) {
+    __shared__ double red[256 / kWave];
+    const ViewK &vw = views.v[blockIdx.x];
+    const int64_t b0 = (int64_t)vw.tile_base * kSplit, n = (int64_t)vw.gw * vw.gh * kSplit;
+    double s = 0.0;
+    for (int64_t k = threadIdx.x; k < n; k += 256) s += l1part[b0 + k];
+    s = block_sum<double, 256>(s, red);
+    if (threadIdx.x == 0) loss[blockIdx.x] = (float)(s / (double)(3 * (int64_t)vw.roi_w * vw.roi_h));
 }
 
 hipError_t launch_ranges(const Layout &L, char *ws, const uint32_t *keys, hipStream_t s) {
@@ -352,9 +389,11 @@ hipError_t launch_ranges(const Layout &L, char *ws, const uint32_t *keys, hipStr
 }
 
 hipError_t launch_raster_fwd(const ViewsK &views, const Layout &L, char *ws, const uint32_t *vals,
-                             bool stats, hipStream_t s) {
+                             bool stats, hipStream_t s, bool l1, float *loss) {
     if (L.total_tiles == 0) return hipSuccess;
     FwdArgs a;
+    a.l1 = l1;
+    a.l1part = l1 && loss ? region<double>(ws, L.l1part) : nullptr;
     a.order = region<uint32_t>(ws, L.tile_order);
     a.ranges = region<uint2>(ws, L.ranges);
     a.vals = vals;
@@ -373,6 +412,9 @@ hipError_t launch_raster_fwd(const ViewsK &views, const Layout &L, char *ws, con
         hipLaunchKernelGGL(k_raster_fwd<true>, grid, dim3(kRasterThreads), 0, s, a, views);
     else
         hipLaunchKernelGGL(k_raster_fwd<false>, grid, dim3(kRasterThreads), 0, s, a, views);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess || !a.l1part) return e;
+    hipLaunchKernelGGL(k_l1_fused_final, dim3(views.count), dim3(256), 0, s, views, a.l1part, loss);
     return hipGetLastError();
 }
 

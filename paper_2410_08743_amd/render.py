@@ -213,6 +213,20 @@ class Rasterizer:
         output buffer (packed tensor or list of per-view [h, w] tensors).
         `images` is an optional output: one packed tensor or a list of
         per-view [3, h, w] tensors; by default a packed tensor is made."""
+        images, al, _ = self._forward(g, cams, poses, alphas, check, images, None, False)
+        return images, al
+
+    def forward_l1(self, g: GaussianParams, cams: Sequence, poses: torch.Tensor, targets,
+                   grad=None, with_loss: bool = False, alphas=False, check: bool = True):
+        """Render and L1 loss in one pass (gsp_render_fwd_l1): returns
+        (per-view losses [V] or None, dL/dimage, alphas or None).  The
+        gradient is the one loss_l1 computes from the rendered images, bit for
+        bit; the images themselves are not kept.  `targets` and `grad` are
+        packed tensors or lists of per-view [3, h, w] tensors."""
+        grad, al, loss = self._forward(g, cams, poses, alphas, check, grad, targets, with_loss)
+        return loss, grad, al
+
+    def _forward(self, g, cams, poses, alphas, check, images, targets, with_loss):
         L = N.lib()
         views = N.view_array(cams)
         poses = poses.contiguous()
@@ -233,9 +247,21 @@ class Rasterizer:
         gs = g.struct()
         img_ptrs = view_ptrs(images, cams, 3)
         al_ptrs = view_ptrs(al, cams, 1)
+        loss = None
+        if targets is not None:
+            if self.store_lists:
+                raise ValueError("the L1-fused forward does not store lists")
+            tgt_ptrs = view_ptrs(targets, cams, 3)
+            if with_loss:
+                loss = torch.empty(len(cams), dtype=torch.float32, device=dev)
         for _ in range(8):
             nbytes = self._ensure(g, views)
-            if self.store_lists:
+            if targets is not None:
+                N.check(L.gsp_render_fwd_l1(context(self.device), ctypes.byref(gs), len(cams),
+                                            views, _ptr(poses), tgt_ptrs, img_ptrs, al_ptrs,
+                                            _ptr(loss), _ptr(self.ws), nbytes, self.capacity,
+                                            _stream()), "gsp_render_fwd_l1")
+            elif self.store_lists:
                 lbytes = self._ensure_lists(views)
                 N.check(L.gsp_render_fwd_store(context(self.device), ctypes.byref(gs), len(cams),
                                                views, _ptr(poses), img_ptrs, al_ptrs, _ptr(self.ws),
@@ -261,7 +287,7 @@ class Rasterizer:
                     continue
             break
         self.generation += 1
-        return images, al
+        return images, al, loss
 
     def backward(self, g: GaussianParams, cams: Sequence, poses: torch.Tensor,
                  dl_dimages, want=("means", "scales", "quats", "opacities", "sh"),
