@@ -535,8 +535,9 @@ def solve_poses(g: GaussianParams, cams: Sequence, targets: torch.Tensor, init_p
                 loss, _ = masked_l1(cams, images, targets, alpha, grad=dl, with_loss=history,
                                     scratch=mscratch)
             else:
-                rast.forward(g, cams, poses, check=False, images=images)
-                loss, _ = loss_l1(cams, images, targets, grad=dl, with_loss=history)
+                # render and L1 gradient in one pass
+                loss, _, _ = rast.forward_l1(g, cams, poses, targets, grad=dl, with_loss=history,
+                                             check=False)
             rast.backward(g, cams, poses, dl, want=(), pose=True, out={"pose": dpose})
             pose_adam(poses, dpose, m, v, st, lr[0], lr[1], steps, betas[0], betas[1], eps,
                       guard=rast.ws, parametrization=parametrization)

@@ -5,7 +5,7 @@ it means `iters` tangent-space Adam iterations on the L1 loss (Sec. III-B,
 the pose-estimation use of Eq. (5)-(13)).  The server keeps the scene on the
 device and runs every request that is in flight in ONE launch per iteration:
 one view per request, each of its own size, through the library's batched
-forward, loss, backward and Adam calls.  Requests that arrive while others
+render-with-L1 (one pass), backward and Adam calls.  Requests that arrive while others
 are running join at the next iteration boundary when a batch slot and enough
 of the HBM budget are free, and leave when their last iteration is done, so
 work from different requests overlaps on the device (continuous batching).
@@ -60,9 +60,8 @@ class PoseResult:
 class _Live:
     """Book-keeping of one admitted request."""
 
-    def __init__(self, req, img, dl, nbytes, admitted):
+    def __init__(self, req, dl, nbytes, admitted):
         self.req = req
-        self.img = img
         self.dl = dl
         self.nbytes = nbytes
         self.admitted = admitted
@@ -131,11 +130,11 @@ class PoseServer:
     def request_bytes(self, cam):
         """HBM a request holds while admitted: its share of the workspace (the
         per-view splat records, sorted instances, slots and per-pixel state,
-        as one single-view workspace) plus its image, image gradient and
-        target."""
+        as one single-view workspace) plus its image gradient and target (the
+        render and its L1 gradient are one pass; no image is kept)."""
         _, _, w, h = R.region(cam)
         ws1 = self._ws_bytes(N.view_array([cam]), self.instances_estimate(cam))
-        return int(ws1 + 3 * 12 * w * h)
+        return int(ws1 + 2 * 12 * w * h)
 
     # -- one iteration -----------------------------------------------------
     def _enqueue(self, running, it, pinned):
@@ -150,15 +149,13 @@ class PoseServer:
         if self.ws is None or self.ws.numel() < nbytes:
             self.ws = torch.zeros(int(nbytes * 1.25) + (1 << 20), dtype=torch.uint8, device=self.dev)
         gs = self.g.struct()
-        img = N.ptr_array([x.img.data_ptr() for x in running])
         dl = N.ptr_array([x.dl.data_ptr() for x in running])
         tgt = N.ptr_array([x.req.target.data_ptr() for x in running])
         wsp = ctypes.c_void_p(self.ws.data_ptr())
         poses = ctypes.c_void_p(self.poses.data_ptr())
         dpose = ctypes.c_void_p(self.dpose.data_ptr())
-        N.check(L.gsp_render_fwd(ctx, ctypes.byref(gs), V, views, poses, img, None, wsp, nbytes,
-                                 cap, st), "gsp_render_fwd")
-        N.check(L.gsp_loss_l1(ctx, V, views, img, tgt, dl, None, None, st), "gsp_loss_l1")
+        N.check(L.gsp_render_fwd_l1(ctx, ctypes.byref(gs), V, views, poses, tgt, dl, None, None,
+                                    wsp, nbytes, cap, st), "gsp_render_fwd_l1")
         gr = N.Grads(None, None, None, None, None, self.dpose.data_ptr())
         N.check(L.gsp_render_bwd(ctx, ctypes.byref(gs), V, views, poses, dl, wsp, nbytes, cap,
                                  ctypes.byref(gr), 0, st), "gsp_render_bwd")
@@ -221,7 +218,6 @@ class PoseServer:
             nonlocal used
             _, _, w, h = R.region(r.camera)
             x = _Live(r, torch.empty((3, h, w), dtype=torch.float32, device=self.dev),
-                      torch.empty((3, h, w), dtype=torch.float32, device=self.dev),
                       self.request_bytes(r.camera), now())
             p = len(running)
             self.poses[p].copy_(r.init_pose)
