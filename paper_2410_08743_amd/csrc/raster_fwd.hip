@@ -69,9 +69,18 @@ __global__ __launch_bounds__(kOrderThreads) void k_tile_order(const uint2 *range
         }
     };
     const int wave0 = t - lane;   // first thread of this wave
+    // the first group's lengths serve both passes (a call with at most kStep
+    // tiles loads its ranges once)
+    int len_first[kOrderRounds];
+    load(0, len_first);
     for (int k0 = 0; k0 < total_tiles; k0 += kStep) {
         int len[kOrderRounds];
-        load(k0, len);
+        if (k0 == 0) {
+#pragma unroll
+            for (int r = 0; r < kOrderRounds; r++) len[r] = len_first[r];
+        } else {
+            load(k0, len);
+        }
         uint32_t full = 0;   // this thread's full chunks in the round
 #pragma unroll
         for (int r = 0; r < kOrderRounds; r++) {
@@ -86,18 +95,26 @@ __global__ __launch_bounds__(kOrderThreads) void k_tile_order(const uint2 *range
         if (lane == 0 && wfull > 0) atomicAdd(&cnt[1][kFull], wfull);
     }
     __syncthreads();
-    if (t < 2) {
-        uint32_t acc = 0;
-        for (int b = 0; b < kOrderBuckets; b++) {
-            base[t][b] = acc;
-            acc += cnt[t][b];
+    // exclusive scans of the two bucket histograms: one wave, a bucket per lane
+    static_assert(kOrderBuckets == kWave, "one bucket per lane");
+    if (t < kWave) {
+#pragma unroll
+        for (int h = 0; h < 2; h++) {
+            const uint32_t c = cnt[h][lane];
+            const uint32_t inc = wave_inclusive_scan(c);
+            base[h][lane] = inc - c;
+            if (h == 1 && lane == kWave - 1) counters[kCntItems] = inc;
         }
-        if (t == 1) counters[kCntItems] = acc;
     }
     __syncthreads();
     for (int k0 = 0; k0 < total_tiles; k0 += kStep) {
         int len[kOrderRounds];
-        load(k0, len);
+        if (k0 == 0) {
+#pragma unroll
+            for (int r = 0; r < kOrderRounds; r++) len[r] = len_first[r];
+        } else {
+            load(k0, len);
+        }
         uint32_t full = 0;
 #pragma unroll
         for (int r = 0; r < kOrderRounds; r++) full += len[r] >= 0 ? (uint32_t)(chunks_of(len[r]) - 1) : 0u;
