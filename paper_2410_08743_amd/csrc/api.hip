@@ -244,7 +244,7 @@ Layout make_layout(int64_t n, int32_t sh_degree, int32_t V, const ViewsK &views,
     L.slots = take(9 * (size_t)kSplitBwd * capz * 4);
     L.slot_flags = take(((size_t)kSplitBwd * capz + 3) & ~size_t(3));
     L.grad2d = take(9 * vn * 4);
-    L.posepart = take((size_t)V * L.nblk_pre * 6 * 8);
+    L.posepart = take((size_t)V * L.nblk_pre * kPoseRowsPerBlock * 6 * 8);
     L.l1part = take((size_t)L.total_tiles * kSplitFwd * 8);
     L.total = off;
     return L;

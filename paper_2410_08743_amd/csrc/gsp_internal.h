@@ -37,6 +37,8 @@ constexpr int kSortItems = kSortThreads * kSortRounds;  // keys per sort block
 constexpr int kSortBits = 8;             // radix digit width
 constexpr int kSortBins = 1 << kSortBits;
 constexpr int kPoseReduceBlock = 256;
+// Rows of per-wavefront pose partials per preprocess-backward block.
+constexpr int kPoseRowsPerBlock = kPoseReduceBlock / 64;
 // Instance-offset scan over the depth-sorted splats: splats per thread and
 // per block.
 constexpr int kScanPerThread = 4;

@@ -7,13 +7,13 @@
 // SSIM uses the 11 x 11 Gaussian window (sigma 1.5) of the 3DGS loss the
 // paper adopts, C1 = 0.01^2, C2 = 0.03^2 and zero padding outside the image.
 // It is computed in two passes over 64 x 16 pixel tiles of one channel: the
-// forward filters the five local moments separably in LDS and stores, per
-// pixel, the three partial derivatives of SSIM with respect to the filtered
-// quantities (mean, E[x^2], E[xy]); the backward filters those three maps
-// with the same (symmetric) window, which is the adjoint of the forward
-// filter, and combines them into dL/dpred together with the L1 term.  Both
-// passes are bound by HBM traffic (x, y in; three maps out; three maps, x, y
-// in; gradient out).
+// forward filters the five local moments separably (columns first, the
+// column sums in LDS) and stores, per pixel, the three partial derivatives
+// of SSIM with respect to the filtered quantities (mean, E[x^2], E[xy]); the
+// backward filters those three maps with the same (symmetric) window, which
+// is the adjoint of the forward filter, and combines them into dL/dpred
+// together with the L1 term.  HBM traffic per pixel and channel: x, y in and
+// three maps out; three maps, x, y in and the gradient out.
 #include "block_ops.h"
 #include "gsp_internal.h"
 
@@ -23,8 +23,7 @@ constexpr int kSsimR = 5;                        // window radius
 constexpr int kSsimTaps = 2 * kSsimR + 1;
 constexpr int kSsimTW = 64, kSsimTH = 16;        // output tile
 constexpr int kSsimThreads = 256;
-constexpr int kSsimLW = kSsimTW + 2 * kSsimR;    // staged tile with halo
-constexpr int kSsimLH = kSsimTH + 2 * kSsimR;
+constexpr int kSsimLW = kSsimTW + 2 * kSsimR;    // columns with halo
 constexpr float kSsimC1 = 0.01f * 0.01f;
 constexpr float kSsimC2 = 0.03f * 0.03f;
 
@@ -38,15 +37,24 @@ __device__ __forceinline__ int rgb_view_of(const RgbViewsK &a, int tile) {
     return v;
 }
 
-// Register blocking of the separable filters: a horizontal work item is a
-// run of kSsimRun outputs of one staged row (kSsimRun + 10 LDS reads instead
-// of 11 per output), a vertical one a run of kSsimRows consecutive output
-// rows of one column.  Each output is still the sum over the taps in tap
-// order.
-constexpr int kSsimRun = 8;
-constexpr int kSsimRows = kSsimTH / (kSsimThreads / kSsimTW);   // 4
-constexpr int kSsimLD = kSsimLW + 2;   // staged row stride: 16-byte aligned runs
-static_assert(kSsimLH * (kSsimTW / kSsimRun) <= kSsimThreads, "one horizontal item per thread");
+// Work split of the separable filters, vertical pass first.  A vertical
+// work item is one staged column (the 64 output columns plus the 5-column
+// halo on each side) and kSsimVR consecutive output rows: it reads its
+// kSsimVR + 10 input rows straight from global memory (consecutive threads
+// take consecutive columns, so each row is one coalesced segment) and leaves
+// the column sums in LDS.  A horizontal item is a run of kSsimHRun outputs
+// of one row, read from LDS as aligned vectors.  Each output is still the
+// sum over the taps in tap order.  Only the column sums live in LDS (24 KB
+// for the forward's five moments), so six blocks fit a CU.
+constexpr int kSsimVR = 4;                                   // output rows per vertical item
+constexpr int kSsimVIn = kSsimVR + 2 * kSsimR;               // input rows it reads
+constexpr int kSsimVItems = kSsimLW * (kSsimTH / kSsimVR);   // 296
+constexpr int kSsimHRun = 4;                                 // outputs per horizontal item
+constexpr int kSsimHIn = kSsimHRun + 2 * kSsimR;             // column sums it reads
+constexpr int kSsimVLD = 76;                                 // row stride of the column sums
+static_assert(kSsimTH * (kSsimTW / kSsimHRun) == kSsimThreads, "one horizontal item per thread");
+static_assert(kSsimVLD % 4 == 0 && kSsimVLD >= kSsimLW, "16-byte aligned rows");
+static_assert(kSsimHIn == 14, "a horizontal item reads three float4 and one float2");
 
 __device__ __forceinline__ void ssim_tile_origin(const RgbViewsK &a, int tile, int &v, int &x0,
                                                  int &y0) {
@@ -56,11 +64,21 @@ __device__ __forceinline__ void ssim_tile_origin(const RgbViewsK &a, int tile, i
     y0 = (lt / a.tiles_x[v]) * kSsimTH;
 }
 
+// The kSsimHIn column sums of a horizontal item, starting at column q0.
+__device__ __forceinline__ void ssim_load_run(const float *row, int q0, float (&h)[kSsimHIn]) {
+    const float4 a = *reinterpret_cast<const float4 *>(row + q0);
+    const float4 b = *reinterpret_cast<const float4 *>(row + q0 + 4);
+    const float4 c = *reinterpret_cast<const float4 *>(row + q0 + 8);
+    const float2 d = *reinterpret_cast<const float2 *>(row + q0 + 12);
+    h[0] = a.x; h[1] = a.y; h[2] = a.z; h[3] = a.w;
+    h[4] = b.x; h[5] = b.y; h[6] = b.z; h[7] = b.w;
+    h[8] = c.x; h[9] = c.y; h[10] = c.z; h[11] = c.w;
+    h[12] = d.x; h[13] = d.y;
+}
+
 // partial[c * total_tiles + tile] = (sum of SSIM, sum of |x - y|) of the tile.
 __global__ __launch_bounds__(kSsimThreads) void k_ssim_fwd(RgbViewsK a, double2 *partial) {
-    __shared__ __align__(16) float sx[kSsimLH][kSsimLD];
-    __shared__ __align__(16) float sy[kSsimLH][kSsimLD];
-    __shared__ float hm[5][kSsimLH][kSsimTW];
+    __shared__ __align__(16) float vm[5][kSsimTH][kSsimVLD];
     __shared__ double red[kSsimThreads / kWave];
     const int tile = blockIdx.x, c = blockIdx.y;
     int v, x0, y0;
@@ -69,29 +87,28 @@ __global__ __launch_bounds__(kSsimThreads) void k_ssim_fwd(RgbViewsK a, double2 
     const size_t plane = (size_t)W * H;
     const float *X = a.pred[v] + c * plane, *Y = a.target[v] + c * plane;
     const int t = threadIdx.x;
-    for (int i = t; i < kSsimLH * kSsimLW; i += kSsimThreads) {
-        const int r = i / kSsimLW, q = i - r * kSsimLW;
-        const int gy = y0 + r - kSsimR, gx = x0 + q - kSsimR;
-        const bool in = gy >= 0 && gy < H && gx >= 0 && gx < W;
-        sx[r][q] = in ? X[(size_t)gy * W + gx] : 0.f;
-        sy[r][q] = in ? Y[(size_t)gy * W + gx] : 0.f;
-    }
-    __syncthreads();
-    if (t < kSsimLH * (kSsimTW / kSsimRun)) {
-        const int r = t / (kSsimTW / kSsimRun), q0 = (t % (kSsimTW / kSsimRun)) * kSsimRun;
-        // the run's values and their squares and products, once each
-        float xv[kSsimRun + 2 * kSsimR], yv[kSsimRun + 2 * kSsimR];
-        float xx[kSsimRun + 2 * kSsimR], yy[kSsimRun + 2 * kSsimR], xy[kSsimRun + 2 * kSsimR];
+    for (int item = t; item < kSsimVItems; item += kSsimThreads) {
+        const int g = item / kSsimLW, q = item - g * kSsimLW;
+        const int gx = x0 + q - kSsimR, gy0 = y0 + kSsimVR * g - kSsimR;
+        const bool colin = gx >= 0 && gx < W;
+        float xv[kSsimVIn], yv[kSsimVIn];
 #pragma unroll
-        for (int j = 0; j < kSsimRun + 2 * kSsimR; j++) {
-            xv[j] = sx[r][q0 + j];
-            yv[j] = sy[r][q0 + j];
+        for (int j = 0; j < kSsimVIn; j++) {
+            const int gy = gy0 + j;
+            const bool in = colin && gy >= 0 && gy < H;
+            xv[j] = in ? X[(size_t)gy * W + gx] : 0.f;
+            yv[j] = in ? Y[(size_t)gy * W + gx] : 0.f;
+        }
+        // the column's values and their squares and products, once each
+        float xx[kSsimVIn], yy[kSsimVIn], xy[kSsimVIn];
+#pragma unroll
+        for (int j = 0; j < kSsimVIn; j++) {
             xx[j] = xv[j] * xv[j];
             yy[j] = yv[j] * yv[j];
             xy[j] = xv[j] * yv[j];
         }
 #pragma unroll
-        for (int o = 0; o < kSsimRun; o++) {
+        for (int o = 0; o < kSsimVR; o++) {
             float s0 = 0.f, s1 = 0.f, s2 = 0.f, s3 = 0.f, s4 = 0.f;
 #pragma unroll
             for (int k = 0; k < kSsimTaps; k++) {
@@ -102,54 +119,55 @@ __global__ __launch_bounds__(kSsimThreads) void k_ssim_fwd(RgbViewsK a, double2 
                 s3 = fmaf(wk, yy[o + k], s3);
                 s4 = fmaf(wk, xy[o + k], s4);
             }
-            hm[0][r][q0 + o] = s0;
-            hm[1][r][q0 + o] = s1;
-            hm[2][r][q0 + o] = s2;
-            hm[3][r][q0 + o] = s3;
-            hm[4][r][q0 + o] = s4;
+            const int r = kSsimVR * g + o;
+            vm[0][r][q] = s0;
+            vm[1][r][q] = s1;
+            vm[2][r][q] = s2;
+            vm[3][r][q] = s3;
+            vm[4][r][q] = s4;
         }
     }
     __syncthreads();
-    const int tx = t % kSsimTW, r0 = (t / kSsimTW) * kSsimRows;
-    float col[5][kSsimRows + 2 * kSsimR];
-#pragma unroll
-    for (int m = 0; m < 5; m++)
-#pragma unroll
-        for (int j = 0; j < kSsimRows + 2 * kSsimR; j++) col[m][j] = hm[m][r0 + j][tx];
+    const int r = t / (kSsimTW / kSsimHRun), q0 = (t % (kSsimTW / kSsimHRun)) * kSsimHRun;
+    const int gy = y0 + r;
     float *G = a.gmap[v];
     double ssum = 0.0, l1sum = 0.0;
+    if (gy < H) {
+        float h[5][kSsimHIn];
 #pragma unroll
-    for (int j = 0; j < kSsimRows; j++) {
-        const int r = r0 + j;
-        const int gy = y0 + r, gx = x0 + tx;
-        if (gy >= H || gx >= W) continue;
-        float mx = 0.f, my = 0.f, exx = 0.f, eyy = 0.f, exy = 0.f;
+        for (int m = 0; m < 5; m++) ssim_load_run(&vm[m][r][0], q0, h[m]);
 #pragma unroll
-        for (int k = 0; k < kSsimTaps; k++) {
-            const float wk = a.win[k];
-            mx = fmaf(wk, col[0][j + k], mx);
-            my = fmaf(wk, col[1][j + k], my);
-            exx = fmaf(wk, col[2][j + k], exx);
-            eyy = fmaf(wk, col[3][j + k], eyy);
-            exy = fmaf(wk, col[4][j + k], exy);
+        for (int o = 0; o < kSsimHRun; o++) {
+            const int gx = x0 + q0 + o;
+            if (gx >= W) continue;
+            float mx = 0.f, my = 0.f, exx = 0.f, eyy = 0.f, exy = 0.f;
+#pragma unroll
+            for (int k = 0; k < kSsimTaps; k++) {
+                const float wk = a.win[k];
+                mx = fmaf(wk, h[0][o + k], mx);
+                my = fmaf(wk, h[1][o + k], my);
+                exx = fmaf(wk, h[2][o + k], exx);
+                eyy = fmaf(wk, h[3][o + k], eyy);
+                exy = fmaf(wk, h[4][o + k], exy);
+            }
+            const float sxx = fmaf(-mx, mx, exx), syy = fmaf(-my, my, eyy), sxy = fmaf(-mx, my, exy);
+            const float a1 = fmaf(2.f * mx, my, kSsimC1), a2 = fmaf(2.f, sxy, kSsimC2);
+            const float b1 = fmaf(mx, mx, fmaf(my, my, kSsimC1)), b2 = sxx + syy + kSsimC2;
+            // one division: 1 / b1 = b2 inv and 1 / b2 = b1 inv
+            const float inv = 1.f / (b1 * b2);
+            const float S = a1 * a2 * inv;
+            // dS/dmu_x, dS/dsigma_x^2, dS/dsigma_xy, then through the raw moments
+            const float ds_dmx = 2.f * my * a2 * inv - 2.f * mx * S * (b2 * inv);
+            const float ds_dsxx = -S * (b1 * inv);
+            const float ds_dsxy = 2.f * a1 * inv;
+            const float g_mean = ds_dmx - 2.f * mx * ds_dsxx - my * ds_dsxy;
+            const size_t p = (size_t)gy * W + gx;
+            G[(size_t)(0 + c) * plane + p] = g_mean;
+            G[(size_t)(3 + c) * plane + p] = ds_dsxx;
+            G[(size_t)(6 + c) * plane + p] = ds_dsxy;
+            ssum += (double)S;
+            l1sum += fabs((double)X[p] - (double)Y[p]);
         }
-        const float sxx = fmaf(-mx, mx, exx), syy = fmaf(-my, my, eyy), sxy = fmaf(-mx, my, exy);
-        const float a1 = fmaf(2.f * mx, my, kSsimC1), a2 = fmaf(2.f, sxy, kSsimC2);
-        const float b1 = fmaf(mx, mx, fmaf(my, my, kSsimC1)), b2 = sxx + syy + kSsimC2;
-        // one division: 1 / b1 = b2 inv and 1 / b2 = b1 inv
-        const float inv = 1.f / (b1 * b2);
-        const float S = a1 * a2 * inv;
-        // dS/dmu_x, dS/dsigma_x^2, dS/dsigma_xy, then through the raw moments
-        const float ds_dmx = 2.f * my * a2 * inv - 2.f * mx * S * (b2 * inv);
-        const float ds_dsxx = -S * (b1 * inv);
-        const float ds_dsxy = 2.f * a1 * inv;
-        const float g_mean = ds_dmx - 2.f * mx * ds_dsxx - my * ds_dsxy;
-        const size_t o = (size_t)gy * W + gx;
-        G[(size_t)(0 + c) * plane + o] = g_mean;
-        G[(size_t)(3 + c) * plane + o] = ds_dsxx;
-        G[(size_t)(6 + c) * plane + o] = ds_dsxy;
-        ssum += (double)S;
-        l1sum += fabs((double)sx[r + kSsimR][tx + kSsimR] - (double)sy[r + kSsimR][tx + kSsimR]);
     }
     ssum = block_sum<double, kSsimThreads>(ssum, red);
     l1sum = block_sum<double, kSsimThreads>(l1sum, red);
@@ -160,8 +178,7 @@ __global__ __launch_bounds__(kSsimThreads) void k_ssim_fwd(RgbViewsK a, double2 
 // y F g_exy), F the window filter (its own adjoint: the window is symmetric
 // and the maps are zero outside the image), N = 3 W H.
 __global__ __launch_bounds__(kSsimThreads) void k_ssim_bwd(RgbViewsK a) {
-    __shared__ __align__(16) float sg[3][kSsimLH][kSsimLD];
-    __shared__ float hg[3][kSsimLH][kSsimTW];
+    __shared__ __align__(16) float vg[3][kSsimTH][kSsimVLD];
     const int tile = blockIdx.x, c = blockIdx.y;
     int v, x0, y0;
     ssim_tile_origin(a, tile, v, x0, y0);
@@ -169,59 +186,57 @@ __global__ __launch_bounds__(kSsimThreads) void k_ssim_bwd(RgbViewsK a) {
     const size_t plane = (size_t)W * H;
     const float *G = a.gmap[v];
     const int t = threadIdx.x;
-    for (int i = t; i < kSsimLH * kSsimLW; i += kSsimThreads) {
-        const int r = i / kSsimLW, q = i - r * kSsimLW;
-        const int gy = y0 + r - kSsimR, gx = x0 + q - kSsimR;
-        const bool in = gy >= 0 && gy < H && gx >= 0 && gx < W;
-        const size_t o = (size_t)gy * W + gx;
-#pragma unroll
-        for (int m = 0; m < 3; m++) sg[m][r][q] = in ? G[(size_t)(3 * m + c) * plane + o] : 0.f;
-    }
-    __syncthreads();
-    if (t < kSsimLH * (kSsimTW / kSsimRun)) {
-        const int r = t / (kSsimTW / kSsimRun), q0 = (t % (kSsimTW / kSsimRun)) * kSsimRun;
+    for (int item = t; item < kSsimVItems; item += kSsimThreads) {
+        const int g = item / kSsimLW, q = item - g * kSsimLW;
+        const int gx = x0 + q - kSsimR, gy0 = y0 + kSsimVR * g - kSsimR;
+        const bool colin = gx >= 0 && gx < W;
 #pragma unroll
         for (int m = 0; m < 3; m++) {
-            float gv[kSsimRun + 2 * kSsimR];
+            const float *Gm = G + (size_t)(3 * m + c) * plane;
+            float gv[kSsimVIn];
 #pragma unroll
-            for (int j = 0; j < kSsimRun + 2 * kSsimR; j++) gv[j] = sg[m][r][q0 + j];
+            for (int j = 0; j < kSsimVIn; j++) {
+                const int gy = gy0 + j;
+                const bool in = colin && gy >= 0 && gy < H;
+                gv[j] = in ? Gm[(size_t)gy * W + gx] : 0.f;
+            }
 #pragma unroll
-            for (int o = 0; o < kSsimRun; o++) {
+            for (int o = 0; o < kSsimVR; o++) {
                 float s = 0.f;
 #pragma unroll
                 for (int k = 0; k < kSsimTaps; k++) s = fmaf(a.win[k], gv[o + k], s);
-                hg[m][r][q0 + o] = s;
+                vg[m][kSsimVR * g + o][q] = s;
             }
         }
     }
     __syncthreads();
-    const int tx = t % kSsimTW, r0 = (t / kSsimTW) * kSsimRows;
-    float col[3][kSsimRows + 2 * kSsimR];
+    const int r = t / (kSsimTW / kSsimHRun), q0 = (t % (kSsimTW / kSsimHRun)) * kSsimHRun;
+    const int gy = y0 + r;
+    if (gy >= H) return;
+    float h[3][kSsimHIn];
 #pragma unroll
-    for (int m = 0; m < 3; m++)
-#pragma unroll
-        for (int j = 0; j < kSsimRows + 2 * kSsimR; j++) col[m][j] = hg[m][r0 + j][tx];
+    for (int m = 0; m < 3; m++) ssim_load_run(&vg[m][r][0], q0, h[m]);
     const float *X = a.pred[v] + c * plane, *Y = a.target[v] + c * plane;
     float *D = a.grad[v] + c * plane;
     const float invn = 1.f / (3.f * (float)plane);
     const float wl1 = (1.f - a.beta) * invn, wss = -a.beta * invn;
 #pragma unroll
-    for (int j = 0; j < kSsimRows; j++) {
-        const int gy = y0 + r0 + j, gx = x0 + tx;
-        if (gy >= H || gx >= W) continue;
+    for (int o = 0; o < kSsimHRun; o++) {
+        const int gx = x0 + q0 + o;
+        if (gx >= W) continue;
         float f0 = 0.f, f1 = 0.f, f2 = 0.f;
 #pragma unroll
         for (int k = 0; k < kSsimTaps; k++) {
             const float wk = a.win[k];
-            f0 = fmaf(wk, col[0][j + k], f0);
-            f1 = fmaf(wk, col[1][j + k], f1);
-            f2 = fmaf(wk, col[2][j + k], f2);
+            f0 = fmaf(wk, h[0][o + k], f0);
+            f1 = fmaf(wk, h[1][o + k], f1);
+            f2 = fmaf(wk, h[2][o + k], f2);
         }
-        const size_t o = (size_t)gy * W + gx;
-        const float x = X[o], y = Y[o];
+        const size_t p = (size_t)gy * W + gx;
+        const float x = X[p], y = Y[p];
         const float d = x - y;
         const float sgn = d > 0.f ? 1.f : (d < 0.f ? -1.f : 0.f);
-        D[o] = fmaf(wss, fmaf(y, f2, fmaf(2.f * x, f1, f0)), wl1 * sgn);
+        D[p] = fmaf(wss, fmaf(y, f2, fmaf(2.f * x, f1, f0)), wl1 * sgn);
     }
 }
 

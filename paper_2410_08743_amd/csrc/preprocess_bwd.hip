@@ -11,16 +11,17 @@
 //   dL/drho += g - R_c h,   dL/dphi += mu^c x g + vee(G_W R_c^T).
 //
 // MI355X design: a first kernel walks the instance slots in their emission
-// order (splats in depth order, each splat's slots contiguous), in windows of
-// balanced size, and sums each splat's slots in a fixed order into its 2D
-// gradient.  The chain-rule kernel then runs one thread per Gaussian over
-// the call's views, geometry in FP64 (the kernel is bound by HBM, and the FP64
-// vector rate equals unpacked FP32), SH in FP32.  Gaussian gradients are
-// summed over views in registers and written once; the six pose sums per view
-// are reduced with wavefront shuffles and an LDS block reduction into
-// per-block partials, and one block per view adds the partials in a fixed
-// order.  No atomics anywhere, so the result is bit-reproducible and a view's
-// pose gradient does not depend on which other views share the launch.
+// order (visible splats in index order, each splat's slots contiguous), in
+// windows of balanced size, and sums each splat's slots in a fixed order
+// into its 2D gradient.  The chain-rule kernel then runs one thread per
+// Gaussian over the call's views, geometry in FP64 (the FP64 vector rate
+// equals unpacked FP32), SH in FP32.  Gaussian gradients are summed over
+// views in registers and written once; the six pose sums per view are
+// reduced with wavefront shuffles into per-wavefront partials (no barrier
+// inside the loop over views), and one block per view adds the partials in
+// a fixed order.  No atomics anywhere, so the result is bit-reproducible and
+// a view's pose gradient does not depend on which other views share the
+// launch.
 #include "block_ops.h"
 #include "gsp_internal.h"
 #include "sh_basis.h"
@@ -34,7 +35,7 @@ struct PbArgs {
     const uint32_t *counters;
     const float *slots;     // [cap][9]
     float *grad2d;          // [vn][9]
-    double *posepart;       // [V][nblk][6]
+    double *posepart;       // [V][nblk * kPoseRowsPerBlock][6]: one row per wavefront
     gsp_grads out;
     size_t cap, vn;
     int nblk;
@@ -126,59 +127,80 @@ __global__ __launch_bounds__(kWindowThreads) void k_slot_reduce(const uint32_t *
     }
 }
 
-// Two waves per SIMD: with every Gaussian gradient wanted the kernel would
-// otherwise take all 256 registers and run one wave per SIMD, exposing the
-// latency of its FP64 chains; the cap costs a few spilled registers and
-// measured 0.95 -> 0.72 ms per joint step (1M Gaussians, 4 views).  3 or 4
-// waves spill too much (1.24, 0.88 ms).
+// Symmetric 3 x 3 matrices are kept as their six upper entries
+// (xx, xy, xz, yy, yz, zz).
+__host__ __device__ constexpr int sym3(int r, int c) {
+    return r <= c ? (r == 0 ? c : (r == 1 ? 2 + c : 5)) : (c == 0 ? r : (c == 1 ? 2 + r : 5));
+}
+
+// Rotation of the unit quaternion q / |q|, with |q| returned.
+__device__ __forceinline__ double quat_rot(const float *qp, double qh[4], double Rq[9]) {
+    double q[4];
+#pragma unroll
+    for (int k = 0; k < 4; k++) q[k] = qp[k];
+    const double qn = sqrt(q[0] * q[0] + q[1] * q[1] + q[2] * q[2] + q[3] * q[3]);
+#pragma unroll
+    for (int k = 0; k < 4; k++) qh[k] = q[k] / qn;
+    const double w = qh[0], x = qh[1], y = qh[2], z = qh[3];
+    Rq[0] = 1 - 2 * (y * y + z * z); Rq[1] = 2 * (x * y - w * z); Rq[2] = 2 * (x * z + w * y);
+    Rq[3] = 2 * (x * y + w * z); Rq[4] = 1 - 2 * (x * x + z * z); Rq[5] = 2 * (y * z - w * x);
+    Rq[6] = 2 * (x * z - w * y); Rq[7] = 2 * (y * z + w * x); Rq[8] = 1 - 2 * (x * x + y * y);
+    return qn;
+}
+
+// Resident waves per SIMD.  What crosses the loop over views stays in
+// registers (the SH coefficients, the mean, the six entries of Sigma and the
+// gradient sums); the rotation and scales are read again at the end.  At SH
+// degree 3 both variants take two waves: 213 registers for the pose-only
+// kernel, 254 with every Gaussian gradient.
+#ifndef GSP_PB_WAVES_POSE
+#define GSP_PB_WAVES_POSE 2
+#endif
+#ifndef GSP_PB_WAVES_GAUSS
+#define GSP_PB_WAVES_GAUSS 2
+#endif
+template <bool WANT_GAUSS>
+constexpr int pb_waves() { return WANT_GAUSS ? GSP_PB_WAVES_GAUSS : GSP_PB_WAVES_POSE; }
+
 template <int D, bool WANT_GAUSS>
-__global__ __launch_bounds__(kPoseReduceBlock) __attribute__((amdgpu_waves_per_eu(2))) void k_preprocess_bwd(PbArgs a, ViewsK views) {
+__global__ __launch_bounds__(kPoseReduceBlock) __attribute__((amdgpu_waves_per_eu(pb_waves<WANT_GAUSS>()))) void k_preprocess_bwd(PbArgs a, ViewsK views) {
     constexpr int S = (D + 1) * (D + 1);
-    __shared__ double red[kPoseReduceBlock / kWave];
+    static_assert(kPoseRowsPerBlock * kWave == kPoseReduceBlock, "one pose row per wavefront");
     const int n = a.g.n;
     const int i = blockIdx.x * kPoseReduceBlock + threadIdx.x;
     const bool valid = i < n;
     const bool ovf = a.counters[kCntOverflow] != 0u;
 
-    double mu[3] = {0, 0, 0}, sc[3] = {1, 1, 1}, qh[4] = {1, 0, 0, 0}, qn = 1;
-    double Rq[9] = {1, 0, 0, 0, 1, 0, 0, 0, 1};
-    double Sig[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
+    double mu[3] = {0, 0, 0};
+    double Sig[6] = {0, 0, 0, 0, 0, 0};
     float sh[S * 3];
 #pragma unroll
     for (int k = 0; k < S * 3; k++) sh[k] = 0.f;
     if (valid) {
-#pragma unroll
-        for (int k = 0; k < 3; k++) {
-            mu[k] = a.g.means[3 * i + k];
-            sc[k] = a.g.scales[3 * i + k];
-        }
-        double q[4];
-#pragma unroll
-        for (int k = 0; k < 4; k++) q[k] = a.g.quats[4 * i + k];
-        qn = sqrt(q[0] * q[0] + q[1] * q[1] + q[2] * q[2] + q[3] * q[3]);
-#pragma unroll
-        for (int k = 0; k < 4; k++) qh[k] = q[k] / qn;
-        const double w = qh[0], x = qh[1], y = qh[2], z = qh[3];
-        Rq[0] = 1 - 2 * (y * y + z * z); Rq[1] = 2 * (x * y - w * z); Rq[2] = 2 * (x * z + w * y);
-        Rq[3] = 2 * (x * y + w * z); Rq[4] = 1 - 2 * (x * x + z * z); Rq[5] = 2 * (y * z - w * x);
-        Rq[6] = 2 * (x * z - w * y); Rq[7] = 2 * (y * z + w * x); Rq[8] = 1 - 2 * (x * x + y * y);
-#pragma unroll
-        for (int r = 0; r < 3; r++)
-#pragma unroll
-            for (int c = 0; c < 3; c++)
-                Sig[3 * r + c] = Rq[3 * r] * Rq[3 * c] * sc[0] * sc[0] +
-                                 Rq[3 * r + 1] * Rq[3 * c + 1] * sc[1] * sc[1] +
-                                 Rq[3 * r + 2] * Rq[3 * c + 2] * sc[2] * sc[2];
         const float *f = a.g.sh + (size_t)i * (S * 3);
 #pragma unroll
         for (int k = 0; k < S * 3; k++) sh[k] = f[k];
+#pragma unroll
+        for (int k = 0; k < 3; k++) mu[k] = a.g.means[3 * i + k];
+        double qh[4], Rq[9], s2[3];
+        quat_rot(a.g.quats + 4 * (size_t)i, qh, Rq);
+#pragma unroll
+        for (int k = 0; k < 3; k++) {
+            const double s = a.g.scales[3 * i + k];
+            s2[k] = s * s;
+        }
+#pragma unroll
+        for (int r = 0; r < 3; r++)
+#pragma unroll
+            for (int c = r; c < 3; c++)
+                Sig[sym3(r, c)] = Rq[3 * r] * Rq[3 * c] * s2[0] + Rq[3 * r + 1] * Rq[3 * c + 1] * s2[1] +
+                                  Rq[3 * r + 2] * Rq[3 * c + 2] * s2[2];
     }
 
     // gradients summed over views
-    double gmu[3] = {0, 0, 0}, gSig[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0}, gop = 0;
+    double gmu[3] = {0, 0, 0}, gSig[6] = {0, 0, 0, 0, 0, 0}, gop = 0;
     // SH gradient accumulators in LDS ([coefficient][thread], conflict-free),
-    // not registers: 3 S floats per thread would cap the kernel at one wave
-    // per SIMD
+    // not registers
     __shared__ float s_gsh[WANT_GAUSS ? S * 3 : 1][kPoseReduceBlock];
     if constexpr (WANT_GAUSS) {
 #pragma unroll
@@ -203,6 +225,48 @@ __global__ __launch_bounds__(kPoseReduceBlock) __attribute__((amdgpu_waves_per_e
                 R[3 * r + 2] = P[4 * r + 2];
                 t[r] = P[4 * r + 3];
             }
+            // colour: viewing direction from the camera centre
+            const double ocx = -(R[0] * t[0] + R[3] * t[1] + R[6] * t[2]);
+            const double ocy = -(R[1] * t[0] + R[4] * t[1] + R[7] * t[2]);
+            const double ocz = -(R[2] * t[0] + R[5] * t[1] + R[8] * t[2]);
+            const double wx = mu[0] - ocx, wy = mu[1] - ocy, wz = mu[2] - ocz;
+            const double dist = sqrt(wx * wx + wy * wy + wz * wz), idist = 1.0 / dist;
+            const double dxn = wx * idist, dyn = wy * idist, dzn = wz * idist;
+            const float fxn = (float)dxn, fyn = (float)dyn, fzn = (float)dzn;
+            float Y[S];
+            sh_eval<D, float>(fxn, fyn, fzn, Y);
+            float wgt[S];
+#pragma unroll
+            for (int k = 0; k < S; k++) wgt[k] = 0.f;
+#pragma unroll
+            for (int ch = 0; ch < 3; ch++) {
+                float shc[S];
+#pragma unroll
+                for (int k = 0; k < S; k++) shc[k] = sh[3 * k + ch];
+                float col = 0.5f;
+#pragma unroll
+                for (int k = 0; k < S; k++) col = fmaf(shc[k], Y[k], col);
+                if (col < 0.f) continue;   // clamped channel: no gradient
+                const float gc = d2f[6 + ch];
+#pragma unroll
+                for (int k = 0; k < S; k++) {
+                    wgt[k] = fmaf(gc, shc[k], wgt[k]);
+                    if constexpr (WANT_GAUSS)
+                        s_gsh[3 * k + ch][threadIdx.x] = fmaf(gc, Y[k], s_gsh[3 * k + ch][threadIdx.x]);
+                }
+            }
+            float gdf[3];
+            sh_weighted_grad<D, float>(fxn, fyn, fzn, wgt, gdf);
+            const double gd[3] = {gdf[0], gdf[1], gdf[2]};
+            const double proj = gd[0] * dxn + gd[1] * dyn + gd[2] * dzn;
+            const double gw[3] = {(gd[0] - dxn * proj) * idist, (gd[1] - dyn * proj) * idist,
+                                  (gd[2] - dzn * proj) * idist};
+#pragma unroll
+            for (int k = 0; k < 3; k++) gmu[k] += gw[k];
+            // pose twist, translation part through the camera centre:
+            // h = dL/do_c = -gw
+#pragma unroll
+            for (int r = 0; r < 3; r++) pose6[r] = R[3 * r] * gw[0] + R[3 * r + 1] * gw[1] + R[3 * r + 2] * gw[2];
             double p[3];
 #pragma unroll
             for (int r = 0; r < 3; r++)
@@ -222,8 +286,8 @@ __global__ __launch_bounds__(kPoseReduceBlock) __attribute__((amdgpu_waves_per_e
             double sa[3], sb[3];
 #pragma unroll
             for (int r = 0; r < 3; r++) {
-                sa[r] = Sig[3 * r] * ta[0] + Sig[3 * r + 1] * ta[1] + Sig[3 * r + 2] * ta[2];
-                sb[r] = Sig[3 * r] * tb[0] + Sig[3 * r + 1] * tb[1] + Sig[3 * r + 2] * tb[2];
+                sa[r] = Sig[sym3(r, 0)] * ta[0] + Sig[sym3(r, 1)] * ta[1] + Sig[sym3(r, 2)] * ta[2];
+                sb[r] = Sig[sym3(r, 0)] * tb[0] + Sig[sym3(r, 1)] * tb[1] + Sig[sym3(r, 2)] * tb[2];
             }
             const double ca = ta[0] * sa[0] + ta[1] * sa[1] + ta[2] * sa[2] + kDilation;
             const double cb = ta[0] * sb[0] + ta[1] * sb[1] + ta[2] * sb[2];
@@ -266,15 +330,20 @@ __global__ __launch_bounds__(kPoseReduceBlock) __attribute__((amdgpu_waves_per_e
             // mean (geometry part): R_c^T gp
 #pragma unroll
             for (int k = 0; k < 3; k++) gmu[k] += R[k] * gp[0] + R[3 + k] * gp[1] + R[6 + k] * gp[2];
-            // dL/dSigma = T2^T Gh T2
 #pragma unroll
-            for (int r = 0; r < 3; r++)
+            for (int r = 0; r < 3; r++) pose6[r] += gp[r];
+            if constexpr (WANT_GAUSS) {
+                // dL/dSigma = T2^T Gh T2 (symmetric)
 #pragma unroll
-                for (int c = 0; c < 3; c++)
-                    gSig[3 * r + c] += dca * ta[r] * ta[c] + 0.5 * dcb * (ta[r] * tb[c] + tb[r] * ta[c]) +
-                                       dcc * tb[r] * tb[c];
-            gop += d2f[5];
-            // dL/dR_c = J^T dL/dT2 ; the phi part is vee(G_W R_c^T)
+                for (int r = 0; r < 3; r++)
+#pragma unroll
+                    for (int c = r; c < 3; c++)
+                        gSig[sym3(r, c)] += dca * ta[r] * ta[c] + 0.5 * dcb * (ta[r] * tb[c] + tb[r] * ta[c]) +
+                                            dcc * tb[r] * tb[c];
+                gop += d2f[5];
+            }
+            // dL/dR_c = J^T dL/dT2 =: G_W; the phi part is vee(G_W R_c^T),
+            // of which only the antisymmetric entries are needed
             double GW[9];
 #pragma unroll
             for (int c = 0; c < 3; c++) {
@@ -282,60 +351,20 @@ __global__ __launch_bounds__(kPoseReduceBlock) __attribute__((amdgpu_waves_per_e
                 GW[3 + c] = j11 * gb[c];
                 GW[6 + c] = j02 * ga[c] + j12 * gb[c];
             }
-            double Bm[9];
-#pragma unroll
-            for (int r = 0; r < 3; r++)
-#pragma unroll
-                for (int c = 0; c < 3; c++)
-                    Bm[3 * r + c] = GW[3 * r] * R[3 * c] + GW[3 * r + 1] * R[3 * c + 1] +
-                                    GW[3 * r + 2] * R[3 * c + 2];
-            // colour: viewing direction from the camera centre
-            const double ocx = -(R[0] * t[0] + R[3] * t[1] + R[6] * t[2]);
-            const double ocy = -(R[1] * t[0] + R[4] * t[1] + R[7] * t[2]);
-            const double ocz = -(R[2] * t[0] + R[5] * t[1] + R[8] * t[2]);
-            const double wx = mu[0] - ocx, wy = mu[1] - ocy, wz = mu[2] - ocz;
-            const double dist = sqrt(wx * wx + wy * wy + wz * wz), idist = 1.0 / dist;
-            const double dxn = wx * idist, dyn = wy * idist, dzn = wz * idist;
-            const float fxn = (float)dxn, fyn = (float)dyn, fzn = (float)dzn;
-            float Y[S];
-            sh_eval<D, float>(fxn, fyn, fzn, Y);
-            float wgt[S];
-#pragma unroll
-            for (int k = 0; k < S; k++) wgt[k] = 0.f;
-#pragma unroll
-            for (int ch = 0; ch < 3; ch++) {
-                float col = 0.5f;
-#pragma unroll
-                for (int k = 0; k < S; k++) col = fmaf(sh[3 * k + ch], Y[k], col);
-                if (col < 0.f) continue;   // clamped channel: no gradient
-                const float gc = d2f[6 + ch];
-#pragma unroll
-                for (int k = 0; k < S; k++) {
-                    wgt[k] = fmaf(gc, sh[3 * k + ch], wgt[k]);
-                    if constexpr (WANT_GAUSS)
-                        s_gsh[3 * k + ch][threadIdx.x] = fmaf(gc, Y[k], s_gsh[3 * k + ch][threadIdx.x]);
-                }
-            }
-            float gdf[3];
-            sh_weighted_grad<D, float>(fxn, fyn, fzn, wgt, gdf);
-            const double gd[3] = {gdf[0], gdf[1], gdf[2]};
-            const double proj = gd[0] * dxn + gd[1] * dyn + gd[2] * dzn;
-            const double gw[3] = {(gd[0] - dxn * proj) * idist, (gd[1] - dyn * proj) * idist,
-                                  (gd[2] - dzn * proj) * idist};
-#pragma unroll
-            for (int k = 0; k < 3; k++) gmu[k] += gw[k];
-            // pose twist contribution, h = dL/do_c = -gw
-#pragma unroll
-            for (int r = 0; r < 3; r++)
-                pose6[r] = gp[r] + (R[3 * r] * gw[0] + R[3 * r + 1] * gw[1] + R[3 * r + 2] * gw[2]);
-            pose6[3] = p[1] * gp[2] - p[2] * gp[1] + Bm[7] - Bm[5];
-            pose6[4] = p[2] * gp[0] - p[0] * gp[2] + Bm[2] - Bm[6];
-            pose6[5] = p[0] * gp[1] - p[1] * gp[0] + Bm[3] - Bm[1];
+            auto bm = [&](int r, int c) {
+                return GW[3 * r] * R[3 * c] + GW[3 * r + 1] * R[3 * c + 1] + GW[3 * r + 2] * R[3 * c + 2];
+            };
+            pose6[3] = p[1] * gp[2] - p[2] * gp[1] + bm(2, 1) - bm(1, 2);
+            pose6[4] = p[2] * gp[0] - p[0] * gp[2] + bm(0, 2) - bm(2, 0);
+            pose6[5] = p[0] * gp[1] - p[1] * gp[0] + bm(1, 0) - bm(0, 1);
         }
+        // per-wavefront sums: no barrier inside the loop over views
+        double *const prow =
+            a.posepart + ((size_t)v * a.nblk + blockIdx.x) * (kPoseRowsPerBlock * 6) + (threadIdx.x / kWave) * 6;
 #pragma unroll
         for (int c = 0; c < 6; c++) {
-            const double s = block_sum<double, kPoseReduceBlock>(pose6[c], red);
-            if (threadIdx.x == 0) a.posepart[((size_t)v * a.nblk + blockIdx.x) * 6 + c] = s;
+            const double s = wave_sum(pose6[c]);
+            if (threadIdx.x % kWave == 0) prow[c] = s;
         }
     }
 
@@ -360,14 +389,18 @@ __global__ __launch_bounds__(kPoseReduceBlock) __attribute__((amdgpu_waves_per_e
         }
         if (o.opacities) o.opacities[i] = (acc ? o.opacities[i] : 0.f) + (float)gop;
         if (o.scales || o.quats) {
+            double qh[4], Rq[9], sc[3];
+            const double qn = quat_rot(a.g.quats + 4 * (size_t)i, qh, Rq);
+#pragma unroll
+            for (int k = 0; k < 3; k++) sc[k] = a.g.scales[3 * i + k];
             // Sigma = M M^T with M = R_q diag(s): dL/dM = 2 dL/dSigma M (dL/dSigma symmetric)
             double GM[9];
 #pragma unroll
             for (int r = 0; r < 3; r++)
 #pragma unroll
                 for (int c = 0; c < 3; c++)
-                    GM[3 * r + c] = 2 * (gSig[3 * r] * Rq[c] + gSig[3 * r + 1] * Rq[3 + c] +
-                                         gSig[3 * r + 2] * Rq[6 + c]) * sc[c];
+                    GM[3 * r + c] = 2 * (gSig[sym3(r, 0)] * Rq[c] + gSig[sym3(r, 1)] * Rq[3 + c] +
+                                         gSig[sym3(r, 2)] * Rq[6 + c]) * sc[c];
             if (o.scales) {
 #pragma unroll
                 for (int c = 0; c < 3; c++) {
@@ -392,24 +425,26 @@ __global__ __launch_bounds__(kPoseReduceBlock) __attribute__((amdgpu_waves_per_e
     }
 }
 
-// One block per view adds the per-block pose partials in a fixed order.
-// dL/dtau of each view: the sum of the preprocess blocks' FP64 partials in a
-// fixed order.  One 64-lane wave per view; every load is issued before the
-// first add, so that the kernel costs one round of memory latency.
-constexpr int kPoseFinalPer = 16;   // partial rows per lane held in flight
+// dL/dtau of each view: the sum of the chain-rule kernel's per-wavefront
+// FP64 partials in a fixed order.  One 256-thread block per view; each
+// thread issues all loads of its rows before the first add (one round of
+// memory latency per kPoseFinalThreads x kPoseFinalPer rows).
+constexpr int kPoseFinalThreads = 256;
+constexpr int kPoseFinalPer = 16;   // partial rows per thread held in flight
 
-__global__ __launch_bounds__(kWave) void k_pose_final(const double *posepart, int nblk, float *dpose,
-                                                      bool accumulate) {
-    const int v = blockIdx.x, lane = threadIdx.x;
-    const double *src = posepart + (size_t)v * nblk * 6;
+__global__ __launch_bounds__(kPoseFinalThreads) void k_pose_final(const double *posepart, int nrows,
+                                                                  float *dpose, bool accumulate) {
+    __shared__ double red[kPoseFinalThreads / kWave];
+    const int v = blockIdx.x, t = threadIdx.x;
+    const double *src = posepart + (size_t)v * nrows * 6;
     double s[6] = {0, 0, 0, 0, 0, 0};
-    for (int b0 = 0; b0 < nblk; b0 += kWave * kPoseFinalPer) {
+    for (int b0 = 0; b0 < nrows; b0 += kPoseFinalThreads * kPoseFinalPer) {
         double x[kPoseFinalPer][6];
 #pragma unroll
         for (int r = 0; r < kPoseFinalPer; r++) {
-            const int b = b0 + r * kWave + lane;
+            const int b = b0 + r * kPoseFinalThreads + t;
 #pragma unroll
-            for (int c = 0; c < 6; c++) x[r][c] = b < nblk ? src[(size_t)b * 6 + c] : 0.0;
+            for (int c = 0; c < 6; c++) x[r][c] = b < nrows ? src[(size_t)b * 6 + c] : 0.0;
         }
 #pragma unroll
         for (int r = 0; r < kPoseFinalPer; r++)
@@ -418,10 +453,10 @@ __global__ __launch_bounds__(kWave) void k_pose_final(const double *posepart, in
     }
     float prev[6];
 #pragma unroll
-    for (int c = 0; c < 6; c++) prev[c] = accumulate && lane == 0 ? dpose[6 * v + c] : 0.f;
+    for (int c = 0; c < 6; c++) prev[c] = accumulate && t == 0 ? dpose[6 * v + c] : 0.f;
 #pragma unroll
-    for (int c = 0; c < 6; c++) s[c] = wave_sum(s[c]);
-    if (lane == 0)
+    for (int c = 0; c < 6; c++) s[c] = block_sum<double, kPoseFinalThreads>(s[c], red);
+    if (t == 0)
 #pragma unroll
         for (int c = 0; c < 6; c++) dpose[6 * v + c] = prev[c] + (float)s[c];
 }
@@ -471,8 +506,8 @@ hipError_t launch_preprocess_bwd(const GaussiansK &g, const ViewsK &views, const
         if (e != hipSuccess) return e;
     }
     if (grads.pose) {
-        hipLaunchKernelGGL(k_pose_final, dim3(L.V), dim3(kWave), 0, s, a.posepart, L.nblk_pre,
-                           grads.pose, accumulate);
+        hipLaunchKernelGGL(k_pose_final, dim3(L.V), dim3(kPoseFinalThreads), 0, s, a.posepart,
+                           L.nblk_pre * kPoseRowsPerBlock, grads.pose, accumulate);
         return hipGetLastError();
     }
     return hipSuccess;
