@@ -198,8 +198,9 @@ Layout make_layout(int64_t n, int32_t sh_degree, int32_t V, const ViewsK &views,
     L.total_pix = pix;
     L.nblk_pre = (int)((n + kPreprocessBlock - 1) / kPreprocessBlock);
     L.nblk_scan = (int)((L.vn + kScanItems - 1) / kScanItems);
-    L.nblk_sort = (int)((L.cap + kSortItems - 1) / kSortItems);
-    L.nblk_emit = (int)((L.cap + kSortItems - 1) / kSortItems);   // blocks of the instance sort
+    L.sort_items = sort_items_for(L.cap);
+    L.nblk_sort = (int)((L.cap + L.sort_items - 1) / L.sort_items);
+    L.nblk_emit = L.nblk_sort;   // emission blocks are the instance sort's first-pass blocks
     L.tile_bits = tile_bits_for(views.total_tiles);
     L.tile_passes = sort_passes(L.tile_bits);
     L.nwin_max = (int)((L.vn + L.cap + kWindow - 1) / kWindow + 1);

@@ -218,6 +218,7 @@ struct DupArgs {
     uint8_t *slot_flags;           // [cap][kSplitBwd], cleared here for positions < M
     unsigned long long cap;
     int vn, nblk, eblk, total_tiles;
+    int sort_items;                // instance positions per emission (and sort) block
 };
 
 // Exclusive offsets of the splats' instance runs in index order (the
@@ -228,11 +229,12 @@ struct DupArgs {
 // the counters).  Splat k's entry sits at position h = k + offsets[k] of the
 // sequence (splat, its instances, next splat, ...), the next at h + 1 + cnt;
 // window b starts at the first splat whose entry is at or after b * kWindow.
-// Emission block p covers instance positions [p, p + 1) * kSortItems and
-// starts at the splat of vis whose run holds position p * kSortItems; entry
-// ceil(M / kSortItems) is the last of vis.  The emission works on vis, not
-// on all splats: the positions of one block then belong to at most
-// kSortItems + 1 splats, however many culled splats lie between them.
+// Emission block p covers instance positions [p, p + 1) * items (items =
+// the sort's block size) and starts at the splat of vis whose run holds
+// position p * items; entry ceil(M / items) is the last of vis.  The
+// emission works on vis, not on all splats: the positions of one block then
+// belong to at most items + 1 splats, however many culled splats lie
+// between them.
 __global__ __launch_bounds__(kPreprocessBlock) void k_offsets(DupArgs a) {
     __shared__ unsigned long long scratch[kPreprocessBlock / kWave];
     const int t = threadIdx.x;
@@ -285,10 +287,11 @@ __global__ __launch_bounds__(kPreprocessBlock) void k_offsets(DupArgs a) {
         if (cnt[j] > 0) {
             a.vis[vexcl] = (uint32_t)k;
             a.offv[vexcl] = (uint32_t)excl;
-            for (unsigned long long p = (excl + kSortItems - 1) / kSortItems; p * kSortItems < e1; p++)
+            const unsigned long long items = (unsigned long long)a.sort_items;
+            for (unsigned long long p = (excl + items - 1) / items; p * items < e1; p++)
                 a.pstart[p] = (uint32_t)vexcl;
             if (e1 == all) {
-                a.pstart[(all + kSortItems - 1) / kSortItems] = (uint32_t)vexcl;
+                a.pstart[(all + items - 1) / items] = (uint32_t)vexcl;
                 a.offv[vexcl + 1] = (uint32_t)all;
             }
             vexcl++;
@@ -314,16 +317,17 @@ static_assert(kEmitThreads >= kSortBins && kEmitThreads <= 1024 && kEmitThreads 
 // outer and columns inner, at the splat's offset; a stable sort of these
 // pairs by tile then yields every tile's list in index order, which the
 // per-tile depth sort turns into (depth, index) order.
-// Block p writes instance positions [p, p + 1) * kSortItems, which are the
+// Block p writes instance positions [p, p + 1) * ITEMS, which are the
 // keys of block p of the first pass of that sort, so it also writes their
 // low-digit histogram (zeros past M); each thread finds the splat owning a
 // position by binary search over the block's offsets in LDS.  The blocks
 // also clear the tile ranges and the backward's slot flags of their
 // positions, which the later stages of this forward and of its backward
 // fill in.
+template <int ITEMS>
 __global__ __launch_bounds__(kEmitThreads) void k_emit(DupArgs a, ViewsK views, int n) {
     static_assert(kEmitThreads % kSortBins == 0, "whole histograms per block");
-    constexpr int kMaxSplats = kSortItems + 1;
+    constexpr int kMaxSplats = ITEMS + 1;
     __shared__ uint32_t s_off[kMaxSplats + 1];
     __shared__ uint32_t s_idx[kMaxSplats];
     __shared__ uint2 s_rect[kMaxSplats];
@@ -336,9 +340,9 @@ __global__ __launch_bounds__(kEmitThreads) void k_emit(DupArgs a, ViewsK views, 
     // blocks past M are stale and unused)
     const uint32_t kb = a.pstart[b], kn = a.pstart[b + 1];
     const uint32_t M = a.counters[kCntMEff];
-    const uint32_t p0 = (uint32_t)b * kSortItems;
+    const uint32_t p0 = (uint32_t)b * ITEMS;
     if (p0 < M) {
-        const uint32_t p1 = min(p0 + (uint32_t)kSortItems, M);
+        const uint32_t p1 = min(p0 + (uint32_t)ITEMS, M);
         const int nk = min((int)(kn + 1 - kb), kMaxSplats);
         for (int j = t; j < nk; j += kEmitThreads) {
             const uint32_t idx = a.vis[kb + j];
@@ -421,6 +425,7 @@ hipError_t launch_offsets_and_duplicate(const ViewsK &views, const Layout &L, ch
     a.nblk = L.nblk_scan;
     a.eblk = L.nblk_emit;
     a.total_tiles = L.total_tiles;
+    a.sort_items = L.sort_items;
     if (a.vn > 0) {
         hipLaunchKernelGGL(k_blocksums, dim3(L.nblk_scan), dim3(kPreprocessBlock), 0, s, a.tiles,
                            region<unsigned long long>(ws, L.blocksum),
@@ -428,7 +433,12 @@ hipError_t launch_offsets_and_duplicate(const ViewsK &views, const Layout &L, ch
     }
     hipLaunchKernelGGL(k_offsets, dim3(L.nblk_scan > 0 ? L.nblk_scan : 1), dim3(kPreprocessBlock),
                        0, s, a);
-    hipLaunchKernelGGL(k_emit, dim3(L.nblk_emit), dim3(kEmitThreads), 0, s, a, views, (int)L.n);
+    if (L.sort_items == kSortThreads * kSortRoundsLarge)
+        hipLaunchKernelGGL(k_emit<kSortThreads * kSortRoundsLarge>, dim3(L.nblk_emit),
+                           dim3(kEmitThreads), 0, s, a, views, (int)L.n);
+    else
+        hipLaunchKernelGGL(k_emit<kSortThreads * kSortRoundsSmall>, dim3(L.nblk_emit),
+                           dim3(kEmitThreads), 0, s, a, views, (int)L.n);
     return hipGetLastError();
 }
 

@@ -10,7 +10,7 @@
 //
 // Each pass is reduce-then-scan: per-block digit histograms, a per-digit
 // scan across blocks, then a scatter in which every block ranks its
-// kSortItems keys stably with wavefront ballots (one ballot per digit bit on
+// 1024 or 2048 keys stably with wavefront ballots (one ballot per digit bit on
 // wave64), sorts them locally in LDS and writes them out digit run by digit
 // run, so global stores are contiguous within each run.  The element count
 // may live in device memory (the instance count), in which case the grid is
@@ -18,6 +18,8 @@
 // synchronisation.  The instance emission writes the first pass's
 // histograms of the instance sort itself (its blocks are the sort's blocks),
 // which saves that pass's histogram launch.
+#include <type_traits>
+
 #include "block_ops.h"
 #include "gsp_internal.h"
 
@@ -41,16 +43,18 @@ __device__ __forceinline__ uint32_t sort_count(const SortPass &a) {
     return a.count_ptr ? *a.count_ptr : a.count_val;
 }
 
+template <int R>
 __global__ __launch_bounds__(kSortThreads) void k_sort_hist(SortPass a) {
+    constexpr int kItems = kSortThreads * R;
     __shared__ uint32_t h[kSortBins];
     const int t = threadIdx.x;
     h[t] = 0;
     __syncthreads();
     const uint32_t M = sort_count(a);
-    const size_t base = (size_t)blockIdx.x * kSortItems;
+    const size_t base = (size_t)blockIdx.x * kItems;
     if (base < M) {
 #pragma unroll 4
-        for (int r = 0; r < kSortRounds; r++) {
+        for (int r = 0; r < R; r++) {
             const size_t k = base + (size_t)r * kSortThreads + t;
             if (k < M) atomicAdd(&h[(a.keys_in[k] >> a.shift) & a.mask], 1u);
         }
@@ -91,10 +95,12 @@ __global__ __launch_bounds__(kSortScanThreads) void k_sort_scan(SortPass a) {
     if (t == 0) a.digit_tot[blockIdx.x] = carry;
 }
 
+template <int R>
 __global__ __launch_bounds__(kSortThreads) void k_sort_scatter(SortPass a) {
     constexpr int NW = kSortThreads / kWave;
-    __shared__ uint32_t skeys[kSortItems];
-    __shared__ uint32_t svals[kSortItems];
+    constexpr int kItems = kSortThreads * R;
+    __shared__ uint32_t skeys[kItems];
+    __shared__ uint32_t svals[kItems];
     __shared__ uint32_t dstart[kSortBins];
     __shared__ uint32_t gbase[kSortBins];
     __shared__ uint32_t run[kSortBins];
@@ -103,17 +109,17 @@ __global__ __launch_bounds__(kSortThreads) void k_sort_scatter(SortPass a) {
     __shared__ uint32_t scratch[kSortThreads / kWave];
 
     const uint32_t M = sort_count(a);
-    const size_t base = (size_t)blockIdx.x * kSortItems;
+    const size_t base = (size_t)blockIdx.x * kItems;
     if (base >= M) return;
-    const int cnt = (int)min((size_t)kSortItems, (size_t)M - base);
+    const int cnt = (int)min((size_t)kItems, (size_t)M - base);
     const int t = threadIdx.x;
     const int lane = t & (kWave - 1);
     const int w = t / kWave;
     const unsigned long long lt_mask = (1ull << lane) - 1ull;
 
-    uint32_t key[kSortRounds], val[kSortRounds];
+    uint32_t key[R], val[R];
 #pragma unroll
-    for (int r = 0; r < kSortRounds; r++) {
+    for (int r = 0; r < R; r++) {
         const int k = r * kSortThreads + t;
         key[r] = k < cnt ? a.keys_in[base + k] : 0u;
         val[r] = k < cnt ? a.vals_in[base + k] : 0u;
@@ -125,7 +131,7 @@ __global__ __launch_bounds__(kSortThreads) void k_sort_scatter(SortPass a) {
     for (int w2 = 0; w2 < NW; w2++) wcnt[w2][t] = 0;
     __syncthreads();
 #pragma unroll
-    for (int r = 0; r < kSortRounds; r++) {
+    for (int r = 0; r < R; r++) {
         if (r * kSortThreads + t < cnt) atomicAdd(&run[(key[r] >> a.shift) & a.mask], 1u);
     }
     __syncthreads();
@@ -141,7 +147,7 @@ __global__ __launch_bounds__(kSortThreads) void k_sort_scatter(SortPass a) {
 
     // stable ranking, round by round, wave by wave, lane by lane
 #pragma unroll 1
-    for (int r = 0; r < kSortRounds; r++) {
+    for (int r = 0; r < R; r++) {
         const bool valid = r * kSortThreads + t < cnt;
         const uint32_t d = (key[r] >> a.shift) & a.mask;
         unsigned long long peers = __ballot(valid);
@@ -184,16 +190,18 @@ __global__ __launch_bounds__(kSortThreads) void k_sort_scatter(SortPass a) {
     }
 }
 
-int launch_sort_pairs(uint32_t *k0, uint32_t *v0, uint32_t *k1, uint32_t *v1, uint32_t *hist,
-                      uint32_t *digit_tot, const uint32_t *count_ptr, uint32_t count_val,
-                      int64_t max_count, int bits, bool hist0_given, hipStream_t s,
-                      hipError_t *err) {
+template <int R>
+static int launch_sort_pairs(uint32_t *k0, uint32_t *v0, uint32_t *k1, uint32_t *v1, uint32_t *hist,
+                             uint32_t *digit_tot, const uint32_t *count_ptr, uint32_t count_val,
+                             int64_t max_count, int bits, bool hist0_given, hipStream_t s,
+                             hipError_t *err) {
+    constexpr int kItems = kSortThreads * R;
     SortPass a;
     a.hist = hist;
     a.digit_tot = digit_tot;
     a.count_ptr = count_ptr;
     a.count_val = count_val;
-    a.nblk = (int)((max_count + kSortItems - 1) / kSortItems);
+    a.nblk = (int)((max_count + kItems - 1) / kItems);
     *err = hipSuccess;
     const int passes = sort_passes(bits);
     const int pbits = digit_bits(bits);
@@ -206,9 +214,9 @@ int launch_sort_pairs(uint32_t *k0, uint32_t *v0, uint32_t *k1, uint32_t *v1, ui
         a.vals_out = (p & 1) ? v0 : v1;
         a.shift = p * pbits;
         if (p > 0 || !hist0_given)
-            hipLaunchKernelGGL(k_sort_hist, dim3(a.nblk), dim3(kSortThreads), 0, s, a);
+            hipLaunchKernelGGL(k_sort_hist<R>, dim3(a.nblk), dim3(kSortThreads), 0, s, a);
         hipLaunchKernelGGL(k_sort_scan, dim3(kSortBins), dim3(kSortScanThreads), 0, s, a);
-        hipLaunchKernelGGL(k_sort_scatter, dim3(a.nblk), dim3(kSortThreads), 0, s, a);
+        hipLaunchKernelGGL(k_sort_scatter<R>, dim3(a.nblk), dim3(kSortThreads), 0, s, a);
         *err = hipGetLastError();
         if (*err != hipSuccess) return passes;
     }
@@ -217,11 +225,16 @@ int launch_sort_pairs(uint32_t *k0, uint32_t *v0, uint32_t *k1, uint32_t *v1, ui
 
 hipError_t launch_tile_sort(const Layout &L, char *ws, hipStream_t s) {
     hipError_t e;
-    launch_sort_pairs(region<uint32_t>(ws, L.keys0), region<uint32_t>(ws, L.vals0),
-                      region<uint32_t>(ws, L.keys1), region<uint32_t>(ws, L.vals1),
-                      region<uint32_t>(ws, L.hist), region<uint32_t>(ws, L.digit_tot),
-                      region<uint32_t>(ws, L.counters) + kCntMEff, 0u, L.cap, L.tile_bits, true, s,
-                      &e);
+    auto run = [&](auto rounds) {
+        launch_sort_pairs<decltype(rounds)::value>(
+            region<uint32_t>(ws, L.keys0), region<uint32_t>(ws, L.vals0), region<uint32_t>(ws, L.keys1),
+            region<uint32_t>(ws, L.vals1), region<uint32_t>(ws, L.hist), region<uint32_t>(ws, L.digit_tot),
+            region<uint32_t>(ws, L.counters) + kCntMEff, 0u, L.cap, L.tile_bits, true, s, &e);
+    };
+    if (L.sort_items == kSortThreads * kSortRoundsLarge)
+        run(std::integral_constant<int, kSortRoundsLarge>{});
+    else
+        run(std::integral_constant<int, kSortRoundsSmall>{});
     return e;
 }
 

@@ -122,10 +122,13 @@ def test_preprocess_records(name):
     assert np.max(np.abs(col[ren, :3] - ref["color"][ren])) < 2e-6
 
 
+# capacities above 6M instances (6 << 20) take the 2048-key blocks of the
+# instance emission and sort
+@pytest.mark.parametrize("cap", [0, (6 << 20) + 1])
 @pytest.mark.parametrize("name", CASES)
-def test_keys_sort_and_ranges_bit_exact(name):
+def test_keys_sort_and_ranges_bit_exact(name, cap):
     sc, cam, pose = _case(name)
-    run = _gpu(sc, [cam], [pose])
+    run = _gpu(sc, [cam], [pose], cap=cap)
     rast, g = run["rast"], run["g"]
     ref = oracle.preprocess(sc, cam, pose)
     gw, gh = oracle.tiles_of(cam)
@@ -140,7 +143,8 @@ def test_keys_sort_and_ranges_bit_exact(name):
         assert np.array_equal(ranges.reshape(-1, 2), oracle.tile_ranges(rkeys, gw * gh))
 
 
-def test_depth_ties_and_long_runs_bit_exact():
+@pytest.mark.parametrize("cap", [0, (6 << 20) + 1])
+def test_depth_ties_and_long_runs_bit_exact(cap):
     """Tile runs several times longer than the per-tile depth sort keeps in
     LDS (its chunked global-memory path), with depth ties everywhere: 25000
     Gaussians at three depths only, seen at the identity pose, so that the
@@ -151,7 +155,7 @@ def test_depth_ties_and_long_runs_bit_exact():
     sc.means[:, :2] *= (z / sc.means[:, 2])[:, None]
     sc.means[:, 2] = z
     pose = S.identity_pose()
-    run = _gpu(sc, [cam], [pose])
+    run = _gpu(sc, [cam], [pose], cap=cap)
     rast, g = run["rast"], run["g"]
     ref = oracle.preprocess(sc, cam, pose)
     gw, gh = oracle.tiles_of(cam)
