@@ -68,7 +68,17 @@ constexpr uint32_t kNoSlot = 0xffffffffu;
 #ifndef GSP_BWD_UNROLL
 #define GSP_BWD_UNROLL 2
 #endif
-constexpr int kBwdUnroll = GSP_BWD_UNROLL;   // entries whose LDS records are read ahead
+constexpr int kBwdUnroll = GSP_BWD_UNROLL;   // entries whose LDS records are read together
+// Entries whose row partials wait in LDS before a flush (at most 7: nine
+// lanes per entry in the flush).
+#ifndef GSP_BWD_PEND
+#define GSP_BWD_PEND 7
+#endif
+static_assert(GSP_BWD_PEND >= 1 && 9 * GSP_BWD_PEND <= 64, "one flush lane per (entry, component)");
+// 1: each group's records are read while the group before it is processed
+#ifndef GSP_BWD_PREFETCH
+#define GSP_BWD_PREFETCH 0
+#endif
 
 // Slot of the instance of splat `id` in tile (tx, ty): its emission position.
 __device__ __forceinline__ uint32_t slot_of(const BwdArgs &a, uint32_t id, int tx, int ty) {
@@ -102,7 +112,7 @@ __global__ __launch_bounds__(kRasterThreads) __attribute__((amdgpu_waves_per_eu(
     // register-major, rows kRowStride floats apart so that the 63 lanes of a
     // flush, each reading its own row, spread over the banks; and the slot
     // and 1/o of each pending entry.
-    constexpr int kPend = 7;
+    constexpr int kPend = GSP_BWD_PEND;
     constexpr int kRowStride = 17;
     constexpr int kRegStride = 4 * kRowStride;
     constexpr int kEntryStride = 3 * kRegStride;
@@ -280,19 +290,44 @@ __global__ __launch_bounds__(kRasterThreads) __attribute__((amdgpu_waves_per_eu(
         }
         __syncthreads();
         if (lo > clo) gather(lo - kBatch + lane);
-        for (int j0 = nkr - kBwdUnroll; j0 >= 0; j0 -= kBwdUnroll) {
-            StagedA es[kBwdUnroll];
-            StagedB et[kBwdUnroll];
-            StagedC ew[kBwdUnroll];
-            float el[kBwdUnroll];
-            uint32_t em[kBwdUnroll];
+        StagedA es[kBwdUnroll];
+        StagedB et[kBwdUnroll];
+        StagedC ew[kBwdUnroll];
+        float el[kBwdUnroll];
+        uint32_t em[kBwdUnroll];
+        auto load_group = [&](int j0, StagedA (&ra)[kBwdUnroll], StagedB (&rb)[kBwdUnroll],
+                              StagedC (&rc)[kBwdUnroll], float (&rl)[kBwdUnroll],
+                              uint32_t (&rm)[kBwdUnroll]) {
 #pragma unroll
             for (int u = 0; u < kBwdUnroll; u++) {
-                es[u] = sA[j0 + u];
-                et[u] = sB[j0 + u];
-                ew[u] = sC[j0 + u];
-                el[u] = sL[j0 + u];
-                em[u] = sM[j0 + u];
+                ra[u] = sA[j0 + u];
+                rb[u] = sB[j0 + u];
+                rc[u] = sC[j0 + u];
+                rl[u] = sL[j0 + u];
+                rm[u] = sM[j0 + u];
+            }
+        };
+        if (GSP_BWD_PREFETCH && nkr > 0) load_group(nkr - kBwdUnroll, es, et, ew, el, em);
+        for (int j0 = nkr - kBwdUnroll; j0 >= 0; j0 -= kBwdUnroll) {
+            // the next group's records (one group ahead: the LDS round trip
+            // overlaps this group's work), or this group's
+            StagedA es_n[kBwdUnroll];
+            StagedB et_n[kBwdUnroll];
+            StagedC ew_n[kBwdUnroll];
+            float el_n[kBwdUnroll];
+            uint32_t em_n[kBwdUnroll];
+            if (GSP_BWD_PREFETCH) {
+                load_group(j0 >= kBwdUnroll ? j0 - kBwdUnroll : 0, es_n, et_n, ew_n, el_n, em_n);
+            } else {
+                load_group(j0, es, et, ew, el, em);
+                // All records of the group are wanted in registers here: the
+                // compiler would otherwise sink the later entries' loads
+                // below the band test, a second LDS round trip per entry.
+#pragma unroll
+                for (int u = 0; u < kBwdUnroll; u++)
+                    asm volatile("" ::"v"(es[u].u), "v"(es[u].v), "v"(es[u].A2), "v"(es[u].B2),
+                                 "v"(et[u].C2), "v"(et[u].lo), "v"(et[u].r), "v"(et[u].g), "v"(ew[u].b),
+                                 "v"(ew[u].inv_o), "v"(ew[u].slot), "v"(el[u]));
             }
 #pragma unroll
             for (int u = kBwdUnroll - 1; u >= 0; u--) {
@@ -402,6 +437,16 @@ __global__ __launch_bounds__(kRasterThreads) __attribute__((amdgpu_waves_per_eu(
                         sPi[npend] = ew[u].inv_o;
                     }
                     if (++npend == kPend) flush();
+                }
+            }
+            if (GSP_BWD_PREFETCH) {
+#pragma unroll
+                for (int u = 0; u < kBwdUnroll; u++) {
+                    es[u] = es_n[u];
+                    et[u] = et_n[u];
+                    ew[u] = ew_n[u];
+                    el[u] = el_n[u];
+                    em[u] = em_n[u];
                 }
             }
         }
