@@ -420,7 +420,8 @@ size_t gsp_loss_masked_l1_scratch_bytes(int32_t V, const gsp_view *views);
  * "ranges" (uint32 pairs per tile), "tfinal" (float per pixel),
  * "ncontrib" (uint32 per pixel), "neval", "nblend" (uint32 per pixel, see
  * GSP_PROFILE_COUNTS), "grad2d" (float [V*n][9]: du dv dA dB dC
- * do dr dg db), "counters" (uint32: M, overflow). */
+ * do dr dg db; do is zero after a backward that asked for no opacity
+ * gradient), "counters" (uint32: M, overflow). */
 gsp_status gsp_inspect(gsp_ctx *ctx, const gsp_gaussians *g, int32_t V, const gsp_view *views,
                        void *workspace, size_t ws_bytes, int64_t instance_capacity,
                        const char *name, void **ptr, int64_t *count);

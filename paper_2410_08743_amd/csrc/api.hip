@@ -540,7 +540,8 @@ gsp_status render_bwd(gsp_ctx *ctx, const gsp_gaussians *g, int32_t V, const gsp
     if ((e = stage(ctx, "raster_bwd", st, [&] {
              return lists ? gsp::launch_raster_bwd_stored(p.views, p.L, ws, vals, Q,
                                                           static_cast<const char *>(lists), st)
-                          : gsp::launch_raster_bwd(p.views, p.L, ws, vals, st);
+                          : gsp::launch_raster_bwd(p.views, p.L, ws, vals, grads->opacities != nullptr,
+                                                   st);
          })) != hipSuccess)
         return hip_fail(e, "raster backward");
     if ((e = stage(ctx, "preprocess_bwd", st, [&] {

@@ -137,6 +137,13 @@ __device__ __forceinline__ void wave_sum9_rows(const float v[9], float &a, float
     c = pair_sum16(w4, w4);
 }
 
+// The same for eight values: a rows 0..3 = v0, v2, v1, v3; b rows 0..3 =
+// v4, v6, v5, v7.
+__device__ __forceinline__ void wave_sum8_rows(const float v[8], float &a, float &b) {
+    a = pair_sum16(pair_sum32(v[0], v[1]), pair_sum32(v[2], v[3]));
+    b = pair_sum16(pair_sum32(v[4], v[5]), pair_sum32(v[6], v[7]));
+}
+
 // Row of the 16-lane row partials that hold value k (register k >> 2 for
 // k < 8, register 2 for k = 8).
 __host__ __device__ constexpr int sum9_row(int k) {

@@ -189,8 +189,9 @@ hipError_t launch_raster_fwd(const ViewsK &views, const Layout &L, char *ws,
                              float *loss = nullptr);
 // raster_bwd.hip; with `lists` the stored-list variant (one workgroup per
 // tile, alpha and T read from the pair records)
+// want_opacity = false leaves the opacity component of every slot zero.
 hipError_t launch_raster_bwd(const ViewsK &views, const Layout &L, char *ws,
-                             const uint32_t *vals, hipStream_t s);
+                             const uint32_t *vals, bool want_opacity, hipStream_t s);
 hipError_t launch_raster_bwd_stored(const ViewsK &views, const Layout &L, char *ws,
                                     const uint32_t *vals, const ListLayout &Q, const char *lists,
                                     hipStream_t s);

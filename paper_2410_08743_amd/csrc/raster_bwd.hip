@@ -101,7 +101,11 @@ constexpr uint32_t kPadPos = 0xfffffffeu;
 // with their alpha and the transmittance in front of them, come from the
 // pair records the forward stored (GSP_STORE_LISTS); the walk, the
 // culling, the gradient formulas and the reduction are the same.
-template <bool STORED>
+// OPA = false (no opacity gradient wanted, e.g. a pose-only solve): the
+// wave reduces eight sums per entry instead of nine (the opacity sum, which
+// only the opacity gradient needs, is left out) and the slot's opacity
+// component is written as zero.
+template <bool STORED, bool OPA>
 __global__ __launch_bounds__(kRasterThreads) __attribute__((amdgpu_waves_per_eu(GSP_BWD_WAVES))) void k_raster_bwd(BwdArgs a, ViewsK views) {
     __shared__ StagedA sA[kBatch];
     __shared__ StagedB sB[kBatch];
@@ -147,7 +151,9 @@ __global__ __launch_bounds__(kRasterThreads) __attribute__((amdgpu_waves_per_eu(
     // the component's scale (see the base-2 conic of raster_common.h; the
     // opacity's 1/o comes with the entry).
     const int pe = lane / 9, pc = lane % 9;
-    const int poff = ((pc == 8 ? 2 : pc >> 2) * 4 + sum9_row(pc)) * kRowStride;
+    const int pc8 = pc < 5 ? pc : pc - 1;   // position among the eight sums (pc != 5)
+    const int poff = OPA ? ((pc == 8 ? 2 : pc >> 2) * 4 + sum9_row(pc)) * kRowStride
+                         : ((pc8 >> 2) * 4 + sum9_row(pc8)) * kRowStride;
     const float pscale = pc == 0 || pc == 1 ? kLn2 : pc == 2 || pc == 4 ? -0.5f : pc == 3 ? -1.f : 1.f;
     int npend = 0;
     auto flush = [&]() {
@@ -163,7 +169,7 @@ __global__ __launch_bounds__(kRasterThreads) __attribute__((amdgpu_waves_per_eu(
             const uint32_t slot = sPs[pe];
             if (slot != kNoSlot) {
                 const float f = pc == 5 ? sPi[pe] : pscale;
-                pslots[9 * kSplit * (size_t)slot + pc] = sum * f;
+                pslots[9 * kSplit * (size_t)slot + pc] = OPA || pc != 5 ? sum * f : 0.f;
                 if (pc == 0) pflags[kSplit * (size_t)slot] = 1;
             }
         }
@@ -323,8 +329,9 @@ __global__ __launch_bounds__(kRasterThreads) __attribute__((amdgpu_waves_per_eu(
                 // All records of the group are wanted in registers here: the
                 // compiler would otherwise sink the later entries' loads
                 // below the band test, a second LDS round trip per entry.
+                // (Not in the stored-list variant, where it would cost spills.)
 #pragma unroll
-                for (int u = 0; u < kBwdUnroll; u++)
+                for (int u = 0; u < (STORED ? 0 : kBwdUnroll); u++)
                     asm volatile("" ::"v"(es[u].u), "v"(es[u].v), "v"(es[u].A2), "v"(es[u].B2),
                                  "v"(et[u].C2), "v"(et[u].lo), "v"(et[u].r), "v"(et[u].g), "v"(ew[u].b),
                                  "v"(ew[u].inv_o), "v"(ew[u].slot), "v"(el[u]));
@@ -422,16 +429,21 @@ __global__ __launch_bounds__(kRasterThreads) __attribute__((amdgpu_waves_per_eu(
                     acc[2] = ct.dx * ct.dx * m0;
                     acc[3] = ct.dx * my;
                     acc[4] = myy;
-                    acc[5] = m0;
-                    acc[6] = gc[0];
-                    acc[7] = gc[1];
+                    acc[5] = OPA ? m0 : gc[0];
+                    acc[6] = OPA ? gc[0] : gc[1];
+                    acc[7] = OPA ? gc[1] : gc[2];
                     acc[8] = gc[2];
-                    float ra, rb, rc;
-                    wave_sum9_rows(acc, ra, rb, rc);
                     float *const dst = sP + npend * kEntryStride + (lane >> 4) * kRowStride + (lane & 15);
+                    float ra, rb;
+                    if (OPA) {
+                        float rc;
+                        wave_sum9_rows(acc, ra, rb, rc);
+                        dst[2 * kRegStride] = rc;
+                    } else {
+                        wave_sum8_rows(acc, ra, rb);
+                    }
                     dst[0] = ra;
                     dst[kRegStride] = rb;
-                    dst[2 * kRegStride] = rc;
                     if (lane == 0) {
                         sPs[npend] = ew[u].slot;
                         sPi[npend] = ew[u].inv_o;
@@ -456,7 +468,7 @@ __global__ __launch_bounds__(kRasterThreads) __attribute__((amdgpu_waves_per_eu(
 }
 
 hipError_t launch_raster_bwd(const ViewsK &views, const Layout &L, char *ws, const uint32_t *vals,
-                             hipStream_t s) {
+                             bool want_opacity, hipStream_t s) {
     if (L.total_tiles == 0) return hipSuccess;
     BwdArgs a;
     std::memset(&a, 0, sizeof a);
@@ -480,8 +492,12 @@ hipError_t launch_raster_bwd(const ViewsK &views, const Layout &L, char *ws, con
     // forward's state, so repeated backwards of one forward agree on it.
     // one workgroup per part of each possible work item; those past the
     // item count of this call exit at once
-    hipLaunchKernelGGL(k_raster_bwd<false>, dim3(raster_blocks<kSplit>((int)L.max_items)),
-                       dim3(kRasterThreads), 0, s, a, views);
+    if (want_opacity)
+        hipLaunchKernelGGL((k_raster_bwd<false, true>), dim3(raster_blocks<kSplit>((int)L.max_items)),
+                           dim3(kRasterThreads), 0, s, a, views);
+    else
+        hipLaunchKernelGGL((k_raster_bwd<false, false>), dim3(raster_blocks<kSplit>((int)L.max_items)),
+                           dim3(kRasterThreads), 0, s, a, views);
     return hipGetLastError();
 }
 
@@ -508,7 +524,7 @@ hipError_t launch_raster_bwd_stored(const ViewsK &views, const Layout &L, char *
     a.lhdr = region<uint32_t>(lw, Q.hdr);
     a.total_tiles = L.total_tiles;
     // one workgroup per part of each tile, in the forward's launch order
-    hipLaunchKernelGGL(k_raster_bwd<true>, dim3(raster_blocks<kSplit>(L.total_tiles)),
+    hipLaunchKernelGGL((k_raster_bwd<true, true>), dim3(raster_blocks<kSplit>(L.total_tiles)),
                        dim3(kRasterThreads), 0, s, a, views);
     return hipGetLastError();
 }

@@ -307,6 +307,29 @@ def test_batched_views_with_and_without_long_lists():
     assert Ms[0] > 1000 * len(_tiles(big)) and Ms[1] < Ms[0] // 10
 
 
+def test_pose_gradient_without_opacity_sum_is_bit_identical():
+    """A backward that wants no opacity gradient reduces eight sums per
+    entry instead of nine; every other 2D gradient component, and the pose
+    gradient, come out bit for bit as with the opacity gradient."""
+    sc, cam, pose = random_case(47, 3, 112, 80, 1500)
+    up = _upstream(47, cam)
+    outs = []
+    for want in [(), ("opacities",)]:
+        g = R.GaussianParams.from_set(sc, DEV)
+        P = torch.tensor(pose[None], device=DEV, dtype=torch.float32)
+        rast = R.Rasterizer(0)
+        rast.forward(g, [cam], P)
+        gr = rast.backward(g, [cam], P, torch.tensor(up.ravel(), device=DEV), want=want, pose=True)
+        g2 = rast.inspect(g, [cam], "grad2d").cpu().numpy().reshape(-1, 9)
+        torch.cuda.synchronize()
+        outs.append((gr["pose"].cpu().numpy(), g2))
+    (p0, a0), (p1, a1) = outs
+    assert np.array_equal(p0, p1)
+    keep = [0, 1, 2, 3, 4, 6, 7, 8]
+    assert np.array_equal(a0[:, keep], a1[:, keep])
+    assert np.all(a0[:, 5] == 0) and np.any(a1[:, 5] != 0)
+
+
 def test_roi_equals_full_image_crop():
     sc, cam, pose = random_case(41, 3, 112, 80, 600)
     full = _gpu(sc, [cam], [pose])["images"][0]
@@ -462,9 +485,12 @@ def test_full_size_single_view_workload():
     rho = assert_grad_close(run["pose"][0, :3], rref["pose"][:3], "rho")
     phi = assert_grad_close(run["pose"][0, 3:], rref["pose"][3:], "phi")
     print(f"full-size pose gradient (rel L2, max element): rho {rho} phi {phi}")
-    # the 2D splat gradients of every Gaussian, element by element
+    # the 2D splat gradients of every Gaussian, element by element; a
+    # backward that wants no opacity gradient leaves that component zero
     g2 = run["rast"].inspect(run["g"], [cam], "grad2d").cpu().numpy().reshape(-1, 9)
-    assert_grad_close(g2, rref["splat2d"], "splat2d")
+    keep = [0, 1, 2, 3, 4, 6, 7, 8]
+    assert_grad_close(g2[:, keep], rref["splat2d"][:, keep], "splat2d")
+    assert np.all(g2[:, 5] == 0)
     # keys and values bit for bit (fragile Gaussians' instances excluded)
     sp = oracle.preprocess(sc, cam, pose)
     gw, gh = oracle.tiles_of(cam)
