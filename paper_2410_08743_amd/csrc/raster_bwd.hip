@@ -92,7 +92,7 @@ __device__ __forceinline__ uint32_t slot_of(const BwdArgs &a, uint32_t id, int t
 #endif
 // Pixel with no stored pair left, and the list position of padding records
 // (never a pixel's next pair; below every pixel's count as a signed int, and
-// the padding's infinite candidate limit rejects it in the recomputing walk).
+// the padding's empty band mask skips it in either walk).
 constexpr uint32_t kNoPos = 0xffffffffu;
 constexpr uint32_t kPadPos = 0xfffffffeu;
 
@@ -110,7 +110,6 @@ __global__ __launch_bounds__(kRasterThreads) __attribute__((amdgpu_waves_per_eu(
     __shared__ StagedA sA[kBatch];
     __shared__ StagedB sB[kBatch];
     __shared__ StagedC sC[kBatch];
-    __shared__ float sL[kBatch];   // candidate limit kLog2AlphaMinLoose - lo
     __shared__ uint32_t sM[kBatch];   // bands the entry may reach (band_mask)
     // Row partials of the nine sums of up to kPend entries (wave_sum9_rows),
     // register-major, rows kRowStride floats apart so that the 63 lanes of a
@@ -283,7 +282,6 @@ __global__ __launch_bounds__(kRasterThreads) __attribute__((amdgpu_waves_per_eu(
             sA[r] = StagedA{u, v, g1.x, g1.y};
             sB[r] = StagedB{g1.z, g1.w, gc.x, gc.y};
             sC[r] = StagedC{gc.z, __builtin_amdgcn_exp2f(-g1.w), gslot, (uint32_t)(lo + lane)};
-            sL[r] = kLog2AlphaMinLoose - g1.w;
             sM[r] = mask;
         }
         const int nkr = (nk + kBwdUnroll - 1) & ~(kBwdUnroll - 1);
@@ -291,7 +289,6 @@ __global__ __launch_bounds__(kRasterThreads) __attribute__((amdgpu_waves_per_eu(
             sA[lane] = StagedA{0.f, 0.f, -1.f, 0.f};
             sB[lane] = StagedB{-1.f, -INFINITY, 0.f, 0.f};
             sC[lane] = StagedC{0.f, 0.f, kNoSlot, kPadPos};
-            sL[lane] = INFINITY;
             sM[lane] = 0u;
         }
         __syncthreads();
@@ -299,33 +296,29 @@ __global__ __launch_bounds__(kRasterThreads) __attribute__((amdgpu_waves_per_eu(
         StagedA es[kBwdUnroll];
         StagedB et[kBwdUnroll];
         StagedC ew[kBwdUnroll];
-        float el[kBwdUnroll];
         uint32_t em[kBwdUnroll];
         auto load_group = [&](int j0, StagedA (&ra)[kBwdUnroll], StagedB (&rb)[kBwdUnroll],
-                              StagedC (&rc)[kBwdUnroll], float (&rl)[kBwdUnroll],
-                              uint32_t (&rm)[kBwdUnroll]) {
+                              StagedC (&rc)[kBwdUnroll], uint32_t (&rm)[kBwdUnroll]) {
 #pragma unroll
             for (int u = 0; u < kBwdUnroll; u++) {
                 ra[u] = sA[j0 + u];
                 rb[u] = sB[j0 + u];
                 rc[u] = sC[j0 + u];
-                rl[u] = sL[j0 + u];
                 rm[u] = sM[j0 + u];
             }
         };
-        if (GSP_BWD_PREFETCH && nkr > 0) load_group(nkr - kBwdUnroll, es, et, ew, el, em);
+        if (GSP_BWD_PREFETCH && nkr > 0) load_group(nkr - kBwdUnroll, es, et, ew, em);
         for (int j0 = nkr - kBwdUnroll; j0 >= 0; j0 -= kBwdUnroll) {
             // the next group's records (one group ahead: the LDS round trip
             // overlaps this group's work), or this group's
             StagedA es_n[kBwdUnroll];
             StagedB et_n[kBwdUnroll];
             StagedC ew_n[kBwdUnroll];
-            float el_n[kBwdUnroll];
             uint32_t em_n[kBwdUnroll];
             if (GSP_BWD_PREFETCH) {
-                load_group(j0 >= kBwdUnroll ? j0 - kBwdUnroll : 0, es_n, et_n, ew_n, el_n, em_n);
+                load_group(j0 >= kBwdUnroll ? j0 - kBwdUnroll : 0, es_n, et_n, ew_n, em_n);
             } else {
-                load_group(j0, es, et, ew, el, em);
+                load_group(j0, es, et, ew, em);
                 // All records of the group are wanted in registers here: the
                 // compiler would otherwise sink the later entries' loads
                 // below the band test, a second LDS round trip per entry.
@@ -334,7 +327,7 @@ __global__ __launch_bounds__(kRasterThreads) __attribute__((amdgpu_waves_per_eu(
                 for (int u = 0; u < (STORED ? 0 : kBwdUnroll); u++)
                     asm volatile("" ::"v"(es[u].u), "v"(es[u].v), "v"(es[u].A2), "v"(es[u].B2),
                                  "v"(et[u].C2), "v"(et[u].lo), "v"(et[u].r), "v"(et[u].g), "v"(ew[u].b),
-                                 "v"(ew[u].inv_o), "v"(ew[u].slot), "v"(el[u]));
+                                 "v"(ew[u].inv_o), "v"(ew[u].slot));
             }
 #pragma unroll
             for (int u = kBwdUnroll - 1; u >= 0; u--) {
@@ -349,7 +342,6 @@ __global__ __launch_bounds__(kRasterThreads) __attribute__((amdgpu_waves_per_eu(
                 const StagedA &s = es[u];
                 const StagedB &t = et[u];
                 const ColTerms ct = col_terms(s, fxl);
-                const float lim = el[u];
                 const float col3[3] = {t.r, t.g, ew[u].b};
                 // Per lane, dx is the same for all its pixels, so the conic
                 // and centre gradients need only the moments sum dp, sum dp dy,
@@ -364,14 +356,18 @@ __global__ __launch_bounds__(kRasterThreads) __attribute__((amdgpu_waves_per_eu(
                 for (int q = 0; q < kPixPerLane; q++) {
                     if (!((bands >> q) & 1u)) continue;
                     const float dy = s.v - fy[q];
-                    float p2;
+                    // candidates: pixels that blend this entry, decided as
+                    // the forward does (power <= 0, alpha >= 1/255), before
+                    // their contributor count
+                    float apre = 0.f, a0 = 0.f;
                     bool cand;
                     if (STORED) {
-                        p2 = 0.f;
                         cand = npos[q] == (uint32_t)pos;
                     } else {
-                        p2 = splat_p2(ct, t.C2, dy);
-                        cand = (pos < last[q]) & (p2 <= 0.f) & (p2 >= lim);
+                        const float p2 = splat_p2(ct, t.C2, dy);
+                        apre = splat_alpha_pre(p2, t.lo);
+                        a0 = fminf(kAlphaMax, apre);
+                        cand = (pos < last[q]) & (p2 <= 0.f) & (a0 >= kAlphaMin);
                     }
                     if (__builtin_amdgcn_ballot_w64(cand) == 0ull) continue;
                     blended = true;
@@ -387,9 +383,7 @@ __global__ __launch_bounds__(kRasterThreads) __attribute__((amdgpu_waves_per_eu(
                         // A pixel that does not blend takes alpha = 0, which
                         // leaves T (times rcp(1) = 1), G.S (plus 0 * diff)
                         // and the sums (plus 0) exactly as they are.
-                        const float apre = splat_alpha_pre(p2, t.lo);
-                        const float a0 = fminf(kAlphaMax, apre);
-                        valid = cand && a0 >= kAlphaMin;
+                        valid = cand;
                         alpha = valid ? a0 : 0.f;
                         unclamped = apre <= kAlphaMax;
                         T[q] = T[q] * __builtin_amdgcn_rcpf(1.f - alpha);
@@ -457,7 +451,6 @@ __global__ __launch_bounds__(kRasterThreads) __attribute__((amdgpu_waves_per_eu(
                     es[u] = es_n[u];
                     et[u] = et_n[u];
                     ew[u] = ew_n[u];
-                    el[u] = el_n[u];
                     em[u] = em_n[u];
                 }
             }

@@ -292,28 +292,29 @@ __global__ __launch_bounds__(kRasterThreads) __attribute__((amdgpu_waves_per_eu(
             for (int u2 = 0; u2 < kUnroll; u2++) {
                 const int jp1 = (int)ef[u2].jp1;   // list position + 1
                 const ColTerms ct = col_terms(es[u2], fxl);
-                // candidates: pixels still compositing (finite fy), power <= 0,
-                // and p2 high enough that alpha may reach 1/255
-                const float lim = kLog2AlphaMinLoose - et[u2].lo;
-                float p2[kPixPerLane];
-                bool cand[kPixPerLane];
+                // hits: pixels still compositing (finite fy; the others get
+                // p2 = -inf and alpha = 0) with power <= 0 and alpha >= 1/255.
+                // (No separate p2 bound first: the staging cull already
+                // dropped the entries that reach 1/255 nowhere in these rows,
+                // and the backward's looser bound on p2 accepts every hit.)
+                float alpha[kPixPerLane];
+                bool hit[kPixPerLane];
                 bool any = false;
 #pragma unroll
                 for (int q = 0; q < kPixPerLane; q++) {
-                    p2[q] = splat_p2(ct, et[u2].C2, es[u2].v - fy[q]);
-                    cand[q] = (p2[q] <= 0.f) & (p2[q] >= lim);
-                    any |= cand[q];
+                    const float p2 = splat_p2(ct, et[u2].C2, es[u2].v - fy[q]);
+                    alpha[q] = fminf(kAlphaMax, splat_alpha_pre(p2, et[u2].lo));
+                    hit[q] = (p2 <= 0.f) & (alpha[q] >= kAlphaMin);
+                    any |= hit[q];
                 }
-                // no pixel of this part can reach 1/255: nothing to do
+                // no pixel of this part reaches 1/255: nothing to do
                 if (!wave_any(any)) continue;
 #pragma unroll
                 for (int q = 0; q < kPixPerLane; q++) {
-                    const float alpha = fminf(kAlphaMax, splat_alpha_pre(p2[q], et[u2].lo));
-                    const float aT = alpha * T[q];
+                    const float aT = alpha[q] * T[q];
                     const float testT = T[q] - aT;   // T (1 - alpha)
-                    const bool hit = cand[q] && alpha >= kAlphaMin;
-                    const bool blend = hit && testT >= kTMin;
-                    const bool stop = hit && !(testT >= kTMin);
+                    const bool blend = hit[q] && testT >= kTMin;
+                    const bool stop = hit[q] && !(testT >= kTMin);
                     if (STATS) {
                         nb[q] += blend ? 1u : 0u;
                         ne[q] = stop ? (uint32_t)jp1 : ne[q];
