@@ -87,6 +87,9 @@ __global__ __launch_bounds__(kSsimThreads) void k_ssim_fwd(RgbViewsK a, double2 
     const size_t plane = (size_t)W * H;
     const float *X = a.pred[v] + c * plane, *Y = a.target[v] + c * plane;
     const int t = threadIdx.x;
+    // the L1 sum over the tile's pixels, taken from the vertical items'
+    // middle rows (each tile pixel lies in exactly one)
+    double l1sum = 0.0;
     for (int item = t; item < kSsimVItems; item += kSsimThreads) {
         const int g = item / kSsimLW, q = item - g * kSsimLW;
         const int gx = x0 + q - kSsimR, gy0 = y0 + kSsimVR * g - kSsimR;
@@ -98,6 +101,11 @@ __global__ __launch_bounds__(kSsimThreads) void k_ssim_fwd(RgbViewsK a, double2 
             const bool in = colin && gy >= 0 && gy < H;
             xv[j] = in ? X[(size_t)gy * W + gx] : 0.f;
             yv[j] = in ? Y[(size_t)gy * W + gx] : 0.f;
+        }
+        if (q >= kSsimR && q < kSsimR + kSsimTW && gx < W) {
+#pragma unroll
+            for (int o = 0; o < kSsimVR; o++)
+                if (gy0 + kSsimR + o < H) l1sum += fabs((double)xv[kSsimR + o] - (double)yv[kSsimR + o]);
         }
         // the column's values and their squares and products, once each
         float xx[kSsimVIn], yy[kSsimVIn], xy[kSsimVIn];
@@ -131,13 +139,15 @@ __global__ __launch_bounds__(kSsimThreads) void k_ssim_fwd(RgbViewsK a, double2 
     const int r = t / (kSsimTW / kSsimHRun), q0 = (t % (kSsimTW / kSsimHRun)) * kSsimHRun;
     const int gy = y0 + r;
     float *G = a.gmap[v];
-    double ssum = 0.0, l1sum = 0.0;
+    double ssum = 0.0;
     if (gy < H) {
         float h[5][kSsimHIn];
 #pragma unroll
         for (int m = 0; m < 5; m++) ssim_load_run(&vm[m][r][0], q0, h[m]);
+        float og[3][kSsimHRun];   // the three maps at the run's pixels
 #pragma unroll
         for (int o = 0; o < kSsimHRun; o++) {
+            og[0][o] = og[1][o] = og[2][o] = 0.f;
             const int gx = x0 + q0 + o;
             if (gx >= W) continue;
             float mx = 0.f, my = 0.f, exx = 0.f, eyy = 0.f, exy = 0.f;
@@ -154,19 +164,31 @@ __global__ __launch_bounds__(kSsimThreads) void k_ssim_fwd(RgbViewsK a, double2 
             const float a1 = fmaf(2.f * mx, my, kSsimC1), a2 = fmaf(2.f, sxy, kSsimC2);
             const float b1 = fmaf(mx, mx, fmaf(my, my, kSsimC1)), b2 = sxx + syy + kSsimC2;
             // one division: 1 / b1 = b2 inv and 1 / b2 = b1 inv
-            const float inv = 1.f / (b1 * b2);
+            const float inv = __builtin_amdgcn_rcpf(b1 * b2);
             const float S = a1 * a2 * inv;
             // dS/dmu_x, dS/dsigma_x^2, dS/dsigma_xy, then through the raw moments
             const float ds_dmx = 2.f * my * a2 * inv - 2.f * mx * S * (b2 * inv);
             const float ds_dsxx = -S * (b1 * inv);
             const float ds_dsxy = 2.f * a1 * inv;
-            const float g_mean = ds_dmx - 2.f * mx * ds_dsxx - my * ds_dsxy;
-            const size_t p = (size_t)gy * W + gx;
-            G[(size_t)(0 + c) * plane + p] = g_mean;
-            G[(size_t)(3 + c) * plane + p] = ds_dsxx;
-            G[(size_t)(6 + c) * plane + p] = ds_dsxy;
+            og[0][o] = ds_dmx - 2.f * mx * ds_dsxx - my * ds_dsxy;
+            og[1][o] = ds_dsxx;
+            og[2][o] = ds_dsxy;
             ssum += (double)S;
-            l1sum += fabs((double)X[p] - (double)Y[p]);
+        }
+        const size_t p = (size_t)gy * W + x0 + q0;
+        const bool vec = x0 + q0 + kSsimHRun <= W && (p & 3) == 0 && (plane & 3) == 0 &&
+                         (reinterpret_cast<uintptr_t>(G) & 15) == 0;
+        if (vec) {   // whole 16-byte aligned run: one vector store per map
+#pragma unroll
+            for (int m = 0; m < 3; m++)
+                *reinterpret_cast<float4 *>(G + (size_t)(3 * m + c) * plane + p) =
+                    make_float4(og[m][0], og[m][1], og[m][2], og[m][3]);
+        } else {
+#pragma unroll
+            for (int o = 0; o < kSsimHRun; o++)
+                if (x0 + q0 + o < W)
+#pragma unroll
+                    for (int m = 0; m < 3; m++) G[(size_t)(3 * m + c) * plane + p + o] = og[m][o];
         }
     }
     ssum = block_sum<double, kSsimThreads>(ssum, red);
@@ -220,10 +242,27 @@ __global__ __launch_bounds__(kSsimThreads) void k_ssim_bwd(RgbViewsK a) {
     float *D = a.grad[v] + c * plane;
     const float invn = 1.f / (3.f * (float)plane);
     const float wl1 = (1.f - a.beta) * invn, wss = -a.beta * invn;
+    const size_t p0 = (size_t)gy * W + x0 + q0;
+    // whole 16-byte aligned runs move as one vector each
+    const bool vec = x0 + q0 + kSsimHRun <= W && (p0 & 3) == 0 && (plane & 3) == 0 &&
+                     ((reinterpret_cast<uintptr_t>(X) | reinterpret_cast<uintptr_t>(Y) |
+                       reinterpret_cast<uintptr_t>(D)) & 15) == 0;
+    float xs[kSsimHRun], ys[kSsimHRun], ds[kSsimHRun];
+    if (vec) {
+        const float4 xv = *reinterpret_cast<const float4 *>(X + p0);
+        const float4 yv = *reinterpret_cast<const float4 *>(Y + p0);
+        xs[0] = xv.x; xs[1] = xv.y; xs[2] = xv.z; xs[3] = xv.w;
+        ys[0] = yv.x; ys[1] = yv.y; ys[2] = yv.z; ys[3] = yv.w;
+    } else {
+#pragma unroll
+        for (int o = 0; o < kSsimHRun; o++) {
+            const bool in = x0 + q0 + o < W;
+            xs[o] = in ? X[p0 + o] : 0.f;
+            ys[o] = in ? Y[p0 + o] : 0.f;
+        }
+    }
 #pragma unroll
     for (int o = 0; o < kSsimHRun; o++) {
-        const int gx = x0 + q0 + o;
-        if (gx >= W) continue;
         float f0 = 0.f, f1 = 0.f, f2 = 0.f;
 #pragma unroll
         for (int k = 0; k < kSsimTaps; k++) {
@@ -232,11 +271,17 @@ __global__ __launch_bounds__(kSsimThreads) void k_ssim_bwd(RgbViewsK a) {
             f1 = fmaf(wk, h[1][o + k], f1);
             f2 = fmaf(wk, h[2][o + k], f2);
         }
-        const size_t p = (size_t)gy * W + gx;
-        const float x = X[p], y = Y[p];
+        const float x = xs[o], y = ys[o];
         const float d = x - y;
         const float sgn = d > 0.f ? 1.f : (d < 0.f ? -1.f : 0.f);
-        D[p] = fmaf(wss, fmaf(y, f2, fmaf(2.f * x, f1, f0)), wl1 * sgn);
+        ds[o] = fmaf(wss, fmaf(y, f2, fmaf(2.f * x, f1, f0)), wl1 * sgn);
+    }
+    if (vec) {
+        *reinterpret_cast<float4 *>(D + p0) = make_float4(ds[0], ds[1], ds[2], ds[3]);
+    } else {
+#pragma unroll
+        for (int o = 0; o < kSsimHRun; o++)
+            if (x0 + q0 + o < W) D[p0 + o] = ds[o];
     }
 }
 
