@@ -220,7 +220,7 @@ Layout make_layout(int64_t n, int32_t sh_degree, int32_t V, const ViewsK &views,
     L.offsets = take((vn + 1) * 4);
     L.vis = take(vn * 4);
     L.offv = take((vn + 1) * 4);
-    L.wstart = take(((size_t)L.nwin_max + 1) * 4);
+    L.wstart = take(((size_t)L.nwin_max + 1) * 8);
     L.pstart = take(((size_t)L.nblk_emit + 1) * 4);
     L.blocksum = take((size_t)L.nblk_scan * 8 + 8);
     L.blockvis = take((size_t)L.nblk_scan * 4 + 4);

@@ -205,7 +205,7 @@ struct DupArgs {
     uint32_t *offsets;             // [vn + 1] first emission position of each view-Gaussian, then M
     uint32_t *vis;                 // [vn] the view-Gaussians with instances, in index order
     uint32_t *offv;                // [vn + 1] first emission position of each of those, then M
-    uint32_t *wstart;              // [windows + 1] first view-Gaussian of each work window
+    uint2 *wstart;                 // [windows + 1] first view-Gaussian of each work window and its first slot
     uint32_t *pstart;              // [emission blocks + 1] rank in vis owning each block's start
     const unsigned long long *blocksum;  // [nblk] per-block tile counts in index order
     const uint32_t *blockvis;      // [nblk] per-block counts of view-Gaussians with instances
@@ -280,10 +280,10 @@ __global__ __launch_bounds__(kPreprocessBlock) void k_offsets(DupArgs a) {
         if (k >= a.vn) break;
         a.offsets[k] = (uint32_t)excl;
         const unsigned long long h = (unsigned long long)k + excl, h1 = h + 1 + cnt[j];
-        if (k == 0) a.wstart[0] = 0u;
-        for (unsigned long long b = h / kWindow + 1; b * kWindow <= h1; b++)
-            a.wstart[b] = (uint32_t)k + 1;
         const unsigned long long e1 = excl + cnt[j];
+        if (k == 0) a.wstart[0] = make_uint2(0u, 0u);
+        for (unsigned long long b = h / kWindow + 1; b * kWindow <= h1; b++)
+            a.wstart[b] = make_uint2((uint32_t)k + 1, (uint32_t)e1);
         if (cnt[j] > 0) {
             a.vis[vexcl] = (uint32_t)k;
             a.offv[vexcl] = (uint32_t)excl;
@@ -298,7 +298,7 @@ __global__ __launch_bounds__(kPreprocessBlock) void k_offsets(DupArgs a) {
         }
         if (k == a.vn - 1) {
             const unsigned long long nwin = (h1 + kWindow - 1) / kWindow;
-            if (nwin * kWindow > h1) a.wstart[nwin] = (uint32_t)a.vn;
+            if (nwin * kWindow > h1) a.wstart[nwin] = make_uint2((uint32_t)a.vn, (uint32_t)e1);
             a.offsets[a.vn] = (uint32_t)e1;
             a.counters[kCntWin] = (uint32_t)nwin;
         }
@@ -410,7 +410,7 @@ hipError_t launch_offsets_and_duplicate(const ViewsK &views, const Layout &L, ch
     a.vis = region<uint32_t>(ws, L.vis);
     a.offv = region<uint32_t>(ws, L.offv);
     a.blockvis = region<uint32_t>(ws, L.blockvis);
-    a.wstart = region<uint32_t>(ws, L.wstart);
+    a.wstart = region<uint2>(ws, L.wstart);
     a.pstart = region<uint32_t>(ws, L.pstart);
     a.blocksum = region<unsigned long long>(ws, L.blocksum);
     a.counters = region<uint32_t>(ws, L.counters);

@@ -67,7 +67,7 @@ constexpr int kSlotFloats = 9 * kSplitBwd;   // one 9-float slot per backward pa
 constexpr int kSlotPerThread = kWindow * kSlotFloats / kWindowThreads;
 
 __global__ __launch_bounds__(kWindowThreads) void k_slot_reduce(const uint32_t *offk,
-                                                                const uint32_t *wstart,
+                                                                const uint2 *wstart,
                                                                 const uint32_t *counters,
                                                                 const float *slots,
                                                                 const uint8_t *flags,
@@ -84,9 +84,11 @@ __global__ __launch_bounds__(kWindowThreads) void k_slot_reduce(const uint32_t *
         return;
     }
     if ((uint32_t)b >= counters[kCntWin]) return;
-    const uint32_t kb = wstart[b], ke = wstart[b + 1];
+    // the window's first splat and first slot, and the next window's
+    const uint2 w0 = wstart[b], w1 = wstart[b + 1];
+    const uint32_t kb = w0.x, ke = w1.x;
     const int nk = (int)(ke - kb);   // at most kWindow
-    const uint32_t e0 = offk[kb], ne = offk[ke] - e0;
+    const uint32_t e0 = w0.y, ne = w1.y - e0;
     const uint32_t nf = (uint32_t)kSlotFloats * min(ne, (uint32_t)kWindow);
     const float *src = slots + kSlotFloats * (size_t)e0;
     const uint8_t *fsrc = flags + kSplitBwd * (size_t)e0;
@@ -152,7 +154,9 @@ __device__ __forceinline__ double quat_rot(const float *qp, double qh[4], double
 // registers (the SH coefficients, the mean, the six entries of Sigma and the
 // gradient sums); the rotation and scales are read again at the end.  At SH
 // degree 3 both variants take two waves: 213 registers for the pose-only
-// kernel, 254 with every Gaussian gradient.
+// kernel, 254 with every Gaussian gradient.  (Reading the pose-only
+// kernel's SH coefficients with each view's inputs instead fits three
+// waves, 160 registers, and measured no faster.)
 #ifndef GSP_PB_WAVES_POSE
 #define GSP_PB_WAVES_POSE 2
 #endif
@@ -434,7 +438,7 @@ constexpr int kPoseFinalPer = 16;   // partial rows per thread held in flight
 
 __global__ __launch_bounds__(kPoseFinalThreads) void k_pose_final(const double *posepart, int nrows,
                                                                   float *dpose, bool accumulate) {
-    __shared__ double red[kPoseFinalThreads / kWave];
+    __shared__ double red[6][kPoseFinalThreads];
     const int v = blockIdx.x, t = threadIdx.x;
     const double *src = posepart + (size_t)v * nrows * 6;
     double s[6] = {0, 0, 0, 0, 0, 0};
@@ -451,14 +455,22 @@ __global__ __launch_bounds__(kPoseFinalThreads) void k_pose_final(const double *
 #pragma unroll
             for (int c = 0; c < 6; c++) s[c] += x[r][c];
     }
-    float prev[6];
+    // the 256 x 6 thread sums through LDS in one step: lane 8 c + h of the
+    // first wave adds 32 of component c's, then 8-lane shuffles finish
+    // (every sum in a fixed order)
 #pragma unroll
-    for (int c = 0; c < 6; c++) prev[c] = accumulate && t == 0 ? dpose[6 * v + c] : 0.f;
-#pragma unroll
-    for (int c = 0; c < 6; c++) s[c] = block_sum<double, kPoseFinalThreads>(s[c], red);
-    if (t == 0)
-#pragma unroll
-        for (int c = 0; c < 6; c++) dpose[6 * v + c] = prev[c] + (float)s[c];
+    for (int c = 0; c < 6; c++) red[c][t] = s[c];
+    __syncthreads();
+    if (t < 6 * 8) {
+        const int c = t >> 3, h = t & 7;
+        double x = 0.0;
+#pragma unroll 8
+        for (int k = 0; k < kPoseFinalThreads / 8; k++) x += red[c][h * (kPoseFinalThreads / 8) + k];
+        x += __shfl_xor(x, 1, 8);
+        x += __shfl_xor(x, 2, 8);
+        x += __shfl_xor(x, 4, 8);
+        if (h == 0) dpose[6 * v + c] = (accumulate ? dpose[6 * v + c] : 0.f) + (float)x;
+    }
 }
 
 template <int D>
@@ -489,7 +501,7 @@ hipError_t launch_preprocess_bwd(const GaussiansK &g, const ViewsK &views, const
     if (L.vn > 0) {
         hipLaunchKernelGGL(k_slot_reduce, dim3(L.nwin_max), dim3(kWindowThreads), 0, s,
                            region<uint32_t>(ws, L.offsets),
-                           region<uint32_t>(ws, L.wstart), a.counters, a.slots,
+                           region<uint2>(ws, L.wstart), a.counters, a.slots,
                            region<uint8_t>(ws, L.slot_flags), a.grad2d,
                            (int)L.vn);
         hipError_t e = hipGetLastError();
