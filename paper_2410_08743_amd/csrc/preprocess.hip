@@ -377,7 +377,7 @@ __global__ __launch_bounds__(kEmitThreads) void k_emit(DupArgs a, ViewsK views, 
         }
     }
     __syncthreads();
-    if (t < kSortBins) a.hist[(size_t)t * a.eblk + b] = s_hist[t];
+    if ((uint32_t)t <= a.mask0) a.hist[(size_t)t * a.eblk + b] = s_hist[t];   // rows of used digits
 }
 
 hipError_t launch_preprocess(const GaussiansK &g, const ViewsK &views, const float *poses,

@@ -60,7 +60,7 @@ __global__ __launch_bounds__(kSortThreads) void k_sort_hist(SortPass a) {
         }
     }
     __syncthreads();
-    a.hist[(size_t)t * a.nblk + blockIdx.x] = h[t];
+    if ((uint32_t)t <= a.mask) a.hist[(size_t)t * a.nblk + blockIdx.x] = h[t];   // rows of used digits
 }
 
 // One block per digit: exclusive scan of that digit's counts across blocks
@@ -137,8 +137,10 @@ __global__ __launch_bounds__(kSortThreads) void k_sort_scatter(SortPass a) {
     __syncthreads();
     uint32_t tot;
     const uint32_t excl = block_exclusive_scan<uint32_t, kSortThreads>(run[t], scratch, &tot);
-    const uint32_t digit_total = a.digit_tot[t];
-    const uint32_t before = a.hist[(size_t)t * a.nblk + blockIdx.x];
+    // rows and totals exist for the pass's digits only (mask + 1 of them)
+    const bool used = (uint32_t)t <= a.mask;
+    const uint32_t digit_total = used ? a.digit_tot[t] : 0u;
+    const uint32_t before = used ? a.hist[(size_t)t * a.nblk + blockIdx.x] : 0u;
     const uint32_t dex = block_exclusive_scan<uint32_t, kSortThreads>(digit_total, scratch, &tot);
     dstart[t] = excl;
     run[t] = excl;
@@ -215,7 +217,7 @@ static int launch_sort_pairs(uint32_t *k0, uint32_t *v0, uint32_t *k1, uint32_t 
         a.shift = p * pbits;
         if (p > 0 || !hist0_given)
             hipLaunchKernelGGL(k_sort_hist<R>, dim3(a.nblk), dim3(kSortThreads), 0, s, a);
-        hipLaunchKernelGGL(k_sort_scan, dim3(kSortBins), dim3(kSortScanThreads), 0, s, a);
+        hipLaunchKernelGGL(k_sort_scan, dim3(a.mask + 1), dim3(kSortScanThreads), 0, s, a);
         hipLaunchKernelGGL(k_sort_scatter<R>, dim3(a.nblk), dim3(kSortThreads), 0, s, a);
         *err = hipGetLastError();
         if (*err != hipSuccess) return passes;
