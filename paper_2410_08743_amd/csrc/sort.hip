@@ -261,11 +261,16 @@ hipError_t launch_tile_sort(const Layout &L, char *ws, hipStream_t s) {
 // LDS) on top of a running per-digit count, then the digit counts' exclusive
 // scan added to those ranks.  Runs of up to CAP entries stay in registers
 // and LDS (CAP is picked per launch from the mean list length the instance
-// capacity allows: 1024 or 2048); longer runs (histograms from one read
-// first) move, CAP entries at a time with every load of a chunk in flight,
-// between the sorted arrays and the tile sort's other key and value buffers,
-// the relative keys carried beside the values (the key array's tile ids are
-// restored afterwards).
+// capacity allows: 1024 or 2048), one 32-bit word per item: after the first
+// pass the relative key's remaining bits sit above the item's position in
+// the run, and the values are gathered by that position once at the end (so
+// a pass scatters and reloads one word per item, and LDS holds CAP words).
+// Longer runs, and runs whose keys are too wide for that packing (depths
+// spread over some sixty binary orders of magnitude), (histograms from one
+// read first) move, CAP entries at a time with every load of a chunk in
+// flight, between the sorted arrays and the tile sort's other key and value
+// buffers, the relative keys carried beside the values (the key array's
+// tile ids are restored afterwards).
 #ifndef GSP_TD_BITS
 #define GSP_TD_BITS 8
 #endif
@@ -345,12 +350,13 @@ template <int CAP>
 __global__ __launch_bounds__(kWave) void k_tile_depth_sort(TileDepthArgs a) {
     constexpr int kTdCap = CAP;
     constexpr int kTdRounds = kTdCap / kWave;
-    // sk, sv: the run (long runs: the histograms of all passes instead)
-    __shared__ uint32_t buf[2 * kTdCap];
+    constexpr int kIdx = CAP == 2048 ? 11 : 10;   // bits of a position in the run
+    static_assert((1 << kIdx) == kTdCap, "CAP is 1024 or 2048");
+    // the run's packed items (long runs: the histograms of all passes instead)
+    __shared__ uint32_t buf[kTdCap];
     __shared__ uint32_t run[kTdBins];
     __shared__ unsigned long long msk[kTdBins];
-    static_assert(kTdPasses * kTdBins <= 2 * kTdCap, "histograms of a long run fit in buf");
-    uint32_t *const sk = buf, *const sv = buf + kTdCap;
+    static_assert(kTdPasses * kTdBins <= kTdCap, "histograms of a long run fit in buf");
     const uint32_t tile = blockIdx.x;
     const uint2 rg = a.ranges[tile];
     const int L = (int)(rg.y - rg.x);
@@ -367,69 +373,95 @@ __global__ __launch_bounds__(kWave) void k_tile_depth_sort(TileDepthArgs a) {
             const int k = r * kWave + lane;
             val[r] = k < L ? vf[k] : 0u;
         }
-        uint32_t kmin = 0xffffffffu;
+        uint32_t kmin = 0xffffffffu, kmax = 0u;
 #pragma unroll
         for (int r = 0; r < kTdRounds; r++) {
             const int k = r * kWave + lane;
-            key[r] = k < L ? a.depth[val[r]] : 0xffffffffu;
-            kmin = min(kmin, key[r]);
+            key[r] = k < L ? a.depth[val[r]] : 0u;
+            if (k < L) {
+                kmin = min(kmin, key[r]);
+                kmax = max(kmax, key[r]);
+            }
         }
         kmin = wave_min_u32(kmin);
+        kmax = wave_max_u32(kmax);
+        // significant bits of the relative keys; runs whose keys span more
+        // than 32 - kIdx + 8 bits (depths over some sixty binary orders of
+        // magnitude) take the long path below
+        const int B = kmax > kmin ? 32 - __clz(kmax - kmin) : 0;
+        if (B <= 32 - kIdx + kTdBits) {
+            // An item is one word: after the first pass, the relative key's
+            // bits above that pass's digit, shifted over the item's position
+            // in the run (kIdx bits); the values follow by that position at
+            // the end.  One LDS word per item and pass, not two.
+            uint32_t pk[kTdRounds], rk[kTdRounds];
+            bool moved = false;
+            // One counting-sort pass over digit d(r) of the items pk (the
+            // first pass's items and digits come from the relative keys).
+            auto sort_pass = [&](auto digit_of, auto item_of) {
+                uint32_t dlo = kTdBins, dhi = 0;
 #pragma unroll
-        for (int r = 0; r < kTdRounds; r++) key[r] -= kmin;   // past L: stays above every key
-        bool moved = false;
-        for (int p = 0; p < kTdPasses; p++) {
-            const int sh = kTdBits * p;
-            uint32_t dlo = kTdBins, dhi = 0;
+                for (int r = 0; r < kTdRounds; r++) {
+                    if (r * kWave + lane < L) {
+                        const uint32_t d = digit_of(r);
+                        dlo = min(dlo, d);
+                        dhi = max(dhi, d);
+                    }
+                }
+                if (wave_min_u32(dlo) == wave_max_u32(dhi)) {   // one digit: nothing moves
 #pragma unroll
-            for (int r = 0; r < kTdRounds; r++) {
-                if (r * kWave + lane < L) {
-                    const uint32_t d = (key[r] >> sh) & (kTdBins - 1);
-                    dlo = min(dlo, d);
-                    dhi = max(dhi, d);
+                    for (int r = 0; r < kTdRounds; r++) pk[r] = item_of(r);
+                    return;
+                }
+                moved = true;
+                td_zero(run);
+                __syncthreads();
+#pragma unroll
+                for (int r = 0; r < kTdRounds; r++) {
+                    rk[r] = 0u;
+                    if (r * kWave >= L) continue;   // uniform
+                    const bool valid = r * kWave + lane < L;
+                    rk[r] = td_rank(valid, digit_of(r), run, msk);
+                }
+                __syncthreads();
+                td_scan(run);
+#pragma unroll
+                for (int r = 0; r < kTdRounds; r++)
+                    if (r * kWave + lane < L) buf[run[digit_of(r)] + rk[r]] = item_of(r);
+                __syncthreads();
+#pragma unroll
+                for (int r = 0; r < kTdRounds; r++) {
+                    const int k = r * kWave + lane;
+                    pk[r] = k < L ? buf[k] : 0u;
+                }
+                __syncthreads();
+            };
+            // pass 0: the relative keys' low digit; items become (key bits
+            // above it, position)
+#pragma unroll
+            for (int r = 0; r < kTdRounds; r++) key[r] -= kmin;
+            sort_pass([&](int r) { return key[r] & (kTdBins - 1); },
+                      [&](int r) { return ((key[r] >> kTdBits) << kIdx) | (uint32_t)(r * kWave + lane); });
+            const int npass = (B + kTdBits - 1) / kTdBits;
+            for (int p = 1; p < npass; p++) {
+                const int sh = kIdx + kTdBits * (p - 1);
+                sort_pass([&](int r) { return (pk[r] >> sh) & (kTdBins - 1); }, [&](int r) { return pk[r]; });
+            }
+            if (moved) {
+                // every value read (by its position in the run) before any is written
+#pragma unroll
+                for (int r = 0; r < kTdRounds; r++) {
+                    const int k = r * kWave + lane;
+                    val[r] = k < L ? vf[pk[r] & (kTdCap - 1)] : 0u;
+                }
+#pragma unroll
+                for (int r = 0; r < kTdRounds; r++) {
+                    const int k = r * kWave + lane;
+                    if (k < L) vf[k] = val[r];
                 }
             }
-            if (wave_min_u32(dlo) == wave_max_u32(dhi)) continue;   // one digit: nothing moves
-            moved = true;
-            td_zero(run);
-            __syncthreads();
-            uint32_t rk[kTdRounds];
-#pragma unroll
-            for (int r = 0; r < kTdRounds; r++) {
-                rk[r] = 0u;
-                if (r * kWave >= L) continue;   // uniform
-                const bool valid = r * kWave + lane < L;
-                rk[r] = td_rank(valid, (key[r] >> sh) & (kTdBins - 1), run, msk);
-            }
-            __syncthreads();
-            td_scan(run);
-#pragma unroll
-            for (int r = 0; r < kTdRounds; r++) {
-                if (r * kWave + lane < L) {
-                    const uint32_t pos = run[(key[r] >> sh) & (kTdBins - 1)] + rk[r];
-                    sk[pos] = key[r];
-                    sv[pos] = val[r];
-                }
-            }
-            __syncthreads();
-#pragma unroll
-            for (int r = 0; r < kTdRounds; r++) {
-                const int k = r * kWave + lane;
-                if (k < L) {
-                    key[r] = sk[k];
-                    val[r] = sv[k];
-                }
-            }
-            __syncthreads();
+            return;
         }
-        if (moved) {
-#pragma unroll
-            for (int r = 0; r < kTdRounds; r++) {
-                const int k = r * kWave + lane;
-                if (k < L) vf[k] = val[r];
-            }
-        }
-        return;
     }
 
     // Long run.  The smallest key, then the histograms of every pass of the
