@@ -202,6 +202,11 @@ Layout make_layout(int64_t n, int32_t sh_degree, int32_t V, const ViewsK &views,
     L.nblk_sort = (int)((L.cap + L.sort_items - 1) / L.sort_items);
     L.nblk_emit = L.nblk_sort;   // emission blocks are the instance sort's first-pass blocks
     L.tile_bits = tile_bits_for(views.total_tiles);
+    {
+        // packed instance-sort items when the tile id and the value fit one word
+        const int vbits = L.vn > 1 ? 64 - __builtin_clzll((unsigned long long)(L.vn - 1)) : 1;
+        L.sort_vbits = L.tile_bits > 0 && L.tile_bits + vbits <= 32 ? vbits : 0;
+    }
     L.tile_passes = sort_passes(L.tile_bits);
     L.nwin_max = (int)((L.vn + L.cap + kWindow - 1) / kWindow + 1);
     const size_t vn = (size_t)L.vn, capz = (size_t)L.cap;

@@ -125,6 +125,9 @@ struct Layout {
     int64_t n, vn, cap, total_pix;
     int32_t V, S, total_tiles, nblk_pre, nblk_scan, nblk_sort, nblk_emit, sort_items, tile_bits,
         tile_passes, nwin_max;
+    // value bits of the instance sort's packed items (tile id above them),
+    // or 0 when tile and value bits exceed 32 together (key and value arrays)
+    int32_t sort_vbits;
     size_t geom, color, rect, depth, tiles, offsets, vis, offv, wstart, pstart, blocksum, blockvis,
         counters;
     size_t keys0, keys1, vals0, vals1, hist, digit_tot, ranges, tile_order;

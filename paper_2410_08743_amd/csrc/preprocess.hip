@@ -219,6 +219,7 @@ struct DupArgs {
     unsigned long long cap;
     int vn, nblk, eblk, total_tiles;
     int sort_items;                // instance positions per emission (and sort) block
+    int vbits;                     // > 0: emit packed (tile << vbits | value) into keys only
 };
 
 // Exclusive offsets of the splats' instance runs in index order (the
@@ -366,8 +367,12 @@ __global__ __launch_bounds__(kEmitThreads) void k_emit(DupArgs a, ViewsK views, 
             const ViewK &vw = views.v[idx / (uint32_t)n];
             const uint32_t ty = (uint32_t)y0 + local / w, tx = (uint32_t)x0 + local % w;
             const uint32_t key = (uint32_t)vw.tile_base + ty * (uint32_t)vw.gw + tx;
-            a.keys[e] = key;
-            a.vals[e] = idx;
+            if (a.vbits > 0) {
+                a.keys[e] = (key << a.vbits) | idx;
+            } else {
+                a.keys[e] = key;
+                a.vals[e] = idx;
+            }
             atomicAdd(&s_hist[key & a.mask0], 1u);
             if constexpr (kSplitBwd == 1) a.slot_flags[e] = 0;
             else if constexpr (kSplitBwd == 2) reinterpret_cast<uint16_t *>(a.slot_flags)[e] = 0;
@@ -426,6 +431,7 @@ hipError_t launch_offsets_and_duplicate(const ViewsK &views, const Layout &L, ch
     a.eblk = L.nblk_emit;
     a.total_tiles = L.total_tiles;
     a.sort_items = L.sort_items;
+    a.vbits = L.sort_vbits;
     if (a.vn > 0) {
         hipLaunchKernelGGL(k_blocksums, dim3(L.nblk_scan), dim3(kPreprocessBlock), 0, s, a.tiles,
                            region<unsigned long long>(ws, L.blocksum),

@@ -37,7 +37,14 @@ struct SortPass {
     int nblk;
     int shift;
     uint32_t mask;     // digit mask of this pass (at most kSortBins - 1)
+    int vbits;         // packed items: the value's bits below the key
 };
+
+// Item layout of a pass: a key and a value array (kPairs); one word per
+// item, the key above the value's vbits bits (kPacked, when the tile bits
+// and the value bits fit 32 between them); or packed items in and the two
+// arrays out (kUnpack, the last pass of a packed sort).
+enum SortMode { kPairs = 0, kPacked = 1, kUnpack = 2 };
 
 __device__ __forceinline__ uint32_t sort_count(const SortPass &a) {
     return a.count_ptr ? *a.count_ptr : a.count_val;
@@ -95,12 +102,12 @@ __global__ __launch_bounds__(kSortScanThreads) void k_sort_scan(SortPass a) {
     if (t == 0) a.digit_tot[blockIdx.x] = carry;
 }
 
-template <int R>
+template <int R, int MODE>
 __global__ __launch_bounds__(kSortThreads) void k_sort_scatter(SortPass a) {
     constexpr int NW = kSortThreads / kWave;
     constexpr int kItems = kSortThreads * R;
     __shared__ uint32_t skeys[kItems];
-    __shared__ uint32_t svals[kItems];
+    __shared__ uint32_t svals[MODE == kPairs ? kItems : 1];
     __shared__ uint32_t dstart[kSortBins];
     __shared__ uint32_t gbase[kSortBins];
     __shared__ uint32_t run[kSortBins];
@@ -122,7 +129,7 @@ __global__ __launch_bounds__(kSortThreads) void k_sort_scatter(SortPass a) {
     for (int r = 0; r < R; r++) {
         const int k = r * kSortThreads + t;
         key[r] = k < cnt ? a.keys_in[base + k] : 0u;
-        val[r] = k < cnt ? a.vals_in[base + k] : 0u;
+        val[r] = MODE == kPairs && k < cnt ? a.vals_in[base + k] : 0u;
     }
 
     // local histogram -> local digit starts
@@ -155,6 +162,7 @@ __global__ __launch_bounds__(kSortThreads) void k_sort_scatter(SortPass a) {
         unsigned long long peers = __ballot(valid);
 #pragma unroll
         for (int b = 0; b < kSortBits; b++) {
+            if (!((a.mask >> b) & 1u)) break;   // the pass's digit bits only
             const bool bit = (d >> b) & 1u;
             const unsigned long long m = __ballot(bit);
             peers &= bit ? m : ~m;
@@ -178,7 +186,7 @@ __global__ __launch_bounds__(kSortThreads) void k_sort_scatter(SortPass a) {
         if (valid) {
             const uint32_t pos = wpre[w][d] + rank;
             skeys[pos] = key[r];
-            svals[pos] = val[r];
+            if (MODE == kPairs) svals[pos] = val[r];
         }
     }
     __syncthreads();
@@ -187,15 +195,24 @@ __global__ __launch_bounds__(kSortThreads) void k_sort_scatter(SortPass a) {
         const uint32_t k = skeys[i];
         const uint32_t d = (k >> a.shift) & a.mask;
         const size_t dst = (size_t)gbase[d] + (uint32_t)(i - dstart[d]);
-        a.keys_out[dst] = k;
-        a.vals_out[dst] = svals[i];
+        if (MODE == kPairs) {
+            a.keys_out[dst] = k;
+            a.vals_out[dst] = svals[i];
+        } else if (MODE == kPacked) {
+            a.keys_out[dst] = k;
+        } else {
+            a.keys_out[dst] = k >> a.vbits;
+            a.vals_out[dst] = k & ((1u << a.vbits) - 1u);
+        }
     }
 }
 
+// vbits > 0: the input is packed (k0 only) and the passes before the last
+// keep it packed; the last pass writes keys and values.
 template <int R>
 static int launch_sort_pairs(uint32_t *k0, uint32_t *v0, uint32_t *k1, uint32_t *v1, uint32_t *hist,
                              uint32_t *digit_tot, const uint32_t *count_ptr, uint32_t count_val,
-                             int64_t max_count, int bits, bool hist0_given, hipStream_t s,
+                             int64_t max_count, int bits, bool hist0_given, int vbits, hipStream_t s,
                              hipError_t *err) {
     constexpr int kItems = kSortThreads * R;
     SortPass a;
@@ -214,11 +231,17 @@ static int launch_sort_pairs(uint32_t *k0, uint32_t *v0, uint32_t *k1, uint32_t 
         a.vals_in = (p & 1) ? v1 : v0;
         a.keys_out = (p & 1) ? k0 : k1;
         a.vals_out = (p & 1) ? v0 : v1;
-        a.shift = p * pbits;
+        a.shift = vbits + p * pbits;
+        a.vbits = vbits;
         if (p > 0 || !hist0_given)
             hipLaunchKernelGGL(k_sort_hist<R>, dim3(a.nblk), dim3(kSortThreads), 0, s, a);
         hipLaunchKernelGGL(k_sort_scan, dim3(a.mask + 1), dim3(kSortScanThreads), 0, s, a);
-        hipLaunchKernelGGL(k_sort_scatter<R>, dim3(a.nblk), dim3(kSortThreads), 0, s, a);
+        if (vbits == 0)
+            hipLaunchKernelGGL((k_sort_scatter<R, kPairs>), dim3(a.nblk), dim3(kSortThreads), 0, s, a);
+        else if (p < passes - 1)
+            hipLaunchKernelGGL((k_sort_scatter<R, kPacked>), dim3(a.nblk), dim3(kSortThreads), 0, s, a);
+        else
+            hipLaunchKernelGGL((k_sort_scatter<R, kUnpack>), dim3(a.nblk), dim3(kSortThreads), 0, s, a);
         *err = hipGetLastError();
         if (*err != hipSuccess) return passes;
     }
@@ -231,7 +254,8 @@ hipError_t launch_tile_sort(const Layout &L, char *ws, hipStream_t s) {
         launch_sort_pairs<decltype(rounds)::value>(
             region<uint32_t>(ws, L.keys0), region<uint32_t>(ws, L.vals0), region<uint32_t>(ws, L.keys1),
             region<uint32_t>(ws, L.vals1), region<uint32_t>(ws, L.hist), region<uint32_t>(ws, L.digit_tot),
-            region<uint32_t>(ws, L.counters) + kCntMEff, 0u, L.cap, L.tile_bits, true, s, &e);
+            region<uint32_t>(ws, L.counters) + kCntMEff, 0u, L.cap, L.tile_bits, true, L.sort_vbits, s,
+            &e);
     };
     if (L.sort_items == kSortThreads * kSortRoundsLarge)
         run(std::integral_constant<int, kSortRoundsLarge>{});
