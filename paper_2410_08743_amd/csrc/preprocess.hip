@@ -353,32 +353,79 @@ __global__ __launch_bounds__(kEmitThreads) void k_emit(DupArgs a, ViewsK views, 
         }
         if (t == 0) s_off[nk] = a.offv[kb + nk];
         __syncthreads();
-        for (uint32_t e = p0 + t; e < p1; e += kEmitThreads) {
-            // largest j with s_off[j] <= e; s_off[0] <= p0 <= e < p1 <= s_off[nk]
+        // Each thread emits kPer consecutive positions: a binary search for
+        // the first, then a walk along the splats' tiles (rows outer,
+        // columns inner), with no division per position.
+        constexpr int kPer = ITEMS / kEmitThreads;
+        static_assert(ITEMS % kEmitThreads == 0, "whole runs of positions per thread");
+        const uint32_t e0 = p0 + (uint32_t)t * kPer;
+        if (e0 < p1) {
+            // largest j with s_off[j] <= e0; s_off[0] <= p0 <= e0 < p1 <= s_off[nk]
             int lo = 0, hi = nk;
             while (hi - lo > 1) {
                 const int mid = (lo + hi) >> 1;
-                if (s_off[mid] <= e) lo = mid; else hi = mid;
+                if (s_off[mid] <= e0) lo = mid; else hi = mid;
             }
-            const uint2 r = s_rect[lo];
-            const int x0 = r.x & 0xffff, y0 = r.x >> 16, x1 = r.y & 0xffff;
-            const uint32_t w = (uint32_t)(x1 - x0), local = e - s_off[lo];
-            const uint32_t idx = s_idx[lo];
-            const ViewK &vw = views.v[idx / (uint32_t)n];
-            const uint32_t ty = (uint32_t)y0 + local / w, tx = (uint32_t)x0 + local % w;
-            const uint32_t key = (uint32_t)vw.tile_base + ty * (uint32_t)vw.gw + tx;
-            if (a.vbits > 0) {
-                a.keys[e] = (key << a.vbits) | idx;
+            uint32_t next = 0, idx = 0, w = 1, x0 = 0, y0 = 0, tbase = 0, gw = 0, tx = 0, ty = 0;
+            // the splat at entry lo, and the tile of position e in it
+            auto enter = [&](uint32_t e) {
+                next = s_off[lo + 1];
+                const uint2 r = s_rect[lo];
+                x0 = r.x & 0xffff;
+                y0 = r.x >> 16;
+                w = (r.y & 0xffff) - x0;
+                idx = s_idx[lo];
+                const ViewK &vw = views.v[idx / (uint32_t)n];
+                tbase = (uint32_t)vw.tile_base;
+                gw = (uint32_t)vw.gw;
+                const uint32_t local = e - s_off[lo];
+                ty = local / w;
+                tx = local - ty * w;
+            };
+            enter(e0);
+            const int cnt = (int)min((uint32_t)kPer, p1 - e0);
+            uint32_t kk[kPer], vv[kPer];
+#pragma unroll
+            for (int q = 0; q < kPer; q++) {
+                if (q < cnt) {
+                    const uint32_t e = e0 + (uint32_t)q;
+                    if (e >= next) {   // a later splat: the last one whose offset is <= e
+                        do lo++;
+                        while (s_off[lo + 1] <= e);
+                        enter(e);
+                    }
+                    const uint32_t key = tbase + (y0 + ty) * gw + x0 + tx;
+                    kk[q] = a.vbits > 0 ? (key << a.vbits) | idx : key;
+                    vv[q] = idx;
+                    atomicAdd(&s_hist[key & a.mask0], 1u);
+                    if (++tx == w) {
+                        tx = 0;
+                        ty++;
+                    }
+                }
+            }
+            // e0 is a multiple of kPer and the regions are 256-byte aligned,
+            // so a full run is stored as 16-byte vectors
+            static_assert(kPer % 4 == 0, "vector stores of a run");
+            if (cnt == kPer) {
+#pragma unroll
+                for (int q = 0; q < kPer; q += 4)
+                    *reinterpret_cast<uint4 *>(a.keys + e0 + q) = make_uint4(kk[q], kk[q + 1], kk[q + 2], kk[q + 3]);
+                if (a.vbits == 0) {
+#pragma unroll
+                    for (int q = 0; q < kPer; q += 4)
+                        *reinterpret_cast<uint4 *>(a.vals + e0 + q) = make_uint4(vv[q], vv[q + 1], vv[q + 2], vv[q + 3]);
+                }
+#pragma unroll
+                for (int q = 0; q < kSplitBwd * kPer / 4; q++)
+                    reinterpret_cast<uint32_t *>(a.slot_flags + (size_t)kSplitBwd * e0)[q] = 0u;
             } else {
-                a.keys[e] = key;
-                a.vals[e] = idx;
+                for (int q = 0; q < cnt; q++) {
+                    a.keys[e0 + q] = kk[q];
+                    if (a.vbits == 0) a.vals[e0 + q] = vv[q];
+                    for (int k = 0; k < kSplitBwd; k++) a.slot_flags[(size_t)kSplitBwd * (e0 + q) + k] = 0;
+                }
             }
-            atomicAdd(&s_hist[key & a.mask0], 1u);
-            if constexpr (kSplitBwd == 1) a.slot_flags[e] = 0;
-            else if constexpr (kSplitBwd == 2) reinterpret_cast<uint16_t *>(a.slot_flags)[e] = 0;
-            else if constexpr (kSplitBwd == 4) reinterpret_cast<uint32_t *>(a.slot_flags)[e] = 0u;
-            else
-                for (int q = 0; q < kSplitBwd; q++) a.slot_flags[(size_t)kSplitBwd * e + q] = 0;
         }
     }
     __syncthreads();
