@@ -278,7 +278,8 @@ hipError_t launch_tile_sort(const Layout &L, char *ws, hipStream_t s) {
 // nothing and many tiles are in flight per CU); workgroup b takes tile b, so
 // that its first load is its range.  The keys are taken relative to the
 // run's smallest (an order-preserving shift that leaves some 25 significant
-// bits for depths in 1.5 .. 8) and sorted LSD over kTdBits-bit digits,
+// bits for depths in 1.5 .. 8) and sorted LSD over kTdBits-bit digits (9:
+// three passes over those 25 bits, where 8-bit digits take four),
 // skipping every pass whose digit is the same for the whole run.  A pass is a
 // stable counting sort: rounds of 64 items, each lane ranked among the
 // round's lanes with the same digit (found through a per-digit lane mask in
@@ -290,18 +291,22 @@ hipError_t launch_tile_sort(const Layout &L, char *ws, hipStream_t s) {
 // the run, and the values are gathered by that position once at the end (so
 // a pass scatters and reloads one word per item, and LDS holds CAP words).
 // Longer runs, and runs whose keys are too wide for that packing (depths
-// spread over some sixty binary orders of magnitude), (histograms from one
-// read first) move, CAP entries at a time with every load of a chunk in
+// spread over some sixty binary orders of magnitude), sorted over 8-bit
+// digits (histograms of every pass from one read first), move, CAP entries at a time with every load of a chunk in
 // flight, between the sorted arrays and the tile sort's other key and value
 // buffers, the relative keys carried beside the values (the key array's
 // tile ids are restored afterwards).
 #ifndef GSP_TD_BITS
-#define GSP_TD_BITS 8
+#define GSP_TD_BITS 9
 #endif
+// digits of the runs sorted in LDS (three passes over 25 significant bits)
 constexpr int kTdBits = GSP_TD_BITS;
 constexpr int kTdBins = 1 << kTdBits;
-constexpr int kTdPasses = (32 + kTdBits - 1) / kTdBits;
-constexpr int kTdPerLane = kTdBins / kWave;
+// digits of the long runs, whose histograms of all passes share buf
+constexpr int kTdLBits = 8;
+constexpr int kTdLBins = 1 << kTdLBits;
+constexpr int kTdLPasses = (32 + kTdLBits - 1) / kTdLBits;
+static_assert(kTdBits >= kTdLBits && kTdBins % kWave == 0, "run and msk hold either digit");
 
 struct TileDepthArgs {
     const uint2 *ranges;
@@ -345,8 +350,10 @@ __device__ __forceinline__ uint32_t td_rank(bool valid, uint32_t d, uint32_t *ru
     return base + below;
 }
 
-// run[] (digit counts) -> exclusive starts, in place.
+// run[] (digit counts of BINS digits) -> exclusive starts, in place.
+template <int BINS>
 __device__ __forceinline__ void td_scan(uint32_t *run) {
+    constexpr int kTdPerLane = BINS / kWave;
     const int lane = threadIdx.x;
     uint32_t c[kTdPerLane], s = 0;
 #pragma unroll
@@ -363,7 +370,9 @@ __device__ __forceinline__ void td_scan(uint32_t *run) {
     __syncthreads();
 }
 
+template <int BINS>
 __device__ __forceinline__ void td_zero(uint32_t *run) {
+    constexpr int kTdPerLane = BINS / kWave;
 #pragma unroll
     for (int j = 0; j < kTdPerLane; j++) run[kTdPerLane * threadIdx.x + j] = 0u;
 }
@@ -380,7 +389,7 @@ __global__ __launch_bounds__(kWave) void k_tile_depth_sort(TileDepthArgs a) {
     __shared__ uint32_t buf[kTdCap];
     __shared__ uint32_t run[kTdBins];
     __shared__ unsigned long long msk[kTdBins];
-    static_assert(kTdPasses * kTdBins <= kTdCap, "histograms of a long run fit in buf");
+    static_assert(kTdLPasses * kTdLBins <= kTdCap, "histograms of a long run fit in buf");
     const uint32_t tile = blockIdx.x;
     const uint2 rg = a.ranges[tile];
     const int L = (int)(rg.y - rg.x);
@@ -389,7 +398,7 @@ __global__ __launch_bounds__(kWave) void k_tile_depth_sort(TileDepthArgs a) {
     uint32_t key[kTdRounds], val[kTdRounds];
     uint32_t *const kf = a.keys + rg.x, *const vf = a.vals + rg.x;
 #pragma unroll
-    for (int j = 0; j < kTdPerLane; j++) msk[kTdPerLane * lane + j] = 0ull;
+    for (int j = 0; j < kTdBins / kWave; j++) msk[kTdBins / kWave * lane + j] = 0ull;
 
     if (L <= kTdCap) {
 #pragma unroll
@@ -438,7 +447,7 @@ __global__ __launch_bounds__(kWave) void k_tile_depth_sort(TileDepthArgs a) {
                     return;
                 }
                 moved = true;
-                td_zero(run);
+                td_zero<kTdBins>(run);
                 __syncthreads();
 #pragma unroll
                 for (int r = 0; r < kTdRounds; r++) {
@@ -448,7 +457,7 @@ __global__ __launch_bounds__(kWave) void k_tile_depth_sort(TileDepthArgs a) {
                     rk[r] = td_rank(valid, digit_of(r), run, msk);
                 }
                 __syncthreads();
-                td_scan(run);
+                td_scan<kTdBins>(run);
 #pragma unroll
                 for (int r = 0; r < kTdRounds; r++)
                     if (r * kWave + lane < L) buf[run[digit_of(r)] + rk[r]] = item_of(r);
@@ -504,8 +513,8 @@ __global__ __launch_bounds__(kWave) void k_tile_depth_sort(TileDepthArgs a) {
         }
     }
     kmin = wave_min_u32(kmin);
-    uint32_t *const hist = buf;   // [kTdPasses][kTdBins]
-    for (int i = lane; i < kTdPasses * kTdBins; i += kWave) hist[i] = 0u;
+    uint32_t *const hist = buf;   // [kTdLPasses][kTdLBins]
+    for (int i = lane; i < kTdLPasses * kTdLBins; i += kWave) hist[i] = 0u;
     __syncthreads();
     for (int c0 = 0; c0 < L; c0 += kTdCap) {
 #pragma unroll
@@ -519,8 +528,8 @@ __global__ __launch_bounds__(kWave) void k_tile_depth_sort(TileDepthArgs a) {
             if (k < L) {
                 const uint32_t kk = a.depth[val[r]] - kmin;
 #pragma unroll
-                for (int p = 0; p < kTdPasses; p++)
-                    atomicAdd(&hist[p * kTdBins + ((kk >> (kTdBits * p)) & (kTdBins - 1))], 1u);
+                for (int p = 0; p < kTdLPasses; p++)
+                    atomicAdd(&hist[p * kTdLBins + ((kk >> (kTdLBits * p)) & (kTdLBins - 1))], 1u);
             }
         }
     }
@@ -528,18 +537,19 @@ __global__ __launch_bounds__(kWave) void k_tile_depth_sort(TileDepthArgs a) {
     // source of the next pass: (keys gathered | skey, sval), destination (dkey, dval)
     uint32_t *skey = nullptr, *sval = vf, *dkey = a.akeys + rg.x, *dval = a.avals + rg.x;
     bool kf_used = false;
-    for (int p = 0; p < kTdPasses; p++) {
-        const int sh = kTdBits * p;
+    for (int p = 0; p < kTdLPasses; p++) {
+        const int sh = kTdLBits * p;
+        constexpr int kTdPerLane = kTdLBins / kWave;
         bool full = false;
 #pragma unroll
         for (int j = 0; j < kTdPerLane; j++) {
-            const uint32_t c = hist[p * kTdBins + kTdPerLane * lane + j];
+            const uint32_t c = hist[p * kTdLBins + kTdPerLane * lane + j];
             full |= c == (uint32_t)L;
             run[kTdPerLane * lane + j] = c;
         }
         if (wave_any(full)) continue;   // one digit: nothing moves
         __syncthreads();
-        td_scan(run);
+        td_scan<kTdLBins>(run);
         for (int c0 = 0; c0 < L; c0 += kTdCap) {
 #pragma unroll
             for (int r = 0; r < kTdRounds; r++) {
@@ -558,7 +568,7 @@ __global__ __launch_bounds__(kWave) void k_tile_depth_sort(TileDepthArgs a) {
             for (int r = 0; r < kTdRounds; r++) {
                 if (c0 + r * kWave >= L) break;   // uniform
                 const bool valid = c0 + r * kWave + lane < L;
-                const uint32_t pos = td_rank(valid, (key[r] >> sh) & (kTdBins - 1), run, msk);
+                const uint32_t pos = td_rank(valid, (key[r] >> sh) & (kTdLBins - 1), run, msk);
                 if (valid) {
                     dkey[pos] = key[r];
                     dval[pos] = val[r];
