@@ -23,9 +23,16 @@ FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-Wall",
          "-I" + os.path.join(HERE, "..", "include")]
 
 
+# Per-source options.  The backward rasterizer branches on a wave-uniform
+# condition between two variants of its walk over a batch; leaving uniform
+# regions unstructured keeps that a plain scalar branch, without the
+# register copies that merged paths need at the join.
+EXTRA = {"raster_bwd.hip": ["-mllvm", "-structurizecfg-skip-uniform-regions=true"]}
+
+
 def _compile(src, verbose):
     obj = os.path.join(BUILD, os.path.splitext(src)[0] + ".o")
-    cmd = [HIPCC, *FLAGS, "-c", os.path.join(CSRC, src), "-o", obj]
+    cmd = [HIPCC, *FLAGS, *EXTRA.get(src, []), "-c", os.path.join(CSRC, src), "-o", obj]
     if verbose:
         print(" ".join(cmd), flush=True)
     r = subprocess.run(cmd, capture_output=True, text=True)

@@ -30,6 +30,7 @@
 // written.  No atomics: the per-splat sum over its slots happens later in a
 // fixed order, so gradients are bit-reproducible.
 #include <cstring>
+#include <type_traits>
 
 #include "block_ops.h"
 #include "raster_common.h"
@@ -64,6 +65,10 @@ struct BwdArgs {
 };
 
 constexpr uint32_t kNoSlot = 0xffffffffu;
+// log2 of an opacity that keeps every unclamped alpha of its splat below the
+// 0.99 clamp: exp2(-0.0155) = 0.98931, so with power <= 0 the alpha stays
+// below 0.99 by far more than the error of the exp2 instruction.
+constexpr float kLoNoClamp = -0.0155f;
 
 #ifndef GSP_BWD_UNROLL
 #define GSP_BWD_UNROLL 2
@@ -277,6 +282,9 @@ __global__ __launch_bounds__(kRasterThreads) __attribute__((amdgpu_waves_per_eu(
             gslot != kNoSlot ? band_mask<kSplit>(u, v, g1.x, g1.y, g1.z, g1.w, row0) : 0u;
         const unsigned long long kept = __ballot(mask != 0u);
         const int nk = __popcll(kept);
+        // an opacity below exp2(kLoNoClamp) keeps o exp(power) below the
+        // clamp wherever power <= 0
+        const bool nc_batch = __ballot(mask != 0u && !(g1.w <= kLoNoClamp)) == 0ull;
         if (mask != 0u) {
             const int r = kept_rank(kept);
             sA[r] = StagedA{u, v, g1.x, g1.y};
@@ -293,168 +301,175 @@ __global__ __launch_bounds__(kRasterThreads) __attribute__((amdgpu_waves_per_eu(
         }
         __syncthreads();
         if (lo > clo) gather(lo - kBatch + lane);
-        StagedA es[kBwdUnroll];
-        StagedB et[kBwdUnroll];
-        StagedC ew[kBwdUnroll];
-        uint32_t em[kBwdUnroll];
-        auto load_group = [&](int j0, StagedA (&ra)[kBwdUnroll], StagedB (&rb)[kBwdUnroll],
-                              StagedC (&rc)[kBwdUnroll], uint32_t (&rm)[kBwdUnroll]) {
-#pragma unroll
-            for (int u = 0; u < kBwdUnroll; u++) {
-                ra[u] = sA[j0 + u];
-                rb[u] = sB[j0 + u];
-                rc[u] = sC[j0 + u];
-                rm[u] = sM[j0 + u];
+        // NC: no staged entry of the batch can reach the 0.99 clamp, whose
+        // tests then drop out of the walk (same results, fewer operations)
+        auto walk = [&](auto nc_c) __attribute__((always_inline)) {
+            constexpr bool NC = decltype(nc_c)::value;
+            StagedA es[kBwdUnroll];
+            StagedB et[kBwdUnroll];
+            StagedC ew[kBwdUnroll];
+            uint32_t em[kBwdUnroll];
+            auto load_group = [&](int j0, StagedA (&ra)[kBwdUnroll], StagedB (&rb)[kBwdUnroll],
+                                  StagedC (&rc)[kBwdUnroll], uint32_t (&rm)[kBwdUnroll]) {
+    #pragma unroll
+                for (int u = 0; u < kBwdUnroll; u++) {
+                    ra[u] = sA[j0 + u];
+                    rb[u] = sB[j0 + u];
+                    rc[u] = sC[j0 + u];
+                    rm[u] = sM[j0 + u];
+                }
+            };
+            if (GSP_BWD_PREFETCH && nkr > 0) load_group(nkr - kBwdUnroll, es, et, ew, em);
+            for (int j0 = nkr - kBwdUnroll; j0 >= 0; j0 -= kBwdUnroll) {
+                // the next group's records (one group ahead: the LDS round trip
+                // overlaps this group's work), or this group's
+                StagedA es_n[kBwdUnroll];
+                StagedB et_n[kBwdUnroll];
+                StagedC ew_n[kBwdUnroll];
+                uint32_t em_n[kBwdUnroll];
+                if (GSP_BWD_PREFETCH) {
+                    load_group(j0 >= kBwdUnroll ? j0 - kBwdUnroll : 0, es_n, et_n, ew_n, em_n);
+                } else {
+                    load_group(j0, es, et, ew, em);
+                    // All records of the group are wanted in registers here: the
+                    // compiler would otherwise sink the later entries' loads
+                    // below the band test, a second LDS round trip per entry.
+                    // (Not in the stored-list variant, where it would cost spills.)
+    #pragma unroll
+                    for (int u = 0; u < (STORED ? 0 : kBwdUnroll); u++)
+                        asm volatile("" ::"v"(es[u].u), "v"(es[u].v), "v"(es[u].A2), "v"(es[u].B2),
+                                     "v"(et[u].C2), "v"(et[u].lo), "v"(et[u].r), "v"(et[u].g), "v"(ew[u].b),
+                                     "v"(ew[u].inv_o), "v"(ew[u].slot));
+                }
+    #pragma unroll
+                for (int u = kBwdUnroll - 1; u >= 0; u--) {
+                    // the bands this entry may reach that still have pixels
+                    // compositing at its list position (wave-uniform)
+                    const int pos = __builtin_amdgcn_readfirstlane((int)ew[u].pm);
+                    uint32_t bands = __builtin_amdgcn_readfirstlane(em[u]);
+    #pragma unroll
+                    for (int q = 0; q < kPixPerLane; q++)
+                        if (pos >= blast[q]) bands &= ~(1u << q);
+                    if (bands == 0u) continue;
+                    const StagedA &s = es[u];
+                    const StagedB &t = et[u];
+                    const ColTerms ct = col_terms(s, fxl);
+                    const float col3[3] = {t.r, t.g, ew[u].b};
+                    // Per lane, dx is the same for all its pixels, so the conic
+                    // and centre gradients need only the moments sum dp, sum dp dy,
+                    // sum dp dy^2 of dL/dpower over them.
+                    float m0 = 0.f, my = 0.f, myy = 0.f, gc[3] = {0.f, 0.f, 0.f};
+                    bool blended = false;
+                    // q-th pixels of all lanes form a 16 x 4 band of the tile: a
+                    // band with no candidate pixel is skipped as a whole; inside a
+                    // band the update is branch-free, pixels that do not blend
+                    // adding exact zeros.
+    #pragma unroll
+                    for (int q = 0; q < kPixPerLane; q++) {
+                        if (!((bands >> q) & 1u)) continue;
+                        const float dy = s.v - fy[q];
+                        // candidates: pixels that blend this entry, decided as
+                        // the forward does (power <= 0, alpha >= 1/255), before
+                        // their contributor count
+                        float apre = 0.f, a0 = 0.f;
+                        bool cand;
+                        if (STORED) {
+                            cand = npos[q] == (uint32_t)pos;
+                        } else {
+                            const float p2 = splat_p2(ct, t.C2, dy);
+                            apre = splat_alpha_pre(p2, t.lo);
+                            a0 = NC ? apre : fminf(kAlphaMax, apre);   // NC: below the clamp
+                            cand = (pos < last[q]) & (p2 <= 0.f) & (a0 >= kAlphaMin);
+                        }
+                        if (__builtin_amdgcn_ballot_w64(cand) == 0ull) continue;
+                        blended = true;
+                        float alpha, wgt;
+                        bool valid, unclamped;
+                        if (STORED) {
+                            // alpha and T_i of this pair as the forward left them
+                            valid = cand;
+                            alpha = valid ? fabsf(nal[q]) : 0.f;
+                            unclamped = nal[q] >= 0.f;
+                            wgt = valid ? alpha * T[q] : 0.f;
+                        } else {
+                            // A pixel that does not blend takes alpha = 0, which
+                            // leaves T (times rcp(1) = 1), G.S (plus 0 * diff)
+                            // and the sums (plus 0) exactly as they are.
+                            valid = cand;
+                            alpha = valid ? a0 : 0.f;
+                            unclamped = NC || apre <= kAlphaMax;
+                            T[q] = T[q] * __builtin_amdgcn_rcpf(1.f - alpha);
+                            wgt = alpha * T[q];
+                        }
+                        const float Gc = fmaf(G[q][2], col3[2], fmaf(G[q][1], col3[1], G[q][0] * col3[0]));
+                        const float diff = Gc - GS[q];
+    #pragma unroll
+                        for (int ch = 0; ch < 3; ch++) gc[ch] = fmaf(G[q][ch], wgt, gc[ch]);
+                        GS[q] = STORED ? (valid ? fmaf(alpha, diff, GS[q]) : GS[q]) : fmaf(alpha, diff, GS[q]);
+                        // dL/dpower; zero where alpha is clamped at 0.99
+                        const float dp = unclamped ? wgt * diff : 0.f;
+                        if (STORED && valid) {
+                            // step to the pixel's previous pair (if any)
+                            npos[q] = kNoPos;
+                            if (pidx[q] > pbase[q]) {
+                                pidx[q]--;
+                                const PairRec r = a.pairs[pidx[q]];
+                                npos[q] = r.pos;
+                                nal[q] = r.alpha;
+                                T[q] = r.T;
+                            }
+                        }
+                        const float dpy = dp * dy;
+                        m0 += dp;
+                        my += dpy;
+                        myy = fmaf(dpy, dy, myy);
+                    }
+                    if (!blended) continue;
+                    {
+                        // dpower/du = -(A dx + B dy), dpower/dv = -(C dy + B dx),
+                        // dpower/d(A, B, C) = -(dx^2 / 2, dx dy, dy^2 / 2), in the
+                        // base-2 conic and before the per-component scale below
+                        float acc[9];
+                        acc[0] = fmaf(s.B2, my, 2.f * s.A2 * ct.dx * m0);
+                        acc[1] = fmaf(2.f * t.C2, my, ct.bdx * m0);
+                        acc[2] = ct.dx * ct.dx * m0;
+                        acc[3] = ct.dx * my;
+                        acc[4] = myy;
+                        acc[5] = OPA ? m0 : gc[0];
+                        acc[6] = OPA ? gc[0] : gc[1];
+                        acc[7] = OPA ? gc[1] : gc[2];
+                        acc[8] = gc[2];
+                        float *const dst = sP + npend * kEntryStride + (lane >> 4) * kRowStride + (lane & 15);
+                        float ra, rb;
+                        if (OPA) {
+                            float rc;
+                            wave_sum9_rows(acc, ra, rb, rc);
+                            dst[2 * kRegStride] = rc;
+                        } else {
+                            wave_sum8_rows(acc, ra, rb);
+                        }
+                        dst[0] = ra;
+                        dst[kRegStride] = rb;
+                        if (lane == 0) {
+                            sPs[npend] = ew[u].slot;
+                            sPi[npend] = ew[u].inv_o;
+                        }
+                        if (++npend == kPend) flush();
+                    }
+                }
+                if (GSP_BWD_PREFETCH) {
+    #pragma unroll
+                    for (int u = 0; u < kBwdUnroll; u++) {
+                        es[u] = es_n[u];
+                        et[u] = et_n[u];
+                        ew[u] = ew_n[u];
+                        em[u] = em_n[u];
+                    }
+                }
             }
         };
-        if (GSP_BWD_PREFETCH && nkr > 0) load_group(nkr - kBwdUnroll, es, et, ew, em);
-        for (int j0 = nkr - kBwdUnroll; j0 >= 0; j0 -= kBwdUnroll) {
-            // the next group's records (one group ahead: the LDS round trip
-            // overlaps this group's work), or this group's
-            StagedA es_n[kBwdUnroll];
-            StagedB et_n[kBwdUnroll];
-            StagedC ew_n[kBwdUnroll];
-            uint32_t em_n[kBwdUnroll];
-            if (GSP_BWD_PREFETCH) {
-                load_group(j0 >= kBwdUnroll ? j0 - kBwdUnroll : 0, es_n, et_n, ew_n, em_n);
-            } else {
-                load_group(j0, es, et, ew, em);
-                // All records of the group are wanted in registers here: the
-                // compiler would otherwise sink the later entries' loads
-                // below the band test, a second LDS round trip per entry.
-                // (Not in the stored-list variant, where it would cost spills.)
-#pragma unroll
-                for (int u = 0; u < (STORED ? 0 : kBwdUnroll); u++)
-                    asm volatile("" ::"v"(es[u].u), "v"(es[u].v), "v"(es[u].A2), "v"(es[u].B2),
-                                 "v"(et[u].C2), "v"(et[u].lo), "v"(et[u].r), "v"(et[u].g), "v"(ew[u].b),
-                                 "v"(ew[u].inv_o), "v"(ew[u].slot));
-            }
-#pragma unroll
-            for (int u = kBwdUnroll - 1; u >= 0; u--) {
-                // the bands this entry may reach that still have pixels
-                // compositing at its list position (wave-uniform)
-                const int pos = __builtin_amdgcn_readfirstlane((int)ew[u].pm);
-                uint32_t bands = __builtin_amdgcn_readfirstlane(em[u]);
-#pragma unroll
-                for (int q = 0; q < kPixPerLane; q++)
-                    if (pos >= blast[q]) bands &= ~(1u << q);
-                if (bands == 0u) continue;
-                const StagedA &s = es[u];
-                const StagedB &t = et[u];
-                const ColTerms ct = col_terms(s, fxl);
-                const float col3[3] = {t.r, t.g, ew[u].b};
-                // Per lane, dx is the same for all its pixels, so the conic
-                // and centre gradients need only the moments sum dp, sum dp dy,
-                // sum dp dy^2 of dL/dpower over them.
-                float m0 = 0.f, my = 0.f, myy = 0.f, gc[3] = {0.f, 0.f, 0.f};
-                bool blended = false;
-                // q-th pixels of all lanes form a 16 x 4 band of the tile: a
-                // band with no candidate pixel is skipped as a whole; inside a
-                // band the update is branch-free, pixels that do not blend
-                // adding exact zeros.
-#pragma unroll
-                for (int q = 0; q < kPixPerLane; q++) {
-                    if (!((bands >> q) & 1u)) continue;
-                    const float dy = s.v - fy[q];
-                    // candidates: pixels that blend this entry, decided as
-                    // the forward does (power <= 0, alpha >= 1/255), before
-                    // their contributor count
-                    float apre = 0.f, a0 = 0.f;
-                    bool cand;
-                    if (STORED) {
-                        cand = npos[q] == (uint32_t)pos;
-                    } else {
-                        const float p2 = splat_p2(ct, t.C2, dy);
-                        apre = splat_alpha_pre(p2, t.lo);
-                        a0 = fminf(kAlphaMax, apre);
-                        cand = (pos < last[q]) & (p2 <= 0.f) & (a0 >= kAlphaMin);
-                    }
-                    if (__builtin_amdgcn_ballot_w64(cand) == 0ull) continue;
-                    blended = true;
-                    float alpha, wgt;
-                    bool valid, unclamped;
-                    if (STORED) {
-                        // alpha and T_i of this pair as the forward left them
-                        valid = cand;
-                        alpha = valid ? fabsf(nal[q]) : 0.f;
-                        unclamped = nal[q] >= 0.f;
-                        wgt = valid ? alpha * T[q] : 0.f;
-                    } else {
-                        // A pixel that does not blend takes alpha = 0, which
-                        // leaves T (times rcp(1) = 1), G.S (plus 0 * diff)
-                        // and the sums (plus 0) exactly as they are.
-                        valid = cand;
-                        alpha = valid ? a0 : 0.f;
-                        unclamped = apre <= kAlphaMax;
-                        T[q] = T[q] * __builtin_amdgcn_rcpf(1.f - alpha);
-                        wgt = alpha * T[q];
-                    }
-                    const float Gc = fmaf(G[q][2], col3[2], fmaf(G[q][1], col3[1], G[q][0] * col3[0]));
-                    const float diff = Gc - GS[q];
-#pragma unroll
-                    for (int ch = 0; ch < 3; ch++) gc[ch] = fmaf(G[q][ch], wgt, gc[ch]);
-                    GS[q] = STORED ? (valid ? fmaf(alpha, diff, GS[q]) : GS[q]) : fmaf(alpha, diff, GS[q]);
-                    // dL/dpower; zero where alpha is clamped at 0.99
-                    const float dp = unclamped ? wgt * diff : 0.f;
-                    if (STORED && valid) {
-                        // step to the pixel's previous pair (if any)
-                        npos[q] = kNoPos;
-                        if (pidx[q] > pbase[q]) {
-                            pidx[q]--;
-                            const PairRec r = a.pairs[pidx[q]];
-                            npos[q] = r.pos;
-                            nal[q] = r.alpha;
-                            T[q] = r.T;
-                        }
-                    }
-                    const float dpy = dp * dy;
-                    m0 += dp;
-                    my += dpy;
-                    myy = fmaf(dpy, dy, myy);
-                }
-                if (!blended) continue;
-                {
-                    // dpower/du = -(A dx + B dy), dpower/dv = -(C dy + B dx),
-                    // dpower/d(A, B, C) = -(dx^2 / 2, dx dy, dy^2 / 2), in the
-                    // base-2 conic and before the per-component scale below
-                    float acc[9];
-                    acc[0] = fmaf(s.B2, my, 2.f * s.A2 * ct.dx * m0);
-                    acc[1] = fmaf(2.f * t.C2, my, ct.bdx * m0);
-                    acc[2] = ct.dx * ct.dx * m0;
-                    acc[3] = ct.dx * my;
-                    acc[4] = myy;
-                    acc[5] = OPA ? m0 : gc[0];
-                    acc[6] = OPA ? gc[0] : gc[1];
-                    acc[7] = OPA ? gc[1] : gc[2];
-                    acc[8] = gc[2];
-                    float *const dst = sP + npend * kEntryStride + (lane >> 4) * kRowStride + (lane & 15);
-                    float ra, rb;
-                    if (OPA) {
-                        float rc;
-                        wave_sum9_rows(acc, ra, rb, rc);
-                        dst[2 * kRegStride] = rc;
-                    } else {
-                        wave_sum8_rows(acc, ra, rb);
-                    }
-                    dst[0] = ra;
-                    dst[kRegStride] = rb;
-                    if (lane == 0) {
-                        sPs[npend] = ew[u].slot;
-                        sPi[npend] = ew[u].inv_o;
-                    }
-                    if (++npend == kPend) flush();
-                }
-            }
-            if (GSP_BWD_PREFETCH) {
-#pragma unroll
-                for (int u = 0; u < kBwdUnroll; u++) {
-                    es[u] = es_n[u];
-                    et[u] = et_n[u];
-                    ew[u] = ew_n[u];
-                    em[u] = em_n[u];
-                }
-            }
-        }
+        if (!STORED && nc_batch) walk(std::true_type{});
+        else walk(std::false_type{});
         __syncthreads();
     }
     if (npend > 0) flush();
