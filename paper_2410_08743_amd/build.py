@@ -23,11 +23,12 @@ FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-Wall",
          "-I" + os.path.join(HERE, "..", "include")]
 
 
-# Per-source options.  The backward rasterizer branches on a wave-uniform
-# condition between two variants of its walk over a batch; leaving uniform
+# Per-source options.  The rasterizers branch on a wave-uniform
+# condition between two variants of their walk over a batch; leaving uniform
 # regions unstructured keeps that a plain scalar branch, without the
 # register copies that merged paths need at the join.
-EXTRA = {"raster_bwd.hip": ["-mllvm", "-structurizecfg-skip-uniform-regions=true"]}
+EXTRA = {f: ["-mllvm", "-structurizecfg-skip-uniform-regions=true"]
+         for f in ("raster_fwd.hip", "raster_bwd.hip")}
 
 
 def _compile(src, verbose):

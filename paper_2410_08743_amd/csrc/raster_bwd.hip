@@ -65,10 +65,6 @@ struct BwdArgs {
 };
 
 constexpr uint32_t kNoSlot = 0xffffffffu;
-// log2 of an opacity that keeps every unclamped alpha of its splat below the
-// 0.99 clamp: exp2(-0.0155) = 0.98931, so with power <= 0 the alpha stays
-// below 0.99 by far more than the error of the exp2 instruction.
-constexpr float kLoNoClamp = -0.0155f;
 
 #ifndef GSP_BWD_UNROLL
 #define GSP_BWD_UNROLL 2

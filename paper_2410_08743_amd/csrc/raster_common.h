@@ -41,6 +41,11 @@ constexpr float kLn2 = 0.6931471805599453f;
 // conservative with respect to v_exp_f32's and the subtraction's rounding, so
 // skipping on it never changes a decision.
 constexpr float kLog2AlphaMinLoose = -7.994353436858858f - 0.01f;
+// log2 of an opacity that keeps every unclamped alpha of its splat below the
+// 0.99 clamp: exp2(-0.0155) = 0.98931, so with power <= 0 the alpha stays
+// below 0.99 by far more than the error of the exp2 instruction, and
+// min(0.99, alpha) is alpha itself.
+constexpr float kLoNoClamp = -0.0155f;
 
 // Splat as staged in LDS: centre relative to the tile's first pixel, scaled
 // conic, log2 opacity and colour; the forward adds its list position + 1, the

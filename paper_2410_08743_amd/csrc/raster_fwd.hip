@@ -16,6 +16,8 @@
 // pixel evaluations of two FMAs and one v_exp_f32.  The waves of a tile need
 // no barrier between them, and each leaves as soon as its pixels are
 // saturated.
+#include <type_traits>
+
 #include "block_ops.h"
 #include "raster_common.h"
 
@@ -264,6 +266,7 @@ __global__ __launch_bounds__(kRasterThreads) __attribute__((amdgpu_waves_per_eu(
         const uint32_t mask = k < len ? band_mask<kSplit>(u, v, g1.x, g1.y, g1.z, g1.w, row0) : 0u;
         const unsigned long long kept = __ballot(mask != 0u);
         const int nk = __popcll(kept);
+        const bool nc_batch = __ballot(mask != 0u && !(g1.w <= kLoNoClamp)) == 0ull;
         if (mask != 0u) {
             const int r = kept_rank(kept);
             sA[r] = StagedA{u, v, g1.x, g1.y};
@@ -278,58 +281,68 @@ __global__ __launch_bounds__(kRasterThreads) __attribute__((amdgpu_waves_per_eu(
         }
         __syncthreads();
         gather(b0 + kBatch + lane);
-        for (int j0 = 0; j0 < nk; j0 += kUnroll) {
-            StagedA es[kUnroll];
-            StagedB et[kUnroll];
-            StagedF ef[kUnroll];
-#pragma unroll
-            for (int u2 = 0; u2 < kUnroll; u2++) {
-                es[u2] = sA[j0 + u2];
-                et[u2] = sB[j0 + u2];
-                ef[u2] = sF[j0 + u2];
-            }
-#pragma unroll
-            for (int u2 = 0; u2 < kUnroll; u2++) {
-                const int jp1 = (int)ef[u2].jp1;   // list position + 1
-                const ColTerms ct = col_terms(es[u2], fxl);
-                // hits: pixels still compositing (finite fy; the others get
-                // p2 = -inf and alpha = 0) with power <= 0 and alpha >= 1/255.
-                // (No separate p2 bound first: the staging cull already
-                // dropped the entries that reach 1/255 nowhere in these rows,
-                // and the backward's looser bound on p2 accepts every hit.)
-                float alpha[kPixPerLane];
-                bool hit[kPixPerLane];
-                bool any = false;
-#pragma unroll
-                for (int q = 0; q < kPixPerLane; q++) {
-                    const float p2 = splat_p2(ct, et[u2].C2, es[u2].v - fy[q]);
-                    alpha[q] = fminf(kAlphaMax, splat_alpha_pre(p2, et[u2].lo));
-                    hit[q] = (p2 <= 0.f) & (alpha[q] >= kAlphaMin);
-                    any |= hit[q];
+        // NC: no staged entry of the batch can reach the 0.99 clamp (same
+        // alphas, one operation fewer per pixel); false once every pixel of
+        // the part has stopped
+        auto walk = [&](auto nc_c) __attribute__((always_inline)) {
+            constexpr bool NC = decltype(nc_c)::value;
+            for (int j0 = 0; j0 < nk; j0 += kUnroll) {
+                StagedA es[kUnroll];
+                StagedB et[kUnroll];
+                StagedF ef[kUnroll];
+    #pragma unroll
+                for (int u2 = 0; u2 < kUnroll; u2++) {
+                    es[u2] = sA[j0 + u2];
+                    et[u2] = sB[j0 + u2];
+                    ef[u2] = sF[j0 + u2];
                 }
-                // no pixel of this part reaches 1/255: nothing to do
-                if (!wave_any(any)) continue;
-#pragma unroll
-                for (int q = 0; q < kPixPerLane; q++) {
-                    const float aT = alpha[q] * T[q];
-                    const float testT = T[q] - aT;   // T (1 - alpha)
-                    const bool blend = hit[q] && testT >= kTMin;
-                    const bool stop = hit[q] && !(testT >= kTMin);
-                    if (STATS) {
-                        nb[q] += blend ? 1u : 0u;
-                        ne[q] = stop ? (uint32_t)jp1 : ne[q];
+    #pragma unroll
+                for (int u2 = 0; u2 < kUnroll; u2++) {
+                    const int jp1 = (int)ef[u2].jp1;   // list position + 1
+                    const ColTerms ct = col_terms(es[u2], fxl);
+                    // hits: pixels still compositing (finite fy; the others get
+                    // p2 = -inf and alpha = 0) with power <= 0 and alpha >= 1/255.
+                    // (No separate p2 bound first: the staging cull already
+                    // dropped the entries that reach 1/255 nowhere in these rows,
+                    // and the backward's looser bound on p2 accepts every hit.)
+                    float alpha[kPixPerLane];
+                    bool hit[kPixPerLane];
+                    bool any = false;
+    #pragma unroll
+                    for (int q = 0; q < kPixPerLane; q++) {
+                        const float p2 = splat_p2(ct, et[u2].C2, es[u2].v - fy[q]);
+                        const float apre = splat_alpha_pre(p2, et[u2].lo);
+                        alpha[q] = NC ? apre : fminf(kAlphaMax, apre);   // NC: below the clamp
+                        hit[q] = (p2 <= 0.f) & (alpha[q] >= kAlphaMin);
+                        any |= hit[q];
                     }
-                    const float wgt = blend ? aT : 0.f;
-                    cr[q] = fmaf(et[u2].r, wgt, cr[q]);
-                    cg[q] = fmaf(et[u2].g, wgt, cg[q]);
-                    cb[q] = fmaf(ef[u2].b, wgt, cb[q]);
-                    last[q] = blend ? jp1 : last[q];
-                    T[q] = blend ? testT : T[q];
-                    fy[q] = stop ? kInactiveRow : fy[q];
+                    // no pixel of this part reaches 1/255: nothing to do
+                    if (!wave_any(any)) continue;
+    #pragma unroll
+                    for (int q = 0; q < kPixPerLane; q++) {
+                        const float aT = alpha[q] * T[q];
+                        const float testT = T[q] - aT;   // T (1 - alpha)
+                        const bool blend = hit[q] && testT >= kTMin;
+                        const bool stop = hit[q] && !(testT >= kTMin);
+                        if (STATS) {
+                            nb[q] += blend ? 1u : 0u;
+                            ne[q] = stop ? (uint32_t)jp1 : ne[q];
+                        }
+                        const float wgt = blend ? aT : 0.f;
+                        cr[q] = fmaf(et[u2].r, wgt, cr[q]);
+                        cg[q] = fmaf(et[u2].g, wgt, cg[q]);
+                        cb[q] = fmaf(ef[u2].b, wgt, cb[q]);
+                        last[q] = blend ? jp1 : last[q];
+                        T[q] = blend ? testT : T[q];
+                        fy[q] = stop ? kInactiveRow : fy[q];
+                    }
                 }
+                if (!any_active(fy)) return false;
             }
-            if (!any_active(fy)) break;
-        }
+            return true;
+        };
+        const bool more = nc_batch ? walk(std::true_type{}) : walk(std::false_type{});
+        if (!more) break;
         __syncthreads();
     }
 
