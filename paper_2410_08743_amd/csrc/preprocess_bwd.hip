@@ -111,12 +111,47 @@ __global__ __launch_bounds__(kWindowThreads) void k_slot_reduce(const uint32_t *
         const uint32_t mid = min(hi, (uint32_t)kWindow);
         float d = 0.f;
         uint32_t e = lo;
+        // slots in LDS, kLdsBatch reads in flight, added in slot order
+        constexpr int kLdsBatch = 4;
+        for (; e + kLdsBatch <= mid; e += kLdsBatch) {
+            float v[kLdsBatch][kSplitBwd];
+            bool fl[kLdsBatch][kSplitBwd];
+#pragma unroll
+            for (int u = 0; u < kLdsBatch; u++)
+#pragma unroll
+                for (int p = 0; p < kSplitBwd; p++) {
+                    v[u][p] = s_sl[kSlotFloats * (e + u) + 9 * p + c];
+                    fl[u][p] = s_fl[kSplitBwd * (e + u) + p] != 0;
+                }
+#pragma unroll
+            for (int u = 0; u < kLdsBatch; u++)
+#pragma unroll
+                for (int p = 0; p < kSplitBwd; p++) d += fl[u][p] ? v[u][p] : 0.f;
+        }
         for (; e < mid; e++) {
 #pragma unroll
             for (int p = 0; p < kSplitBwd; p++) {
                 const float v = s_sl[kSlotFloats * e + 9 * p + c];
                 d += s_fl[kSplitBwd * e + p] ? v : 0.f;
             }
+        }
+        // the tail past the window, from global memory: the loads of
+        // kTailBatch slots are issued together, then added in slot order
+        constexpr int kTailBatch = 8;
+        for (; e + kTailBatch <= hi; e += kTailBatch) {
+            float v[kTailBatch][kSplitBwd];
+            uint8_t fl[kTailBatch][kSplitBwd];
+#pragma unroll
+            for (int u = 0; u < kTailBatch; u++)
+#pragma unroll
+                for (int p = 0; p < kSplitBwd; p++) {
+                    v[u][p] = src[kSlotFloats * (size_t)(e + u) + 9 * p + c];
+                    fl[u][p] = fsrc[kSplitBwd * (size_t)(e + u) + p];
+                }
+#pragma unroll
+            for (int u = 0; u < kTailBatch; u++)
+#pragma unroll
+                for (int p = 0; p < kSplitBwd; p++) d += fl[u][p] ? v[u][p] : 0.f;
         }
         for (; e < hi; e++) {
 #pragma unroll
