@@ -47,6 +47,14 @@ def _case(name):
         sc.scales[idx, (k + 1) % 3] *= np.float32(3.0)
         sc.opacities[:] = rng.uniform(0.005, 0.99, sc.n).astype(np.float32)
         return sc, cam, pose
+    if name == "sh1-opaque":
+        # opacities of 0.95-0.999: alpha reaches the 0.99 clamp near the
+        # splats' centres, and most batches take the rasterizers' clamping
+        # walk rather than the walk for splats that cannot reach it
+        sc, cam, pose = random_case(18, 1, 96, 72, 500, depth=(0.8, 5.0))
+        rng = S.rng_for(18, 9)
+        sc.opacities[:] = rng.uniform(0.95, 0.999, sc.n).astype(np.float32)
+        return sc, cam, pose
     if name == "sh2-deep":
         # tile lists of 1000-1200 entries, pixels compositing past several
         # cuts: the backward's chunks start from the forward's cut states
@@ -58,8 +66,8 @@ def _case(name):
     raise KeyError(name)
 
 
-CASES = ["tiny", "sh0", "sh1-ragged", "sh2-near", "sh3-roi", "sh3-dense", "sh1-thin", "sh2-deep",
-         "sh2-deeper"]
+CASES = ["tiny", "sh0", "sh1-ragged", "sh2-near", "sh3-roi", "sh3-dense", "sh1-thin", "sh1-opaque",
+         "sh2-deep", "sh2-deeper"]
 # chunk length of the backward's work items and their most per tile
 CHUNK = 128
 MAX_CHUNKS = 16
