@@ -36,18 +36,20 @@ __global__ __launch_bounds__(256) void k_ranges(const uint32_t *keys, const uint
     if (k == M - 1 || keys[k + 1] != tile) ranges[tile].y = (uint32_t)(k + 1);
 }
 
-// Launch order of the tiles: longest lists first (in buckets of 16
-// entries), so that the longest tiles do not start last and leave a tail.
+// Launch order of the tiles: longest lists first (in buckets of 4 entries:
+// 256 buckets spread the same-address LDS atomics of the counting sort
+// four times thinner than buckets of 16), so that the longest tiles do not
+// start last and leave a tail.
 // The same kernel lists the backward work items (tile, chunk), also longest
 // first by chunk length; their count goes to counters[kCntItems].  The
 // orders only decide which workgroup takes which tile or chunk; every
 // result is the same in any order.
-constexpr int kOrderBuckets = 64;
+constexpr int kOrderBuckets = 256;
 constexpr int kOrderThreads = 1024;
 constexpr int kOrderRounds = 8;   // tiles per thread whose ranges are loaded together
 
 __host__ __device__ constexpr int order_bucket(int len) {
-    return kOrderBuckets - 1 - ((len >> 4) < kOrderBuckets - 1 ? (len >> 4) : kOrderBuckets - 1);
+    return kOrderBuckets - 1 - ((len >> 2) < kOrderBuckets - 1 ? (len >> 2) : kOrderBuckets - 1);
 }
 
 __global__ __launch_bounds__(kOrderThreads) void k_tile_order(const uint2 *ranges, int total_tiles,
@@ -98,13 +100,23 @@ __global__ __launch_bounds__(kOrderThreads) void k_tile_order(const uint2 *range
     }
     __syncthreads();
     // exclusive scans of the two bucket histograms: one wave, a bucket per lane
-    static_assert(kOrderBuckets == kWave, "one bucket per lane");
+    static_assert(kOrderBuckets == 4 * kWave, "four buckets per lane");
     if (t < kWave) {
 #pragma unroll
         for (int h = 0; h < 2; h++) {
-            const uint32_t c = cnt[h][lane];
-            const uint32_t inc = wave_inclusive_scan(c);
-            base[h][lane] = inc - c;
+            uint32_t c[4], s = 0;
+#pragma unroll
+            for (int j = 0; j < 4; j++) {
+                c[j] = cnt[h][4 * lane + j];
+                s += c[j];
+            }
+            const uint32_t inc = wave_inclusive_scan(s);
+            uint32_t e = inc - s;
+#pragma unroll
+            for (int j = 0; j < 4; j++) {
+                base[h][4 * lane + j] = e;
+                e += c[j];
+            }
             if (h == 1 && lane == kWave - 1) counters[kCntItems] = inc;
         }
     }
