@@ -172,8 +172,10 @@ def main():
     def step(s, total):
         # render and L1 gradient in one pass (gsp_render_fwd_l1)
         rast.forward_l1(g, [cam], s["pose"], target, grad=dl, check=False)
-        rast.backward(g, [cam], s["pose"], dl, want=(), pose=True, out={"pose": s["dpose"]})
-        R.pose_adam(s["pose"], s["dpose"], s["m"], s["v"], s["st"], 1e-2, 1e-4, total, guard=rast.ws)
+        # pose-only backward whose final pose reduction applies the Adam step
+        # (gsp_render_bwd_pose_step: bit-identical to backward + pose_adam)
+        rast.backward_pose_step(g, [cam], s["pose"], dl, s["dpose"], s["m"], s["v"], s["st"],
+                                1e-2, 1e-4, total)
 
     rast._ensure(g, N.view_array([cam]))
     s = new_state()

@@ -169,6 +169,21 @@ gsp_status gsp_render_bwd(gsp_ctx *ctx, const gsp_gaussians *g, int32_t V, const
                           void *workspace, size_t ws_bytes, int64_t instance_capacity,
                           const gsp_grads *grads, uint32_t flags, void *stream);
 
+/* One pose-solve iteration's backward and update (Sec. III-B): the pose-only
+ * gsp_render_bwd (grads->pose = dpose, no Gaussian gradient, no flags)
+ * followed by gsp_pose_adam(V, poses, dpose, m, v, steps, params,
+ * guard_workspace = workspace), in the same launches as the backward alone:
+ * the kernel that sums each view's pose gradient also applies its Adam
+ * step.  Results are bit-identical to the two calls.  poses is read by the
+ * backward (the poses of the forward) and then updated in place; dpose
+ * [V][6], m, v [V][6], steps [V]: device.  Argument errors as the two
+ * calls; an overflowed render skips the step on the device. */
+gsp_status gsp_render_bwd_pose_step(gsp_ctx *ctx, const gsp_gaussians *g, int32_t V,
+                                    const gsp_view *views, float *poses,
+                                    const float *const *dl_dimages, void *workspace, size_t ws_bytes,
+                                    int64_t instance_capacity, float *dpose, float *m, float *v,
+                                    int32_t *steps, const gsp_adam_params *params, void *stream);
+
 /* Render and L1 photometric loss in one pass (the pose-estimation objective
  * of Sec. III-B with the L1 term of Eq. (16)): renders exactly as
  * gsp_render_fwd, and in place of each image writes into dl_dimages[v] the

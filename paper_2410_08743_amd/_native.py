@@ -25,7 +25,7 @@ EXPORTS = (
     "gsp_loss_masked_l1_scratch_bytes", "gsp_loss_l1_noalloc", "gsp_render_fwd_store",
     "gsp_render_fwd_l1",
     "gsp_render_bwd_stored", "gsp_lists_bytes", "gsp_list_pairs", "gsp_twist_apply",
-    "gsp_twist_chain",
+    "gsp_twist_chain", "gsp_render_bwd_pose_step",
 )
 
 
@@ -127,6 +127,7 @@ def lib():
         "gsp_list_pairs": ([P, P, P, ctypes.POINTER(I64), ctypes.POINTER(I32)], I32),
         "gsp_twist_apply": ([P, I32, P, P, P, P], I32),
         "gsp_twist_chain": ([P, I32, P, P, P, P], I32),
+        "gsp_render_bwd_pose_step": ([P, P, I32, P, P, P, P, SZ, I64, P, P, P, P, P, P], I32),
         "gsp_status_string": ([I32], ctypes.c_char_p),
         "gsp_last_error": ([], ctypes.c_char_p),
         "gsp_version": ([], ctypes.c_int),

@@ -519,7 +519,7 @@ gsp_status render_bwd(gsp_ctx *ctx, const gsp_gaussians *g, int32_t V, const gsp
                       const float *poses, const float *const *dl_dimages, void *workspace,
                       size_t ws_bytes, int64_t instance_capacity, const void *lists,
                       size_t lists_bytes, int64_t pair_capacity, const gsp_grads *grads,
-                      uint32_t flags, void *stream) {
+                      uint32_t flags, void *stream, const gsp::PoseAdamK *adam = nullptr) {
     gsp_status s = check_device(ctx);
     if (s != GSP_OK) return s;
     Prepared p;
@@ -551,7 +551,7 @@ gsp_status render_bwd(gsp_ctx *ctx, const gsp_gaussians *g, int32_t V, const gsp
         return hip_fail(e, "raster backward");
     if ((e = stage(ctx, "preprocess_bwd", st, [&] {
              return gsp::launch_preprocess_bwd(kernel_gaussians(g), p.views, poses, p.L, ws, *grads,
-                                               (flags & GSP_ACCUMULATE) != 0, st);
+                                               (flags & GSP_ACCUMULATE) != 0, st, adam);
          })) != hipSuccess)
         return hip_fail(e, "preprocess backward");
     return GSP_OK;
@@ -565,6 +565,32 @@ gsp_status gsp_render_bwd(gsp_ctx *ctx, const gsp_gaussians *g, int32_t V, const
                           uint32_t flags, void *stream) {
     return render_bwd(ctx, g, V, views, poses, dl_dimages, workspace, ws_bytes, instance_capacity,
                       nullptr, 0, 0, grads, flags, stream);
+}
+
+gsp_status gsp_render_bwd_pose_step(gsp_ctx *ctx, const gsp_gaussians *g, int32_t V,
+                                    const gsp_view *views, float *poses,
+                                    const float *const *dl_dimages, void *workspace, size_t ws_bytes,
+                                    int64_t instance_capacity, float *dpose, float *m, float *v,
+                                    int32_t *steps, const gsp_adam_params *params, void *stream) {
+    if (!poses || !dpose || !m || !v || !steps || !params) return fail(GSP_EINVAL, "null argument");
+    if (!(params->beta1 >= 0.f && params->beta1 < 1.f && params->beta2 >= 0.f &&
+          params->beta2 < 1.f && params->eps > 0.f))
+        return fail(GSP_EINVAL, "bad Adam hyper-parameters");
+    if (params->parametrization != GSP_POSE_SE3 && params->parametrization != GSP_POSE_T_SO3)
+        return fail(GSP_EINVAL, "unknown pose parametrization %d", params->parametrization);
+    if (!workspace) return fail(GSP_EINVAL, "null workspace");
+    gsp_grads grads;
+    std::memset(&grads, 0, sizeof grads);
+    grads.pose = dpose;
+    gsp::PoseAdamK ad;
+    ad.poses = poses;
+    ad.m = m;
+    ad.v = v;
+    ad.steps = steps;
+    ad.p = *params;
+    ad.guard = static_cast<const uint32_t *>(workspace);   // the counters open the workspace
+    return render_bwd(ctx, g, V, views, poses, dl_dimages, workspace, ws_bytes, instance_capacity,
+                      nullptr, 0, 0, &grads, 0u, stream, &ad);
 }
 
 gsp_status gsp_render_bwd_stored(gsp_ctx *ctx, const gsp_gaussians *g, int32_t V,

@@ -203,9 +203,18 @@ ListLayout make_list_layout(const Layout &L, int64_t pair_capacity);
 hipError_t launch_store_lists(const ViewsK &views, const Layout &L, char *ws, const uint32_t *vals,
                               const ListLayout &Q, char *lists, hipStream_t s);
 // preprocess_bwd.hip
+// Optional Adam step that the backward's final pose reduction applies to
+// each view once its gradient is summed (the arguments of gsp_pose_adam;
+// guard: the counters of the backward's workspace).
+struct PoseAdamK {
+    float *poses, *m, *v;
+    int32_t *steps;
+    gsp_adam_params p;
+    const uint32_t *guard;
+};
 hipError_t launch_preprocess_bwd(const GaussiansK &g, const ViewsK &views, const float *poses,
                                  const Layout &L, char *ws, const gsp_grads &grads,
-                                 bool accumulate, hipStream_t s);
+                                 bool accumulate, hipStream_t s, const PoseAdamK *adam = nullptr);
 // misc.hip
 struct LossViewsK {
     const float *pred[GSP_MAX_VIEWS];

@@ -22,8 +22,11 @@
 // a fixed order.  No atomics anywhere, so the result is bit-reproducible and
 // a view's pose gradient does not depend on which other views share the
 // launch.
+#include <cstring>
+
 #include "block_ops.h"
 #include "gsp_internal.h"
+#include "pose_step.h"
 #include "sh_basis.h"
 
 namespace gsp {
@@ -472,9 +475,30 @@ constexpr int kPoseFinalThreads = 256;
 constexpr int kPoseFinalPer = 16;   // partial rows per thread held in flight
 
 __global__ __launch_bounds__(kPoseFinalThreads) void k_pose_final(const double *posepart, int nrows,
-                                                                  float *dpose, bool accumulate) {
+                                                                  float *dpose, bool accumulate,
+                                                                  PoseAdamK ad, bool adam) {
     __shared__ double red[6][kPoseFinalThreads];
+    __shared__ float dp6[6];
     const int v = blockIdx.x, t = threadIdx.x;
+    // with the Adam step: its state, read before the rows (one round of
+    // memory latency for both)
+    uint32_t ovf = 0u;
+    int k = 0;
+    double m0[6] = {0, 0, 0, 0, 0, 0}, v0[6] = {0, 0, 0, 0, 0, 0};
+    float T0[12];
+#pragma unroll
+    for (int e = 0; e < 12; e++) T0[e] = 0.f;
+    if (adam && t == 0) {
+        ovf = ad.guard[kCntOverflow];
+        k = ad.steps[v] + 1;
+#pragma unroll
+        for (int e = 0; e < 6; e++) {
+            m0[e] = ad.m[6 * v + e];
+            v0[e] = ad.v[6 * v + e];
+        }
+#pragma unroll
+        for (int e = 0; e < 12; e++) T0[e] = ad.poses[12 * v + e];
+    }
     const double *src = posepart + (size_t)v * nrows * 6;
     double s[6] = {0, 0, 0, 0, 0, 0};
     for (int b0 = 0; b0 < nrows; b0 += kPoseFinalThreads * kPoseFinalPer) {
@@ -504,7 +528,22 @@ __global__ __launch_bounds__(kPoseFinalThreads) void k_pose_final(const double *
         x += __shfl_xor(x, 1, 8);
         x += __shfl_xor(x, 2, 8);
         x += __shfl_xor(x, 4, 8);
-        if (h == 0) dpose[6 * v + c] = (accumulate ? dpose[6 * v + c] : 0.f) + (float)x;
+        if (h == 0) {
+            const float g = (accumulate ? dpose[6 * v + c] : 0.f) + (float)x;
+            dpose[6 * v + c] = g;
+            dp6[c] = g;
+        }
+    }
+    if (adam) {
+        // the step gsp_pose_adam would take from this gradient (skipped when
+        // the render overflowed its instance capacity)
+        __syncthreads();
+        if (t == 0 && ovf == 0u) {
+            double gv[6];
+#pragma unroll
+            for (int e = 0; e < 6; e++) gv[e] = dp6[e];
+            pose_adam_apply(v, k, gv, m0, v0, T0, ad.poses, ad.m, ad.v, ad.steps, ad.p);
+        }
     }
 }
 
@@ -518,7 +557,7 @@ static void launch_pb(const PbArgs &a, const ViewsK &views, bool want, int nblk,
 
 hipError_t launch_preprocess_bwd(const GaussiansK &g, const ViewsK &views, const float *poses,
                                  const Layout &L, char *ws, const gsp_grads &grads,
-                                 bool accumulate, hipStream_t s) {
+                                 bool accumulate, hipStream_t s, const PoseAdamK *adam) {
     const bool want = grads.means || grads.scales || grads.quats || grads.opacities || grads.sh;
     PbArgs a;
     a.g = g;
@@ -553,8 +592,12 @@ hipError_t launch_preprocess_bwd(const GaussiansK &g, const ViewsK &views, const
         if (e != hipSuccess) return e;
     }
     if (grads.pose) {
+        PoseAdamK ad;
+        std::memset(&ad, 0, sizeof ad);
+        if (adam) ad = *adam;
         hipLaunchKernelGGL(k_pose_final, dim3(L.V), dim3(kPoseFinalThreads), 0, s, a.posepart,
-                           L.nblk_pre * kPoseRowsPerBlock, grads.pose, accumulate);
+                           L.nblk_pre * kPoseRowsPerBlock, grads.pose, accumulate, ad,
+                           adam != nullptr);
         return hipGetLastError();
     }
     return hipSuccess;

@@ -326,6 +326,29 @@ class Rasterizer:
                                      _stream()), "gsp_render_bwd")
         return out
 
+    def backward_pose_step(self, g: GaussianParams, cams: Sequence, poses: torch.Tensor, dl_dimages,
+                           dpose, m, v, steps, lr_start, lr_end, total_steps, beta1=0.9,
+                           beta2=0.999, eps=1e-8, parametrization: str = "se3"):
+        """The pose-only backward of the last forward followed by the Adam
+        step of `pose_adam` (guarded by this workspace), in the backward's
+        launches: `dpose` receives the pose gradient and `poses`, `m`, `v`,
+        `steps` are updated in place, bit for bit as the two calls would."""
+        if self.store_lists:
+            raise ValueError("backward_pose_step runs the recomputing backward only")
+        L = N.lib()
+        views = N.view_array(cams)
+        gs = g.struct()
+        nbytes = self._ws_bytes(g.n, g.sh_degree, views, self.capacity)
+        prm = N.AdamParams(lr_start, lr_end, int(total_steps), beta1, beta2, eps,
+                           PARAMETRIZATIONS[parametrization])
+        if not poses.is_contiguous():
+            raise ValueError("poses must be contiguous: they are updated in place")
+        N.check(L.gsp_render_bwd_pose_step(context(self.device), ctypes.byref(gs), len(cams), views,
+                                           _ptr(poses), view_ptrs(dl_dimages, cams, 3),
+                                           _ptr(self.ws), nbytes, self.capacity, _ptr(dpose),
+                                           _ptr(m), _ptr(v), _ptr(steps), ctypes.byref(prm),
+                                           _stream()), "gsp_render_bwd_pose_step")
+
     def inspect(self, g: GaussianParams, cams: Sequence, name: str, dtype=torch.float32):
         """A copy of an intermediate workspace array of the last call."""
         L = N.lib()
