@@ -561,9 +561,14 @@ def solve_poses(g: GaussianParams, cams: Sequence, targets: torch.Tensor, init_p
                 # render and L1 gradient in one pass
                 loss, _, _ = rast.forward_l1(g, cams, poses, targets, grad=dl, with_loss=history,
                                              check=False)
-            rast.backward(g, cams, poses, dl, want=(), pose=True, out={"pose": dpose})
-            pose_adam(poses, dpose, m, v, st, lr[0], lr[1], steps, betas[0], betas[1], eps,
-                      guard=rast.ws, parametrization=parametrization)
+            if rast.store_lists:
+                rast.backward(g, cams, poses, dl, want=(), pose=True, out={"pose": dpose})
+                pose_adam(poses, dpose, m, v, st, lr[0], lr[1], steps, betas[0], betas[1], eps,
+                          guard=rast.ws, parametrization=parametrization)
+            else:
+                # the same step applied by the backward's final pose reduction
+                rast.backward_pose_step(g, cams, poses, dl, dpose, m, v, st, lr[0], lr[1], steps,
+                                        betas[0], betas[1], eps, parametrization=parametrization)
             return loss
 
         if graph:
