@@ -156,13 +156,13 @@ class PoseServer:
         dpose = ctypes.c_void_p(self.dpose.data_ptr())
         N.check(L.gsp_render_fwd_l1(ctx, ctypes.byref(gs), V, views, poses, tgt, dl, None, None,
                                     wsp, nbytes, cap, st), "gsp_render_fwd_l1")
-        gr = N.Grads(None, None, None, None, None, self.dpose.data_ptr())
-        N.check(L.gsp_render_bwd(ctx, ctypes.byref(gs), V, views, poses, dl, wsp, nbytes, cap,
-                                 ctypes.byref(gr), 0, st), "gsp_render_bwd")
-        N.check(L.gsp_pose_adam(ctx, V, poses, dpose, ctypes.c_void_p(self.m.data_ptr()),
-                                ctypes.c_void_p(self.v.data_ptr()),
-                                ctypes.c_void_p(self.steps.data_ptr()), ctypes.byref(self.adam),
-                                wsp, st), "gsp_pose_adam")
+        # pose-only backward whose final pose reduction applies the Adam step
+        # (bit-identical to gsp_render_bwd + gsp_pose_adam guarded by wsp)
+        N.check(L.gsp_render_bwd_pose_step(ctx, ctypes.byref(gs), V, views, poses, dl, wsp, nbytes,
+                                           cap, dpose, ctypes.c_void_p(self.m.data_ptr()),
+                                           ctypes.c_void_p(self.v.data_ptr()),
+                                           ctypes.c_void_p(self.steps.data_ptr()),
+                                           ctypes.byref(self.adam), st), "gsp_render_bwd_pose_step")
         pinned.copy_(self.ws[:16], non_blocking=True)
         ev = torch.cuda.Event(enable_timing=True)
         ev.record()
